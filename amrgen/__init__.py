@@ -1,0 +1,252 @@
+"""Seeded synthetic AMR cell sets.
+
+This module only *produces inputs*: flat, unsorted lists of AMR cells
+(int32 lower corner, int32 level, float32 value) plus an iso-value.  It holds
+none of the dual-mesh / iso-surface arithmetic; both the CPU oracle and the
+HIP library consume its arrays.
+
+Cell convention (paper, section 3.1): level 0 is the finest level, a level-l
+cell has width 2^l and a lower corner that is a multiple of 2^l.
+
+Randomness is counter based: every random number is a pure function of
+(seed, stream, key) through the SplitMix64 output function (Steele, Lea and
+Flood, "Fast splittable pseudorandom number generators", OOPSLA 2014), so a
+cell's random draw does not depend on the order in which cells are visited.
+The final cell order is a seeded shuffle (sort by a hash of the cell key).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_U64 = np.uint64
+_MASK = (1 << 64) - 1
+
+
+def _mix64(z: np.ndarray) -> np.ndarray:
+    """SplitMix64 finaliser on a uint64 array (wrapping arithmetic)."""
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> _U64(30))) * _U64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> _U64(27))) * _U64(0x94D049BB133111EB)
+    return z ^ (z >> _U64(31))
+
+
+def hash64(seed: int, stream: int, key) -> np.ndarray:
+    """64-bit hash of (seed, stream, key); key is a uint64 array."""
+    s = ((seed * 0x9E3779B97F4A7C15) ^ (stream * 0xD1B54A32D192ED03)) & _MASK
+    s = int(_mix64(np.array([s], dtype=np.uint64))[0])
+    return _mix64(np.asarray(key, dtype=np.uint64) ^ _U64(s))
+
+
+def uniform(seed: int, stream: int, key) -> np.ndarray:
+    """Uniform doubles in [0, 1) from the top 53 bits of hash64."""
+    return (hash64(seed, stream, key) >> _U64(11)).astype(np.float64) * (1.0 / (1 << 53))
+
+
+def cell_key(x, y, z, level) -> np.ndarray:
+    """Unique uint64 label of a cell (x, y, z >= -2^19 and < 2^19 assumed)."""
+    off = 1 << 19
+    ux = (np.asarray(x, np.int64) + off).astype(np.uint64)
+    uy = (np.asarray(y, np.int64) + off).astype(np.uint64)
+    uz = (np.asarray(z, np.int64) + off).astype(np.uint64)
+    lv = np.asarray(level, np.int64).astype(np.uint64)
+    return (lv << _U64(60)) | (uz << _U64(40)) | (uy << _U64(20)) | ux
+
+
+@dataclass
+class CellSet:
+    """A flat AMR cell list in structure-of-arrays form."""
+    xyz: np.ndarray          # int32 [n, 3], lower corners
+    level: np.ndarray        # int32 [n]
+    value: np.ndarray        # float32 [n]
+    iso: float = 0.0         # default iso-value for this workload
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.level.shape[0])
+
+    def shuffled(self, seed: int) -> "CellSet":
+        key = cell_key(self.xyz[:, 0], self.xyz[:, 1], self.xyz[:, 2], self.level)
+        order = np.argsort(hash64(seed, 99, key), kind="stable")
+        return CellSet(np.ascontiguousarray(self.xyz[order]), np.ascontiguousarray(self.level[order]),
+                       np.ascontiguousarray(self.value[order]), self.iso, self.name, dict(self.meta))
+
+    def centres(self) -> np.ndarray:
+        w = (1 << self.level.astype(np.int64)).astype(np.float64)
+        return self.xyz.astype(np.float64) + 0.5 * w[:, None]
+
+
+def _make(xyz, level, value, iso, name, seed, **meta) -> CellSet:
+    cs = CellSet(np.ascontiguousarray(np.asarray(xyz, np.int32).reshape(-1, 3)),
+                 np.ascontiguousarray(np.asarray(level, np.int32)),
+                 np.ascontiguousarray(np.asarray(value, np.float32)), float(np.float32(iso)), name, meta)
+    return cs.shuffled(seed)
+
+
+_CHILD = np.array([[i & 1, (i >> 1) & 1, (i >> 2) & 1] for i in range(8)], dtype=np.int64)
+
+
+# ---------------------------------------------------------------------------
+# Workload 1: tiny two-level set, 16^3 domain
+# ---------------------------------------------------------------------------
+
+def two_level_sphere(seed: int = 1) -> CellSet:
+    """512 level-0 cells filling [4,12)^3 and 448 level-1 cells filling the rest
+    of [0,16)^3; value = |centre - (8,8,8)| (computed in float64, stored as
+    float32); iso 5.0."""
+    r = np.arange(4, 12)
+    fine = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(-1, 3)
+    r2 = np.arange(0, 16, 2)
+    coarse = np.stack(np.meshgrid(r2, r2, r2, indexing="ij"), -1).reshape(-1, 3)
+    inside = np.all((coarse >= 4) & (coarse < 12), axis=1)
+    coarse = coarse[~inside]
+    xyz = np.concatenate([fine, coarse])
+    lvl = np.concatenate([np.zeros(len(fine), np.int32), np.ones(len(coarse), np.int32)])
+    c = xyz.astype(np.float64) + 0.5 * (1 << lvl)[:, None]
+    val = np.sqrt(((c - 8.0) ** 2).sum(1))
+    return _make(xyz, lvl, val, 5.0, "two-level-sphere-16", seed)
+
+
+# ---------------------------------------------------------------------------
+# Octree sets: random refinement concentrated on a spherical shell
+# ---------------------------------------------------------------------------
+
+def _box_hits_shell(lo, w, c, r0, r1):
+    lo = lo.astype(np.float64)
+    hi = lo + w
+    d = np.maximum(np.maximum(lo - c, 0.0), c - hi)
+    dmin = np.sqrt((d * d).sum(1))
+    far = np.maximum(np.abs(lo - c), np.abs(hi - c))
+    dmax = np.sqrt((far * far).sum(1))
+    return (dmin < r1) & (dmax > r0)
+
+
+def _gaussian_field(pts, seed, domain, n_g=8, sig=(10.0, 40.0), amp=(0.5, 1.5)):
+    k = np.arange(n_g, dtype=np.uint64)
+    mu = np.stack([uniform(seed, 10 + a, k) * domain for a in range(3)], 1)
+    sg = sig[0] + (sig[1] - sig[0]) * uniform(seed, 13, k)
+    am = amp[0] + (amp[1] - amp[0]) * uniform(seed, 14, k)
+    out = np.zeros(len(pts), np.float64)
+    for g in range(n_g):
+        d2 = ((pts - mu[g]) ** 2).sum(1)
+        out += am[g] * np.exp(-d2 / (2.0 * sg[g] ** 2))
+    return out, dict(mu=mu, sigma=sg, amp=am)
+
+
+def octree_shell(domain: int = 256, root_level: int = 4, shell=(60.0, 70.0), p_in: float = 0.6,
+                 p_out: float = 0.1, seed: int = 2, sigma=(10.0, 40.0), n_gauss: int = 8,
+                 name: str | None = None) -> CellSet:
+    """Octree AMR without 2:1 balance.  Roots are level-`root_level` cells tiling
+    [0, domain)^3; every cell above level 0 is split into its 8 children with
+    probability p_in if its box meets the shell r0 < |x - c| < r1 around the
+    domain centre, else p_out.  Value: sum of `n_gauss` seeded isotropic
+    Gaussians at the cell centre; iso: the lower median of the cell values."""
+    w0 = 1 << root_level
+    assert domain % w0 == 0
+    n = domain // w0
+    r = np.arange(n, dtype=np.int64) * w0
+    g = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(-1, 3)
+    c = domain / 2.0
+    leaves, lvls = [], []
+    lvl = root_level
+    while True:
+        w = 1 << lvl
+        if lvl == 0 or len(g) == 0:
+            leaves.append(g)
+            lvls.append(np.full(len(g), lvl, np.int32))
+            break
+        hit = _box_hits_shell(g, w, c, shell[0], shell[1])
+        u = uniform(seed, 1, cell_key(g[:, 0], g[:, 1], g[:, 2], np.full(len(g), lvl)))
+        split = u < np.where(hit, p_in, p_out)
+        leaves.append(g[~split])
+        lvls.append(np.full(int((~split).sum()), lvl, np.int32))
+        g = (g[split][:, None, :] + _CHILD[None] * (w // 2)).reshape(-1, 3)
+        lvl -= 1
+    xyz = np.concatenate(leaves)
+    lv = np.concatenate(lvls)
+    ctr = xyz.astype(np.float64) + 0.5 * (1 << lv.astype(np.int64))[:, None]
+    val, gp = _gaussian_field(ctr, seed, float(domain), n_gauss, sigma)
+    v32 = val.astype(np.float32)
+    iso = np.sort(v32)[(len(v32) - 1) // 2]
+    nm = name or f"octree-shell-{domain}"
+    return _make(xyz, lv, v32, float(iso), nm, seed, domain=domain, root_level=root_level,
+                 shell=tuple(shell), p_in=p_in, p_out=p_out, **gp)
+
+
+def octree_sized(target_cells: int, seed: int) -> CellSet:
+    """Octree-shell set whose domain is scaled (shell radii with it) so that the
+    cell count lands near `target_cells`; used for batches of uneven sets."""
+    base = 136_669.0  # cells of the 256^3 recipe at seed 2
+    s = (max(target_cells, 1000) / base) ** (1.0 / 3.0)
+    domain = max(32, int(round(256 * s / 16.0)) * 16)
+    k = domain / 256.0
+    return octree_shell(domain=domain, shell=(60.0 * k, 70.0 * k), seed=seed,
+                        sigma=(10.0 * k, 40.0 * k), name=f"octree-shell-{domain}-s{seed}")
+
+
+# ---------------------------------------------------------------------------
+# Small sets for property tests
+# ---------------------------------------------------------------------------
+
+def uniform_grid(n: int, level: int = 0, seed: int = 5, origin=(0, 0, 0), field_kind: str = "gauss") -> CellSet:
+    """n^3 cells on one level; value from a smooth seeded field."""
+    w = 1 << level
+    r = np.arange(n, dtype=np.int64) * w
+    xyz = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(-1, 3) + np.asarray(origin, np.int64)
+    ctr = xyz.astype(np.float64) + 0.5 * w
+    if field_kind == "gauss":
+        val, _ = _gaussian_field(ctr - np.asarray(origin, np.float64), seed, float(n * w), 4,
+                                 (0.15 * n * w, 0.4 * n * w))
+    else:
+        val = uniform(seed, 7, cell_key(xyz[:, 0], xyz[:, 1], xyz[:, 2], np.full(len(xyz), level)))
+    v32 = val.astype(np.float32)
+    iso = np.sort(v32)[(len(v32) - 1) // 2]
+    return _make(xyz, np.full(len(xyz), level, np.int32), v32, float(iso), f"grid-{n}-l{level}", seed)
+
+
+def random_octree(seed: int, roots: int = 2, root_level: int = 3, p_split: float = 0.45,
+                  p_hole: float = 0.0, origin=(0, 0, 0), values: str = "random") -> CellSet:
+    """Tiny random octree: roots^3 root cells, each cell split with probability
+    p_split, leaves dropped (holes) with probability p_hole.  Level jumps are
+    unrestricted.  Values are seeded uniforms (or a smooth field)."""
+    w0 = 1 << root_level
+    r = np.arange(roots, dtype=np.int64) * w0
+    g = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(-1, 3) + np.asarray(origin, np.int64)
+    leaves, lvls = [], []
+    lvl = root_level
+    while len(g):
+        w = 1 << lvl
+        key = cell_key(g[:, 0], g[:, 1], g[:, 2], np.full(len(g), lvl))
+        split = (uniform(seed, 1, key) < p_split) if lvl > 0 else np.zeros(len(g), bool)
+        keep = ~split
+        leaves.append(g[keep])
+        lvls.append(np.full(int(keep.sum()), lvl, np.int32))
+        g = (g[split][:, None, :] + _CHILD[None] * (w // 2)).reshape(-1, 3)
+        lvl -= 1
+    xyz = np.concatenate(leaves)
+    lv = np.concatenate(lvls)
+    if p_hole > 0:
+        u = uniform(seed, 2, cell_key(xyz[:, 0], xyz[:, 1], xyz[:, 2], lv))
+        m = u >= p_hole
+        xyz, lv = xyz[m], lv[m]
+    key = cell_key(xyz[:, 0], xyz[:, 1], xyz[:, 2], lv)
+    if values == "random":
+        val = uniform(seed, 3, key)
+    else:
+        ctr = xyz.astype(np.float64) + 0.5 * (1 << lv.astype(np.int64))[:, None]
+        ext = float(roots * w0)
+        val, _ = _gaussian_field(ctr - np.asarray(origin, np.float64), seed, ext, 3, (0.2 * ext, 0.5 * ext))
+    v32 = val.astype(np.float32)
+    iso = np.sort(v32)[(len(v32) - 1) // 2] if len(v32) else 0.0
+    return _make(xyz, lv, v32, float(iso), f"random-octree-s{seed}", seed)
+
+
+WORKLOADS = {
+    "two-level-sphere-16": two_level_sphere,
+    "octree-shell-256": octree_shell,
+}
