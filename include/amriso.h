@@ -1,0 +1,149 @@
+/*
+ * amriso.h -- C ABI of libamriso.so: dual cells and crack-free iso-surfaces
+ * of AMR data on an AMD Instinct MI355X (gfx950).
+ *
+ * Method: I. Wald, "A Simple, General, and GPU Friendly Method for Computing
+ * Dual Mesh and Iso-Surfaces of Adaptive Mesh Refinement (AMR) Data"
+ * (arXiv 2004.08475).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Cells (paper sec. 3.1): an AMR data set is a flat, unsorted list of
+ *    cells (i,j,k;l).  Level 0 is the finest; a level-l cell has width 2^l, a
+ *    lower corner that is a multiple of 2^l and covers [lo, lo + 2^l) on
+ *    each axis.  Cells carry one float value at their centre lo + 2^l/2.
+ *    No hierarchy, bricks or level balance are assumed (sec. 3.1, sec. 6):
+ *    any level jumps and holes are allowed; cells must not overlap.
+ *  - Memory: every pointer marked "device" is device memory of the set's
+ *    GPU, owned by the caller (for instance a torch tensor).  The library
+ *    only borrows it.  The library itself allocates one small control block
+ *    per set (a few KB, freed by amr_destroy).
+ *  - Streams: every call enqueues its work on the given HIP stream.  Calls
+ *    on one set must be issued on one stream at a time (they share the
+ *    set's scratch space inside the index workspace).
+ *  - Errors: functions return an amr_status; they never abort or throw.
+ *    amr_last_error() gives a message for the calling thread.
+ *  - Limits: 0 <= level <= 20; every coordinate c satisfies
+ *    -2^23 <= c and c + 2^level <= 2^23 (cell centres are then exact in
+ *    float32); per axis, max(c + 2^level) - min(c) + 2^(Lmax+3) <= 2^20
+ *    finest units, Lmax being the coarsest level present.  Outside:
+ *    AMR_ERANGE.
+ */
+#ifndef AMRISO_H
+#define AMRISO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct amr_set amr_set; /* opaque, library-owned host handle */
+
+typedef enum amr_status {
+    AMR_OK = 0,
+    AMR_EINVAL = -1,   /* bad argument, misaligned corner, level < 0, non-finite value */
+    AMR_ERANGE = -2,   /* outside the coordinate / level limits above */
+    AMR_EOVERLAP = -3, /* two cells overlap (duplicates or nested cells) */
+    AMR_ENOSPACE = -4, /* a caller buffer or the index workspace is too small */
+    AMR_ESTATE = -5,   /* call out of order (e.g. extraction before amr_build_index) */
+    AMR_EHIP = -6,     /* a HIP runtime call failed */
+    AMR_ENOMEM = -7    /* host or control-block allocation failed */
+} amr_status;
+
+/* Create an empty set bound to HIP device `hip_device`.  *out receives the
+   handle.  Returns AMR_EINVAL for a bad device, AMR_EHIP / AMR_ENOMEM on
+   allocation failure. */
+int amr_create(amr_set** out, int hip_device);
+
+/* Destroy a set (NULL is allowed).  Waits for nothing: the caller must have
+   synchronised the set's stream. */
+void amr_destroy(amr_set* set);
+
+/* Input stage (paper sec. 3.1; the cell list of the pipeline in the figure
+   of its sec. 5.2).  Borrows n cells in structure-of-arrays form:
+     xyz   device int32 [n][3]  lower corners, in finest-level units
+     level device int32 [n]     levels
+     value device float [n]     cell values
+   The arrays must stay alive and unchanged until the set is destroyed or
+   re-uploaded.  Validates every cell on the device (level range, alignment
+   of the corner to 2^level, finite value, coordinate limits) and reduces
+   the bounding box and per-level counts; then synchronises `stream` to read
+   them back.  Returns AMR_EINVAL / AMR_ERANGE for bad cells (message names
+   the first offending index).  n == 0 is allowed (an empty set).
+   Invalidates any index built before. */
+int amr_upload(amr_set* set, const int32_t* xyz, const int32_t* level, const float* value, int64_t n,
+               hipStream_t stream);
+
+/* Bytes of device workspace amr_build_index needs for the uploaded set
+   (host-only, no GPU work).  After amr_build_index returned AMR_ENOSPACE
+   the answer grows to fit the set. */
+int amr_index_bytes(const amr_set* set, size_t* bytes);
+
+/* Cell-location index (paper sec. 3.2: the paper sorts the cells by their
+   integer coordinates and binary-searches per level; this library stores
+   the cells of each level in an open-addressing hash keyed by the integer
+   coordinates of their 2x2x2 sibling block, so one probe returns up to
+   eight same-level cells).  `workspace` is caller-owned device memory of at
+   least amr_index_bytes() bytes, 256-byte aligned; it must stay alive while
+   the set is used.  Also checks that no two cells overlap.  Synchronises
+   `stream` to read the result.  Returns AMR_EOVERLAP for duplicate or
+   nested cells, AMR_ENOSPACE if the hash table was too small (query
+   amr_index_bytes again and retry with a larger workspace), AMR_ESTATE
+   before amr_upload. */
+int amr_build_index(amr_set* set, void* workspace, size_t bytes, hipStream_t stream);
+
+/* Dual cells (paper sec. 4.2-4.4).  For every cell and each of its 8
+   corners, the logical same-level dual centred on that corner is snapped to
+   the actual cells around it and emitted unless a vertex is missing
+   (rule 1), lies on a finer level (rule 2) or is a same-level cell that
+   precedes the generating one (rule 3), so every dual is emitted once.
+   Outputs (device, may be NULL when cap == 0):
+     corner_level int32 [cap][4]  (P.x, P.y, P.z, l): the dual's centre
+                                  vertex P (a cell corner) and its level
+     verts        int32 [cap][8]  indices (into the uploaded arrays) of the
+                                  cells at slots s = ex + 2*ey + 4*ez,
+                                  i.e. the cells containing P + (e - 1)*2^l
+   counts: device int64 [2]; counts[0] = counts[1] = number of emitted duals.
+   Records past cap are not written.  Asynchronous: the caller reads counts
+   and re-runs with a larger buffer when counts[0] > cap.  The order of the
+   records is fixed for a given index.  Returns AMR_ESTATE before
+   amr_build_index. */
+int amr_dual_cells(amr_set* set, int32_t* corner_level, int32_t* verts, int64_t cap, int64_t* counts,
+                   hipStream_t stream);
+
+/* Iso-surface (paper sec. 5): every emitted dual, degenerate or not, is a
+   hexahedron with its vertices at the centres of its 8 cells and goes
+   through Marching Cubes (bit s of the case is set when the value at slot s
+   is >= iso).  Triangles whose three vertices are not distinct (two of
+   their hexahedron edges join the same pair of cells) are dropped.  On a
+   cut edge, A is the end with value < iso and B the end with value >= iso;
+   the vertex is fmaf(t, cB - cA, cA) with t = (iso - vA) / (vB - vA) in
+   IEEE float32.  The surface is crack-free: faces shared by two duals yield
+   identical vertices.
+   Outputs (device, each may be NULL; all NULL with cap == 0 counts only):
+     tris      float [cap][3][3]  vertex positions, ordered so that the
+                                  right-hand normal points into the >= iso
+                                  side
+     tri_cells int32 [cap][3][2]  per vertex, the (A, B) cell indices of its
+                                  edge (a weld key for an indexed mesh)
+     tri_dual  int32 [cap]        index of the generating dual in the order
+                                  amr_dual_cells writes them
+   counts: device int64 [2]; counts[0] = triangles, counts[1] = emitted
+   duals.  Triangles past cap are not written.  Asynchronous and free of
+   host synchronisation, so it can be captured in a HIP graph.  Returns
+   AMR_EINVAL for a non-finite iso, AMR_ESTATE before amr_build_index. */
+int amr_isosurface(amr_set* set, float iso, float* tris, int32_t* tri_cells, int32_t* tri_dual, int64_t cap,
+                   int64_t* counts, hipStream_t stream);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char* amr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AMRISO_H */

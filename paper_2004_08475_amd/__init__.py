@@ -1,0 +1,214 @@
+"""amriso -- dual cells and crack-free iso-surfaces of AMR data on MI355X.
+
+Thin ctypes binding over ``libamriso.so`` (C ABI in include/amriso.h).  It
+only marshals arguments: torch supplies device memory and the current HIP
+stream, every step of the method runs in the library's HIP kernels.  There
+is no CPU fallback: if the library is not built, importing works but any use
+raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libamriso.so")
+
+AMR_OK, AMR_EINVAL, AMR_ERANGE, AMR_EOVERLAP, AMR_ENOSPACE, AMR_ESTATE, AMR_EHIP, AMR_ENOMEM = 0, -1, -2, -3, -4, -5, -6, -7
+_NAMES = {0: "AMR_OK", -1: "AMR_EINVAL", -2: "AMR_ERANGE", -3: "AMR_EOVERLAP", -4: "AMR_ENOSPACE",
+          -5: "AMR_ESTATE", -6: "AMR_EHIP", -7: "AMR_ENOMEM"}
+
+# Every entry point of the C ABI (include/amriso.h).
+ABI_SYMBOLS = ("amr_create", "amr_destroy", "amr_upload", "amr_index_bytes", "amr_build_index", "amr_dual_cells",
+               "amr_isosurface", "amr_last_error")
+
+_lib = None
+
+
+class AmrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s: %s" % (_NAMES.get(code, str(code)), msg))
+        self.code = code
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libamriso.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libamriso.so is not built (%s); run __graft_entry__.build() or "
+                           "python paper_2004_08475_amd/_build.py" % path)
+    L = C.CDLL(path)
+    vp, i64, i32p, f32p, i64p = C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p
+    L.amr_create.argtypes = [C.POINTER(C.c_void_p), C.c_int]
+    L.amr_create.restype = C.c_int
+    L.amr_destroy.argtypes = [vp]
+    L.amr_destroy.restype = None
+    L.amr_upload.argtypes = [vp, i32p, i32p, f32p, i64, vp]
+    L.amr_upload.restype = C.c_int
+    L.amr_index_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+    L.amr_index_bytes.restype = C.c_int
+    L.amr_build_index.argtypes = [vp, vp, C.c_size_t, vp]
+    L.amr_build_index.restype = C.c_int
+    L.amr_dual_cells.argtypes = [vp, i32p, i32p, i64, i64p, vp]
+    L.amr_dual_cells.restype = C.c_int
+    L.amr_isosurface.argtypes = [vp, C.c_float, f32p, i32p, i32p, i64, i64p, vp]
+    L.amr_isosurface.restype = C.c_int
+    L.amr_last_error.argtypes = []
+    L.amr_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _check(code: int):
+    if code != AMR_OK:
+        raise AmrError(code, _lib.amr_last_error().decode(errors="replace"))
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class AmrSet:
+    """One AMR cell set on one GPU: upload, index, dual cells, iso-surfaces.
+
+    Calls on one set are issued on the caller's current torch stream and must
+    not overlap with calls on another stream."""
+
+    def __init__(self, device=None):
+        self.lib = load_library()
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = torch.device("cuda", device if isinstance(device, int) else torch.device(device).index or 0)
+        h = C.c_void_p()
+        _check(self.lib.amr_create(C.byref(h), self.device.index))
+        self._h = h
+        self.counts = torch.zeros(2, dtype=torch.int64, device=self.device)
+        self._cells = None
+        self.workspace = None
+        self.n = 0
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            torch.cuda.synchronize(self.device)
+            self.lib.amr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- input ------------------------------------------------------------
+    def upload(self, xyz: torch.Tensor, level: torch.Tensor, value: torch.Tensor):
+        """Borrow device tensors xyz int32 [n,3], level int32 [n], value
+        float32 [n] (validated on the device)."""
+        for t, dt, nm in ((xyz, torch.int32, "xyz"), (level, torch.int32, "level"), (value, torch.float32, "value")):
+            if t.dtype != dt or t.device != self.device or not t.is_contiguous():
+                raise ValueError("%s must be a contiguous %s tensor on %s" % (nm, dt, self.device))
+        n = int(level.shape[0])
+        if tuple(xyz.shape) != (n, 3) or tuple(value.shape) != (n,):
+            raise ValueError("shapes: xyz [n,3], level [n], value [n]")
+        self._cells = (xyz, level, value)
+        self.n = n
+        self.workspace = None
+        _check(self.lib.amr_upload(self._h, _ptr(xyz), _ptr(level), _ptr(value), n, _stream(self.device)))
+        return self
+
+    def index_bytes(self) -> int:
+        b = C.c_size_t(0)
+        _check(self.lib.amr_index_bytes(self._h, C.byref(b)))
+        return int(b.value)
+
+    def build_index(self, max_attempts: int = 6):
+        """Allocate the index workspace (torch) and build the index; grows the
+        workspace when the hash table turns out too small."""
+        for _ in range(max_attempts):
+            nbytes = self.index_bytes()
+            if self.workspace is None or self.workspace.numel() < nbytes:
+                self.workspace = None
+                self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            code = self.lib.amr_build_index(self._h, _ptr(self.workspace), self.workspace.numel(),
+                                            _stream(self.device))
+            if code == AMR_ENOSPACE:
+                continue
+            _check(code)
+            return self
+        raise AmrError(AMR_ENOSPACE, "index workspace kept overflowing")
+
+    # -- extraction -------------------------------------------------------
+    def dual_cells_into(self, corner_level, verts, cap: int):
+        """Enqueue dual-cell extraction into preallocated buffers; returns
+        the device counts tensor (no synchronisation)."""
+        _check(self.lib.amr_dual_cells(self._h, _ptr(corner_level), _ptr(verts), int(cap), _ptr(self.counts),
+                                       _stream(self.device)))
+        return self.counts
+
+    def dual_cells(self, cap: int | None = None):
+        """(corner_level int32 [M,4], verts int32 [M,8]) of every emitted dual."""
+        if cap is None:
+            self.dual_cells_into(None, None, 0)
+            cap = int(self.counts[0].item())
+        cl = torch.empty((max(cap, 1), 4), dtype=torch.int32, device=self.device)
+        vv = torch.empty((max(cap, 1), 8), dtype=torch.int32, device=self.device)
+        self.dual_cells_into(cl, vv, cap)
+        m = int(self.counts[0].item())
+        if m > cap:
+            return self.dual_cells(m)
+        return cl[:m], vv[:m]
+
+    def isosurface_into(self, iso: float, tris, cap: int, tri_cells=None, tri_dual=None):
+        """Enqueue iso-surface extraction into preallocated buffers; returns
+        the device counts tensor [triangles, duals] (no synchronisation)."""
+        _check(self.lib.amr_isosurface(self._h, C.c_float(iso), _ptr(tris), _ptr(tri_cells), _ptr(tri_dual),
+                                       int(cap), _ptr(self.counts), _stream(self.device)))
+        return self.counts
+
+    def count(self, iso: float) -> tuple[int, int]:
+        """(triangles, duals) for `iso` without writing any triangle."""
+        self.isosurface_into(iso, None, 0)
+        c = self.counts.tolist()
+        return int(c[0]), int(c[1])
+
+    def isosurface(self, iso: float, cap: int | None = None, cells: bool = False, dual: bool = False):
+        """Triangles float32 [T,9] (+ cells int32 [T,6], dual int32 [T]).
+        Without `cap` a count pass sizes the output first (the paper's
+        two-pass scheme); with `cap` a single pass runs and repeats only if
+        the capacity was too small."""
+        if cap is None:
+            cap = self.count(iso)[0]
+        tris = torch.empty((max(cap, 1), 9), dtype=torch.float32, device=self.device)
+        tc = torch.empty((max(cap, 1), 6), dtype=torch.int32, device=self.device) if cells else None
+        td = torch.empty((max(cap, 1),), dtype=torch.int32, device=self.device) if dual else None
+        self.isosurface_into(iso, tris, cap, tc, td)
+        t = int(self.counts[0].item())
+        if t > cap:
+            return self.isosurface(iso, t, cells, dual)
+        out = {"tris": tris[:t], "n_duals": int(self.counts[1].item())}
+        if cells:
+            out["cells"] = tc[:t]
+        if dual:
+            out["dual"] = td[:t]
+        return out
+
+
+def from_numpy(xyz, level, value, device=None) -> AmrSet:
+    """Convenience: copy numpy arrays to the GPU, upload and build the index."""
+    import numpy as np
+
+    s = AmrSet(device)
+    dev = s.device
+    tx = torch.from_numpy(np.ascontiguousarray(xyz, np.int32)).to(dev)
+    tl = torch.from_numpy(np.ascontiguousarray(level, np.int32)).to(dev)
+    tv = torch.from_numpy(np.ascontiguousarray(value, np.float32)).to(dev)
+    s.upload(tx, tl, tv)
+    s.build_index()
+    return s

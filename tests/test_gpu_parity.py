@@ -1,0 +1,218 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Bar: dual cells bit-exact (corner, level, 8 cell indices), triangle topology
+bit-exact (per-vertex cell pairs, per-dual triangle sets), triangle counts
+exact, vertex positions within max(1e-5 * finest width, 2 ulp_f32).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import amrgen
+import oracle
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from _util import canon_by_cells, directed_edges, position_tolerance  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def amr():
+    import paper_2004_08475_amd as amr
+
+    amr.load_library()  # raises if the library is not built: no silent fallback
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return amr
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def gpu_set(amr, cs):
+    return amr.from_numpy(cs.xyz, cs.level, cs.value)
+
+
+def check_duals(s, o):
+    pl_g, ids_g = s.dual_cells()
+    pl_o, ids_o = o.dual_cells()
+    a = oracle.canonical_duals(pl_g.cpu().numpy(), ids_g.cpu().numpy())
+    b = oracle.canonical_duals(pl_o, ids_o)
+    assert len(a[0]) == len(b[0])
+    assert np.array_equal(a[0], b[0])
+    assert np.array_equal(a[1], b[1])
+    return pl_g.cpu().numpy(), ids_g.cpu().numpy()
+
+
+def check_iso(s, o, iso, pl_g=None):
+    r = s.isosurface(iso, cells=True, dual=True)
+    ro = o.isosurface(iso)
+    tg, cg, dg = r["tris"].cpu().numpy(), r["cells"].cpu().numpy(), r["dual"].cpu().numpy()
+    assert len(tg) == len(ro["tris"])
+    assert r["n_duals"] == ro["n_duals"]
+    A, AC, AD = canon_by_cells(tg, cg, dg)
+    B, BC, BD = canon_by_cells(ro["tris"], ro["cells"], ro["dual"])
+    assert np.array_equal(AC, BC)
+    tol = position_tolerance(B)
+    assert np.all(np.abs(A.astype(np.float64) - B.astype(np.float64)) <= tol)
+    if pl_g is not None and len(AD):
+        # per-dual triangle sets: the generating dual of each triangle agrees
+        pl_o, _ = o.dual_cells()
+        kg = [tuple(pl_g[d]) for d in AD]
+        ko = [tuple(pl_o[d]) for d in BD]
+        assert kg == ko
+    return r, A
+
+
+CASES = {
+    "two-level-sphere-16": lambda: amrgen.two_level_sphere(),
+    "octree-shell-256": lambda: amrgen.octree_shell(),
+    "random-octree-holes": lambda: amrgen.random_octree(7, roots=4, root_level=4, p_split=0.45, p_hole=0.15,
+                                                        values="smooth", origin=(-64, 32, -16)),
+    "random-octree-dense": lambda: amrgen.random_octree(8, roots=5, root_level=3, p_split=0.6, p_hole=0.0,
+                                                        values="random", origin=(0, 0, 0)),
+    "grid-33-level1": lambda: amrgen.uniform_grid(33, 1, 3, origin=(-40, 10, 6)),
+    "grid-17-level0": lambda: amrgen.uniform_grid(17, 0, 4, origin=(5, -3, 100)),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_parity(amr, name):
+    cs = CASES[name]()
+    _say("parity %s: %d cells" % (name, cs.n))
+    o = oracle.Oracle(cs.xyz, cs.level, cs.value)
+    s = gpu_set(amr, cs)
+    pl_g, _ = check_duals(s, o)
+    check_iso(s, o, cs.iso, pl_g)
+    # a second iso on the same index
+    iso2 = float(np.quantile(cs.value, 0.3))
+    check_iso(s, o, iso2, pl_g)
+
+
+def test_two_level_closed_surface_on_gpu(amr):
+    cs = amrgen.two_level_sphere()
+    s = gpu_set(amr, cs)
+    pl, _ = s.dual_cells()
+    assert len(pl) == 947
+    r = s.isosurface(cs.iso, cells=True)
+    cnt = directed_edges(r["cells"].cpu().numpy())
+    assert all(cnt.get((b, a), 0) == c for (a, b), c in cnt.items())
+
+
+def test_deterministic_and_capacity_contract(amr):
+    cs = amrgen.octree_shell()
+    s = gpu_set(amr, cs)
+    full = s.isosurface(cs.iso)["tris"].clone()
+    again = s.isosurface(cs.iso, cap=len(full))["tris"]
+    assert torch.equal(full, again)
+    # too small: counts report the full number, only cap triangles written
+    cap = len(full) // 3
+    buf = torch.full((cap + 16, 9), -7.0, dtype=torch.float32, device=s.device)
+    counts = s.isosurface_into(cs.iso, buf, cap)
+    torch.cuda.synchronize()
+    assert int(counts[0]) == len(full)
+    assert torch.equal(buf[:cap], full[:cap])
+    assert torch.all(buf[cap:] == -7.0)
+    # count-only pass
+    assert s.count(cs.iso)[0] == len(full)
+
+
+def test_tri_dual_points_at_generating_dual(amr):
+    cs = amrgen.random_octree(9, roots=4, root_level=3, p_split=0.5, p_hole=0.1, values="smooth")
+    s = gpu_set(amr, cs)
+    pl, ids = s.dual_cells()
+    r = s.isosurface(cs.iso, cells=True, dual=True)
+    ids = ids.cpu().numpy()
+    cells = r["cells"].cpu().numpy()
+    for tcell, d in zip(cells, r["dual"].cpu().numpy()):
+        assert set(tcell.tolist()) <= set(ids[d].tolist())
+
+
+def test_edge_cases(amr):
+    # empty set
+    s = amr.AmrSet()
+    e = torch.empty((0, 3), dtype=torch.int32, device="cuda")
+    s.upload(e, torch.empty(0, dtype=torch.int32, device="cuda"), torch.empty(0, dtype=torch.float32, device="cuda"))
+    s.build_index()
+    assert s.count(0.5) == (0, 0)
+    assert len(s.dual_cells()[0]) == 0
+    # one cell: no dual has all 8 vertices
+    one = amr.from_numpy(np.array([[8, 8, 8]]), np.array([3]), np.array([1.0], np.float32))
+    assert len(one.dual_cells()[0]) == 0
+    # 2x2x2 level-3 cells: exactly one dual
+    xyz = np.array([[x, y, z] for z in (0, 8) for y in (0, 8) for x in (0, 8)])
+    eight = amr.from_numpy(xyz, np.full(8, 3), np.arange(8, dtype=np.float32))
+    pl, ids = eight.dual_cells()
+    assert pl.cpu().tolist() == [[8, 8, 8, 3]]
+    assert ids.cpu().tolist() == [list(range(8))]
+    # coordinates near the limits
+    cs = amrgen.random_octree(5, roots=2, root_level=3, p_split=0.5, values="smooth", origin=(-(1 << 22), (1 << 22), 0))
+    o = oracle.Oracle(cs.xyz, cs.level, cs.value)
+    s2 = gpu_set(amr, cs)
+    check_duals(s2, o)
+    check_iso(s2, o, cs.iso)
+
+
+def test_sparse_set_grows_index(amr):
+    """One cell per sibling block: more groups than the first table size
+    allows, so the build reports ENOSPACE and the binding retries."""
+    g = np.arange(0, 64, 2)
+    xyz = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    val = amrgen.uniform(3, 1, np.arange(len(xyz), dtype=np.uint64)).astype(np.float32)
+    s = amr.from_numpy(xyz, np.zeros(len(xyz)), val)
+    assert len(s.dual_cells()[0]) == 0  # isolated cells: no dual is covered
+    # now fill in the odd cells too: every dual inside is a unit cube
+    g1 = np.arange(0, 16)
+    xyz1 = np.stack(np.meshgrid(g1, g1, g1, indexing="ij"), -1).reshape(-1, 3)
+    keep = np.any(xyz1 % 2 == 1, axis=1)
+    xyz2 = np.concatenate([xyz1[~keep][::1], xyz1[keep]])
+    v2 = amrgen.uniform(4, 1, np.arange(len(xyz2), dtype=np.uint64)).astype(np.float32)
+    o = oracle.Oracle(xyz2, np.zeros(len(xyz2)), v2)
+    s2 = amr.from_numpy(xyz2, np.zeros(len(xyz2)), v2)
+    check_duals(s2, o)
+
+
+def test_error_codes(amr):
+    def up(xyz, lvl, val):
+        s = amr.AmrSet()
+        s.upload(torch.tensor(np.asarray(xyz), dtype=torch.int32, device="cuda").reshape(-1, 3),
+                 torch.tensor(np.asarray(lvl), dtype=torch.int32, device="cuda"),
+                 torch.tensor(np.asarray(val), dtype=torch.float32, device="cuda"))
+        return s
+
+    with pytest.raises(amr.AmrError) as ei:
+        up([[1, 0, 0]], [1], [0.0])
+    assert ei.value.code == amr.AMR_EINVAL
+    with pytest.raises(amr.AmrError) as ei:
+        up([[0, 0, 0]], [21], [0.0])
+    assert ei.value.code == amr.AMR_EINVAL
+    with pytest.raises(amr.AmrError) as ei:
+        up([[0, 0, 0]], [0], [float("nan")])
+    assert ei.value.code == amr.AMR_EINVAL
+    with pytest.raises(amr.AmrError) as ei:
+        up([[1 << 23, 0, 0]], [0], [0.0])
+    assert ei.value.code == amr.AMR_ERANGE
+    with pytest.raises(amr.AmrError) as ei:
+        up([[0, 0, 0], [1 << 20, 0, 0]], [0, 0], [0.0, 0.0])
+    assert ei.value.code == amr.AMR_ERANGE
+    s = up([[0, 0, 0], [0, 0, 0]], [0, 0], [0.0, 1.0])
+    with pytest.raises(amr.AmrError) as ei:
+        s.build_index()
+    assert ei.value.code == amr.AMR_EOVERLAP
+    s = up([[0, 0, 0], [2, 2, 2]], [2, 0], [0.0, 1.0])
+    with pytest.raises(amr.AmrError) as ei:
+        s.build_index()
+    assert ei.value.code == amr.AMR_EOVERLAP
+    s = up([[0, 0, 0]], [0], [0.0])
+    with pytest.raises(amr.AmrError) as ei:
+        s.count(0.5)
+    assert ei.value.code == amr.AMR_ESTATE
+    s.build_index()
+    with pytest.raises(amr.AmrError) as ei:
+        s.count(float("nan"))
+    assert ei.value.code == amr.AMR_EINVAL
