@@ -7,20 +7,23 @@
 //
 // Data layout in HBM
 //   input (caller, borrowed): SoA  xyz int32[n][3], level int32[n], value f32[n]
-//   index workspace (caller): [records | cell ids | group list | tile states]
+//   index workspace (caller): records | cell ids | group list | scan states
 //     record (64 B, one per hash slot): val f32[8] | key u64 | pad
-//       A record holds the cells of one level that share a 2x2x2 sibling
-//       block (a "group"): key = (level, block coordinates), val[c] = value
-//       of child c (c = bx + 2 by + 4 bz), NaN where that child is not an
-//       actual cell of this level.  One probe thus returns up to 8 cells.
-//     cell ids  int32[slots][8]: input index of child c of the slot's group
-//     group list int32[]: slots of all occupied records (work list)
-//     tile states u64[2][tiles + 1]: decoupled look-back of the extraction
+//       A record belongs to one 2x2x2 block of level-m logical cells (a
+//       "group"): key = (m, block coordinates).  val[c] is the value of
+//       child c (c = bx + 2 by + 4 bz) when that child is an actual cell of
+//       level m, the NaN "empty" when it is not, or the NaN "refined" when
+//       finer cells exist inside it.  One probe thus returns up to 8 cells,
+//       and the refined markers end a snap as soon as it meets finer cells.
+//     cell ids  int32[slots][8]: input index of the cell in each child slot
+//     group list int32[]: slots of the records that hold at least one cell
+//     scan states: decoupled look-back words of the group-list compaction
+//       and of the extraction
 //
 // Extraction kernel (paper sec. 4.2-5): one work-group processes 32 groups,
-// eight lanes per group.  The lanes first fetch the 27 neighbouring groups
-// of their group (same level; absent ones are resolved to the coarser cell
-// covering them) into LDS, then evaluate the 27 corners of the group's 2x2x2
+// eight lanes per group.  The lanes fetch the 27 neighbouring groups of
+// their group (same level; absent ones are resolved to the coarser cell that
+// covers them) into LDS, then evaluate the 27 corners of the group's 2x2x2
 // cell block.  A corner's logical dual is emitted when its 8 slots are all
 // covered by cells of this level or coarser and the lowest-numbered slot on
 // this level belongs to this group -- rules 1-3 of the paper, with the
@@ -28,13 +31,14 @@
 // order of the lower corners of same-level cells).  Marching Cubes runs on
 // each emitted dual from a 256-entry table kept in LDS; degenerate triangles
 // are culled by comparing cell references; counts are prefix-summed within
-// the work-group and across work-groups by decoupled look-back, so output
+// the work-group and across work-groups by a decoupled look-back, so output
 // positions are deterministic and no count pass is needed.
 
 #include <hip/hip_runtime.h>
 
 #include <math.h>
 #include <stdarg.h>
+#include <stddef.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -48,10 +52,16 @@ namespace {
 constexpr int kMaxLevel = 20;
 constexpr int kCoordLimit = 1 << 23;    // |corner| bound: centres exact in f32
 constexpr int kSpanLimit = 1 << 20;     // offset coordinates u < 2^20
-constexpr uint64_t kEmpty = ~0ull;
+constexpr uint64_t kEmpty = ~0ull;      // key of a free slot
+constexpr uint32_t kValEmpty = 0x7fc00000u;    // NaN: no cell of this level here
+constexpr uint32_t kValRefined = 0x7fc00001u;  // NaN: finer cells inside
 constexpr int kGroupsPerTile = 32;
 constexpr int kBlock = 256;             // 32 groups x 8 lanes
+constexpr int kTriList = 256;           // triangle entries staged per round
 constexpr uint32_t kMaxCap = 1u << 28;  // slot * 8 + child fits int32
+constexpr uint32_t kMaxProbe = 1024;    // longer chains mean the table is too full
+constexpr int kCompactMaxPerThread = 16;
+constexpr int kReplicas = 64;           // spread of the upload reduction atomics
 constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
 
 enum : uint32_t { kErrLevel = 1, kErrAlign = 2, kErrValue = 4, kErrCoord = 8 };
@@ -63,21 +73,36 @@ struct alignas(64) Record {
 };
 static_assert(sizeof(Record) == 64, "record is one 64-byte line");
 
-// Device control block, one per set (library-allocated).
-struct Ctrl {
+// One replica of the upload reduction: work-group b updates replica b % 64,
+// so no address receives more than 1/64 of the atomics; the host combines.
+struct alignas(256) Partial {
     int32_t lo[3];
     int32_t hi[3];
     int32_t lmin, lmax;
     uint32_t err;
     uint32_t pad0;
     unsigned long long bad;
-    unsigned long long level_count[32];
-    // index build
-    uint32_t n_groups;
+    unsigned long long level_count[kMaxLevel + 1];
+};
+
+// Device control block, one per set (library-allocated).
+struct Ctrl {
+    Partial part[kReplicas];
     uint32_t overflow;
     uint32_t dup;
     uint32_t overlap;
+    uint32_t pad0;
     unsigned long long bad_build;
+    unsigned long long n_groups;   // written by the compaction's last tile
+    unsigned long long n_records;
+};
+
+// Scan bookkeeping inside the workspace.
+struct Sched {
+    unsigned long long ticket;   // extraction tiles started, over all calls
+    unsigned long long call;     // extraction calls completed
+    unsigned long long cticket;  // compaction tiles started
+    unsigned long long pad;
 };
 
 __device__ __forceinline__ uint64_t group_key(int m, uint32_t gx, uint32_t gy, uint32_t gz) {
@@ -88,9 +113,33 @@ __device__ __forceinline__ uint32_t slot_of(uint64_t key, int shift) {
     return (uint32_t)((key * kGolden) >> shift);
 }
 
-__device__ __forceinline__ float nan_marker() { return __int_as_float(0x7fc00000); }
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
-// Linear probe for `key`; returns the slot or -1.  At most cap steps.
+template <typename T, typename Op>
+__device__ __forceinline__ T wave_reduce(T x, Op op) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x = op(x, __shfl_xor(x, off, 64));
+    return x;
+}
+
+__device__ __forceinline__ unsigned long long wave_incl_scan(unsigned long long x) {
+    int lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        unsigned long long y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ unsigned long long ld_relaxed(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Linear probe for `key`; returns the slot or -1 (never more than cap steps).
 __device__ __forceinline__ int probe(const Record* __restrict__ rec, uint64_t key, int shift, uint32_t mask) {
     uint32_t h = slot_of(key, shift);
     for (uint32_t i = 0; i <= mask; ++i) {
@@ -103,33 +152,123 @@ __device__ __forceinline__ int probe(const Record* __restrict__ rec, uint64_t ke
 }
 
 // ---------------------------------------------------------------------------
+// Decoupled look-back over tiles (called by one whole wave).  A tile's state
+// is two words, one per running total, each: flag (2 bits) | parity (1 bit)
+// | value; flag 1 = the tile's own aggregate, flag 2 = inclusive prefix.
+// Every call rewrites every tile's words, so words left by the previous call
+// (other parity) read as "not yet written" and need no clearing.  The wave
+// reads 256 predecessors per step; relaxed device-scope accesses suffice
+// because the words carry the data themselves.
+// ---------------------------------------------------------------------------
+
+constexpr unsigned long long kFlagShift = 62;
+constexpr unsigned long long kParityBit = 1ull << 61;
+constexpr unsigned long long kValMask = kParityBit - 1;
+constexpr unsigned long long kFlagAgg = 1, kFlagIncl = 2;
+constexpr int kLookWindows = 4;
+
+__device__ void lookback(unsigned long long* s0, unsigned long long* s1, uint32_t tile, unsigned long long par,
+                         unsigned long long a0, unsigned long long a1, unsigned long long& p0,
+                         unsigned long long& p1) {
+    const int lane = lane_id();
+    p0 = 0;
+    p1 = 0;
+    if (tile == 0) {
+        if (lane == 0) {
+            st_relaxed(&s1[0], (kFlagIncl << kFlagShift) | par | a1);
+            st_relaxed(&s0[0], (kFlagIncl << kFlagShift) | par | a0);
+        }
+        return;
+    }
+    if (lane == 0) {
+        st_relaxed(&s1[tile], (kFlagAgg << kFlagShift) | par | a1);
+        st_relaxed(&s0[tile], (kFlagAgg << kFlagShift) | par | a0);
+    }
+    auto add = [](unsigned long long x, unsigned long long y) { return x + y; };
+    int base = (int)tile - 1;
+    while (true) {
+        unsigned long long w0[kLookWindows], w1[kLookWindows];
+#pragma unroll
+        for (int r = 0; r < kLookWindows; ++r) {
+            int idx = base - lane - 64 * r;
+            w0[r] = 0;
+            w1[r] = 0;
+            if (idx >= 0) {
+                w0[r] = ld_relaxed(&s0[idx]);
+                w1[r] = ld_relaxed(&s1[idx]);
+            }
+        }
+        bool found = false, stall = false;
+        unsigned long long q0 = 0, q1 = 0;
+#pragma unroll
+        for (int r = 0; r < kLookWindows; ++r) {
+            if (found || stall) continue;
+            int idx = base - lane - 64 * r;
+            unsigned long long f0 = w0[r] >> kFlagShift, f1 = w1[r] >> kFlagShift;
+            bool ready = idx < 0 || (f0 != 0 && f0 == f1 && (w0[r] & kParityBit) == par &&
+                                     (w1[r] & kParityBit) == par);
+            bool incl = idx >= 0 && ready && f0 == kFlagIncl;
+            unsigned long long pm = __ballot(incl);
+            unsigned long long nr = __ballot(!ready);
+            // lanes up to and including the nearest inclusive prefix count
+            unsigned long long need = pm ? (((pm & (~pm + 1)) << 1) - 1) : ~0ull;
+            if (nr & need) {
+                stall = true;
+                continue;
+            }
+            bool take = idx >= 0 && ((need >> lane) & 1);
+            q0 += take ? (w0[r] & kValMask) : 0;
+            q1 += take ? (w1[r] & kValMask) : 0;
+            if (pm) found = true;
+        }
+        if (stall) {
+            // a predecessor has not published yet: wait, then re-read the stretch
+            __builtin_amdgcn_s_sleep(2);
+            continue;
+        }
+        p0 += wave_reduce(q0, add);
+        p1 += wave_reduce(q1, add);
+        if (found) break;
+        base -= 64 * kLookWindows;
+    }
+    if (lane == 0) {
+        st_relaxed(&s1[tile], (kFlagIncl << kFlagShift) | par | (p1 + a1));
+        st_relaxed(&s0[tile], (kFlagIncl << kFlagShift) | par | (p0 + a0));
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Upload: validation and reductions
 // ---------------------------------------------------------------------------
 
 __global__ void k_ctrl_reset(Ctrl* c) {
-    int t = threadIdx.x;
-    if (t < 3) {
-        c->lo[t] = INT32_MAX;
-        c->hi[t] = INT32_MIN;
+    for (int r = threadIdx.x; r < kReplicas; r += blockDim.x) {
+        Partial& p = c->part[r];
+        for (int a = 0; a < 3; ++a) {
+            p.lo[a] = INT32_MAX;
+            p.hi[a] = INT32_MIN;
+        }
+        p.lmin = INT32_MAX;
+        p.lmax = INT32_MIN;
+        p.err = 0;
+        p.bad = ~0ull;
+        for (int l = 0; l <= kMaxLevel; ++l) p.level_count[l] = 0;
     }
-    if (t == 0) {
-        c->lmin = INT32_MAX;
-        c->lmax = INT32_MIN;
-        c->err = 0;
-        c->bad = ~0ull;
-        c->n_groups = 0;
+    if (threadIdx.x == 0) {
         c->overflow = 0;
         c->dup = 0;
         c->overlap = 0;
         c->bad_build = ~0ull;
+        c->n_groups = 0;
+        c->n_records = 0;
     }
-    if (t < 32) c->level_count[t] = 0;
 }
 
 __global__ __launch_bounds__(256) void k_upload(const int32_t* __restrict__ xyz, const int32_t* __restrict__ lvl,
                                                 const float* __restrict__ val, int64_t n, Ctrl* c) {
     __shared__ int s_lo[3], s_hi[3], s_lmin, s_lmax;
     __shared__ unsigned long long s_cnt[kMaxLevel + 1];
+    Partial& P = c->part[blockIdx.x % kReplicas];
     int t = threadIdx.x;
     if (t < 3) {
         s_lo[t] = INT32_MAX;
@@ -143,55 +282,81 @@ __global__ __launch_bounds__(256) void k_upload(const int32_t* __restrict__ xyz,
     __syncthreads();
     int lo0 = INT32_MAX, lo1 = INT32_MAX, lo2 = INT32_MAX, hi0 = INT32_MIN, hi1 = INT32_MIN, hi2 = INT32_MIN;
     int lmin = INT32_MAX, lmax = INT32_MIN;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + t; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        int x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
-        int l = lvl[i];
-        float v = val[i];
-        uint32_t bad = 0;
-        if (l < 0 || l > kMaxLevel) {
-            bad |= kErrLevel;
-        } else {
-            int w = 1 << l;
-            if ((x | y | z) & (w - 1)) bad |= kErrAlign;
-            int64_t mn = x < y ? (x < z ? x : z) : (y < z ? y : z);
-            int64_t mx = x > y ? (x > z ? x : z) : (y > z ? y : z);
-            if (mn < -(int64_t)kCoordLimit || mx + w > (int64_t)kCoordLimit) bad |= kErrCoord;
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * blockDim.x) {
+        int64_t i = i0 + t;
+        int l = -1;
+        if (i < n) {
+            int x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+            l = lvl[i];
+            float v = val[i];
+            uint32_t bad = 0;
+            if (l < 0 || l > kMaxLevel) {
+                bad |= kErrLevel;
+            } else {
+                int w = 1 << l;
+                if ((x | y | z) & (w - 1)) bad |= kErrAlign;
+                int64_t mn = x < y ? (x < z ? x : z) : (y < z ? y : z);
+                int64_t mx = x > y ? (x > z ? x : z) : (y > z ? y : z);
+                if (mn < -(int64_t)kCoordLimit || mx + w > (int64_t)kCoordLimit) bad |= kErrCoord;
+            }
+            if (!isfinite(v)) bad |= kErrValue;
+            if (bad) {
+                atomicOr(&P.err, bad);
+                atomicMin(&P.bad, (unsigned long long)i);
+                l = -1;
+            } else {
+                int w = 1 << l;
+                lo0 = min(lo0, x);
+                lo1 = min(lo1, y);
+                lo2 = min(lo2, z);
+                hi0 = max(hi0, x + w);
+                hi1 = max(hi1, y + w);
+                hi2 = max(hi2, z + w);
+                lmin = min(lmin, l);
+                lmax = max(lmax, l);
+            }
         }
-        if (!isfinite(v)) bad |= kErrValue;
-        if (bad) {
-            atomicOr(&c->err, bad);
-            atomicMin(&c->bad, (unsigned long long)i);
-            continue;
+        // per-level counts: one ballot per level present in the wave
+        unsigned long long bit = l >= 0 ? (1ull << l) : 0ull;
+        unsigned long long present =
+            wave_reduce(bit, [](unsigned long long a, unsigned long long b) { return a | b; });
+        while (present) {
+            int L = __ffsll((long long)present) - 1;
+            present &= present - 1;
+            unsigned long long b = __ballot(l == L);
+            if (lane_id() == 0) atomicAdd(&s_cnt[L], (unsigned long long)__popcll(b));
         }
-        int w = 1 << l;
-        lo0 = min(lo0, x);
-        lo1 = min(lo1, y);
-        lo2 = min(lo2, z);
-        hi0 = max(hi0, x + w);
-        hi1 = max(hi1, y + w);
-        hi2 = max(hi2, z + w);
-        lmin = min(lmin, l);
-        lmax = max(lmax, l);
-        atomicAdd(&s_cnt[l], 1ull);
     }
-    atomicMin(&s_lo[0], lo0);
-    atomicMin(&s_lo[1], lo1);
-    atomicMin(&s_lo[2], lo2);
-    atomicMax(&s_hi[0], hi0);
-    atomicMax(&s_hi[1], hi1);
-    atomicMax(&s_hi[2], hi2);
-    atomicMin(&s_lmin, lmin);
-    atomicMax(&s_lmax, lmax);
+    auto mn = [](int a, int b) { return a < b ? a : b; };
+    auto mx = [](int a, int b) { return a > b ? a : b; };
+    lo0 = wave_reduce(lo0, mn);
+    lo1 = wave_reduce(lo1, mn);
+    lo2 = wave_reduce(lo2, mn);
+    hi0 = wave_reduce(hi0, mx);
+    hi1 = wave_reduce(hi1, mx);
+    hi2 = wave_reduce(hi2, mx);
+    lmin = wave_reduce(lmin, mn);
+    lmax = wave_reduce(lmax, mx);
+    if (lane_id() == 0) {
+        atomicMin(&s_lo[0], lo0);
+        atomicMin(&s_lo[1], lo1);
+        atomicMin(&s_lo[2], lo2);
+        atomicMax(&s_hi[0], hi0);
+        atomicMax(&s_hi[1], hi1);
+        atomicMax(&s_hi[2], hi2);
+        atomicMin(&s_lmin, lmin);
+        atomicMax(&s_lmax, lmax);
+    }
     __syncthreads();
     if (t < 3) {
-        atomicMin(&c->lo[t], s_lo[t]);
-        atomicMax(&c->hi[t], s_hi[t]);
+        atomicMin(&P.lo[t], s_lo[t]);
+        atomicMax(&P.hi[t], s_hi[t]);
     }
     if (t == 0) {
-        atomicMin(&c->lmin, s_lmin);
-        atomicMax(&c->lmax, s_lmax);
+        atomicMin(&P.lmin, s_lmin);
+        atomicMax(&P.lmax, s_lmax);
     }
-    if (t <= kMaxLevel && s_cnt[t]) atomicAdd(&c->level_count[t], s_cnt[t]);
+    if (t <= kMaxLevel && s_cnt[t]) atomicAdd(&P.level_count[t], s_cnt[t]);
 }
 
 // ---------------------------------------------------------------------------
@@ -206,10 +371,10 @@ struct Geo {
 };
 
 __global__ __launch_bounds__(256) void k_index_init(Record* __restrict__ rec, int32_t* __restrict__ ids, uint32_t cap) {
-    float nanv = nan_marker();
+    float e = __uint_as_float(kValEmpty);
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += gridDim.x * blockDim.x) {
         Record r;
-        for (int c = 0; c < 8; ++c) r.val[c] = nanv;
+        for (int c = 0; c < 8; ++c) r.val[c] = e;
         r.key = kEmpty;
         for (int c = 0; c < 6; ++c) r.pad[c] = 0;
         rec[i] = r;
@@ -219,74 +384,131 @@ __global__ __launch_bounds__(256) void k_index_init(Record* __restrict__ rec, in
     }
 }
 
+// A key never changes once written, so a plain (possibly stale) read can only
+// show "free" too often; the compare-and-swap then returns the truth.
+__device__ __forceinline__ int find_or_insert(Record* __restrict__ rec, uint64_t key, const Geo& g) {
+    uint32_t h = slot_of(key, g.shift);
+    for (uint32_t step = 0; step < kMaxProbe && step <= g.mask; ++step) {
+        uint64_t k = rec[h].key;
+        if (k == key) return (int)h;
+        if (k == kEmpty) {
+            uint64_t prev = atomicCAS((unsigned long long*)&rec[h].key, (unsigned long long)kEmpty,
+                                      (unsigned long long)key);
+            if (prev == kEmpty || prev == key) return (int)h;
+        }
+        h = (h + 1) & g.mask;
+    }
+    return -1;
+}
+
+// Every cell stores its value in its group record, then marks its ancestors
+// as refined, level by level, until it meets a mark someone else set.  A
+// leaf exchanged over a refined mark, or a mark set over a leaf, is a nested
+// cell; a leaf exchanged over a leaf is a duplicate.
 __global__ __launch_bounds__(256) void k_index_insert(const int32_t* __restrict__ xyz, const int32_t* __restrict__ lvl,
                                                       const float* __restrict__ val, int64_t n, Geo g,
-                                                      Record* __restrict__ rec, int32_t* __restrict__ ids,
-                                                      int32_t* __restrict__ glist, uint32_t glist_cap, Ctrl* c) {
+                                                      Record* __restrict__ rec, int32_t* __restrict__ ids, Ctrl* c) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         int m = lvl[i];
         uint32_t ux = (uint32_t)(xyz[3 * i] - g.ox), uy = (uint32_t)(xyz[3 * i + 1] - g.oy),
                  uz = (uint32_t)(xyz[3 * i + 2] - g.oz);
-        uint64_t key = group_key(m, ux >> (m + 1), uy >> (m + 1), uz >> (m + 1));
-        int child = ((ux >> m) & 1) | (((uy >> m) & 1) << 1) | (((uz >> m) & 1) << 2);
-        uint32_t h = slot_of(key, g.shift);
-        int slot = -1;
-        for (uint32_t step = 0; step <= g.mask; ++step) {
-            uint64_t k = __hip_atomic_load(&rec[h].key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (k == key) {
-                slot = (int)h;
-                break;
-            }
-            if (k == kEmpty) {
-                uint64_t prev = atomicCAS((unsigned long long*)&rec[h].key, (unsigned long long)kEmpty,
-                                          (unsigned long long)key);
-                if (prev == kEmpty) {
-                    uint32_t pos = atomicAdd(&c->n_groups, 1u);
-                    if (pos < glist_cap) glist[pos] = (int32_t)h;
-                    else atomicOr(&c->overflow, 1u);
-                    slot = (int)h;
-                    break;
-                }
-                if (prev == key) {
-                    slot = (int)h;
-                    break;
-                }
-            }
-            if (__hip_atomic_load(&c->overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-            h = (h + 1) & g.mask;
-        }
+        int slot = find_or_insert(rec, group_key(m, ux >> (m + 1), uy >> (m + 1), uz >> (m + 1)), g);
         if (slot < 0) {
             atomicOr(&c->overflow, 1u);
             continue;
         }
-        rec[slot].val[child] = val[i];
-        int old = atomicExch(&ids[(size_t)slot * 8 + child], (int)i);
-        if (old != -1) {
-            atomicOr(&c->dup, 1u);
+        int child = ((ux >> m) & 1) | (((uy >> m) & 1) << 1) | (((uz >> m) & 1) << 2);
+        uint32_t old = atomicExch(reinterpret_cast<unsigned int*>(&rec[slot].val[child]), __float_as_uint(val[i]));
+        ids[(size_t)slot * 8 + child] = (int32_t)i;
+        if (old != kValEmpty) {
+            atomicOr(old == kValRefined ? &c->overlap : &c->dup, 1u);
             atomicMin(&c->bad_build, (unsigned long long)i);
+        }
+        for (int L = m + 1; L <= g.lmax; ++L) {
+            int s2 = find_or_insert(rec, group_key(L, ux >> (L + 1), uy >> (L + 1), uz >> (L + 1)), g);
+            if (s2 < 0) {
+                atomicOr(&c->overflow, 1u);
+                break;
+            }
+            int c2 = ((ux >> L) & 1) | (((uy >> L) & 1) << 1) | (((uz >> L) & 1) << 2);
+            uint32_t prev =
+                atomicCAS(reinterpret_cast<unsigned int*>(&rec[s2].val[c2]), kValEmpty, kValRefined);
+            if (prev == kValEmpty) continue;  // marked here: carry on upwards
+            if (prev != kValRefined) {        // a coarser cell contains this one
+                atomicOr(&c->overlap, 1u);
+                atomicMin(&c->bad_build, (unsigned long long)i);
+            }
+            break;
         }
     }
 }
 
-// Nested cells: a cell of level m' > l containing the lower corner of a
-// level-l cell.  (Equal corners on one level were caught as duplicates.)
-__global__ __launch_bounds__(256) void k_index_overlap(const int32_t* __restrict__ xyz, const int32_t* __restrict__ lvl,
-                                                       int64_t n, Geo g, const Record* __restrict__ rec, Ctrl* c) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        int l = lvl[i];
-        uint32_t ux = (uint32_t)(xyz[3 * i] - g.ox), uy = (uint32_t)(xyz[3 * i + 1] - g.oy),
-                 uz = (uint32_t)(xyz[3 * i + 2] - g.oz);
-        for (int m = l + 1; m <= g.lmax; ++m) {
-            int h = probe(rec, group_key(m, ux >> (m + 1), uy >> (m + 1), uz >> (m + 1)), g.shift, g.mask);
-            if (h < 0) continue;
-            int child = ((ux >> m) & 1) | (((uy >> m) & 1) << 1) | (((uz >> m) & 1) << 2);
-            float v = rec[h].val[child];
-            if (v == v) {
-                atomicOr(&c->overlap, 1u);
-                atomicMin(&c->bad_build, (unsigned long long)i);
+// Group list: the slots of all records holding at least one cell, in slot
+// order, by a block scan plus look-back over tiles of 4096 slots.  Also
+// counts all occupied records (groups plus marker-only records).
+__global__ __launch_bounds__(kBlock) void k_index_compact(const Record* __restrict__ rec, uint32_t cap,
+                                                          int32_t* __restrict__ glist, unsigned long long* s0,
+                                                          unsigned long long* s1, Sched* sc, uint32_t n_tiles,
+                                                          int per, Ctrl* c) {
+    __shared__ uint32_t s_rcount[kCompactMaxPerThread][kBlock / 64];
+    __shared__ unsigned long long s_wave[kBlock / 64];
+    __shared__ unsigned long long s_pre0;
+    __shared__ uint32_t s_tile;
+    const int t = threadIdx.x;
+    const int wave = t >> 6, lane = lane_id();
+    if (t == 0) s_tile = (uint32_t)atomicAdd(&sc->cticket, 1ull);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    // thread t looks at slots base + r*256 + t, r < per (coalesced)
+    const uint32_t base = tile * (uint32_t)(kBlock * per);
+    uint32_t grp_bits = 0, n_rec = 0;
+#pragma unroll 4
+    for (int r = 0; r < per; ++r) {
+        uint32_t s = base + r * kBlock + t;
+        if (s >= cap) continue;
+        const Record& R = rec[s];
+        if (R.key == kEmpty) continue;
+        ++n_rec;
+        const float4* pv = reinterpret_cast<const float4*>(R.val);
+        float4 a = pv[0], b = pv[1];
+        bool any = a.x == a.x || a.y == a.y || a.z == a.z || a.w == a.w || b.x == b.x || b.y == b.y ||
+                   b.z == b.z || b.w == b.w;
+        if (any) grp_bits |= 1u << r;
+    }
+    for (int r = 0; r < per; ++r) {
+        unsigned long long b = __ballot((grp_bits >> r) & 1);
+        if (lane == 0) s_rcount[r][wave] = (uint32_t)__popcll(b);
+    }
+    unsigned long long recs = wave_reduce((unsigned long long)n_rec,
+                                          [](unsigned long long x, unsigned long long y) { return x + y; });
+    if (lane == 0) s_wave[wave] = recs;
+    __syncthreads();
+    uint32_t total_g = 0;
+    unsigned long long total_r = 0;
+    for (int r = 0; r < per; ++r)
+        for (int w = 0; w < kBlock / 64; ++w) total_g += s_rcount[r][w];
+    for (int w = 0; w < kBlock / 64; ++w) total_r += s_wave[w];
+    if (wave == 0) {
+        unsigned long long p0, p1;
+        lookback(s0, s1, tile, 0ull, total_g, total_r, p0, p1);
+        if (lane == 0) {
+            s_pre0 = p0;
+            if (tile == n_tiles - 1) {
+                c->n_groups = p0 + total_g;
+                c->n_records = p1 + total_r;
             }
-            break;  // a present group at level m decides: no coarser cell can contain the corner
         }
+    }
+    __syncthreads();
+    // slot-ordered positions: all of row r's entries precede row r+1's
+    uint32_t pos = (uint32_t)s_pre0;
+    for (int r = 0; r < per; ++r) {
+        unsigned long long b = __ballot((grp_bits >> r) & 1);
+        uint32_t before = 0;
+        for (int w = 0; w < wave; ++w) before += s_rcount[r][w];
+        if ((grp_bits >> r) & 1)
+            glist[pos + before + (uint32_t)__popcll(b & ((1ull << lane) - 1))] = (int32_t)(base + r * kBlock + t);
+        for (int w = 0; w < kBlock / 64; ++w) pos += s_rcount[r][w];
     }
 }
 
@@ -310,39 +532,26 @@ struct ExtractArgs {
     int32_t* verts;
     int64_t cap;
     int64_t* counts;
-    unsigned long long* st_t;  // per tile: flag | call parity | triangles
-    unsigned long long* st_d;  // per tile: flag | call parity | duals
-    struct Sched* sched;
+    unsigned long long* st_t;  // per tile: triangles
+    unsigned long long* st_d;  // per tile: duals
+    Sched* sched;
     uint32_t n_tiles;
 };
 
-// Look-back state word: flag (2 bits) | parity of the call (1 bit) | value.
-// Every call rewrites the state of every tile, so a word left by the
-// previous call is recognised by its parity and read as "not yet written";
-// the states therefore need no clearing between calls.  Tickets and the
-// done-counter grow monotonically; the call number is read at kernel start
-// and advanced by the tile that finishes last.
-constexpr unsigned long long kFlagShift = 62;
-constexpr unsigned long long kParityBit = 1ull << 61;
-constexpr unsigned long long kValMask = kParityBit - 1;
-constexpr unsigned long long kFlagAgg = 1, kFlagIncl = 2;
-
-struct Sched {
-    unsigned long long ticket;  // tiles started, over all calls
-    unsigned long long done;    // tiles finished, over all calls
-    unsigned long long call;    // calls completed
-    unsigned long long pad;
-};
-
-__global__ void k_sched_reset(Sched* sc, unsigned long long* st_t, unsigned long long* st_d, uint32_t n) {
+__global__ void k_sched_reset(Sched* sc, unsigned long long* st_t, unsigned long long* st_d, uint32_t n,
+                              unsigned long long* ct0, unsigned long long* ct1, uint32_t nc) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         st_t[i] = 0;
         st_d[i] = 0;
     }
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += gridDim.x * blockDim.x) {
+        ct0[i] = 0;
+        ct1[i] = 0;
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc->ticket = 0;
-        sc->done = 0;
         sc->call = 0;
+        sc->cticket = 0;
         sc->pad = 0;
     }
 }
@@ -354,29 +563,21 @@ __global__ void k_counts_zero(int64_t* counts) {
     }
 }
 
-// hexahedron edge e -> lower slot a (upper slot b = a | (1 << axis))
-__device__ __forceinline__ int edge_lo(int e) {
-    // edges 0-3 along x: a = 0,2,4,6; 4-7 along y: a = 0,1,4,5; 8-11 along z: a = 0,1,2,3
-    constexpr uint64_t kLo = 0x3210541064200ull;  // nibble e = lower slot
-    return (int)((kLo >> (4 * e)) & 0xF);
+// Hexahedron edge e -> lower slot (upper slot = lower | (1 << axis)).  Edges
+// 0-3 run along x, 4-7 along y, 8-11 along z; the i-th edge of an axis starts
+// at the slot whose bits are i with a 0 inserted at that axis:
+// x: 0,2,4,6   y: 0,1,4,5   z: 0,1,2,3
+__host__ __device__ constexpr int edge_lo(int e) {
+    return (((e & 3) >> (e >> 2)) << ((e >> 2) + 1)) | ((e & 3) & ((1 << (e >> 2)) - 1));
 }
-__device__ __forceinline__ int edge_hi(int e) { return edge_lo(e) | (1 << (e >> 2)); }
+__host__ __device__ constexpr int edge_hi(int e) { return edge_lo(e) | (1 << (e >> 2)); }
 
-__device__ __forceinline__ unsigned long long wave_incl_scan(unsigned long long x) {
-    int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        unsigned long long y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
-    }
-    return x;
-}
-
-__device__ __forceinline__ unsigned long long ld_acq(unsigned long long* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_rel(unsigned long long* p, unsigned long long v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+// LDS cell of slot s of corner k (corner in {0,1,2}^3, slot in {0,1}^3,
+// around the group): neighbour index dd in [0,27) and child in [0,8)
+__device__ __forceinline__ void slot_cell(int kx, int ky, int kz, int s, int& dd, int& child) {
+    int rx = kx + (s & 1) - 1, ry = ky + ((s >> 1) & 1) - 1, rz = kz + ((s >> 2) & 1) - 1;
+    dd = ((rx + 2) >> 1) + 3 * ((ry + 2) >> 1) + 9 * ((rz + 2) >> 1);
+    child = (rx & 1) | ((ry & 1) << 1) | ((rz & 1) << 2);
 }
 
 template <bool kDuals>
@@ -389,12 +590,19 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
     __shared__ unsigned long long s_pre_t, s_pre_d;
     __shared__ uint32_t s_tile;
     __shared__ unsigned long long s_call;
+    __shared__ uint32_t s_items[kBlock][4];
+    __shared__ uint32_t s_dual[kBlock];
+    __shared__ uint32_t s_list[kTriList];
+    __shared__ int s_gm[kGroupsPerTile];
+    __shared__ uint32_t s_gx[kGroupsPerTile][3];
 
     const int t = threadIdx.x;
     const int gi = t >> 3;  // group within the tile
     const int j = t & 7;    // lane within the group
     if (t == 0) {
-        unsigned long long call = __hip_atomic_load(&a.sched->call, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        // the call number is read before the ticket is taken, so once the last
+        // tile holds its ticket every tile of this call has read it
+        unsigned long long call = __hip_atomic_load(&a.sched->call, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         unsigned long long tk = atomicAdd(&a.sched->ticket, 1ull);
         s_call = call;
         s_tile = (uint32_t)(tk - call * a.n_tiles);
@@ -420,22 +628,52 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
 
     // ---- phase 1: the 27 neighbouring groups of this group, into LDS ----
     if (valid) {
-        for (int dd = j; dd < 27; dd += 8) {
+        // lane j owns neighbours j, j+8, j+16 (and j+24 for j < 3); the home
+        // slots of all of them are loaded before any is examined
+        uint64_t want[4], got[4];
+        uint32_t home[4];
+        float4 va[4], vb[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int dd = j + 8 * q;
+            if (dd >= 27) continue;
             int dx = dd % 3 - 1, dy = (dd / 3) % 3 - 1, dz = dd / 9 - 1;
+            want[q] = group_key(m, gx + dx, gy + dy, gz + dz);
+            home[q] = dd == 13 ? (uint32_t)own : slot_of(want[q], g.shift);
+            const Record* r = a.rec + home[q];
+            va[q] = reinterpret_cast<const float4*>(r->val)[0];
+            vb[q] = reinterpret_cast<const float4*>(r->val)[1];
+            got[q] = r->key;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int dd = j + 8 * q;
+            if (dd >= 27) continue;
             int lv = -1, ref = -1;
-            float v8[8];
-            int h = own;
-            if (dd != 13) h = probe(a.rec, group_key(m, gx + dx, gy + dy, gz + dz), g.shift, g.mask);
-            if (h >= 0) {
-                const float4* pv = reinterpret_cast<const float4*>(a.rec[h].val);
-                float4 p0 = pv[0], p1 = pv[1];
-                v8[0] = p0.x; v8[1] = p0.y; v8[2] = p0.z; v8[3] = p0.w;
-                v8[4] = p1.x; v8[5] = p1.y; v8[6] = p1.z; v8[7] = p1.w;
+            uint32_t h = home[q];
+            uint64_t k = got[q];
+            float4 xa = va[q], xb = vb[q];
+            if (k != want[q] && k != kEmpty) {
+                for (uint32_t step = 0; k != want[q] && k != kEmpty && step <= g.mask; ++step) {
+                    h = (h + 1) & g.mask;
+                    k = a.rec[h].key;
+                }
+                if (k == want[q]) {
+                    xa = reinterpret_cast<const float4*>(a.rec[h].val)[0];
+                    xb = reinterpret_cast<const float4*>(a.rec[h].val)[1];
+                }
+            }
+            float* dst = s_val[gi][dd];
+            if (k == want[q]) {
+                reinterpret_cast<float4*>(dst)[0] = xa;
+                reinterpret_cast<float4*>(dst)[1] = xb;
                 lv = m;
-                ref = h;
+                ref = (int)h;
             } else {
-                // no cell of level m in this block: find the coarser cell that
-                // covers the whole level-(m+1) block, if any
+                // The block holds neither cells of level m nor finer cells (either
+                // would have left a record): it lies inside a coarser cell or in a
+                // hole.  The first record found going up decides.
+                int dx = dd % 3 - 1, dy = (dd / 3) % 3 - 1, dz = dd / 9 - 1;
                 uint32_t bx = gx + dx, by = gy + dy, bz = gz + dz;
                 for (int L = m + 1; L <= g.lmax; ++L) {
                     int sh = L - m - 1;
@@ -447,15 +685,10 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
                     if (v == v) {
                         lv = L;
                         ref = h2 * 8 + child;
-                        v8[0] = v;
+                        dst[0] = v;
                     }
                     break;
                 }
-            }
-            if (lv == m) {
-                for (int c = 0; c < 8; ++c) s_val[gi][dd][c] = v8[c];
-            } else if (lv > m) {
-                s_val[gi][dd][0] = v8[0];
             }
             s_ref[gi][dd] = ref;
             s_lvl[gi][dd] = (int8_t)lv;
@@ -475,52 +708,54 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
         int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
         int refs[8];
         float vals[8];
-        bool ok = true, owner_seen = false;
-        for (int s = 0; s < 8 && ok; ++s) {
-            int rx = kx + (s & 1) - 1, ry = ky + ((s >> 1) & 1) - 1, rz = kz + ((s >> 2) & 1) - 1;
-            int dd = ((rx + 2) >> 1) + 3 * ((ry + 2) >> 1) + 9 * ((rz + 2) >> 1);
+        bool ok = true;
+        uint32_t same = 0, mine = 0;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            int dd, child;
+            slot_cell(kx, ky, kz, s, dd, child);
             int lv = s_lvl[gi][dd];
-            if (lv < 0) {
-                ok = false;  // rule 1 (hole) or rule 2 (finer cells)
-                break;
-            }
-            if (lv == m) {
-                int child = (rx & 1) | ((ry & 1) << 1) | ((rz & 1) << 2);
-                float v = s_val[gi][dd][child];
-                if (v != v) {
-                    ok = false;  // not a cell of this level: finer or hole
-                    break;
-                }
-                if (!owner_seen) {
-                    owner_seen = true;
-                    if (dd != 13) ok = false;  // rule 3: a preceding same-level cell owns it
-                }
-                vals[s] = v;
-                refs[s] = s_ref[gi][dd] * 8 + child;
-            } else {
-                vals[s] = s_val[gi][dd][0];
-                refs[s] = s_ref[gi][dd];
-            }
+            float v = s_val[gi][dd][lv == m ? child : 0];
+            int r = s_ref[gi][dd];
+            refs[s] = lv == m ? r * 8 + child : r;
+            vals[s] = v;
+            // rule 1 (hole) and rule 2 (finer cells) both show as lv < 0 or a NaN
+            ok = ok && lv >= 0 && v == v;
+            same |= (lv == m ? 1u : 0u) << s;
+            mine |= (dd == 13 ? 1u : 0u) << s;
         }
-        if (!ok || !owner_seen) continue;
+        // rule 3: the lowest same-level slot must be a cell of this group
+        if (!ok || !same || !((mine >> (__ffs(same) - 1)) & 1)) continue;
         ++n_dual;
         uint32_t cs = 0, keep = 0;
         if (!kDuals) {
+#pragma unroll
             for (int s = 0; s < 8; ++s) cs |= (vals[s] >= iso ? 1u : 0u) << s;
             unsigned long long e = s_tab[cs];
             int nt = (int)(e >> 60);
-            for (int tt = 0; tt < nt; ++tt) {
-                int ea = (int)((e >> (12 * tt)) & 0xF), eb = (int)((e >> (12 * tt + 4)) & 0xF),
-                    ec = (int)((e >> (12 * tt + 8)) & 0xF);
-                int a0 = refs[edge_lo(ea)], a1 = refs[edge_hi(ea)];
-                int b0 = refs[edge_lo(eb)], b1 = refs[edge_hi(eb)];
-                int c0 = refs[edge_lo(ec)], c1 = refs[edge_hi(ec)];
-                bool ab = (a0 == b0 && a1 == b1) || (a0 == b1 && a1 == b0);
-                bool bc = (b0 == c0 && b1 == c1) || (b0 == c1 && b1 == c0);
-                bool ac = (a0 == c0 && a1 == c1) || (a0 == c1 && a1 == c0);
-                if (!(ab || bc || ac)) {
-                    keep |= 1u << tt;
-                    ++n_tri;
+            if (nt) {
+                // dup[e]: the lowest edge joining the same two cells as edge e
+                uint64_t dup = 0;
+#pragma unroll
+                for (int e1 = 0; e1 < 12; ++e1) {
+                    int a0 = refs[edge_lo(e1)], a1 = refs[edge_hi(e1)];
+                    int d = e1;
+#pragma unroll
+                    for (int e0 = e1 - 1; e0 >= 0; --e0) {
+                        int b0 = refs[edge_lo(e0)], b1 = refs[edge_hi(e0)];
+                        if ((a0 == b0 && a1 == b1) || (a0 == b1 && a1 == b0)) d = e0;
+                    }
+                    dup |= (uint64_t)d << (4 * e1);
+                }
+                for (int tt = 0; tt < nt; ++tt) {
+                    int ea = (int)((e >> (12 * tt)) & 0xF), eb = (int)((e >> (12 * tt + 4)) & 0xF),
+                        ec = (int)((e >> (12 * tt + 8)) & 0xF);
+                    int da = (int)((dup >> (4 * ea)) & 0xF), db = (int)((dup >> (4 * eb)) & 0xF),
+                        dc = (int)((dup >> (4 * ec)) & 0xF);
+                    if (da != db && db != dc && da != dc) {
+                        keep |= 1u << tt;
+                        ++n_tri;
+                    }
                 }
             }
         }
@@ -541,141 +776,161 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
     unsigned long long excl = wave_pre + incl - mine;
 
     // ---- decoupled look-back across tiles ----
-    if (t == 0) {
+    if (wave == 0) {
         const unsigned long long par = (s_call & 1) ? kParityBit : 0ull;
-        unsigned long long agg_t = total >> 32, agg_d = total & 0xFFFFFFFFull;
-        unsigned long long pre_t = 0, pre_d = 0;
-        if (tile == 0) {
-            st_rel(&a.st_d[0], (kFlagIncl << kFlagShift) | par | agg_d);
-            st_rel(&a.st_t[0], (kFlagIncl << kFlagShift) | par | agg_t);
-        } else {
-            st_rel(&a.st_d[tile], (kFlagAgg << kFlagShift) | par | agg_d);
-            st_rel(&a.st_t[tile], (kFlagAgg << kFlagShift) | par | agg_t);
-            int p = (int)tile - 1;
-            while (true) {
-                unsigned long long wt = ld_acq(&a.st_t[p]);
-                unsigned long long wd = ld_acq(&a.st_d[p]);
-                unsigned long long ft = wt >> kFlagShift, fd = wd >> kFlagShift;
-                if (ft == 0 || ft != fd || (wt & kParityBit) != par || (wd & kParityBit) != par) {
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
+        unsigned long long pre_t, pre_d;
+        const unsigned long long agg_t = total >> 32, agg_d = total & 0xFFFFFFFFull;
+        lookback(a.st_t, a.st_d, tile, par, agg_t, agg_d, pre_t, pre_d);
+        if (lane_id() == 0) {
+            s_pre_t = pre_t;
+            s_pre_d = pre_d;
+            if (tile == a.n_tiles - 1) {
+                if (a.counts) {
+                    a.counts[0] = kDuals ? (int64_t)(pre_d + agg_d) : (int64_t)(pre_t + agg_t);
+                    a.counts[1] = (int64_t)(pre_d + agg_d);
                 }
-                pre_t += wt & kValMask;
-                pre_d += wd & kValMask;
-                if (ft == kFlagIncl) break;
-                --p;
+                // every tile of this call read the call number before its ticket
+                __hip_atomic_store(&a.sched->call, s_call + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            st_rel(&a.st_d[tile], (kFlagIncl << kFlagShift) | par | (pre_d + agg_d));
-            st_rel(&a.st_t[tile], (kFlagIncl << kFlagShift) | par | (pre_t + agg_t));
-        }
-        s_pre_t = pre_t;
-        s_pre_d = pre_d;
-        if (tile == a.n_tiles - 1 && a.counts) {
-            a.counts[0] = kDuals ? (int64_t)(pre_d + agg_d) : (int64_t)(pre_t + agg_t);
-            a.counts[1] = (int64_t)(pre_d + agg_d);
         }
     }
     __syncthreads();
 
     // ---- phase 3: write ----
-    int64_t out_t = (int64_t)s_pre_t + (int64_t)(excl >> 32);
-    int64_t out_d = (int64_t)s_pre_d + (int64_t)(excl & 0xFFFFFFFFull);
-    for (int q = 0; q < 4; ++q) {
-        uint32_t it = items[q];
-        if (!(it & 0x80000000u)) continue;
-        int k = (it >> 20) & 31;
-        int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
-        int refs[8], lvs[8];
-        float vals[8];
-        for (int s = 0; s < 8; ++s) {
-            int rx = kx + (s & 1) - 1, ry = ky + ((s >> 1) & 1) - 1, rz = kz + ((s >> 2) & 1) - 1;
-            int dd = ((rx + 2) >> 1) + 3 * ((ry + 2) >> 1) + 9 * ((rz + 2) >> 1);
-            int lv = s_lvl[gi][dd];
-            if (lv == m) {
-                int child = (rx & 1) | ((ry & 1) << 1) | ((rz & 1) << 2);
-                vals[s] = s_val[gi][dd][child];
-                refs[s] = s_ref[gi][dd] * 8 + child;
-            } else {
-                vals[s] = s_val[gi][dd][0];
-                refs[s] = s_ref[gi][dd];
-            }
-            lvs[s] = lv;
-        }
-        if (kDuals) {
+    if (kDuals) {
+        int64_t out_d = (int64_t)s_pre_d + (int64_t)(excl & 0xFFFFFFFFull);
+        for (int q = 0; q < 4; ++q) {
+            uint32_t it = items[q];
+            if (!(it & 0x80000000u)) continue;
+            int k = (it >> 20) & 31;
+            int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
             if (out_d < a.cap) {
                 if (a.corner_level) {
                     int4 pl;
-                    pl.x = (int)(((2 * gx + kx) << m)) + g.ox;
-                    pl.y = (int)(((2 * gy + ky) << m)) + g.oy;
-                    pl.z = (int)(((2 * gz + kz) << m)) + g.oz;
+                    pl.x = (int)((2 * gx + kx) << m) + g.ox;
+                    pl.y = (int)((2 * gy + ky) << m) + g.oy;
+                    pl.z = (int)((2 * gz + kz) << m) + g.oz;
                     pl.w = m;
                     reinterpret_cast<int4*>(a.corner_level)[out_d] = pl;
                 }
                 if (a.verts) {
-                    int4 v0, v1;
-                    v0.x = a.ids[refs[0]]; v0.y = a.ids[refs[1]]; v0.z = a.ids[refs[2]]; v0.w = a.ids[refs[3]];
-                    v1.x = a.ids[refs[4]]; v1.y = a.ids[refs[5]]; v1.z = a.ids[refs[6]]; v1.w = a.ids[refs[7]];
-                    reinterpret_cast<int4*>(a.verts)[2 * out_d] = v0;
-                    reinterpret_cast<int4*>(a.verts)[2 * out_d + 1] = v1;
+                    int id[8];
+#pragma unroll
+                    for (int s = 0; s < 8; ++s) {
+                        int dd, child;
+                        slot_cell(kx, ky, kz, s, dd, child);
+                        int lv = s_lvl[gi][dd];
+                        int r = s_ref[gi][dd];
+                        id[s] = a.ids[lv == m ? r * 8 + child : r];
+                    }
+                    reinterpret_cast<int4*>(a.verts)[2 * out_d] = make_int4(id[0], id[1], id[2], id[3]);
+                    reinterpret_cast<int4*>(a.verts)[2 * out_d + 1] = make_int4(id[4], id[5], id[6], id[7]);
                 }
             }
             ++out_d;
-            continue;
         }
-        uint32_t cs = (it >> 8) & 0xFF, keep = it & 0x1F;
-        unsigned long long e = s_tab[cs];
-        int nt = (int)(e >> 60);
-        for (int tt = 0; tt < nt; ++tt) {
-            if (!((keep >> tt) & 1)) continue;
-            if (out_t < a.cap) {
+        return;
+    }
+    // Triangles are spread over all lanes: every kept triangle gets an entry
+    // (owner lane, item, triangle) in an LDS list, in output order, and lanes
+    // take entries round-robin.  Long tiles go through the list in chunks.
+    {
+        const uint32_t tile_tris = (uint32_t)(total >> 32);
+        const uint32_t my_first = (uint32_t)(excl >> 32);
+        if (j == 0) {
+            s_gm[gi] = m;
+            s_gx[gi][0] = gx;
+            s_gx[gi][1] = gy;
+            s_gx[gi][2] = gz;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s_items[t][q] = items[q];
+        s_dual[t] = (uint32_t)(excl & 0xFFFFFFFFull);
+        for (uint32_t c0 = 0; c0 < tile_tris; c0 += kTriList) {
+            __syncthreads();
+            // publish my triangles that fall into [c0, c0 + kTriList)
+            uint32_t idx = my_first;
+            for (int q = 0; q < 4; ++q) {
+                uint32_t it = items[q];
+                uint32_t keep = it & 0x1F;
+                for (int tt = 0; tt < 5; ++tt) {
+                    if (!((keep >> tt) & 1)) continue;
+                    if (idx >= c0 && idx < c0 + kTriList) s_list[idx - c0] = ((uint32_t)t << 8) | (q << 4) | tt;
+                    ++idx;
+                }
+            }
+            __syncthreads();
+            uint32_t n_here = tile_tris - c0 < (uint32_t)kTriList ? tile_tris - c0 : (uint32_t)kTriList;
+            for (uint32_t w = t; w < n_here; w += kBlock) {
+                uint32_t en = s_list[w];
+                int owner = (int)(en >> 8), q = (int)((en >> 4) & 3), tt = (int)(en & 15);
+                int og = owner >> 3;
+                uint32_t it = s_items[owner][q];
+                int k = (it >> 20) & 31;
+                int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
+                int om = s_gm[og];
+                uint32_t gg[3] = {s_gx[og][0], s_gx[og][1], s_gx[og][2]};
+                unsigned long long e = s_tab[(it >> 8) & 0xFF];
+                int64_t o_t = (int64_t)s_pre_t + c0 + w;
+                if (o_t >= a.cap) continue;
                 float p[9];
                 int cells[6];
+#pragma unroll
                 for (int v = 0; v < 3; ++v) {
                     int ed = (int)((e >> (12 * tt + 4 * v)) & 0xF);
-                    int sa = edge_lo(ed), sb = edge_hi(ed);
-                    if (vals[sa] >= iso) {
-                        int tmp = sa;
-                        sa = sb;
-                        sb = tmp;
+                    float ev[2];
+                    int el[2], er[2], epos[2][3];
+#pragma unroll
+                    for (int side = 0; side < 2; ++side) {
+                        int sl = side ? edge_hi(ed) : edge_lo(ed);
+                        int dd, child;
+                        slot_cell(kx, ky, kz, sl, dd, child);
+                        int lv = s_lvl[og][dd];
+                        int r = s_ref[og][dd];
+                        ev[side] = s_val[og][dd][lv == om ? child : 0];
+                        er[side] = lv == om ? r * 8 + child : r;
+                        el[side] = lv;
+                        epos[side][0] = kx + (sl & 1) - 1;
+                        epos[side][1] = ky + ((sl >> 1) & 1) - 1;
+                        epos[side][2] = kz + ((sl >> 2) & 1) - 1;
                     }
-                    float va = vals[sa], vb = vals[sb];
+                    // A = the end below iso, B = the end at or above it
+                    const bool swap = ev[0] >= iso;
+                    const float va = swap ? ev[1] : ev[0], vb = swap ? ev[0] : ev[1];
+                    const int la = swap ? el[1] : el[0], lb = swap ? el[0] : el[1];
                     float tp = (iso - va) / (vb - va);
-                    int ra[3] = {kx + (sa & 1) - 1, ky + ((sa >> 1) & 1) - 1, kz + ((sa >> 2) & 1) - 1};
-                    int rb[3] = {kx + (sb & 1) - 1, ky + ((sb >> 1) & 1) - 1, kz + ((sb >> 2) & 1) - 1};
-                    uint32_t gg[3] = {gx, gy, gz};
-                    int oo[3] = {g.ox, g.oy, g.oz};
+                    const int oo[3] = {g.ox, g.oy, g.oz};
+#pragma unroll
                     for (int ax = 0; ax < 3; ++ax) {
+                        int ra = swap ? epos[1][ax] : epos[0][ax], rb = swap ? epos[0][ax] : epos[1][ax];
                         // finest-unit offset coordinate of the slot position, floored to the cell's level
-                        uint32_t pa = ((2 * gg[ax] + (uint32_t)ra[ax]) << m) & ~((1u << lvs[sa]) - 1u);
-                        uint32_t pb = ((2 * gg[ax] + (uint32_t)rb[ax]) << m) & ~((1u << lvs[sb]) - 1u);
-                        float ca = (float)((int)pa + oo[ax]) + 0.5f * (float)(1 << lvs[sa]);
-                        float cb = (float)((int)pb + oo[ax]) + 0.5f * (float)(1 << lvs[sb]);
+                        uint32_t pa = ((2 * gg[ax] + (uint32_t)ra) << om) & ~((1u << la) - 1u);
+                        uint32_t pb = ((2 * gg[ax] + (uint32_t)rb) << om) & ~((1u << lb) - 1u);
+                        float ca = (float)((int)pa + oo[ax]) + 0.5f * (float)(1 << la);
+                        float cb = (float)((int)pb + oo[ax]) + 0.5f * (float)(1 << lb);
                         p[3 * v + ax] = fmaf(tp, cb - ca, ca);
                     }
-                    cells[2 * v] = refs[sa];
-                    cells[2 * v + 1] = refs[sb];
+                    cells[2 * v] = swap ? er[1] : er[0];
+                    cells[2 * v + 1] = swap ? er[0] : er[1];
                 }
                 if (a.tris) {
-                    float* o = a.tris + 9 * out_t;
+                    float* o = a.tris + 9 * o_t;
+#pragma unroll
                     for (int c = 0; c < 9; ++c) o[c] = p[c];
                 }
                 if (a.tri_cells) {
-                    int32_t* o = a.tri_cells + 6 * out_t;
+                    int32_t* o = a.tri_cells + 6 * o_t;
+#pragma unroll
                     for (int c = 0; c < 6; ++c) o[c] = a.ids[cells[c]];
                 }
-                if (a.tri_dual) a.tri_dual[out_t] = (int32_t)out_d;
+                if (a.tri_dual) {
+                    // the owner lane's emitted duals before item q
+                    uint32_t rank = 0;
+                    for (int q2 = 0; q2 < q; ++q2) rank += s_items[owner][q2] >> 31;
+                    a.tri_dual[o_t] = (int32_t)((int64_t)s_pre_d + s_dual[owner] + rank);
+                }
             }
-            ++out_t;
         }
-        ++out_d;
-    }
-
-    // ---- the tile that finishes last advances the call number ----
-    __syncthreads();
-    if (t == 0) {
-        unsigned long long d = atomicAdd(&a.sched->done, 1ull) + 1;
-        if (d == (s_call + 1) * (unsigned long long)a.n_tiles)
-            __hip_atomic_store(&a.sched->call, s_call + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -716,8 +971,8 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct amr_set {
     int device = 0;
-    Ctrl* ctrl = nullptr;     // device
-    Ctrl host_ctrl{};
+    Ctrl* ctrl = nullptr;  // device
+    Ctrl* host_ctrl = nullptr;
     // upload
     const int32_t* xyz = nullptr;
     const int32_t* lvl = nullptr;
@@ -727,25 +982,25 @@ struct amr_set {
     int lmin = 0, lmax = 0;
     int32_t origin[3] = {0, 0, 0};
     uint64_t level_count[kMaxLevel + 1] = {};
-    uint64_t group_hint = 0;
+    uint64_t record_hint = 0;
     // index
     bool built = false;
     uint32_t cap = 0;
-    int shift = 0;
     uint32_t n_groups = 0;
     Record* rec = nullptr;
     int32_t* ids = nullptr;
     int32_t* glist = nullptr;
     unsigned long long* st_t = nullptr;
     unsigned long long* st_d = nullptr;
+    unsigned long long* ct0 = nullptr;
+    unsigned long long* ct1 = nullptr;
     Sched* sched = nullptr;
-    uint32_t max_tiles = 0;
 };
 
 namespace {
 
 uint32_t table_cap(const amr_set* s) {
-    uint64_t want = s->group_hint * 2;
+    uint64_t want = s->record_hint * 2;
     if (want < 1024) want = 1024;
     uint64_t cap = 1;
     while (cap < want) cap <<= 1;
@@ -753,14 +1008,19 @@ uint32_t table_cap(const amr_set* s) {
 }
 
 struct Layout {
-    size_t rec, ids, glist, st_t, st_d, sched, total;
-    uint32_t max_tiles;
+    size_t rec, ids, glist, st_t, st_d, ct0, ct1, sched, total;
+    uint32_t max_tiles, compact_tiles;
+    int compact_per;
 };
 
 Layout layout_for(uint32_t cap) {
     Layout L{};
-    uint32_t max_groups = cap / 2;
+    uint32_t max_groups = cap;  // at most one group per slot
     L.max_tiles = (max_groups + kGroupsPerTile - 1) / kGroupsPerTile + 1;
+    // small tables: more, smaller compaction tiles (latency); large: fewer tickets
+    L.compact_per = cap <= (1u << 20) ? 4 : kCompactMaxPerThread;
+    uint32_t ctile = (uint32_t)(kBlock * L.compact_per);
+    L.compact_tiles = (cap + ctile - 1) / ctile;
     size_t off = 0;
     L.rec = off;
     off = align256(off + (size_t)cap * sizeof(Record));
@@ -772,6 +1032,10 @@ Layout layout_for(uint32_t cap) {
     off = align256(off + (size_t)L.max_tiles * 8);
     L.st_d = off;
     off = align256(off + (size_t)L.max_tiles * 8);
+    L.ct0 = off;
+    off = align256(off + (size_t)L.compact_tiles * 8);
+    L.ct1 = off;
+    off = align256(off + (size_t)L.compact_tiles * 8);
     L.sched = off;
     off = align256(off + sizeof(Sched));
     L.total = off;
@@ -847,8 +1111,14 @@ int amr_create(amr_set** out, int hip_device) {
     amr_set* s = new (std::nothrow) amr_set();
     if (!s) return fail(AMR_ENOMEM, "amr_create: out of host memory");
     s->device = hip_device;
+    s->host_ctrl = (Ctrl*)calloc(1, sizeof(Ctrl));
+    if (!s->host_ctrl) {
+        delete s;
+        return fail(AMR_ENOMEM, "amr_create: out of host memory");
+    }
     hipError_t e = hipMalloc((void**)&s->ctrl, sizeof(Ctrl));
     if (e != hipSuccess) {
+        free(s->host_ctrl);
         delete s;
         return hipfail(e, "amr_create: control block");
     }
@@ -863,6 +1133,7 @@ void amr_destroy(amr_set* s) {
         DeviceGuard dg(s->device);
         if (s->ctrl) (void)hipFree(s->ctrl);
     }
+    free(s->host_ctrl);
     delete s;
 }
 
@@ -882,7 +1153,7 @@ int amr_upload(amr_set* s, const int32_t* xyz, const int32_t* level, const float
     for (int l = 0; l <= kMaxLevel; ++l) s->level_count[l] = 0;
     s->lmin = s->lmax = 0;
     s->origin[0] = s->origin[1] = s->origin[2] = 0;
-    s->group_hint = 0;
+    s->record_hint = 0;
     if (n == 0) {
         s->uploaded = true;
         return AMR_OK;
@@ -891,11 +1162,30 @@ int amr_upload(amr_set* s, const int32_t* xyz, const int32_t* level, const float
     hipLaunchKernelGGL(k_upload, dim3(grid_for(n, 256)), dim3(256), 0, stream, xyz, level, value, n, s->ctrl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hipfail(e, "amr_upload: launch");
-    e = hipMemcpyAsync(&s->host_ctrl, s->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream);
+    e = hipMemcpyAsync(s->host_ctrl, s->ctrl, sizeof(Partial) * kReplicas, hipMemcpyDeviceToHost, stream);
     if (e != hipSuccess) return hipfail(e, "amr_upload: readback");
     e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hipfail(e, "amr_upload: synchronize");
-    const Ctrl& c = s->host_ctrl;
+    Partial c{};
+    for (int a = 0; a < 3; ++a) {
+        c.lo[a] = INT32_MAX;
+        c.hi[a] = INT32_MIN;
+    }
+    c.lmin = INT32_MAX;
+    c.lmax = INT32_MIN;
+    c.bad = ~0ull;
+    for (int r = 0; r < kReplicas; ++r) {
+        const Partial& p = s->host_ctrl->part[r];
+        for (int a = 0; a < 3; ++a) {
+            c.lo[a] = p.lo[a] < c.lo[a] ? p.lo[a] : c.lo[a];
+            c.hi[a] = p.hi[a] > c.hi[a] ? p.hi[a] : c.hi[a];
+        }
+        c.lmin = p.lmin < c.lmin ? p.lmin : c.lmin;
+        c.lmax = p.lmax > c.lmax ? p.lmax : c.lmax;
+        c.err |= p.err;
+        c.bad = p.bad < c.bad ? p.bad : c.bad;
+        for (int l = 0; l <= kMaxLevel; ++l) c.level_count[l] += p.level_count[l];
+    }
     if (c.err) {
         const char* why = (c.err & kErrLevel)   ? "level outside [0, 20]"
                           : (c.err & kErrAlign) ? "lower corner not a multiple of 2^level"
@@ -915,12 +1205,14 @@ int amr_upload(amr_set* s, const int32_t* xyz, const int32_t* level, const float
         int64_t fl = lo >= 0 ? (lo / blk) * blk : -((-lo + blk - 1) / blk) * blk;
         s->origin[a] = (int32_t)(fl - blk);
     }
+    // records: one per group of each level, plus refined markers (about one
+    // record per 7 groups for octrees)
     uint64_t hint = 0;
     for (int l = 0; l <= kMaxLevel; ++l) {
         s->level_count[l] = c.level_count[l];
         hint += (c.level_count[l] + 7) / 8;
     }
-    s->group_hint = hint;
+    s->record_hint = hint + hint / 7 + 64;
     s->uploaded = true;
     g_err[0] = 0;
     return AMR_OK;
@@ -953,36 +1245,38 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     s->glist = (int32_t*)(base + L.glist);
     s->st_t = (unsigned long long*)(base + L.st_t);
     s->st_d = (unsigned long long*)(base + L.st_d);
+    s->ct0 = (unsigned long long*)(base + L.ct0);
+    s->ct1 = (unsigned long long*)(base + L.ct1);
     s->sched = (Sched*)(base + L.sched);
-    s->max_tiles = L.max_tiles;
     s->n_groups = 0;
     Geo g = geo_of(s);
     hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, stream, s->ctrl);
     hipLaunchKernelGGL(k_index_init, dim3(grid_for(cap, 256)), dim3(256), 0, stream, s->rec, s->ids, cap);
     hipLaunchKernelGGL(k_sched_reset, dim3(grid_for(L.max_tiles, 256)), dim3(256), 0, stream, s->sched, s->st_t,
-                       s->st_d, L.max_tiles);
-    if (s->n > 0) {
+                       s->st_d, L.max_tiles, s->ct0, s->ct1, L.compact_tiles);
+    if (s->n > 0)
         hipLaunchKernelGGL(k_index_insert, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->val,
-                           s->n, g, s->rec, s->ids, s->glist, cap / 2, s->ctrl);
-        hipLaunchKernelGGL(k_index_overlap, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->n, g,
-                           s->rec, s->ctrl);
-    }
+                           s->n, g, s->rec, s->ids, s->ctrl);
+    hipLaunchKernelGGL(k_index_compact, dim3(L.compact_tiles), dim3(kBlock), 0, stream, s->rec, cap, s->glist,
+                       s->ct0, s->ct1, s->sched, L.compact_tiles, L.compact_per, s->ctrl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hipfail(e, "amr_build_index: launch");
-    e = hipMemcpyAsync(&s->host_ctrl, s->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream);
+    const size_t tail = offsetof(Ctrl, overflow);
+    e = hipMemcpyAsync((char*)s->host_ctrl + tail, (char*)s->ctrl + tail, sizeof(Ctrl) - tail,
+                       hipMemcpyDeviceToHost, stream);
     if (e != hipSuccess) return hipfail(e, "amr_build_index: readback");
     e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hipfail(e, "amr_build_index: synchronize");
-    const Ctrl& c = s->host_ctrl;
-    if (c.overflow) {
-        uint64_t seen = c.n_groups;
-        s->group_hint = seen > s->group_hint * 4 ? seen : s->group_hint * 4;
+    const Ctrl& c = *s->host_ctrl;
+    if (c.overflow || c.n_records * 4 > (unsigned long long)cap * 3) {
+        uint64_t seen = c.n_records;
+        s->record_hint = seen * 2 > s->record_hint * 4 ? seen * 2 : s->record_hint * 4;
         return fail(AMR_ENOSPACE, "amr_build_index: hash table too small (%u slots); query amr_index_bytes again",
                     cap);
     }
     if (c.dup) return fail(AMR_EOVERLAP, "amr_build_index: duplicate cell (index %llu)", c.bad_build);
-    if (c.overlap) return fail(AMR_EOVERLAP, "amr_build_index: cell %llu lies inside a coarser cell", c.bad_build);
-    s->n_groups = c.n_groups;
+    if (c.overlap) return fail(AMR_EOVERLAP, "amr_build_index: cell %llu overlaps a coarser cell", c.bad_build);
+    s->n_groups = (uint32_t)c.n_groups;
     s->built = true;
     g_err[0] = 0;
     return AMR_OK;
