@@ -250,3 +250,151 @@ WORKLOADS = {
     "two-level-sphere-16": two_level_sphere,
     "octree-shell-256": octree_shell,
 }
+
+
+# ---------------------------------------------------------------------------
+# Block-structured set with holes: 8^3-cell bricks on 4 levels around
+# synthetic vortex tubes
+# ---------------------------------------------------------------------------
+
+def _helices(seed, n, domain):
+    k = np.arange(n, dtype=np.uint64)
+    rnd = lambda st: uniform(seed, st, k)
+    c = np.stack([domain * (0.3 + 0.4 * rnd(20 + a)) for a in range(3)], 1)
+    # axis from a uniform direction
+    zc = 2.0 * rnd(23) - 1.0
+    ph = 2.0 * np.pi * rnd(24)
+    ax = np.stack([np.sqrt(1 - zc * zc) * np.cos(ph), np.sqrt(1 - zc * zc) * np.sin(ph), zc], 1)
+    tmp = np.where(np.abs(ax[:, :1]) < 0.9, np.array([[1.0, 0, 0]]), np.array([[0, 1.0, 0]]))
+    u = np.cross(ax, tmp)
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    v = np.cross(ax, u)
+    R = 40.0 + 100.0 * rnd(25)
+    P = 150.0 + 250.0 * rnd(26)
+    # circulation: log-normal spread, core radius uniform
+    z = np.sqrt(-2.0 * np.log(np.maximum(rnd(27), 1e-300))) * np.cos(2 * np.pi * rnd(28))
+    gamma = np.exp(z)
+    rc = 8.0 + 24.0 * rnd(29)
+    return dict(c=c, a=ax, u=u, v=v, R=R, P=P, gamma=gamma, rc=rc)
+
+
+def _helix_dist(pts, H, i):
+    """Distance from pts [n,3] to helix i and the unit tangent at the nearest
+    of three candidate turns (nearest in axial position)."""
+    d = pts - H["c"][i]
+    z = d @ H["a"][i]
+    th = np.arctan2(d @ H["v"][i], d @ H["u"][i])
+    R, P = H["R"][i], H["P"][i]
+    k0 = np.round((2 * np.pi * z / P - th) / (2 * np.pi))
+    best = np.full(len(pts), np.inf)
+    best_s = np.zeros(len(pts))
+    for dk in (-1.0, 0.0, 1.0):
+        s = th + 2 * np.pi * (k0 + dk)
+        h = (R * np.cos(s))[:, None] * H["u"][i] + (R * np.sin(s))[:, None] * H["v"][i] + \
+            (P * s / (2 * np.pi))[:, None] * H["a"][i]
+        dd = ((d - h) ** 2).sum(1)
+        better = dd < best
+        best = np.where(better, dd, best)
+        best_s = np.where(better, s, best_s)
+    t = (-R * np.sin(best_s))[:, None] * H["u"][i] + (R * np.cos(best_s))[:, None] * H["v"][i] + \
+        (P / (2 * np.pi)) * H["a"][i]
+    t /= np.linalg.norm(t, axis=1, keepdims=True)
+    return np.sqrt(best), t
+
+
+def _vortex_values_torch(xyz, lv, H, n_helix, device, chunk):
+    """Same field as the numpy path, evaluated with torch (float64) on
+    `device`; used to generate large sets quickly.  Results can differ from
+    the numpy path in the last bit of some values."""
+    import torch
+
+    out = np.empty(len(xyz), np.float32)
+    Ht = {k: torch.as_tensor(np.asarray(v), dtype=torch.float64, device=device) for k, v in H.items()}
+    for s0 in range(0, len(xyz), chunk):
+        p = torch.as_tensor(xyz[s0:s0 + chunk], device=device).to(torch.float64)
+        w = torch.as_tensor(lv[s0:s0 + chunk], device=device).to(torch.int64)
+        p = p + 0.5 * torch.pow(2.0, w.to(torch.float64))[:, None]
+        om = torch.zeros_like(p)
+        for i in range(n_helix):
+            d = p - Ht["c"][i]
+            z = d @ Ht["a"][i]
+            th = torch.atan2(d @ Ht["v"][i], d @ Ht["u"][i])
+            R, P = Ht["R"][i], Ht["P"][i]
+            k0 = torch.round((2 * np.pi * z / P - th) / (2 * np.pi))
+            best = torch.full_like(z, float("inf"))
+            best_s = torch.zeros_like(z)
+            for dk in (-1.0, 0.0, 1.0):
+                sp = th + 2 * np.pi * (k0 + dk)
+                h = (R * torch.cos(sp))[:, None] * Ht["u"][i] + (R * torch.sin(sp))[:, None] * Ht["v"][i] + \
+                    (P * sp / (2 * np.pi))[:, None] * Ht["a"][i]
+                dd = ((d - h) ** 2).sum(1)
+                better = dd < best
+                best = torch.where(better, dd, best)
+                best_s = torch.where(better, sp, best_s)
+            t = (-R * torch.sin(best_s))[:, None] * Ht["u"][i] + (R * torch.cos(best_s))[:, None] * Ht["v"][i] + \
+                (P / (2 * np.pi)) * Ht["a"][i]
+            t = t / torch.linalg.norm(t, dim=1, keepdim=True)
+            rc = Ht["rc"][i]
+            om += (Ht["gamma"][i] / (np.pi * rc * rc) * torch.exp(-best / (rc * rc)))[:, None] * t
+        out[s0:s0 + chunk] = torch.sqrt((om * om).sum(1)).to(torch.float32).cpu().numpy()
+    return out
+
+
+def block_vortex(domain: int = 1024, tube: float = 13.5, n_helix: int = 5, seed: int = 3,
+                 obstacle=((560, 720), (380, 540), (400, 560)), chunk: int = 1 << 22, device=None) -> CellSet:
+    """Block-structured AMR: 8^3-cell bricks on levels 0..3 (a level-l brick
+    spans 8*2^l units); level-3 bricks tile [0, domain)^3 and a brick of level
+    l > 0 is replaced by its 8 half-size bricks when it comes within
+    tube * 2^(l-1) of one of `n_helix` seeded helices.  Every cell meeting the
+    axis-aligned obstacle box is removed (a hole, no parent structure).
+    Value: |sum of Lamb-Oseen tube vorticities| (log-normal circulations);
+    iso: 90th percentile of the cell values."""
+    H = _helices(seed, n_helix, float(domain))
+    top = 3
+    wb = 8 << top
+    r = np.arange(domain // wb, dtype=np.int64) * wb
+    b = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(-1, 3)
+    leaves = []
+    for lvl in range(top, -1, -1):
+        span = 8 << lvl
+        if lvl == 0 or len(b) == 0:
+            leaves.append((b, lvl))
+            break
+        ctr = b.astype(np.float64) + span / 2.0
+        dmin = np.full(len(b), np.inf)
+        for i in range(n_helix):
+            dmin = np.minimum(dmin, _helix_dist(ctr, H, i)[0])
+        refine = dmin - np.sqrt(3.0) * span / 2.0 < tube * (1 << (lvl - 1))
+        leaves.append((b[~refine], lvl))
+        half = span // 2
+        b = (b[refine][:, None, :] + _CHILD[None] * half).reshape(-1, 3)
+    cell8 = np.stack(np.meshgrid(np.arange(8), np.arange(8), np.arange(8), indexing="ij"), -1).reshape(-1, 3)
+    xyz_parts, lv_parts = [], []
+    (ox0, ox1), (oy0, oy1), (oz0, oz1) = obstacle
+    for bb, lvl in leaves:
+        if len(bb) == 0:
+            continue
+        w = 1 << lvl
+        cells = (bb[:, None, :] + cell8[None] * w).reshape(-1, 3)
+        hit = ((cells[:, 0] < ox1) & (cells[:, 0] + w > ox0) & (cells[:, 1] < oy1) & (cells[:, 1] + w > oy0) &
+               (cells[:, 2] < oz1) & (cells[:, 2] + w > oz0))
+        cells = cells[~hit]
+        xyz_parts.append(cells.astype(np.int32))
+        lv_parts.append(np.full(len(cells), lvl, np.int32))
+    xyz = np.concatenate(xyz_parts)
+    lv = np.concatenate(lv_parts)
+    if device is not None:
+        val = _vortex_values_torch(xyz, lv, H, n_helix, device, chunk)
+    else:
+        val = np.empty(len(xyz), np.float32)
+        for s0 in range(0, len(xyz), chunk):
+            p = xyz[s0:s0 + chunk].astype(np.float64) + 0.5 * (1 << lv[s0:s0 + chunk].astype(np.int64))[:, None]
+            om = np.zeros((len(p), 3))
+            for i in range(n_helix):
+                d, t = _helix_dist(p, H, i)
+                rc = H["rc"][i]
+                om += (H["gamma"][i] / (np.pi * rc * rc) * np.exp(-(d * d) / (rc * rc)))[:, None] * t
+            val[s0:s0 + chunk] = np.sqrt((om * om).sum(1)).astype(np.float32)
+    iso = np.sort(val)[int(0.9 * (len(val) - 1))]
+    return _make(xyz, lv, val, float(iso), "block-vortex-%d" % domain, seed, domain=domain, tube=tube,
+                 obstacle=obstacle, n_helix=n_helix)

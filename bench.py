@@ -28,6 +28,8 @@ def make_workload(name):
         return amrgen.octree_shell()
     if name == "two-level-sphere-16":
         return amrgen.two_level_sphere()
+    if name == "block-vortex-1024":
+        return amrgen.block_vortex(device="cuda")
     raise SystemExit("unknown workload %s" % name)
 
 

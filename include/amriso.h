@@ -139,6 +139,59 @@ int amr_dual_cells(amr_set* set, int32_t* corner_level, int32_t* verts, int64_t 
 int amr_isosurface(amr_set* set, float iso, float* tris, int32_t* tri_cells, int32_t* tri_dual, int64_t cap,
                    int64_t* counts, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+   Batched iso-surfaces (many iso-values and/or many sets in one launch).
+   Topology is iso-independent (paper sec. 4: the dual cells do not depend on
+   the field), so each set's dual cells are computed once with amr_dual_cells
+   and every job runs Marching Cubes (paper sec. 5) over that list.  One
+   persistent kernel handles all jobs: a counting phase, a per-job scan over
+   tiles and a writing phase, separated by grid-wide barriers.  For a job on
+   set s with iso v, the triangles, their order and every bit of their
+   positions equal those of amr_isosurface(s, v) (no cell pairs / dual
+   indices are written here).
+   --------------------------------------------------------------------------- */
+
+typedef struct amr_batch amr_batch; /* opaque, library-owned host handle */
+
+/* One job of a batch; the array of jobs lives in device memory, so iso-values
+   can be changed between launches (e.g. between replays of a HIP graph). */
+typedef struct amr_iso_job {
+    float iso;          /* iso-value (finite) */
+    int32_t set;        /* index into the batch's sets */
+    int64_t out_offset; /* first triangle slot of this job in the output */
+    int64_t out_cap;    /* triangles this job may write (more are counted only) */
+} amr_iso_job;
+
+/* Create a batch over n_sets indexed sets.  dual_verts[i] is the device
+   int32 [n_duals[i]][8] list written by amr_dual_cells for sets[i] (caller-
+   owned, kept alive and unchanged with the set's input arrays).  Allocates
+   a small device table (freed by amr_batch_destroy); synchronous.  Returns
+   AMR_ESTATE if a set has no index, AMR_EINVAL for bad arguments. */
+int amr_batch_create(amr_batch** out, amr_set* const* sets, const int32_t* const* dual_verts,
+                     const int64_t* n_duals, int n_sets);
+
+void amr_batch_destroy(amr_batch* batch);
+
+/* Device workspace bytes for up to max_jobs jobs with `block` threads per
+   work-group and `per_thread` duals per thread (tile = block * per_thread). */
+int amr_batch_workspace_bytes(const amr_batch* batch, int max_jobs, int block, int per_thread, size_t* bytes);
+
+/* Enqueue one persistent launch for n_jobs jobs (1 <= n_jobs <= 256).
+     jobs      device amr_iso_job [n_jobs]
+     tris      device float [..][3][3]: job j writes triangles
+               out_offset .. out_offset + min(count, out_cap) - 1
+     counts    device int64 [n_jobs]: full triangle count of each job
+     workspace device, >= amr_batch_workspace_bytes(n_jobs, block,
+               per_thread), 256-byte aligned, zero-filled before its first
+               use; it holds the grid barrier, so launches that share a
+               workspace, and batched launches on one GPU, must not overlap
+               in time.  Its bytes 8..11 become non-zero if a barrier wait
+               ever gave up (the results of that launch are then invalid).
+     block     64, 128, 256 or 512;  per_thread 1, 2 or 4
+   No host synchronisation: capturable in a HIP graph. */
+int amr_batch_isosurface(amr_batch* batch, const amr_iso_job* jobs, int n_jobs, float* tris, int64_t* counts,
+                         void* workspace, size_t bytes, int block, int per_thread, hipStream_t stream);
+
 /* Message describing the last error on the calling thread ("" if none). */
 const char* amr_last_error(void);
 

@@ -22,7 +22,8 @@ _NAMES = {0: "AMR_OK", -1: "AMR_EINVAL", -2: "AMR_ERANGE", -3: "AMR_EOVERLAP", -
 
 # Every entry point of the C ABI (include/amriso.h).
 ABI_SYMBOLS = ("amr_create", "amr_destroy", "amr_upload", "amr_index_bytes", "amr_build_index", "amr_dual_cells",
-               "amr_isosurface", "amr_last_error")
+               "amr_isosurface", "amr_batch_create", "amr_batch_destroy", "amr_batch_workspace_bytes",
+               "amr_batch_isosurface", "amr_last_error")
 
 _lib = None
 
@@ -57,6 +58,15 @@ def load_library(path: str = LIB_PATH):
     L.amr_dual_cells.restype = C.c_int
     L.amr_isosurface.argtypes = [vp, C.c_float, f32p, i32p, i32p, i64, i64p, vp]
     L.amr_isosurface.restype = C.c_int
+    L.amr_batch_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                   C.POINTER(C.c_int64), C.c_int]
+    L.amr_batch_create.restype = C.c_int
+    L.amr_batch_destroy.argtypes = [vp]
+    L.amr_batch_destroy.restype = None
+    L.amr_batch_workspace_bytes.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_size_t)]
+    L.amr_batch_workspace_bytes.restype = C.c_int
+    L.amr_batch_isosurface.argtypes = [vp, vp, C.c_int, vp, vp, vp, C.c_size_t, C.c_int, C.c_int, vp]
+    L.amr_batch_isosurface.restype = C.c_int
     L.amr_last_error.argtypes = []
     L.amr_last_error.restype = C.c_char_p
     _lib = L
@@ -198,6 +208,105 @@ class AmrSet:
         if dual:
             out["dual"] = td[:t]
         return out
+
+
+# amr_iso_job: float iso, int32 set, int64 out_offset, int64 out_cap (24 bytes)
+JOB_DTYPE = None
+
+
+def _job_dtype():
+    global JOB_DTYPE
+    if JOB_DTYPE is None:
+        import numpy as np
+
+        JOB_DTYPE = np.dtype([("iso", "<f4"), ("set", "<i4"), ("out_offset", "<i8"), ("out_cap", "<i8")])
+        assert JOB_DTYPE.itemsize == 24
+    return JOB_DTYPE
+
+
+class AmrBatch:
+    """Many (set, iso) jobs in one persistent launch over the sets' dual cell
+    lists (computed once per set with amr_dual_cells)."""
+
+    def __init__(self, sets):
+        self.lib = load_library()
+        self.sets = list(sets)
+        self.device = self.sets[0].device
+        self.duals = []
+        for s in self.sets:
+            cl, vv = s.dual_cells()
+            self.duals.append(vv.contiguous())
+        n = len(self.sets)
+        hs = (C.c_void_p * n)(*[s._h.value for s in self.sets])
+        dv = (C.c_void_p * n)(*[d.data_ptr() for d in self.duals])
+        nd = (C.c_int64 * n)(*[int(d.shape[0]) for d in self.duals])
+        h = C.c_void_p()
+        _check(self.lib.amr_batch_create(C.byref(h), hs, dv, nd, n))
+        self._h = h
+        self._ws = {}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            torch.cuda.synchronize(self.device)
+            self.lib.amr_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self, n_jobs: int, block: int = 256, per_thread: int = 1):
+        """Zero-filled workspace (cached per launch shape)."""
+        b = C.c_size_t(0)
+        _check(self.lib.amr_batch_workspace_bytes(self._h, n_jobs, block, per_thread, C.byref(b)))
+        key = (block, per_thread)
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < b.value:
+            ws = torch.zeros(max(int(b.value), 256), dtype=torch.uint8, device=self.device)
+            self._ws[key] = ws
+        return ws
+
+    def jobs_tensor(self, set_idx, isos, offsets, caps):
+        import numpy as np
+
+        arr = np.zeros(len(isos), dtype=_job_dtype())
+        arr["iso"] = np.asarray(isos, np.float32)
+        arr["set"] = np.asarray(set_idx, np.int32)
+        arr["out_offset"] = np.asarray(offsets, np.int64)
+        arr["out_cap"] = np.asarray(caps, np.int64)
+        return torch.from_numpy(arr.view(np.uint8)).to(self.device)
+
+    def run_into(self, jobs, n_jobs: int, tris, counts, block: int = 256, per_thread: int = 1, workspace=None):
+        """Enqueue one launch (no synchronisation); capturable in a graph."""
+        ws = workspace if workspace is not None else self.workspace(n_jobs, block, per_thread)
+        _check(self.lib.amr_batch_isosurface(self._h, _ptr(jobs), int(n_jobs), _ptr(tris), _ptr(counts), _ptr(ws),
+                                             ws.numel(), int(block), int(per_thread), _stream(self.device)))
+        return counts
+
+    def barrier_timed_out(self, block: int = 256, per_thread: int = 1) -> bool:
+        ws = self._ws.get((block, per_thread))
+        return ws is not None and bool(ws[8:12].any().item())
+
+    def isosurface(self, set_idx, isos, block: int = 256, per_thread: int = 1):
+        """List of float32 [T_j, 9] triangle tensors, one per job: a count
+        launch sizes the output, a second launch writes it."""
+        import numpy as np
+
+        n = len(isos)
+        counts = torch.zeros(n, dtype=torch.int64, device=self.device)
+        jobs = self.jobs_tensor(set_idx, isos, np.zeros(n), np.zeros(n))
+        self.run_into(jobs, n, None, counts, block, per_thread)
+        c = counts.cpu().numpy()
+        off = np.concatenate([[0], np.cumsum(c)[:-1]])
+        tris = torch.empty((max(int(c.sum()), 1), 9), dtype=torch.float32, device=self.device)
+        jobs = self.jobs_tensor(set_idx, isos, off, c)
+        self.run_into(jobs, n, tris, counts, block, per_thread)
+        torch.cuda.synchronize(self.device)
+        if self.barrier_timed_out(block, per_thread):
+            raise AmrError(AMR_EHIP, "batched launch: a grid barrier wait gave up")
+        return [tris[int(o):int(o) + int(k)] for o, k in zip(off, c)]
 
 
 def from_numpy(xyz, level, value, device=None) -> AmrSet:

@@ -935,6 +935,328 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Batched iso-surfaces over explicit dual lists (many iso-values and/or many
+// sets in one persistent launch).  Phase A counts triangles per (job, tile),
+// phase B scans each job's tile counts, phase C writes; grid-wide barriers
+// separate them.  The grid never exceeds what the GPU keeps resident, and
+// every wait is bounded, so the kernel always drains.
+// ---------------------------------------------------------------------------
+
+constexpr int kMaxJobs = 256;
+constexpr int kMaxSets = 256;
+
+struct BatchSet {
+    const int32_t* verts;  // [n_duals][8] cell indices in slot order
+    const int32_t* xyz;
+    const int32_t* lvl;
+    const float* val;
+    int64_t n_duals;
+};
+
+struct alignas(256) GridBar {
+    unsigned int count;
+    unsigned int sense;
+    unsigned int timeout;  // set when a barrier wait gave up (results invalid)
+    unsigned int pad;
+};
+
+struct BatchArgs {
+    const BatchSet* sets;
+    int n_sets;
+    const amr_iso_job* jobs;
+    int n_jobs;
+    float* tris;
+    int64_t* counts;
+    uint32_t* tcount;  // per (job, tile of its set): count, then exclusive prefix
+    GridBar* bar;
+};
+
+__device__ void grid_barrier(GridBar* bar, unsigned int& sense) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        sense ^= 1u;
+        __threadfence();
+        unsigned int arrived = atomicAdd(&bar->count, 1u) + 1u;
+        if (arrived == gridDim.x) {
+            __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+            __hip_atomic_store(&bar->sense, sense, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            // bounded wait (about 10 s): the grid fits on the GPU, so this only
+            // gives up if something else holds the compute units that long
+            for (long long spin = 0;; ++spin) {
+                if (__hip_atomic_load(&bar->sense, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == sense) break;
+                if (spin > (1ll << 26)) {
+                    atomicOr(&bar->timeout, 1u);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(8);
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+// exclusive block scan of x (blockDim.x <= 512); returns the prefix, *total = sum
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s_w, uint32_t* total) {
+    const int lane = lane_id(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    unsigned long long incl = wave_incl_scan((unsigned long long)x);
+    if (lane == 63) s_w[wave] = (uint32_t)incl;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+    for (int w = 0; w < nw; ++w) {
+        if (w < wave) pre += s_w[w];
+        tot += s_w[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + (uint32_t)incl - x;
+}
+
+// Triangles of one dual for one iso: case and keep mask (degenerate ones dropped).
+struct DualMc {
+    int32_t id[8];
+    float v[8];
+    uint64_t dup;
+    bool dup_ready;
+};
+
+__device__ __forceinline__ void dual_dup(DualMc& d) {
+    uint64_t dup = 0;
+#pragma unroll
+    for (int e1 = 0; e1 < 12; ++e1) {
+        int a0 = d.id[edge_lo(e1)], a1 = d.id[edge_hi(e1)];
+        int dd = e1;
+#pragma unroll
+        for (int e0 = e1 - 1; e0 >= 0; --e0) {
+            int b0 = d.id[edge_lo(e0)], b1 = d.id[edge_hi(e0)];
+            if ((a0 == b0 && a1 == b1) || (a0 == b1 && a1 == b0)) dd = e0;
+        }
+        dup |= (uint64_t)dd << (4 * e1);
+    }
+    d.dup = dup;
+    d.dup_ready = true;
+}
+
+__device__ __forceinline__ uint32_t dual_case(const DualMc& d, float iso) {
+    uint32_t cs = 0;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) cs |= (d.v[s] >= iso ? 1u : 0u) << s;
+    return cs;
+}
+
+__device__ __forceinline__ uint32_t dual_keep(DualMc& d, unsigned long long e) {
+    int nt = (int)(e >> 60);
+    if (!nt) return 0;
+    if (!d.dup_ready) dual_dup(d);
+    uint32_t keep = 0;
+    for (int tt = 0; tt < nt; ++tt) {
+        int ea = (int)((e >> (12 * tt)) & 0xF), eb = (int)((e >> (12 * tt + 4)) & 0xF),
+            ec = (int)((e >> (12 * tt + 8)) & 0xF);
+        int da = (int)((d.dup >> (4 * ea)) & 0xF), db = (int)((d.dup >> (4 * eb)) & 0xF),
+            dc = (int)((d.dup >> (4 * ec)) & 0xF);
+        if (da != db && db != dc && da != dc) keep |= 1u << tt;
+    }
+    return keep;
+}
+
+template <int PER>
+__global__ __launch_bounds__(512) void k_batch(BatchArgs a) {
+    __shared__ unsigned long long s_tab[256];
+    __shared__ amr_iso_job s_job[kMaxJobs];
+    __shared__ int64_t s_tbase[kMaxSets + 1];  // first global tile of each set
+    __shared__ int64_t s_jbase[kMaxJobs + 1];  // first tcount entry of each job
+    __shared__ uint32_t s_w[8];
+    __shared__ unsigned int s_sense;
+    const int t = threadIdx.x;
+    const int64_t TS = (int64_t)blockDim.x * PER;
+    for (int i = t; i < 256; i += blockDim.x) s_tab[i] = kMcTable[i];
+    for (int i = t; i < a.n_jobs; i += blockDim.x) s_job[i] = a.jobs[i];
+    if (t == 0) {
+        int64_t acc = 0;
+        for (int i = 0; i < a.n_sets; ++i) {
+            s_tbase[i] = acc;
+            acc += (a.sets[i].n_duals + TS - 1) / TS;
+        }
+        s_tbase[a.n_sets] = acc;
+        s_sense = __hip_atomic_load(&a.bar->sense, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (t == 0) {
+        int64_t acc = 0;
+        for (int j = 0; j < a.n_jobs; ++j) {
+            s_jbase[j] = acc;
+            int sj = s_job[j].set;
+            acc += s_tbase[sj + 1] - s_tbase[sj];
+        }
+        s_jbase[a.n_jobs] = acc;
+    }
+    __syncthreads();
+    const int64_t n_tiles = s_tbase[a.n_sets];
+    unsigned int sense = s_sense;
+
+    // loads the duals of one tile for this thread
+    auto load_duals = [&](int sidx, int64_t lt, DualMc* d, bool* live) {
+        const BatchSet& S = a.sets[sidx];
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            int64_t di = lt * TS + (int64_t)p * blockDim.x + t;
+            live[p] = di < S.n_duals;
+            d[p].dup_ready = false;
+            if (!live[p]) continue;
+            const int4* vv = reinterpret_cast<const int4*>(S.verts + 8 * di);
+            int4 lo = vv[0], hi = vv[1];
+            d[p].id[0] = lo.x; d[p].id[1] = lo.y; d[p].id[2] = lo.z; d[p].id[3] = lo.w;
+            d[p].id[4] = hi.x; d[p].id[5] = hi.y; d[p].id[6] = hi.z; d[p].id[7] = hi.w;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) d[p].v[s] = S.val[d[p].id[s]];
+        }
+    };
+    auto set_of = [&](int64_t tile) {
+        int lo = 0, hi = a.n_sets;  // s_tbase[lo] <= tile < s_tbase[hi]
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (s_tbase[mid] <= tile) lo = mid;
+            else hi = mid;
+        }
+        return lo;
+    };
+
+    // ---- phase A: triangle counts per (job, tile) ----
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        int sidx = set_of(tile);
+        int64_t lt = tile - s_tbase[sidx];
+        DualMc d[PER];
+        bool live[PER];
+        load_duals(sidx, lt, d, live);
+        for (int j = 0; j < a.n_jobs; ++j) {
+            if (s_job[j].set != sidx) continue;
+            float iso = s_job[j].iso;
+            uint32_t c = 0;
+#pragma unroll
+            for (int p = 0; p < PER; ++p)
+                if (live[p]) c += __popc(dual_keep(d[p], s_tab[dual_case(d[p], iso)]));
+            uint32_t tot;
+            (void)block_excl_scan(c, s_w, &tot);
+            if (t == 0) a.tcount[s_jbase[j] + lt] = tot;
+        }
+    }
+    grid_barrier(a.bar, sense);
+
+    // ---- phase B: exclusive scan over each job's tiles ----
+    for (int j = blockIdx.x; j < a.n_jobs; j += gridDim.x) {
+        int64_t base = s_jbase[j], n = s_jbase[j + 1] - base;
+        uint64_t carry = 0;
+        for (int64_t c0 = 0; c0 < n; c0 += blockDim.x) {
+            int64_t i = c0 + t;
+            uint32_t x = i < n ? a.tcount[base + i] : 0u;
+            uint32_t tot;
+            uint32_t pre = block_excl_scan(x, s_w, &tot);
+            if (i < n) a.tcount[base + i] = (uint32_t)(carry + pre);
+            carry += tot;
+        }
+        if (t == 0) a.counts[j] = (int64_t)carry;
+    }
+    grid_barrier(a.bar, sense);
+
+    // ---- phase C: write ----
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        int sidx = set_of(tile);
+        int64_t lt = tile - s_tbase[sidx];
+        const BatchSet& S = a.sets[sidx];
+        DualMc d[PER];
+        bool live[PER];
+        load_duals(sidx, lt, d, live);
+        for (int j = 0; j < a.n_jobs; ++j) {
+            if (s_job[j].set != sidx) continue;
+            const float iso = s_job[j].iso;
+            uint32_t keep[PER], cs[PER];
+            uint32_t c = 0;
+#pragma unroll
+            for (int p = 0; p < PER; ++p) {
+                cs[p] = live[p] ? dual_case(d[p], iso) : 0u;
+                keep[p] = live[p] ? dual_keep(d[p], s_tab[cs[p]]) : 0u;
+                c += __popc(keep[p]);
+            }
+            uint32_t tot;
+            uint32_t pre = block_excl_scan(c, s_w, &tot);
+            // the thread's triangles in dual order: p = 0..PER-1 is not dual
+            // order within the tile when PER > 1 (duals are strided), so the
+            // rank of each triangle is recomputed per p
+            int64_t rel0 = (int64_t)a.tcount[s_jbase[j] + lt];
+            if (PER == 1) {
+                if (!c) continue;
+                int64_t rel = rel0 + pre;
+                int64_t di = lt * TS + t;
+                unsigned long long e = s_tab[cs[0]];
+                for (int tt = 0; tt < 5; ++tt) {
+                    if (!((keep[0] >> tt) & 1)) continue;
+                    if (rel < s_job[j].out_cap) {
+                        float* o = a.tris + 9 * (s_job[j].out_offset + rel);
+                        for (int v = 0; v < 3; ++v) {
+                            int ed = (int)((e >> (12 * tt + 4 * v)) & 0xF);
+                            int ia = S.verts[8 * di + edge_lo(ed)], ib = S.verts[8 * di + edge_hi(ed)];
+                            if (S.val[ia] >= iso) {
+                                int tmp = ia;
+                                ia = ib;
+                                ib = tmp;
+                            }
+                            float va = S.val[ia], vb = S.val[ib];
+                            float tp = (iso - va) / (vb - va);
+                            int la = S.lvl[ia], lb = S.lvl[ib];
+                            for (int ax = 0; ax < 3; ++ax) {
+                                float ca = (float)S.xyz[3 * ia + ax] + 0.5f * (float)(1 << la);
+                                float cb = (float)S.xyz[3 * ib + ax] + 0.5f * (float)(1 << lb);
+                                o[3 * v + ax] = fmaf(tp, cb - ca, ca);
+                            }
+                        }
+                    }
+                    ++rel;
+                }
+            } else {
+                // PER > 1: per slice p, a block scan keeps dual order
+                int64_t rel_slice = rel0;
+                (void)pre;
+                for (int p = 0; p < PER; ++p) {
+                    uint32_t cp = __popc(keep[p]);
+                    uint32_t totp;
+                    uint32_t prep = block_excl_scan(cp, s_w, &totp);
+                    int64_t rel = rel_slice + prep;
+                    int64_t di = lt * TS + (int64_t)p * blockDim.x + t;
+                    unsigned long long e = s_tab[cs[p]];
+                    for (int tt = 0; tt < 5 && cp; ++tt) {
+                        if (!((keep[p] >> tt) & 1)) continue;
+                        if (rel < s_job[j].out_cap) {
+                            float* o = a.tris + 9 * (s_job[j].out_offset + rel);
+                            for (int v = 0; v < 3; ++v) {
+                                int ed = (int)((e >> (12 * tt + 4 * v)) & 0xF);
+                                int ia = S.verts[8 * di + edge_lo(ed)], ib = S.verts[8 * di + edge_hi(ed)];
+                                if (S.val[ia] >= iso) {
+                                    int tmp = ia;
+                                    ia = ib;
+                                    ib = tmp;
+                                }
+                                float va = S.val[ia], vb = S.val[ib];
+                                float tp = (iso - va) / (vb - va);
+                                int la = S.lvl[ia], lb = S.lvl[ib];
+                                for (int ax = 0; ax < 3; ++ax) {
+                                    float ca = (float)S.xyz[3 * ia + ax] + 0.5f * (float)(1 << la);
+                                    float cb = (float)S.xyz[3 * ib + ax] + 0.5f * (float)(1 << lb);
+                                    o[3 * v + ax] = fmaf(tp, cb - ca, ca);
+                                }
+                            }
+                        }
+                        ++rel;
+                    }
+                    rel_slice += totp;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 
@@ -1094,6 +1416,34 @@ int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_
         hipLaunchKernelGGL(k_extract<false>, dim3(n_tiles), dim3(kBlock), 0, stream, a);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? AMR_OK : hipfail(e, "extract launch");
+}
+
+}  // namespace
+
+struct amr_batch {
+    int device = 0;
+    int n_sets = 0;
+    BatchSet* d_sets = nullptr;  // device table
+    int64_t max_set_duals = 0;
+    int cu_count = 0;
+};
+
+namespace {
+
+int batch_grid(const amr_batch* b, int block, int per, int64_t n_tiles) {
+    // at most two resident work-groups per compute unit (the barrier needs
+    // every work-group of the grid on the GPU at once)
+    int per_cu = 0;
+    hipError_t e;
+    if (per == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<1>, block, 0);
+    else if (per == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<2>, block, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<4>, block, 0);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    if (per_cu > 2) per_cu = 2;
+    int64_t g = (int64_t)b->cu_count * per_cu;
+    if (g > n_tiles) g = n_tiles;
+    if (g < 1) g = 1;
+    return (int)g;
 }
 
 }  // namespace
@@ -1299,6 +1649,118 @@ int amr_isosurface(amr_set* s, float iso, float* tris, int32_t* tri_cells, int32
     if (cap < 0) return fail(AMR_EINVAL, "amr_isosurface: negative capacity");
     DeviceGuard dg(s->device);
     return launch_extract(s, false, iso, tris, tri_cells, tri_dual, nullptr, nullptr, cap, counts, stream);
+}
+
+
+int amr_batch_create(amr_batch** out, amr_set* const* sets, const int32_t* const* dual_verts, const int64_t* n_duals,
+                     int n_sets) {
+    if (!out) return fail(AMR_EINVAL, "amr_batch_create: out is NULL");
+    *out = nullptr;
+    if (!sets || !dual_verts || !n_duals || n_sets < 1 || n_sets > kMaxSets)
+        return fail(AMR_EINVAL, "amr_batch_create: need 1..%d sets", kMaxSets);
+    int dev = sets[0] ? sets[0]->device : -1;
+    BatchSet* host = (BatchSet*)calloc((size_t)n_sets, sizeof(BatchSet));
+    if (!host) return fail(AMR_ENOMEM, "amr_batch_create: out of host memory");
+    int64_t mx = 0;
+    for (int i = 0; i < n_sets; ++i) {
+        const amr_set* s = sets[i];
+        if (!s || s->device != dev) {
+            free(host);
+            return fail(AMR_EINVAL, "amr_batch_create: set %d is NULL or on another device", i);
+        }
+        if (!s->built) {
+            free(host);
+            return fail(AMR_ESTATE, "amr_batch_create: set %d has no index", i);
+        }
+        if (n_duals[i] < 0 || (n_duals[i] > 0 && !dual_verts[i])) {
+            free(host);
+            return fail(AMR_EINVAL, "amr_batch_create: bad dual list for set %d", i);
+        }
+        host[i].verts = dual_verts[i];
+        host[i].xyz = s->xyz;
+        host[i].lvl = s->lvl;
+        host[i].val = s->val;
+        host[i].n_duals = n_duals[i];
+        if (n_duals[i] > mx) mx = n_duals[i];
+    }
+    DeviceGuard dg(dev);
+    amr_batch* b = new (std::nothrow) amr_batch();
+    if (!b) {
+        free(host);
+        return fail(AMR_ENOMEM, "amr_batch_create: out of host memory");
+    }
+    b->device = dev;
+    b->n_sets = n_sets;
+    b->max_set_duals = mx;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) prop.multiProcessorCount = 1;
+    b->cu_count = prop.multiProcessorCount;
+    hipError_t e = hipMalloc((void**)&b->d_sets, sizeof(BatchSet) * (size_t)n_sets);
+    if (e == hipSuccess) e = hipMemcpy(b->d_sets, host, sizeof(BatchSet) * (size_t)n_sets, hipMemcpyHostToDevice);
+    free(host);
+    if (e != hipSuccess) {
+        if (b->d_sets) (void)hipFree(b->d_sets);
+        delete b;
+        return hipfail(e, "amr_batch_create");
+    }
+    *out = b;
+    g_err[0] = 0;
+    return AMR_OK;
+}
+
+void amr_batch_destroy(amr_batch* b) {
+    if (!b) return;
+    {
+        DeviceGuard dg(b->device);
+        if (b->d_sets) (void)hipFree(b->d_sets);
+    }
+    delete b;
+}
+
+int amr_batch_workspace_bytes(const amr_batch* b, int max_jobs, int block, int per_thread, size_t* bytes) {
+    if (!b || !bytes) return fail(AMR_EINVAL, "amr_batch_workspace_bytes: NULL argument");
+    if (max_jobs < 1 || max_jobs > kMaxJobs) return fail(AMR_EINVAL, "amr_batch_workspace_bytes: 1..%d jobs", kMaxJobs);
+    if (block != 64 && block != 128 && block != 256 && block != 512)
+        return fail(AMR_EINVAL, "amr_batch_workspace_bytes: block must be 64, 128, 256 or 512");
+    if (per_thread != 1 && per_thread != 2 && per_thread != 4)
+        return fail(AMR_EINVAL, "amr_batch_workspace_bytes: per_thread must be 1, 2 or 4");
+    int64_t ts = (int64_t)block * per_thread;
+    int64_t tiles = (b->max_set_duals + ts - 1) / ts;
+    *bytes = align256(sizeof(GridBar)) + align256((size_t)max_jobs * (size_t)tiles * sizeof(uint32_t));
+    return AMR_OK;
+}
+
+int amr_batch_isosurface(amr_batch* b, const amr_iso_job* jobs, int n_jobs, float* tris, int64_t* counts, void* ws,
+                         size_t bytes, int block, int per_thread, hipStream_t stream) {
+    if (!b || !jobs || !counts) return fail(AMR_EINVAL, "amr_batch_isosurface: NULL argument");
+    size_t need = 0;
+    int st = amr_batch_workspace_bytes(b, n_jobs, block, per_thread, &need);
+    if (st != AMR_OK) return st;
+    if (!ws || ((uintptr_t)ws & 255)) return fail(AMR_EINVAL, "amr_batch_isosurface: workspace NULL or unaligned");
+    if (bytes < need) return fail(AMR_ENOSPACE, "amr_batch_isosurface: workspace %zu bytes, need %zu", bytes, need);
+    DeviceGuard dg(b->device);
+    BatchArgs a;
+    a.sets = b->d_sets;
+    a.n_sets = b->n_sets;
+    a.jobs = jobs;
+    a.n_jobs = n_jobs;
+    a.tris = tris;
+    a.counts = counts;
+    a.bar = (GridBar*)ws;
+    a.tcount = (uint32_t*)((char*)ws + align256(sizeof(GridBar)));
+    int64_t ts = (int64_t)block * per_thread;
+    int64_t n_tiles = 0;
+    // an upper bound is enough for the grid size: every set's tile count
+    n_tiles = ((b->max_set_duals + ts - 1) / ts) * b->n_sets;
+    int grid = batch_grid(b, block, per_thread, n_tiles);
+    if (per_thread == 1)
+        hipLaunchKernelGGL(k_batch<1>, dim3(grid), dim3(block), 0, stream, a);
+    else if (per_thread == 2)
+        hipLaunchKernelGGL(k_batch<2>, dim3(grid), dim3(block), 0, stream, a);
+    else
+        hipLaunchKernelGGL(k_batch<4>, dim3(grid), dim3(block), 0, stream, a);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? AMR_OK : hipfail(e, "amr_batch_isosurface: launch");
 }
 
 const char* amr_last_error(void) { return g_err; }

