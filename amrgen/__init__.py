@@ -398,3 +398,104 @@ def block_vortex(domain: int = 1024, tube: float = 13.5, n_helix: int = 5, seed:
     iso = np.sort(val)[int(0.9 * (len(val) - 1))]
     return _make(xyz, lv, val, float(iso), "block-vortex-%d" % domain, seed, domain=domain, tube=tube,
                  obstacle=obstacle, n_helix=n_helix)
+
+
+# ---------------------------------------------------------------------------
+# torch port of the octree generator for very large sets (same draws, same
+# cells; values may differ from the numpy path in the last bit)
+# ---------------------------------------------------------------------------
+
+def _i64(u: int) -> int:
+    u &= _MASK
+    return u - (1 << 64) if u >= (1 << 63) else u
+
+
+def _lsr_t(z, k: int):
+    import torch
+
+    return (z >> k) & ((1 << (64 - k)) - 1)
+
+
+def _mix64_t(z):
+    z = z ^ _lsr_t(z, 30)
+    z = z * _i64(0xBF58476D1CE4E5B9)
+    z = z ^ _lsr_t(z, 27)
+    z = z * _i64(0x94D049BB133111EB)
+    return z ^ _lsr_t(z, 31)
+
+
+def _uniform_t(seed: int, stream: int, key):
+    s = ((seed * 0x9E3779B97F4A7C15) ^ (stream * 0xD1B54A32D192ED03)) & _MASK
+    s = int(_mix64(np.array([s], dtype=np.uint64))[0])
+    h = _mix64_t(key ^ _i64(s))
+    return _lsr_t(h, 11).double() * (1.0 / (1 << 53))
+
+
+def _cell_key_t(g, lvl: int):
+    off = 1 << 19
+    return ((lvl << 60) | ((g[:, 2] + off) << 40) | ((g[:, 1] + off) << 20) | (g[:, 0] + off))
+
+
+def octree_shell_torch(domain: int, root_level: int, shell, p_in: float, p_out: float, seed: int, device,
+                       sigma=(10.0, 40.0), n_gauss: int = 8, name: str | None = None):
+    """octree_shell on a torch device.  Returns (xyz int32 [n,3], level int32
+    [n], value float32 [n]) device tensors, shuffled by the same seeded hash
+    order as the numpy path, and the iso (lower median)."""
+    import torch
+
+    w0 = 1 << root_level
+    n = domain // w0
+    r = torch.arange(n, dtype=torch.int64, device=device) * w0
+    gx, gy, gz = torch.meshgrid(r, r, r, indexing="ij")
+    g = torch.stack([gx.reshape(-1), gy.reshape(-1), gz.reshape(-1)], 1)
+    c = domain / 2.0
+    child = torch.as_tensor(_CHILD, device=device)
+    xs, ls = [], []
+    lvl = root_level
+    while True:
+        w = 1 << lvl
+        if lvl == 0 or len(g) == 0:
+            xs.append(g.to(torch.int32))
+            ls.append(torch.full((len(g),), lvl, dtype=torch.int32, device=device))
+            break
+        lo = g.double()
+        hi = lo + w
+        d = torch.maximum(torch.maximum(lo - c, torch.zeros_like(lo)), c - hi)
+        dmin = torch.sqrt((d * d).sum(1))
+        far = torch.maximum((lo - c).abs(), (hi - c).abs())
+        dmax = torch.sqrt((far * far).sum(1))
+        hit = (dmin < shell[1]) & (dmax > shell[0])
+        u = _uniform_t(seed, 1, _cell_key_t(g, lvl))
+        split = u < torch.where(hit, torch.full_like(u, p_in), torch.full_like(u, p_out))
+        keep = g[~split]
+        xs.append(keep.to(torch.int32))
+        ls.append(torch.full((len(keep),), lvl, dtype=torch.int32, device=device))
+        g = (g[split][:, None, :] + child[None] * (w // 2)).reshape(-1, 3)
+        del lo, hi, d, dmin, far, dmax, hit, u, split, keep
+        lvl -= 1
+    xyz = torch.cat(xs)
+    lv = torch.cat(ls)
+    del xs, ls, g
+    k = np.arange(n_gauss, dtype=np.uint64)
+    mu = np.stack([uniform(seed, 10 + a, k) * float(domain) for a in range(3)], 1)
+    sg = sigma[0] + (sigma[1] - sigma[0]) * uniform(seed, 13, k)
+    am = 0.5 + 1.0 * uniform(seed, 14, k)
+    val = torch.empty(len(xyz), dtype=torch.float32, device=device)
+    step = 1 << 25
+    for s0 in range(0, len(xyz), step):
+        ctr = xyz[s0:s0 + step].double() + 0.5 * torch.pow(2.0, lv[s0:s0 + step].double())[:, None]
+        acc = torch.zeros(len(ctr), dtype=torch.float64, device=device)
+        for gi in range(n_gauss):
+            d2 = ((ctr - torch.as_tensor(mu[gi], device=device)) ** 2).sum(1)
+            acc += am[gi] * torch.exp(-d2 / (2.0 * sg[gi] ** 2))
+        val[s0:s0 + step] = acc.float()
+        del ctr, acc
+    key = _cell_key_t(xyz.long(), 0) ^ (lv.long() << 60)
+    h = _mix64_t(key ^ _i64(int(_mix64(np.array([((seed * 0x9E3779B97F4A7C15) ^ (99 * 0xD1B54A32D192ED03)) & _MASK],
+                                                   dtype=np.uint64))[0])))
+    order = torch.argsort(h ^ _i64(1 << 63), stable=True)  # unsigned order of the hash
+    del h, key
+    xyz, lv, val = xyz[order].contiguous(), lv[order].contiguous(), val[order].contiguous()
+    iso = float(torch.kthvalue(val.cpu(), (len(val) - 1) // 2 + 1).values) if len(val) < (1 << 27) else \
+        float(torch.sort(val).values[(len(val) - 1) // 2])
+    return xyz, lv, val, iso

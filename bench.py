@@ -62,6 +62,102 @@ def cpu_baseline(cs, min_seconds=10.0):
                       "%d repetitions, %.1f s" % (cs.name, cs.n, tris, reps, t_total)}
 
 
+def batched_measurement(amr, s, cs, n_isos):
+    """Many iso-values of one set in one fused persistent launch (autotuned
+    launch shape, replayed from a HIP graph) against the plain path run once
+    per iso on the same stream."""
+    import numpy as np
+    import torch
+
+    from paper_2004_08475_amd import autotune
+
+    dev = s.device
+    isos = np.quantile(cs.value, 0.05 + 0.90 * np.arange(n_isos) / max(n_isos - 1, 1)).astype(np.float32)
+    t0 = time.perf_counter()
+    b = amr.AmrBatch([s])
+    torch.cuda.synchronize()
+    t_duals = time.perf_counter() - t0
+    counts = torch.zeros(n_isos, dtype=torch.int64, device=dev)
+    probe = b.jobs_tensor([0] * n_isos, isos, np.zeros(n_isos), np.zeros(n_isos))
+    b.run_into(probe, n_isos, None, counts)
+    c = counts.cpu().numpy()
+    off = np.concatenate([[0], np.cumsum(c)[:-1]])
+    tris = torch.empty((max(int(c.sum()), 1), 9), dtype=torch.float32, device=dev)
+    jobs = b.jobs_tensor([0] * n_isos, isos, off, c)
+    block, per, table = autotune.tune(b, jobs, n_isos, tris, counts)
+    ws = b.workspace(n_isos, block, per)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        b.run_into(jobs, n_isos, tris, counts, block, per, ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.run_into(jobs, n_isos, tris, counts, block, per, ws)
+    reps = 10
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g.replay()
+    e0.record()
+    for _ in range(reps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    fused_ms = e0.elapsed_time(e1) / reps
+    assert counts.cpu().numpy().tolist() == c.tolist()
+    # plain path, one launch per iso, into preallocated buffers
+    bufs = [torch.empty((max(int(k), 1), 9), dtype=torch.float32, device=dev) for k in c]
+    for k in range(n_isos):
+        s.isosurface_into(float(isos[k]), bufs[k], int(c[k]))
+    e0.record()
+    for _ in range(3):
+        for k in range(n_isos):
+            s.isosurface_into(float(isos[k]), bufs[k], int(c[k]))
+    e1.record()
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1) / 3
+    for k in range(n_isos):
+        assert torch.equal(bufs[k][:int(c[k])], tris[int(off[k]):int(off[k]) + int(c[k])])
+    return {"workload": "%s x %d isos (percentiles 5..95), one fused launch replayed from a HIP graph" % (cs.name, n_isos),
+            "fused_ms": fused_ms, "plain_ms_for_all_isos": plain_ms, "speedup_vs_plain": plain_ms / fused_ms,
+            "iso_cells_per_s": n_isos * cs.n / (fused_ms * 1e-3), "triangles": int(c.sum()),
+            "dual_list_ms": t_duals * 1e3, "autotuned_shape": {"block": block, "per_thread": per},
+            "autotune_ms": table}
+
+
+def serving_measurement(amr, s, cs, seconds, rate):
+    """Poisson iso/upload requests against the resident set: continuous
+    batching server vs. the serial plain path on the same trace."""
+    import numpy as np
+    import torch
+
+    import amrgen
+    from paper_2004_08475_amd import serve
+
+    rng = np.random.default_rng(5)
+    sizes = np.exp(rng.uniform(np.log(1e4), np.log(2e6), 6)).astype(int)
+    pool = [amrgen.octree_sized(int(n), seed=50 + k) for k, n in enumerate(sizes)]
+    isos = np.quantile(cs.value, rng.uniform(0.05, 0.95, 97)).astype(np.float32)
+
+    def up(k):
+        u = pool[k % len(pool)]
+        return serve.UploadRequest(u.xyz, u.level, u.value, u.iso)
+
+    trace = serve.poisson_trace(rate, seconds, 5, lambda k: isos[k % len(isos)], up, p_upload=0.3)
+    srv = serve.IsoServer(s)
+    t0 = time.perf_counter()
+    res = srv.serve(trace, keep_outputs=False)
+    wall = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    base = serve.serve_serial(s, trace)
+    wall_b = time.perf_counter() - t0
+    return {"workload": "resident %s + uploads of %s-cell octree sets; Poisson %.0f req/s for %.0f s, 30%% uploads"
+                        % (cs.name, "/".join(str(p.n) for p in pool), rate, seconds),
+            "server": serve.summarize(res, wall), "serial_plain": serve.summarize(base, wall_b),
+            "hbm_peak_reserved_bytes": srv.mem.peak}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +166,9 @@ def main():
     ap.add_argument("--workload", default="octree-shell-256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-requests", type=int, default=200)
+    ap.add_argument("--batch-isos", type=int, default=64, help="isos in the batched (fused) measurement; 0 = skip")
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of the serving run; 0 = skip")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the serving run")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -180,6 +279,10 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes": alg_bytes, "avg_launch_ms": iso_avg},
     }
+    if args.batch_isos:
+        out["batched"] = batched_measurement(amr, s, cs, args.batch_isos)
+    if args.serve_seconds > 0:
+        out["serving"] = serving_measurement(amr, s, cs, args.serve_seconds, args.serve_rate)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cs)
     print(json.dumps(out), flush=True)

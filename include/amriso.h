@@ -107,13 +107,15 @@ int amr_build_index(amr_set* set, void* workspace, size_t bytes, hipStream_t str
      verts        int32 [cap][8]  indices (into the uploaded arrays) of the
                                   cells at slots s = ex + 2*ey + 4*ez,
                                   i.e. the cells containing P + (e - 1)*2^l
+     vals         float [cap][8]  the values of those cells (so that later
+                                  passes over the duals read them in order)
    counts: device int64 [2]; counts[0] = counts[1] = number of emitted duals.
    Records past cap are not written.  Asynchronous: the caller reads counts
    and re-runs with a larger buffer when counts[0] > cap.  The order of the
    records is fixed for a given index.  Returns AMR_ESTATE before
    amr_build_index. */
-int amr_dual_cells(amr_set* set, int32_t* corner_level, int32_t* verts, int64_t cap, int64_t* counts,
-                   hipStream_t stream);
+int amr_dual_cells(amr_set* set, int32_t* corner_level, int32_t* verts, float* vals, int64_t cap,
+                   int64_t* counts, hipStream_t stream);
 
 /* Iso-surface (paper sec. 5): every emitted dual, degenerate or not, is a
    hexahedron with its vertices at the centres of its 8 cells and goes
@@ -162,13 +164,14 @@ typedef struct amr_iso_job {
     int64_t out_cap;    /* triangles this job may write (more are counted only) */
 } amr_iso_job;
 
-/* Create a batch over n_sets indexed sets.  dual_verts[i] is the device
-   int32 [n_duals[i]][8] list written by amr_dual_cells for sets[i] (caller-
-   owned, kept alive and unchanged with the set's input arrays).  Allocates
-   a small device table (freed by amr_batch_destroy); synchronous.  Returns
-   AMR_ESTATE if a set has no index, AMR_EINVAL for bad arguments. */
+/* Create a batch over n_sets indexed sets.  dual_verts[i] and dual_vals[i]
+   are the device int32 / float [n_duals[i]][8] lists written by
+   amr_dual_cells for sets[i] (caller-owned, kept alive and unchanged with
+   the set's input arrays).  Allocates a small device table (freed by
+   amr_batch_destroy); synchronous.  Returns AMR_ESTATE if a set has no
+   index, AMR_EINVAL for bad arguments. */
 int amr_batch_create(amr_batch** out, amr_set* const* sets, const int32_t* const* dual_verts,
-                     const int64_t* n_duals, int n_sets);
+                     const float* const* dual_vals, const int64_t* n_duals, int n_sets);
 
 void amr_batch_destroy(amr_batch* batch);
 

@@ -54,12 +54,12 @@ def load_library(path: str = LIB_PATH):
     L.amr_index_bytes.restype = C.c_int
     L.amr_build_index.argtypes = [vp, vp, C.c_size_t, vp]
     L.amr_build_index.restype = C.c_int
-    L.amr_dual_cells.argtypes = [vp, i32p, i32p, i64, i64p, vp]
+    L.amr_dual_cells.argtypes = [vp, i32p, i32p, f32p, i64, i64p, vp]
     L.amr_dual_cells.restype = C.c_int
     L.amr_isosurface.argtypes = [vp, C.c_float, f32p, i32p, i32p, i64, i64p, vp]
     L.amr_isosurface.restype = C.c_int
     L.amr_batch_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
-                                   C.POINTER(C.c_int64), C.c_int]
+                                   C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.c_int]
     L.amr_batch_create.restype = C.c_int
     L.amr_batch_destroy.argtypes = [vp]
     L.amr_batch_destroy.restype = None
@@ -155,24 +155,28 @@ class AmrSet:
         raise AmrError(AMR_ENOSPACE, "index workspace kept overflowing")
 
     # -- extraction -------------------------------------------------------
-    def dual_cells_into(self, corner_level, verts, cap: int):
+    def dual_cells_into(self, corner_level, verts, cap: int, vals=None):
         """Enqueue dual-cell extraction into preallocated buffers; returns
         the device counts tensor (no synchronisation)."""
-        _check(self.lib.amr_dual_cells(self._h, _ptr(corner_level), _ptr(verts), int(cap), _ptr(self.counts),
-                                       _stream(self.device)))
+        _check(self.lib.amr_dual_cells(self._h, _ptr(corner_level), _ptr(verts), _ptr(vals), int(cap),
+                                       _ptr(self.counts), _stream(self.device)))
         return self.counts
 
-    def dual_cells(self, cap: int | None = None):
-        """(corner_level int32 [M,4], verts int32 [M,8]) of every emitted dual."""
+    def dual_cells(self, cap: int | None = None, values: bool = False):
+        """(corner_level int32 [M,4], verts int32 [M,8]) of every emitted dual
+        (plus their values float32 [M,8] with values=True)."""
         if cap is None:
             self.dual_cells_into(None, None, 0)
             cap = int(self.counts[0].item())
         cl = torch.empty((max(cap, 1), 4), dtype=torch.int32, device=self.device)
         vv = torch.empty((max(cap, 1), 8), dtype=torch.int32, device=self.device)
-        self.dual_cells_into(cl, vv, cap)
+        va = torch.empty((max(cap, 1), 8), dtype=torch.float32, device=self.device) if values else None
+        self.dual_cells_into(cl, vv, cap, va)
         m = int(self.counts[0].item())
         if m > cap:
-            return self.dual_cells(m)
+            return self.dual_cells(m, values)
+        if values:
+            return cl[:m], vv[:m], va[:m]
         return cl[:m], vv[:m]
 
     def isosurface_into(self, iso: float, tris, cap: int, tri_cells=None, tri_dual=None):
@@ -234,14 +238,15 @@ class AmrBatch:
         self.device = self.sets[0].device
         self.duals = []
         for s in self.sets:
-            cl, vv = s.dual_cells()
-            self.duals.append(vv.contiguous())
+            _, vv, va = s.dual_cells(values=True)
+            self.duals.append((vv, va))
         n = len(self.sets)
         hs = (C.c_void_p * n)(*[s._h.value for s in self.sets])
-        dv = (C.c_void_p * n)(*[d.data_ptr() for d in self.duals])
-        nd = (C.c_int64 * n)(*[int(d.shape[0]) for d in self.duals])
+        dv = (C.c_void_p * n)(*[d[0].data_ptr() for d in self.duals])
+        dw = (C.c_void_p * n)(*[d[1].data_ptr() for d in self.duals])
+        nd = (C.c_int64 * n)(*[int(d[0].shape[0]) for d in self.duals])
         h = C.c_void_p()
-        _check(self.lib.amr_batch_create(C.byref(h), hs, dv, nd, n))
+        _check(self.lib.amr_batch_create(C.byref(h), hs, dv, dw, nd, n))
         self._h = h
         self._ws = {}
 

@@ -530,6 +530,7 @@ struct ExtractArgs {
     // dual-cell outputs
     int32_t* corner_level;
     int32_t* verts;
+    float* dvals;
     int64_t cap;
     int64_t* counts;
     unsigned long long* st_t;  // per tile: triangles
@@ -826,6 +827,17 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
                     reinterpret_cast<int4*>(a.verts)[2 * out_d] = make_int4(id[0], id[1], id[2], id[3]);
                     reinterpret_cast<int4*>(a.verts)[2 * out_d + 1] = make_int4(id[4], id[5], id[6], id[7]);
                 }
+                if (a.dvals) {
+                    float v[8];
+#pragma unroll
+                    for (int s = 0; s < 8; ++s) {
+                        int dd, child;
+                        slot_cell(kx, ky, kz, s, dd, child);
+                        v[s] = s_val[gi][dd][s_lvl[gi][dd] == m ? child : 0];
+                    }
+                    reinterpret_cast<float4*>(a.dvals)[2 * out_d] = make_float4(v[0], v[1], v[2], v[3]);
+                    reinterpret_cast<float4*>(a.dvals)[2 * out_d + 1] = make_float4(v[4], v[5], v[6], v[7]);
+                }
             }
             ++out_d;
         }
@@ -947,9 +959,9 @@ constexpr int kMaxSets = 256;
 
 struct BatchSet {
     const int32_t* verts;  // [n_duals][8] cell indices in slot order
+    const float* dvals;    // [n_duals][8] their values
     const int32_t* xyz;
     const int32_t* lvl;
-    const float* val;
     int64_t n_duals;
 };
 
@@ -1109,8 +1121,10 @@ __global__ __launch_bounds__(512) void k_batch(BatchArgs a) {
             int4 lo = vv[0], hi = vv[1];
             d[p].id[0] = lo.x; d[p].id[1] = lo.y; d[p].id[2] = lo.z; d[p].id[3] = lo.w;
             d[p].id[4] = hi.x; d[p].id[5] = hi.y; d[p].id[6] = hi.z; d[p].id[7] = hi.w;
-#pragma unroll
-            for (int s = 0; s < 8; ++s) d[p].v[s] = S.val[d[p].id[s]];
+            const float4* pv = reinterpret_cast<const float4*>(S.dvals + 8 * di);
+            float4 v0 = pv[0], v1 = pv[1];
+            d[p].v[0] = v0.x; d[p].v[1] = v0.y; d[p].v[2] = v0.z; d[p].v[3] = v0.w;
+            d[p].v[4] = v1.x; d[p].v[5] = v1.y; d[p].v[6] = v1.z; d[p].v[7] = v1.w;
         }
     };
     auto set_of = [&](int64_t tile) {
@@ -1196,13 +1210,17 @@ __global__ __launch_bounds__(512) void k_batch(BatchArgs a) {
                         float* o = a.tris + 9 * (s_job[j].out_offset + rel);
                         for (int v = 0; v < 3; ++v) {
                             int ed = (int)((e >> (12 * tt + 4 * v)) & 0xF);
-                            int ia = S.verts[8 * di + edge_lo(ed)], ib = S.verts[8 * di + edge_hi(ed)];
-                            if (S.val[ia] >= iso) {
+                            int sa = edge_lo(ed), sb = edge_hi(ed);
+                            int ia = S.verts[8 * di + sa], ib = S.verts[8 * di + sb];
+                            float va = S.dvals[8 * di + sa], vb = S.dvals[8 * di + sb];
+                            if (va >= iso) {
                                 int tmp = ia;
                                 ia = ib;
                                 ib = tmp;
+                                float tv = va;
+                                va = vb;
+                                vb = tv;
                             }
-                            float va = S.val[ia], vb = S.val[ib];
                             float tp = (iso - va) / (vb - va);
                             int la = S.lvl[ia], lb = S.lvl[ib];
                             for (int ax = 0; ax < 3; ++ax) {
@@ -1231,13 +1249,17 @@ __global__ __launch_bounds__(512) void k_batch(BatchArgs a) {
                             float* o = a.tris + 9 * (s_job[j].out_offset + rel);
                             for (int v = 0; v < 3; ++v) {
                                 int ed = (int)((e >> (12 * tt + 4 * v)) & 0xF);
-                                int ia = S.verts[8 * di + edge_lo(ed)], ib = S.verts[8 * di + edge_hi(ed)];
-                                if (S.val[ia] >= iso) {
+                                int sa = edge_lo(ed), sb = edge_hi(ed);
+                                int ia = S.verts[8 * di + sa], ib = S.verts[8 * di + sb];
+                                float va = S.dvals[8 * di + sa], vb = S.dvals[8 * di + sb];
+                                if (va >= iso) {
                                     int tmp = ia;
                                     ia = ib;
                                     ib = tmp;
+                                    float tv = va;
+                                    va = vb;
+                                    vb = tv;
                                 }
-                                float va = S.val[ia], vb = S.val[ib];
                                 float tp = (iso - va) / (vb - va);
                                 int la = S.lvl[ia], lb = S.lvl[ib];
                                 for (int ax = 0; ax < 3; ++ax) {
@@ -1385,7 +1407,8 @@ int grid_for(int64_t n, int block) {
 }
 
 int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_cells, int32_t* tri_dual,
-                   int32_t* corner_level, int32_t* verts, int64_t cap, int64_t* counts, hipStream_t stream) {
+                   int32_t* corner_level, int32_t* verts, float* dvals, int64_t cap, int64_t* counts,
+                   hipStream_t stream) {
     uint32_t n_tiles = (s->n_groups + kGroupsPerTile - 1) / kGroupsPerTile;
     if (n_tiles == 0) {
         hipLaunchKernelGGL(k_counts_zero, dim3(1), dim3(64), 0, stream, counts);
@@ -1404,6 +1427,7 @@ int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_
     a.tri_dual = tri_dual;
     a.corner_level = corner_level;
     a.verts = verts;
+    a.dvals = dvals;
     a.cap = cap;
     a.counts = counts;
     a.st_t = s->st_t;
@@ -1632,13 +1656,14 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     return AMR_OK;
 }
 
-int amr_dual_cells(amr_set* s, int32_t* corner_level, int32_t* verts, int64_t cap, int64_t* counts,
+int amr_dual_cells(amr_set* s, int32_t* corner_level, int32_t* verts, float* vals, int64_t cap, int64_t* counts,
                    hipStream_t stream) {
     if (!s) return fail(AMR_EINVAL, "amr_dual_cells: set is NULL");
     if (!s->built) return fail(AMR_ESTATE, "amr_dual_cells: call amr_build_index first");
-    if (cap < 0 || (cap > 0 && !corner_level && !verts)) return fail(AMR_EINVAL, "amr_dual_cells: bad capacity");
+    if (cap < 0 || (cap > 0 && !corner_level && !verts && !vals))
+        return fail(AMR_EINVAL, "amr_dual_cells: bad capacity");
     DeviceGuard dg(s->device);
-    return launch_extract(s, true, 0.0f, nullptr, nullptr, nullptr, corner_level, verts, cap, counts, stream);
+    return launch_extract(s, true, 0.0f, nullptr, nullptr, nullptr, corner_level, verts, vals, cap, counts, stream);
 }
 
 int amr_isosurface(amr_set* s, float iso, float* tris, int32_t* tri_cells, int32_t* tri_dual, int64_t cap,
@@ -1648,15 +1673,15 @@ int amr_isosurface(amr_set* s, float iso, float* tris, int32_t* tri_cells, int32
     if (!isfinite(iso)) return fail(AMR_EINVAL, "amr_isosurface: iso is not finite");
     if (cap < 0) return fail(AMR_EINVAL, "amr_isosurface: negative capacity");
     DeviceGuard dg(s->device);
-    return launch_extract(s, false, iso, tris, tri_cells, tri_dual, nullptr, nullptr, cap, counts, stream);
+    return launch_extract(s, false, iso, tris, tri_cells, tri_dual, nullptr, nullptr, nullptr, cap, counts, stream);
 }
 
 
-int amr_batch_create(amr_batch** out, amr_set* const* sets, const int32_t* const* dual_verts, const int64_t* n_duals,
-                     int n_sets) {
+int amr_batch_create(amr_batch** out, amr_set* const* sets, const int32_t* const* dual_verts,
+                     const float* const* dual_vals, const int64_t* n_duals, int n_sets) {
     if (!out) return fail(AMR_EINVAL, "amr_batch_create: out is NULL");
     *out = nullptr;
-    if (!sets || !dual_verts || !n_duals || n_sets < 1 || n_sets > kMaxSets)
+    if (!sets || !dual_verts || !dual_vals || !n_duals || n_sets < 1 || n_sets > kMaxSets)
         return fail(AMR_EINVAL, "amr_batch_create: need 1..%d sets", kMaxSets);
     int dev = sets[0] ? sets[0]->device : -1;
     BatchSet* host = (BatchSet*)calloc((size_t)n_sets, sizeof(BatchSet));
@@ -1672,14 +1697,14 @@ int amr_batch_create(amr_batch** out, amr_set* const* sets, const int32_t* const
             free(host);
             return fail(AMR_ESTATE, "amr_batch_create: set %d has no index", i);
         }
-        if (n_duals[i] < 0 || (n_duals[i] > 0 && !dual_verts[i])) {
+        if (n_duals[i] < 0 || (n_duals[i] > 0 && (!dual_verts[i] || !dual_vals[i]))) {
             free(host);
             return fail(AMR_EINVAL, "amr_batch_create: bad dual list for set %d", i);
         }
         host[i].verts = dual_verts[i];
+        host[i].dvals = dual_vals[i];
         host[i].xyz = s->xyz;
         host[i].lvl = s->lvl;
-        host[i].val = s->val;
         host[i].n_duals = n_duals[i];
         if (n_duals[i] > mx) mx = n_duals[i];
     }

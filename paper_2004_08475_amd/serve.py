@@ -1,0 +1,297 @@
+"""Continuous-batching iso-surface server on one GPU.
+
+A resident AMR set stays on the device with its index and dual cells.
+Requests arrive over time:
+
+  * IsoRequest(iso): an iso-surface of the resident set.  Requests that are
+    waiting when the batch stream becomes free are fused into one batched
+    launch (amr_batch_isosurface over the resident set's dual cells), so
+    the iso-independent topology is never recomputed and new requests join
+    at the next launch instead of waiting for a queue to drain.
+  * UploadRequest(xyz, level, value, iso): a new small set; it is copied
+    to the GPU, validated, indexed and extracted on one of several upload
+    streams, overlapping on the device with the batched launches.
+
+Admission is by memory: every request reserves an estimate of the device
+memory it needs against an HBM budget and waits (first come, first served)
+until it fits, so a small budget makes requests queue instead of running
+out of memory.  Latency is measured from arrival to the result being ready
+on the device.  `serve_serial` replays the same trace one request at a
+time through the plain single-iso path, as the baseline.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import threading
+import time
+
+import numpy as np
+import torch
+
+from . import AmrBatch, AmrSet
+
+
+@dataclasses.dataclass
+class IsoRequest:
+    iso: float
+    rid: int = -1
+
+
+@dataclasses.dataclass
+class UploadRequest:
+    xyz: np.ndarray
+    level: np.ndarray
+    value: np.ndarray
+    iso: float
+    rid: int = -1
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    kind: str
+    arrival: float
+    start: float = 0.0
+    done: float = 0.0
+    triangles: int = 0
+    tris: torch.Tensor | None = None
+
+    @property
+    def latency_ms(self) -> float:
+        return (self.done - self.arrival) * 1e3
+
+
+class HbmBudget:
+    """Bytes of device memory that admitted requests may hold at once."""
+
+    def __init__(self, budget: int):
+        self.budget = int(budget)
+        self.used = 0
+        self.peak = 0
+        self.cv = threading.Condition()
+
+    def acquire(self, nbytes: int, stop: threading.Event):
+        nbytes = min(int(nbytes), self.budget)
+        with self.cv:
+            while self.used + nbytes > self.budget and not stop.is_set():
+                self.cv.wait(0.01)
+            self.used += nbytes
+            self.peak = max(self.peak, self.used)
+        return nbytes
+
+    def release(self, nbytes: int):
+        with self.cv:
+            self.used -= nbytes
+            self.cv.notify_all()
+
+
+def upload_bytes(n_cells: int, triangles_guess: int) -> int:
+    """Device memory of one upload request: cells, index, triangles."""
+    return 20 * n_cells + 64 * n_cells + 36 * triangles_guess + (1 << 20)
+
+
+class IsoServer:
+    def __init__(self, resident: AmrSet, hbm_budget: int | None = None, upload_slots: int = 4,
+                 max_batch: int = 64, block: int = 256, per_thread: int = 1, curve_points: int = 64):
+        self.resident = resident
+        self.device = resident.device
+        self.batch = AmrBatch([resident])
+        self.max_batch = max_batch
+        self.block, self.per_thread = block, per_thread
+        if hbm_budget is None:
+            free, _ = torch.cuda.mem_get_info(self.device)
+            hbm_budget = int(free * 0.8)
+        self.mem = HbmBudget(hbm_budget)
+        # triangle-count curve of the resident set: sizes batched outputs
+        vals = resident._cells[2]
+        qs = torch.linspace(0.0, 1.0, curve_points, device=self.device, dtype=torch.float64)
+        sample = vals if vals.numel() <= 1 << 24 else vals[torch.randint(0, vals.numel(), (1 << 24,),
+                                                                           device=self.device)]
+        self.curve_iso = torch.quantile(sample.double(), qs).float().cpu().numpy()
+        counts = torch.zeros(curve_points, dtype=torch.int64, device=self.device)
+        jobs = self.batch.jobs_tensor([0] * curve_points, self.curve_iso, np.zeros(curve_points),
+                                      np.zeros(curve_points))
+        self.batch.run_into(jobs, curve_points, None, counts, block, per_thread)
+        self.curve_tri = counts.cpu().numpy()
+        self.upload_slots = upload_slots
+        self.stop = threading.Event()
+        self._slot_sets = []  # kept until the server is dropped
+
+    # -- sizing -----------------------------------------------------------
+    def iso_cap(self, iso: float) -> int:
+        k = int(np.searchsorted(self.curve_iso, iso))
+        lo, hi = max(k - 1, 0), min(k, len(self.curve_iso) - 1)
+        return int(2 * max(self.curve_tri[lo], self.curve_tri[hi]) + 4096)
+
+    # -- resident iso requests --------------------------------------------
+    def _run_batch(self, reqs, results, stream):
+        n = len(reqs)
+        isos = [r.iso for r in reqs]
+        caps = np.array([self.iso_cap(v) for v in isos], np.int64)
+        need = int(caps.sum()) * 36 + (1 << 20)
+        held = self.mem.acquire(need, self.stop)
+        t_start = time.perf_counter()
+        try:
+            with torch.cuda.stream(stream):
+                off = np.concatenate([[0], np.cumsum(caps)[:-1]])
+                tris = torch.empty((max(int(caps.sum()), 1), 9), dtype=torch.float32, device=self.device)
+                counts = torch.zeros(n, dtype=torch.int64, device=self.device)
+                jobs = self.batch.jobs_tensor([0] * n, isos, off, caps)
+                self.batch.run_into(jobs, n, tris, counts, self.block, self.per_thread)
+                stream.synchronize()
+                c = counts.cpu().numpy()
+                for k, r in enumerate(reqs):
+                    out = tris[int(off[k]):int(off[k]) + int(c[k])]
+                    if c[k] > caps[k]:  # the estimate was short: exact rerun
+                        out = self.resident.isosurface(isos[k], int(c[k]))["tris"]
+                        stream.synchronize()
+                    res = results[r.rid]
+                    res.start, res.done, res.triangles, res.tris = t_start, time.perf_counter(), int(c[k]), out
+        finally:
+            self.mem.release(held)
+
+    def _batch_worker(self, q, results):
+        stream = torch.cuda.Stream(self.device)
+        while True:
+            with q["cv"]:
+                while not q["items"] and not q["closed"]:
+                    q["cv"].wait(0.005)
+                if not q["items"] and q["closed"]:
+                    return
+                reqs = []
+                while q["items"] and len(reqs) < self.max_batch:
+                    reqs.append(q["items"].popleft())
+            self._run_batch(reqs, results, stream)
+
+    # -- upload requests --------------------------------------------------
+    def _run_upload(self, r: UploadRequest, results, stream, s: AmrSet):
+        n = len(r.level)
+        held = self.mem.acquire(upload_bytes(n, n // 2), self.stop)
+        t_start = time.perf_counter()
+        try:
+            with torch.cuda.stream(stream):
+                xyz = torch.from_numpy(np.ascontiguousarray(r.xyz, np.int32)).pin_memory().to(self.device,
+                                                                                              non_blocking=True)
+                lvl = torch.from_numpy(np.ascontiguousarray(r.level, np.int32)).pin_memory().to(self.device,
+                                                                                               non_blocking=True)
+                val = torch.from_numpy(np.ascontiguousarray(r.value, np.float32)).pin_memory().to(self.device,
+                                                                                                 non_blocking=True)
+                s.upload(xyz, lvl, val)
+                s.build_index()
+                out = s.isosurface(r.iso)["tris"]
+                stream.synchronize()
+                res = results[r.rid]
+                res.start, res.done, res.triangles, res.tris = t_start, time.perf_counter(), int(out.shape[0]), out
+        finally:
+            self.mem.release(held)
+
+    def _upload_worker(self, q, results):
+        stream = torch.cuda.Stream(self.device)
+        # one set handle per upload slot, reused: freeing device memory
+        # would synchronise the whole device and stall the other streams
+        s = AmrSet(self.device.index)
+        while True:
+            with q["cv"]:
+                while not q["items"] and not q["closed"]:
+                    q["cv"].wait(0.005)
+                if not q["items"] and q["closed"]:
+                    break
+                r = q["items"].popleft()
+            self._run_upload(r, results, stream, s)
+        self._slot_sets.append(s)
+
+    # -- driver -----------------------------------------------------------
+    def serve(self, trace, keep_outputs: bool = True):
+        """Replay `trace` = [(arrival seconds from start, request)] in real
+        time.  Returns the list of Results (one per request, in trace order)."""
+        mk = lambda: {"items": collections.deque(), "cv": threading.Condition(), "closed": False}
+        iso_q, up_q = mk(), mk()
+        results = {}
+        workers = [threading.Thread(target=self._batch_worker, args=(iso_q, results), daemon=True)]
+        workers += [threading.Thread(target=self._upload_worker, args=(up_q, results), daemon=True)
+                    for _ in range(self.upload_slots)]
+        for w in workers:
+            w.start()
+        t0 = time.perf_counter()
+        for rid, (at, req) in enumerate(trace):
+            req.rid = rid
+            now = time.perf_counter() - t0
+            if at > now:
+                time.sleep(at - now)
+            arrival = time.perf_counter()
+            kind = "iso" if isinstance(req, IsoRequest) else "upload"
+            results[rid] = Result(rid, kind, arrival)
+            q = iso_q if kind == "iso" else up_q
+            with q["cv"]:
+                q["items"].append(req)
+                q["cv"].notify()
+        for q in (iso_q, up_q):
+            with q["cv"]:
+                q["closed"] = True
+                q["cv"].notify_all()
+        for w in workers:
+            w.join()
+        out = [results[i] for i in range(len(trace))]
+        if not keep_outputs:
+            for r in out:
+                r.tris = None
+        return out
+
+
+def serve_serial(resident: AmrSet, trace, keep_outputs: bool = False):
+    """Baseline: the same trace, one request at a time, plain single-iso path
+    (count pass + write pass), in arrival order on one stream."""
+    results = []
+    t0 = time.perf_counter()
+    dev = resident.device
+    for rid, (at, req) in enumerate(trace):
+        now = time.perf_counter() - t0
+        if at > now:
+            time.sleep(at - now)
+        arrival = t0 + at
+        start = time.perf_counter()
+        if isinstance(req, IsoRequest):
+            out = resident.isosurface(req.iso)["tris"]
+            kind = "iso"
+        else:
+            s = AmrSet(dev.index)
+            s.upload(torch.from_numpy(np.ascontiguousarray(req.xyz, np.int32)).to(dev),
+                     torch.from_numpy(np.ascontiguousarray(req.level, np.int32)).to(dev),
+                     torch.from_numpy(np.ascontiguousarray(req.value, np.float32)).to(dev))
+            s.build_index()
+            out = s.isosurface(req.iso)["tris"]
+            kind = "upload"
+        torch.cuda.synchronize(dev)
+        r = Result(rid, kind, arrival, start, time.perf_counter(), int(out.shape[0]), out if keep_outputs else None)
+        results.append(r)
+    return results
+
+
+def poisson_trace(rate_hz: float, duration_s: float, seed: int, make_iso, make_upload, p_upload: float):
+    """Arrivals of a Poisson process; each request is an upload with
+    probability p_upload, else a resident iso request."""
+    rng = np.random.default_rng(seed)
+    t, trace, k = 0.0, [], 0
+    while True:
+        t += rng.exponential(1.0 / rate_hz)
+        if t > duration_s:
+            return trace
+        if rng.random() < p_upload:
+            trace.append((t, make_upload(k)))
+        else:
+            trace.append((t, IsoRequest(float(make_iso(k)))))
+        k += 1
+
+
+def summarize(results, wall_s: float) -> dict:
+    lat = np.array([r.latency_ms for r in results]) if results else np.zeros(1)
+    by = {}
+    for kind in ("iso", "upload"):
+        sel = np.array([r.latency_ms for r in results if r.kind == kind])
+        if len(sel):
+            by[kind] = {"n": int(len(sel)), "p50_ms": float(np.percentile(sel, 50)),
+                        "p99_ms": float(np.percentile(sel, 99))}
+    return {"requests": len(results), "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "throughput_req_per_s": len(results) / max(wall_s, 1e-9),
+            "triangles": int(sum(r.triangles for r in results)), "by_kind": by}

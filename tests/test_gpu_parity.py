@@ -39,7 +39,9 @@ def gpu_set(amr, cs):
 
 
 def check_duals(s, o):
-    pl_g, ids_g = s.dual_cells()
+    pl_g, ids_g, vals_g = s.dual_cells(values=True)
+    # the values written beside the duals are the cells' values
+    assert np.array_equal(vals_g.cpu().numpy(), o.value[ids_g.cpu().numpy()])
     pl_o, ids_o = o.dual_cells()
     a = oracle.canonical_duals(pl_g.cpu().numpy(), ids_g.cpu().numpy())
     b = oracle.canonical_duals(pl_o, ids_o)

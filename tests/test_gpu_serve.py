@@ -1,0 +1,81 @@
+"""Serving loop: continuous batching of resident iso requests plus uploads of
+new sets, admitted by HBM budget.  Each result must be the same alone and in
+the mix (bit for bit), and a tiny budget must only make requests wait."""
+import numpy as np
+import pytest
+
+import amrgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def env():
+    import paper_2004_08475_amd as amr
+    from paper_2004_08475_amd import serve
+
+    amr.load_library()
+    assert torch.cuda.is_available()
+    cs = amrgen.octree_shell()
+    res = amr.from_numpy(cs.xyz, cs.level, cs.value)
+    uploads = [amrgen.random_octree(300 + k, roots=3 + k % 3, root_level=3, p_split=0.5, p_hole=0.05 * (k % 3),
+                                    values="smooth") for k in range(6)]
+    return amr, serve, cs, res, uploads
+
+
+def _trace(serve, cs, uploads, rate, duration, seed):
+    isos = np.quantile(cs.value, np.linspace(0.05, 0.95, 37)).astype(np.float32)
+
+    def up(k):
+        u = uploads[k % len(uploads)]
+        return serve.UploadRequest(u.xyz, u.level, u.value, u.iso)
+
+    return serve.poisson_trace(rate, duration, seed, lambda k: isos[(7 * k) % len(isos)], up, p_upload=0.3)
+
+
+def _same(serve, req, got, want):
+    """Resident iso requests share one index: identical bits and order.
+    Uploads are indexed afresh (the hash layout, hence the output order, can
+    differ between builds): identical triangles after canonical ordering."""
+    if isinstance(req, serve.IsoRequest):
+        return torch.equal(got, want)
+    a = oracle.canonical_triangles(got.cpu().numpy())[0]
+    b = oracle.canonical_triangles(want.cpu().numpy())[0]
+    return np.array_equal(a, b)
+
+
+def _alone(amr, serve, res, req):
+    if isinstance(req, serve.IsoRequest):
+        return res.isosurface(req.iso)["tris"]
+    s = amr.from_numpy(req.xyz, req.level, req.value)
+    return s.isosurface(req.iso)["tris"]
+
+
+def test_each_result_same_alone_and_in_mix(env):
+    amr, serve, cs, res, uploads = env
+    trace = _trace(serve, cs, uploads, rate=150.0, duration=1.0, seed=11)
+    print("serving %d requests" % len(trace), flush=True)
+    srv = serve.IsoServer(res, upload_slots=3)
+    out = srv.serve(trace)
+    assert len(out) == len(trace)
+    assert {r.kind for r in out} == {"iso", "upload"}
+    for (at, req), r in zip(trace, out):
+        want = _alone(amr, serve, res, req)
+        assert r.done >= r.arrival
+        assert r.triangles == len(want)
+        assert _same(serve, req, r.tris, want)
+
+
+def test_small_hbm_budget_queues_instead_of_failing(env):
+    amr, serve, cs, res, uploads = env
+    trace = _trace(serve, cs, uploads, rate=200.0, duration=0.5, seed=12)
+    budget = 6 << 20
+    srv = serve.IsoServer(res, hbm_budget=budget, upload_slots=4)
+    out = srv.serve(trace)
+    assert srv.mem.peak <= budget
+    assert srv.mem.used == 0
+    for (at, req), r in zip(trace, out):
+        assert _same(serve, req, r.tris, _alone(amr, serve, res, req))
