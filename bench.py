@@ -33,6 +33,10 @@ def make_workload(name):
     raise SystemExit("unknown workload %s" % name)
 
 
+def say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -136,7 +140,10 @@ def serving_measurement(amr, s, cs, seconds, rate):
 
     rng = np.random.default_rng(5)
     sizes = np.exp(rng.uniform(np.log(1e4), np.log(2e6), 6)).astype(int)
-    pool = [amrgen.octree_sized(int(n), seed=50 + k) for k, n in enumerate(sizes)]
+    pool = []
+    for k, n in enumerate(sizes):
+        pool.append(amrgen.octree_sized(int(n), seed=50 + k))
+        say("serving: upload set %d: %d cells" % (k, pool[-1].n))
     isos = np.quantile(cs.value, rng.uniform(0.05, 0.95, 97)).astype(np.float32)
 
     def up(k):
@@ -148,6 +155,7 @@ def serving_measurement(amr, s, cs, seconds, rate):
     t0 = time.perf_counter()
     res = srv.serve(trace, keep_outputs=False)
     wall = time.perf_counter() - t0
+    say("serving: server run done (%d requests, %.1f s)" % (len(res), wall))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     base = serve.serve_serial(s, trace)
@@ -186,7 +194,7 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     cs = make_workload(args.workload)
-    print("workload %s: %d cells" % (cs.name, cs.n), file=sys.stderr, flush=True)
+    say("workload %s: %d cells" % (cs.name, cs.n))
     xyz = torch.from_numpy(cs.xyz).to(dev)
     lvl = torch.from_numpy(cs.level).to(dev)
     val = torch.from_numpy(cs.value).to(dev)
@@ -279,12 +287,18 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes": alg_bytes, "avg_launch_ms": iso_avg},
     }
+    say("timed steps done: %.3f ms/step" % ms_per_step)
     if args.batch_isos:
         out["batched"] = batched_measurement(amr, s, cs, args.batch_isos)
+        say("batched: fused %.3f ms, plain %.3f ms" % (out["batched"]["fused_ms"],
+                                                        out["batched"]["plain_ms_for_all_isos"]))
     if args.serve_seconds > 0:
         out["serving"] = serving_measurement(amr, s, cs, args.serve_seconds, args.serve_rate)
+        say("serving: p99 %.2f ms (server) vs %.2f ms (serial)" % (out["serving"]["server"]["p99_ms"],
+                                                                  out["serving"]["serial_plain"]["p99_ms"]))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cs)
+        say("cpu baseline: %.3g cells/s on %d threads" % (out["cpu_baseline"]["value"], out["cpu_baseline"]["cores"]))
     print(json.dumps(out), flush=True)
 
 

@@ -195,6 +195,29 @@ int amr_batch_workspace_bytes(const amr_batch* batch, int max_jobs, int block, i
 int amr_batch_isosurface(amr_batch* batch, const amr_iso_job* jobs, int n_jobs, float* tris, int64_t* counts,
                          void* workspace, size_t bytes, int block, int per_thread, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+   Indexed face set (paper sec. 5.2): the fat triangles share vertices; each
+   shared vertex gets one index.  The paper sorts the vertices by position
+   and numbers the first of every run; here a vertex is identified by the
+   (A, B) cell pair of its edge (amr_isosurface's tri_cells output), an exact
+   integer key -- equal keys always have bit-identical positions.  Vertices
+   are numbered in order of first appearance (triangle-major, corner-minor),
+   so the result does not depend on scheduling.
+   --------------------------------------------------------------------------- */
+
+/* Workspace bytes for n_tris triangles (host-only). */
+int amr_indexed_mesh_bytes(int64_t n_tris, size_t* bytes);
+
+/* tris      device float [n_tris][3][3], tri_cells device int32 [n_tris][3][2]
+   verts     device float [cap_verts][3]: unique vertices, first appearance order
+   idx       device int32 [n_tris][3]: vertex index of every corner
+   n_verts   device int64 [1]: number of unique vertices (verts past cap_verts
+             are not written; idx is always complete)
+   workspace device, >= amr_indexed_mesh_bytes(n_tris), 256-byte aligned.
+   No host synchronisation.  n_tris must be below 2^29. */
+int amr_indexed_mesh(const float* tris, const int32_t* tri_cells, int64_t n_tris, float* verts, int32_t* idx,
+                     int64_t cap_verts, int64_t* n_verts, void* workspace, size_t bytes, hipStream_t stream);
+
 /* Message describing the last error on the calling thread ("" if none). */
 const char* amr_last_error(void);
 

@@ -236,3 +236,25 @@ def canonical_triangles(tris: np.ndarray, cells: np.ndarray | None = None):
     if cc is not None:
         cc = cc.reshape(n, 6)[order]
     return flat, cc
+
+
+# ---------------------------------------------------------------------------
+# Indexed face set (paper sec. 5.2): shared vertices of the fat triangles get
+# one index.  A vertex is identified by the cell pair of its edge; vertices
+# are numbered in order of first appearance (triangle-major, corner-minor).
+# ---------------------------------------------------------------------------
+
+def indexed_mesh(tris: np.ndarray, cells: np.ndarray):
+    """(verts float32 [V,3], idx int32 [T,3]) for fat triangles tris [T,9]
+    with per-corner cell pairs cells [T,6]."""
+    t = np.asarray(tris, np.float32).reshape(-1, 3)
+    c = np.asarray(cells, np.int64).reshape(-1, 2)
+    key = (c[:, 0] << 32) | c[:, 1]
+    _, first, inv = np.unique(key, return_index=True, return_inverse=True)
+    # renumber unique keys by their first corner
+    order = np.argsort(first, kind="stable")
+    rank = np.empty_like(order)
+    rank[order] = np.arange(len(order))
+    idx = rank[inv].reshape(-1, 3).astype(np.int32)
+    verts = t[np.sort(first)]
+    return verts, idx

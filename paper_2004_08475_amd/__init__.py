@@ -23,7 +23,7 @@ _NAMES = {0: "AMR_OK", -1: "AMR_EINVAL", -2: "AMR_ERANGE", -3: "AMR_EOVERLAP", -
 # Every entry point of the C ABI (include/amriso.h).
 ABI_SYMBOLS = ("amr_create", "amr_destroy", "amr_upload", "amr_index_bytes", "amr_build_index", "amr_dual_cells",
                "amr_isosurface", "amr_batch_create", "amr_batch_destroy", "amr_batch_workspace_bytes",
-               "amr_batch_isosurface", "amr_last_error")
+               "amr_batch_isosurface", "amr_indexed_mesh_bytes", "amr_indexed_mesh", "amr_last_error")
 
 _lib = None
 
@@ -67,6 +67,10 @@ def load_library(path: str = LIB_PATH):
     L.amr_batch_workspace_bytes.restype = C.c_int
     L.amr_batch_isosurface.argtypes = [vp, vp, C.c_int, vp, vp, vp, C.c_size_t, C.c_int, C.c_int, vp]
     L.amr_batch_isosurface.restype = C.c_int
+    L.amr_indexed_mesh_bytes.argtypes = [i64, C.POINTER(C.c_size_t)]
+    L.amr_indexed_mesh_bytes.restype = C.c_int
+    L.amr_indexed_mesh.argtypes = [f32p, i32p, i64, f32p, i32p, i64, i64p, vp, C.c_size_t, vp]
+    L.amr_indexed_mesh.restype = C.c_int
     L.amr_last_error.argtypes = []
     L.amr_last_error.restype = C.c_char_p
     _lib = L
@@ -312,6 +316,40 @@ class AmrBatch:
         if self.barrier_timed_out(block, per_thread):
             raise AmrError(AMR_EHIP, "batched launch: a grid barrier wait gave up")
         return [tris[int(o):int(o) + int(k)] for o, k in zip(off, c)]
+
+
+def indexed_mesh_into(tris, cells, verts, idx, n_verts, workspace=None):
+    """Enqueue the weld of fat triangles `tris` [T,9] with their edge cell
+    pairs `cells` [T,6] (no synchronisation).  Writes unique vertices into
+    `verts` [cap,3] (first-appearance order), corner indices into `idx`
+    [T,3] and the vertex count into `n_verts` (int64 [1])."""
+    lib = load_library()
+    n = int(tris.shape[0])
+    b = C.c_size_t(0)
+    _check(lib.amr_indexed_mesh_bytes(n, C.byref(b)))
+    if workspace is None or workspace.numel() < b.value:
+        workspace = torch.empty(max(int(b.value), 256), dtype=torch.uint8, device=tris.device)
+    cap = int(verts.shape[0]) if verts is not None else 0
+    _check(lib.amr_indexed_mesh(_ptr(tris), _ptr(cells), n, _ptr(verts), _ptr(idx), cap, _ptr(n_verts),
+                                _ptr(workspace), workspace.numel(), _stream(tris.device)))
+    return workspace
+
+
+def indexed_mesh(tris, cells):
+    """Indexed face set of an iso-surface: (vertices float32 [V,3], indices
+    int32 [T,3]).  `tris`, `cells` as returned by AmrSet.isosurface(...,
+    cells=True).  A vertex is shared by every corner with the same edge cell
+    pair; vertices are numbered in order of first appearance."""
+    dev = tris.device
+    tris = tris.contiguous()
+    cells = cells.contiguous()
+    n = int(tris.shape[0])
+    idx = torch.empty((max(n, 1), 3), dtype=torch.int32, device=dev)
+    nv = torch.zeros(1, dtype=torch.int64, device=dev)
+    verts = torch.empty((max(3 * n, 1), 3), dtype=torch.float32, device=dev)
+    indexed_mesh_into(tris, cells, verts, idx, nv)
+    v = int(nv.item())
+    return verts[:v], idx[:n]
 
 
 def from_numpy(xyz, level, value, device=None) -> AmrSet:

@@ -1279,6 +1279,123 @@ __global__ __launch_bounds__(512) void k_batch(BatchArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Indexed face set: weld the corners of fat triangles by their edge's cell
+// pair.  A hash table maps each key to the lowest corner index carrying it;
+// a scan over corners numbers those first corners in corner order.
+// ---------------------------------------------------------------------------
+
+constexpr int kWeldTile = 4096;  // corners per scan tile (256 threads x 16)
+
+struct WeldWs {
+    unsigned long long* key;   // [cap]
+    unsigned int* first;       // [cap] lowest corner with this key
+    unsigned int* vid;         // [cap] vertex index of the key
+    unsigned int* cslot;       // [3 n_tris] slot of each corner
+    unsigned long long* s0;    // scan states
+    unsigned long long* s1;
+    Sched* sched;
+    uint32_t cap;
+    int shift;
+};
+
+__global__ void k_weld_init(WeldWs w, uint32_t n_tiles) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < w.cap; i += gridDim.x * blockDim.x) {
+        w.key[i] = kEmpty;
+        w.first[i] = 0xFFFFFFFFu;
+    }
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= n_tiles; i += gridDim.x * blockDim.x) {
+        w.s0[i] = 0;
+        w.s1[i] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) w.sched->cticket = 0;
+}
+
+__global__ void k_weld_empty(int64_t* n_verts) {
+    if (threadIdx.x == 0) *n_verts = 0;
+}
+
+__global__ __launch_bounds__(256) void k_weld_insert(const int32_t* __restrict__ cells, int64_t n_corners, WeldWs w) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_corners;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        unsigned long long key = ((unsigned long long)(uint32_t)cells[2 * i] << 32) | (uint32_t)cells[2 * i + 1];
+        uint32_t mask = w.cap - 1, h = (uint32_t)((key * kGolden) >> w.shift);
+        for (uint32_t step = 0; step <= mask; ++step) {
+            unsigned long long k = w.key[h];
+            if (k == kEmpty) {
+                unsigned long long prev = atomicCAS(&w.key[h], kEmpty, key);
+                if (prev == kEmpty) k = key;
+                else k = prev;
+            }
+            if (k == key) {
+                atomicMin(&w.first[h], (unsigned int)i);
+                w.cslot[i] = h;
+                break;
+            }
+            h = (h + 1) & mask;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_weld_scan(const float* __restrict__ tris, int64_t n_corners, WeldWs w,
+                                                      uint32_t n_tiles, float* __restrict__ verts, int64_t cap_v,
+                                                      int64_t* n_verts) {
+    __shared__ uint32_t s_rc[16][kBlock / 64];
+    __shared__ unsigned long long s_pre;
+    __shared__ uint32_t s_tile;
+    const int t = threadIdx.x, wave = t >> 6, lane = lane_id();
+    if (t == 0) s_tile = (uint32_t)atomicAdd(&w.sched->cticket, 1ull);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const int64_t base = (int64_t)tile * kWeldTile;
+    uint32_t bits = 0;
+#pragma unroll 4
+    for (int r = 0; r < 16; ++r) {
+        int64_t i = base + r * kBlock + t;
+        if (i < n_corners && w.first[w.cslot[i]] == (unsigned int)i) bits |= 1u << r;
+    }
+    for (int r = 0; r < 16; ++r) {
+        unsigned long long b = __ballot((bits >> r) & 1);
+        if (lane == 0) s_rc[r][wave] = (uint32_t)__popcll(b);
+    }
+    __syncthreads();
+    uint32_t total = 0;
+    for (int r = 0; r < 16; ++r)
+        for (int q = 0; q < kBlock / 64; ++q) total += s_rc[r][q];
+    if (wave == 0) {
+        unsigned long long p0, p1;
+        lookback(w.s0, w.s1, tile, 0ull, total, 0ull, p0, p1);
+        if (lane == 0) {
+            s_pre = p0;
+            if (tile == n_tiles - 1) *n_verts = (int64_t)(p0 + total);
+        }
+    }
+    __syncthreads();
+    uint64_t pos = s_pre;
+    for (int r = 0; r < 16; ++r) {
+        unsigned long long b = __ballot((bits >> r) & 1);
+        uint32_t before = 0;
+        for (int q = 0; q < wave; ++q) before += s_rc[r][q];
+        if ((bits >> r) & 1) {
+            int64_t i = base + r * kBlock + t;
+            uint64_t v = pos + before + (uint64_t)__popcll(b & ((1ull << lane) - 1));
+            w.vid[w.cslot[i]] = (unsigned int)v;
+            if ((int64_t)v < cap_v) {
+                verts[3 * v] = tris[3 * i];
+                verts[3 * v + 1] = tris[3 * i + 1];
+                verts[3 * v + 2] = tris[3 * i + 2];
+            }
+        }
+        for (int q = 0; q < kBlock / 64; ++q) pos += s_rc[r][q];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_weld_index(int64_t n_corners, WeldWs w, int32_t* __restrict__ idx) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_corners;
+         i += (int64_t)gridDim.x * blockDim.x)
+        idx[i] = (int32_t)w.vid[w.cslot[i]];
+}
+
+// ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 
@@ -1786,6 +1903,84 @@ int amr_batch_isosurface(amr_batch* b, const amr_iso_job* jobs, int n_jobs, floa
         hipLaunchKernelGGL(k_batch<4>, dim3(grid), dim3(block), 0, stream, a);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? AMR_OK : hipfail(e, "amr_batch_isosurface: launch");
+}
+
+namespace {
+struct WeldLayout {
+    uint32_t cap;
+    uint32_t n_tiles;
+    size_t key, first, vid, cslot, s0, s1, sched, total;
+};
+
+bool weld_layout(int64_t n_tris, WeldLayout& L) {
+    if (n_tris < 0 || n_tris >= ((int64_t)1 << 29)) return false;
+    int64_t corners = 3 * n_tris;
+    uint64_t cap = 1024;
+    while (cap < (uint64_t)(2 * corners)) cap <<= 1;  // load <= 1/2 even with no sharing
+    L.cap = (uint32_t)cap;
+    L.n_tiles = (uint32_t)((corners + kWeldTile - 1) / kWeldTile);
+    size_t off = 0;
+    L.key = off;
+    off = align256(off + cap * 8);
+    L.first = off;
+    off = align256(off + cap * 4);
+    L.vid = off;
+    off = align256(off + cap * 4);
+    L.cslot = off;
+    off = align256(off + (size_t)corners * 4 + 4);
+    L.s0 = off;
+    off = align256(off + ((size_t)L.n_tiles + 1) * 8);
+    L.s1 = off;
+    off = align256(off + ((size_t)L.n_tiles + 1) * 8);
+    L.sched = off;
+    off = align256(off + sizeof(Sched));
+    L.total = off;
+    return true;
+}
+}  // namespace
+
+int amr_indexed_mesh_bytes(int64_t n_tris, size_t* bytes) {
+    if (!bytes) return fail(AMR_EINVAL, "amr_indexed_mesh_bytes: NULL argument");
+    WeldLayout L;
+    if (!weld_layout(n_tris, L)) return fail(AMR_ERANGE, "amr_indexed_mesh_bytes: n_tris out of range");
+    *bytes = L.total;
+    return AMR_OK;
+}
+
+int amr_indexed_mesh(const float* tris, const int32_t* tri_cells, int64_t n_tris, float* verts, int32_t* idx,
+                     int64_t cap_verts, int64_t* n_verts, void* ws, size_t bytes, hipStream_t stream) {
+    WeldLayout L;
+    if (!weld_layout(n_tris, L)) return fail(AMR_ERANGE, "amr_indexed_mesh: n_tris out of range");
+    if (!n_verts || (n_tris > 0 && (!tris || !tri_cells || !idx)) || cap_verts < 0 || (cap_verts > 0 && !verts))
+        return fail(AMR_EINVAL, "amr_indexed_mesh: bad argument");
+    if (!ws || ((uintptr_t)ws & 255)) return fail(AMR_EINVAL, "amr_indexed_mesh: workspace NULL or unaligned");
+    if (bytes < L.total) return fail(AMR_ENOSPACE, "amr_indexed_mesh: workspace %zu bytes, need %zu", bytes, L.total);
+    if (n_tris == 0) {
+        hipLaunchKernelGGL(k_weld_empty, dim3(1), dim3(64), 0, stream, n_verts);
+        hipError_t e = hipGetLastError();
+        return e == hipSuccess ? AMR_OK : hipfail(e, "amr_indexed_mesh");
+    }
+    char* b = (char*)ws;
+    WeldWs w;
+    w.key = (unsigned long long*)(b + L.key);
+    w.first = (unsigned int*)(b + L.first);
+    w.vid = (unsigned int*)(b + L.vid);
+    w.cslot = (unsigned int*)(b + L.cslot);
+    w.s0 = (unsigned long long*)(b + L.s0);
+    w.s1 = (unsigned long long*)(b + L.s1);
+    w.sched = (Sched*)(b + L.sched);
+    w.cap = L.cap;
+    int log2cap = 0;
+    while ((1u << log2cap) < L.cap) ++log2cap;
+    w.shift = 64 - log2cap;
+    int64_t corners = 3 * n_tris;
+    hipLaunchKernelGGL(k_weld_init, dim3(grid_for(L.cap, 256)), dim3(256), 0, stream, w, L.n_tiles);
+    hipLaunchKernelGGL(k_weld_insert, dim3(grid_for(corners, 256)), dim3(256), 0, stream, tri_cells, corners, w);
+    hipLaunchKernelGGL(k_weld_scan, dim3(L.n_tiles), dim3(kBlock), 0, stream, tris, corners, w, L.n_tiles, verts,
+                       cap_verts, n_verts);
+    hipLaunchKernelGGL(k_weld_index, dim3(grid_for(corners, 256)), dim3(256), 0, stream, corners, w, idx);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? AMR_OK : hipfail(e, "amr_indexed_mesh: launch");
 }
 
 const char* amr_last_error(void) { return g_err; }

@@ -512,3 +512,22 @@ def test_vertex_placement_within_fp32_bound():
     eps = 2.0 ** -24
     bound = 4 * eps * np.abs(ctr[B] - ctr[A]) + 2 * eps * np.abs(exact) + 1e-30
     assert np.all(np.abs(got - exact) <= bound)
+
+
+def test_indexed_mesh_reproduces_fat_triangles_and_counts_vertices(sphere16):
+    cs, o = sphere16
+    r = o.isosurface(cs.iso)
+    verts, idx = oracle.indexed_mesh(r["tris"], r["cells"])
+    # every fat triangle is recovered exactly from the indexed one
+    assert np.array_equal(verts[idx].reshape(-1, 9), r["tris"])
+    # one vertex per distinct cut edge; closed genus-0 surface: V - E + F = 2
+    keys = {tuple(v) for v in r["cells"].reshape(-1, 2)}
+    assert len(verts) == len(keys)
+    edges = {frozenset((int(a), int(b))) for tri in idx for a, b in ((tri[0], tri[1]), (tri[1], tri[2]), (tri[2], tri[0]))}
+    assert len(verts) - len(edges) + len(idx) == 2
+    # numbering by first appearance
+    seen = []
+    for v in idx.reshape(-1):
+        if v not in seen:
+            seen.append(v)
+    assert seen == list(range(len(verts)))
