@@ -99,8 +99,8 @@ struct Ctrl {
 
 // Scan bookkeeping inside the workspace.
 struct Sched {
-    unsigned long long ticket;   // extraction tiles started, over all calls
-    unsigned long long call;     // extraction calls completed
+    unsigned long long xticket;  // extraction scan tiles started (reset by each count pass)
+    unsigned long long pad0;
     unsigned long long cticket;  // compaction tiles started
     unsigned long long pad;
 };
@@ -109,9 +109,22 @@ __device__ __forceinline__ uint64_t group_key(int m, uint32_t gx, uint32_t gy, u
     return ((uint64_t)m << 57) | ((uint64_t)gz << 38) | ((uint64_t)gy << 19) | (uint64_t)gx;
 }
 
+// Home slot of a group.  The table is cut into buckets of 64 slots, one per
+// brick of 4x4x4 groups of one level: the brick's key is hashed (Fibonacci)
+// to a bucket and the group's position inside the brick picks the slot, its
+// 6 bits XORed with 6 more bits of the brick hash so that sparse patterns
+// still spread over all 64 positions.  Spatial neighbours therefore share a
+// 4 KB bucket, and a collision moves on to the same position of the next
+// bucket (probe stride 64).
+constexpr uint32_t kBucket = 64;
+
 __device__ __forceinline__ uint32_t slot_of(uint64_t key, int shift) {
-    return (uint32_t)((key * kGolden) >> shift);
+    const uint64_t brick = key & ~((3ull << 38) | (3ull << 19) | 3ull);
+    const uint32_t local = (uint32_t)((key & 3) | (((key >> 19) & 3) << 2) | (((key >> 38) & 3) << 4));
+    return (uint32_t)((brick * kGolden) >> shift) ^ local;
 }
+
+__device__ __forceinline__ uint32_t next_slot(uint32_t h, uint32_t mask) { return (h + kBucket) & mask; }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
@@ -146,7 +159,7 @@ __device__ __forceinline__ int probe(const Record* __restrict__ rec, uint64_t ke
         uint64_t k = rec[h].key;
         if (k == key) return (int)h;
         if (k == kEmpty) return -1;
-        h = (h + 1) & mask;
+        h = next_slot(h, mask);
     }
     return -1;
 }
@@ -396,7 +409,7 @@ __device__ __forceinline__ int find_or_insert(Record* __restrict__ rec, uint64_t
                                       (unsigned long long)key);
             if (prev == kEmpty || prev == key) return (int)h;
         }
-        h = (h + 1) & g.mask;
+        h = next_slot(h, g.mask);
     }
     return -1;
 }
@@ -533,25 +546,24 @@ struct ExtractArgs {
     float* dvals;
     int64_t cap;
     int64_t* counts;
-    unsigned long long* st_t;  // per tile: triangles
-    unsigned long long* st_d;  // per tile: duals
+    unsigned long long* tot;    // per tile: triangles << 32 | duals (count pass)
+    unsigned long long* pre_t;  // per tile: exclusive prefix of triangles (scan)
+    unsigned long long* pre_d;  // per tile: exclusive prefix of duals (scan)
+    unsigned long long* sc0;    // per scan tile: look-back states
+    unsigned long long* sc1;
     Sched* sched;
     uint32_t n_tiles;
+    uint32_t n_scan_tiles;
 };
 
-__global__ void k_sched_reset(Sched* sc, unsigned long long* st_t, unsigned long long* st_d, uint32_t n,
-                              unsigned long long* ct0, unsigned long long* ct1, uint32_t nc) {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        st_t[i] = 0;
-        st_d[i] = 0;
-    }
+__global__ void k_sched_reset(Sched* sc, unsigned long long* ct0, unsigned long long* ct1, uint32_t nc) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += gridDim.x * blockDim.x) {
         ct0[i] = 0;
         ct1[i] = 0;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        sc->ticket = 0;
-        sc->call = 0;
+        sc->xticket = 0;
+        sc->pad0 = 0;
         sc->cticket = 0;
         sc->pad = 0;
     }
@@ -581,7 +593,11 @@ __device__ __forceinline__ void slot_cell(int kx, int ky, int kz, int s, int& dd
     child = (rx & 1) | ((ry & 1) << 1) | ((rz & 1) << 2);
 }
 
-template <bool kDuals>
+// Extraction runs as three launches: a count pass (phases 1-2, per-tile
+// totals), a scan of the tile totals, and a write pass that repeats phases
+// 1-2 for the tiles that have output below the capacity and writes it at the
+// scanned positions.  No tile ever waits for another in the heavy passes.
+template <bool kDuals, bool kWrite>
 __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
     __shared__ float s_val[kGroupsPerTile][27][8];
     __shared__ int32_t s_ref[kGroupsPerTile][27];
@@ -589,8 +605,6 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
     __shared__ unsigned long long s_tab[256];
     __shared__ unsigned long long s_wave[kBlock / 64];
     __shared__ unsigned long long s_pre_t, s_pre_d;
-    __shared__ uint32_t s_tile;
-    __shared__ unsigned long long s_call;
     __shared__ uint32_t s_items[kBlock][4];
     __shared__ uint32_t s_dual[kBlock];
     __shared__ uint32_t s_list[kTriList];
@@ -600,17 +614,27 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
     const int t = threadIdx.x;
     const int gi = t >> 3;  // group within the tile
     const int j = t & 7;    // lane within the group
-    if (t == 0) {
-        // the call number is read before the ticket is taken, so once the last
-        // tile holds its ticket every tile of this call has read it
-        unsigned long long call = __hip_atomic_load(&a.sched->call, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned long long tk = atomicAdd(&a.sched->ticket, 1ull);
-        s_call = call;
-        s_tile = (uint32_t)(tk - call * a.n_tiles);
+    const uint32_t tile = blockIdx.x;
+    if (kWrite) {
+        // nothing of this tile lands below the capacity: done
+        const unsigned long long tt = a.tot[tile];
+        const unsigned long long mine_n = kDuals ? (tt & 0xFFFFFFFFull) : (tt >> 32);
+        const unsigned long long mine_pre = kDuals ? a.pre_d[tile] : a.pre_t[tile];
+        if (mine_n == 0 || (int64_t)mine_pre >= a.cap) return;
+        if (t == 0) {
+            s_pre_t = a.pre_t[tile];
+            s_pre_d = a.pre_d[tile];
+        }
+    } else if (t == 0) {
+        // the scan that follows starts from clean states
+        if (tile < a.n_scan_tiles) {
+            a.sc0[tile] = 0;
+            a.sc1[tile] = 0;
+        }
+        if (tile == 0) a.sched->xticket = 0;
     }
     if (!kDuals) s_tab[t] = kMcTable[t];
     __syncthreads();
-    const uint32_t tile = s_tile;
     const uint32_t gidx = tile * kGroupsPerTile + gi;
     const bool valid = gidx < a.n_groups;
     const Geo g = a.g;
@@ -656,7 +680,7 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
             float4 xa = va[q], xb = vb[q];
             if (k != want[q] && k != kEmpty) {
                 for (uint32_t step = 0; k != want[q] && k != kEmpty && step <= g.mask; ++step) {
-                    h = (h + 1) & g.mask;
+                    h = next_slot(h, g.mask);
                     k = a.rec[h].key;
                 }
                 if (k == want[q]) {
@@ -776,26 +800,10 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
     }
     unsigned long long excl = wave_pre + incl - mine;
 
-    // ---- decoupled look-back across tiles ----
-    if (wave == 0) {
-        const unsigned long long par = (s_call & 1) ? kParityBit : 0ull;
-        unsigned long long pre_t, pre_d;
-        const unsigned long long agg_t = total >> 32, agg_d = total & 0xFFFFFFFFull;
-        lookback(a.st_t, a.st_d, tile, par, agg_t, agg_d, pre_t, pre_d);
-        if (lane_id() == 0) {
-            s_pre_t = pre_t;
-            s_pre_d = pre_d;
-            if (tile == a.n_tiles - 1) {
-                if (a.counts) {
-                    a.counts[0] = kDuals ? (int64_t)(pre_d + agg_d) : (int64_t)(pre_t + agg_t);
-                    a.counts[1] = (int64_t)(pre_d + agg_d);
-                }
-                // every tile of this call read the call number before its ticket
-                __hip_atomic_store(&a.sched->call, s_call + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
+    if (!kWrite) {
+        if (t == 0) a.tot[tile] = total;
+        return;
     }
-    __syncthreads();
 
     // ---- phase 3: write ----
     if (kDuals) {
@@ -943,6 +951,67 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
                 }
             }
         }
+    }
+}
+
+// Exclusive scan of the per-tile (triangles, duals) totals of a count pass:
+// 4096 tiles per work-group, decoupled look-back across work-groups (tickets
+// keep the look-back waiting only on work-groups that already run).  The
+// last work-group writes the grand totals.
+constexpr int kScanPer = 16;
+
+__global__ __launch_bounds__(kBlock) void k_tile_scan(ExtractArgs a, int duals) {
+    __shared__ unsigned long long s_row[kScanPer][kBlock / 64];
+    __shared__ unsigned long long s_p0, s_p1;
+    __shared__ uint32_t s_st;
+    const int t = threadIdx.x, wave = t >> 6, lane = lane_id();
+    if (t == 0) s_st = (uint32_t)atomicAdd(&a.sched->xticket, 1ull);
+    __syncthreads();
+    const uint32_t st = s_st;
+    const uint64_t base = (uint64_t)st * (kBlock * kScanPer);
+    // row r covers tiles base + r*256 + [0, 256); values are packed
+    // triangles << 32 | duals, and no half carries inside one work-group
+    // (at most 4096 tiles of at most 4320 triangles each)
+    unsigned long long v[kScanPer], incl[kScanPer];
+#pragma unroll
+    for (int r = 0; r < kScanPer; ++r) {
+        uint64_t i = base + (uint64_t)r * kBlock + t;
+        v[r] = i < a.n_tiles ? a.tot[i] : 0ull;
+        incl[r] = wave_incl_scan(v[r]);
+        if (lane == 63) s_row[r][wave] = incl[r];
+    }
+    __syncthreads();
+    unsigned long long total = 0;
+    for (int r = 0; r < kScanPer; ++r)
+        for (int q = 0; q < kBlock / 64; ++q) total += s_row[r][q];
+    if (wave == 0) {
+        unsigned long long p0, p1;
+        lookback(a.sc0, a.sc1, st, 0ull, total >> 32, total & 0xFFFFFFFFull, p0, p1);
+        if (lane == 0) {
+            s_p0 = p0;
+            s_p1 = p1;
+            if (st == a.n_scan_tiles - 1 && a.counts) {
+                a.counts[0] = (int64_t)(duals ? p1 + (total & 0xFFFFFFFFull) : p0 + (total >> 32));
+                a.counts[1] = (int64_t)(p1 + (total & 0xFFFFFFFFull));
+            }
+        }
+    }
+    __syncthreads();
+    const unsigned long long p0 = s_p0, p1 = s_p1;
+    unsigned long long carry = 0;
+    for (int r = 0; r < kScanPer; ++r) {
+        unsigned long long wave_pre = 0, row = 0;
+        for (int q = 0; q < kBlock / 64; ++q) {
+            if (q < wave) wave_pre += s_row[r][q];
+            row += s_row[r][q];
+        }
+        uint64_t i = base + (uint64_t)r * kBlock + t;
+        if (i < a.n_tiles) {
+            unsigned long long ex = carry + wave_pre + incl[r] - v[r];
+            a.pre_t[i] = p0 + (ex >> 32);
+            a.pre_d[i] = p1 + (ex & 0xFFFFFFFFull);
+        }
+        carry += row;
     }
 }
 
@@ -1451,8 +1520,11 @@ struct amr_set {
     Record* rec = nullptr;
     int32_t* ids = nullptr;
     int32_t* glist = nullptr;
-    unsigned long long* st_t = nullptr;
+    unsigned long long* tot = nullptr;   // extraction: per-tile totals
+    unsigned long long* st_t = nullptr;  // extraction: per-tile prefixes
     unsigned long long* st_d = nullptr;
+    unsigned long long* xs0 = nullptr;   // extraction scan: look-back states
+    unsigned long long* xs1 = nullptr;
     unsigned long long* ct0 = nullptr;
     unsigned long long* ct1 = nullptr;
     Sched* sched = nullptr;
@@ -1469,8 +1541,8 @@ uint32_t table_cap(const amr_set* s) {
 }
 
 struct Layout {
-    size_t rec, ids, glist, st_t, st_d, ct0, ct1, sched, total;
-    uint32_t max_tiles, compact_tiles;
+    size_t rec, ids, glist, tot, st_t, st_d, xs0, xs1, ct0, ct1, sched, total;
+    uint32_t max_tiles, max_scan_tiles, compact_tiles;
     int compact_per;
 };
 
@@ -1489,10 +1561,17 @@ Layout layout_for(uint32_t cap) {
     off = align256(off + (size_t)cap * 8 * sizeof(int32_t));
     L.glist = off;
     off = align256(off + (size_t)max_groups * sizeof(int32_t));
+    L.max_scan_tiles = (L.max_tiles + kBlock * kScanPer - 1) / (kBlock * kScanPer);
+    L.tot = off;
+    off = align256(off + (size_t)L.max_tiles * 8);
     L.st_t = off;
     off = align256(off + (size_t)L.max_tiles * 8);
     L.st_d = off;
     off = align256(off + (size_t)L.max_tiles * 8);
+    L.xs0 = off;
+    off = align256(off + (size_t)L.max_scan_tiles * 8);
+    L.xs1 = off;
+    off = align256(off + (size_t)L.max_scan_tiles * 8);
     L.ct0 = off;
     off = align256(off + (size_t)L.compact_tiles * 8);
     L.ct1 = off;
@@ -1547,14 +1626,27 @@ int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_
     a.dvals = dvals;
     a.cap = cap;
     a.counts = counts;
-    a.st_t = s->st_t;
-    a.st_d = s->st_d;
+    a.tot = s->tot;
+    a.pre_t = s->st_t;
+    a.pre_d = s->st_d;
+    a.sc0 = s->xs0;
+    a.sc1 = s->xs1;
     a.sched = s->sched;
     a.n_tiles = n_tiles;
+    a.n_scan_tiles = (n_tiles + kBlock * kScanPer - 1) / (kBlock * kScanPer);
+    // count pass, scan, then the write pass only when something is written
+    const bool write = cap > 0 && (duals ? (corner_level || verts || dvals) : (tris || tri_cells || tri_dual));
     if (duals)
-        hipLaunchKernelGGL(k_extract<true>, dim3(n_tiles), dim3(kBlock), 0, stream, a);
+        hipLaunchKernelGGL((k_extract<true, false>), dim3(n_tiles), dim3(kBlock), 0, stream, a);
     else
-        hipLaunchKernelGGL(k_extract<false>, dim3(n_tiles), dim3(kBlock), 0, stream, a);
+        hipLaunchKernelGGL((k_extract<false, false>), dim3(n_tiles), dim3(kBlock), 0, stream, a);
+    hipLaunchKernelGGL(k_tile_scan, dim3(a.n_scan_tiles), dim3(kBlock), 0, stream, a, duals ? 1 : 0);
+    if (write) {
+        if (duals)
+            hipLaunchKernelGGL((k_extract<true, true>), dim3(n_tiles), dim3(kBlock), 0, stream, a);
+        else
+            hipLaunchKernelGGL((k_extract<false, true>), dim3(n_tiles), dim3(kBlock), 0, stream, a);
+    }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? AMR_OK : hipfail(e, "extract launch");
 }
@@ -1734,8 +1826,11 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     s->rec = (Record*)(base + L.rec);
     s->ids = (int32_t*)(base + L.ids);
     s->glist = (int32_t*)(base + L.glist);
+    s->tot = (unsigned long long*)(base + L.tot);
     s->st_t = (unsigned long long*)(base + L.st_t);
     s->st_d = (unsigned long long*)(base + L.st_d);
+    s->xs0 = (unsigned long long*)(base + L.xs0);
+    s->xs1 = (unsigned long long*)(base + L.xs1);
     s->ct0 = (unsigned long long*)(base + L.ct0);
     s->ct1 = (unsigned long long*)(base + L.ct1);
     s->sched = (Sched*)(base + L.sched);
@@ -1743,8 +1838,8 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     Geo g = geo_of(s);
     hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, stream, s->ctrl);
     hipLaunchKernelGGL(k_index_init, dim3(grid_for(cap, 256)), dim3(256), 0, stream, s->rec, s->ids, cap);
-    hipLaunchKernelGGL(k_sched_reset, dim3(grid_for(L.max_tiles, 256)), dim3(256), 0, stream, s->sched, s->st_t,
-                       s->st_d, L.max_tiles, s->ct0, s->ct1, L.compact_tiles);
+    hipLaunchKernelGGL(k_sched_reset, dim3(grid_for(L.compact_tiles, 256)), dim3(256), 0, stream, s->sched, s->ct0,
+                       s->ct1, L.compact_tiles);
     if (s->n > 0)
         hipLaunchKernelGGL(k_index_insert, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->val,
                            s->n, g, s->rec, s->ids, s->ctrl);
