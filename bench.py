@@ -129,9 +129,10 @@ def batched_measurement(amr, s, cs, n_isos):
             "autotune_ms": table}
 
 
-def serving_measurement(amr, s, cs, seconds, rate):
+def serving_measurement(amr, s, name, iso_pool, seconds, rate, serial_requests=0):
     """Poisson iso/upload requests against the resident set: continuous
-    batching server vs. the serial plain path on the same trace."""
+    batching server vs. the serial plain path on the same trace (or on its
+    first `serial_requests` requests, when that is set)."""
     import numpy as np
     import torch
 
@@ -144,26 +145,138 @@ def serving_measurement(amr, s, cs, seconds, rate):
     for k, n in enumerate(sizes):
         pool.append(amrgen.octree_sized(int(n), seed=50 + k))
         say("serving: upload set %d: %d cells" % (k, pool[-1].n))
-    isos = np.quantile(cs.value, rng.uniform(0.05, 0.95, 97)).astype(np.float32)
+    isos = np.asarray(iso_pool, np.float32)
 
     def up(k):
         u = pool[k % len(pool)]
         return serve.UploadRequest(u.xyz, u.level, u.value, u.iso)
 
+    def progress(k, n):
+        say("serving: %d/%d requests" % (k, n))
+
     trace = serve.poisson_trace(rate, seconds, 5, lambda k: isos[k % len(isos)], up, p_upload=0.3)
     srv = serve.IsoServer(s)
+    say("serving: server ready, %d requests in the trace" % len(trace))
     t0 = time.perf_counter()
-    res = srv.serve(trace, keep_outputs=False)
+    res = srv.serve(trace, keep_outputs=False, progress=progress)
     wall = time.perf_counter() - t0
     say("serving: server run done (%d requests, %.1f s)" % (len(res), wall))
     torch.cuda.synchronize()
+    strace = trace[:serial_requests] if serial_requests else trace
     t0 = time.perf_counter()
-    base = serve.serve_serial(s, trace)
+    base = serve.serve_serial(s, strace, progress=progress)
     wall_b = time.perf_counter() - t0
-    return {"workload": "resident %s + uploads of %s-cell octree sets; Poisson %.0f req/s for %.0f s, 30%% uploads"
-                        % (cs.name, "/".join(str(p.n) for p in pool), rate, seconds),
-            "server": serve.summarize(res, wall), "serial_plain": serve.summarize(base, wall_b),
-            "hbm_peak_reserved_bytes": srv.mem.peak}
+    out = {"workload": "resident %s + uploads of %s-cell octree sets; Poisson %.0f req/s for %.0f s, 30%% uploads"
+                       % (name, "/".join(str(p.n) for p in pool), rate, seconds),
+           "server": serve.summarize(res, wall), "serial_plain": serve.summarize(base, wall_b),
+           "hbm_peak_reserved_bytes": srv.mem.peak}
+    if serial_requests and serial_requests < len(trace):
+        out["serial_plain"]["note"] = ("first %d requests of the same trace only (the serial path is saturated, "
+                                       "so its latencies only grow with more requests)" % len(strace))
+        srv_part = serve.summarize(res[:len(strace)], wall)
+        out["server_same_prefix"] = {k: srv_part[k] for k in ("requests", "p50_ms", "p99_ms", "by_kind")}
+    return out
+
+
+def large_serving(amr, seconds, rate, serial_requests):
+    """Serving against a ~600M-cell octree held resident with its index: the
+    octree-shell recipe on 2048^3 with 6 levels (roots of width 32), shell
+    480 < r < 560, split probability 0.6 on the shell and 0.575 elsewhere,
+    Gaussian widths scaled by 8; generated on the GPU."""
+    import numpy as np
+    import torch
+
+    import amrgen
+
+    dev = torch.device("cuda", 0)
+    t0 = time.perf_counter()
+    xyz, lv, val, iso = amrgen.octree_shell_torch(2048, 5, (480.0, 560.0), 0.6, 0.575, 5, dev,
+                                                  sigma=(80.0, 320.0))
+    torch.cuda.synchronize()
+    n = int(lv.numel())
+    say("large serving set: %d cells generated in %.1f s" % (n, time.perf_counter() - t0))
+    s = amr.AmrSet(0)
+    s.upload(xyz, lv, val)
+    t0 = time.perf_counter()
+    s.build_index()
+    torch.cuda.synchronize()
+    say("large serving set: index built in %.1f ms" % ((time.perf_counter() - t0) * 1e3))
+    sample = val[torch.randint(0, n, (1 << 24,), device=dev, generator=torch.Generator(dev).manual_seed(5))]
+    qs = np.random.default_rng(5).uniform(0.05, 0.95, 97)
+    isos = torch.quantile(sample.double(), torch.as_tensor(qs, device=dev)).float().cpu().numpy()
+    name = "octree-shell-2048 (%d cells, levels 0..5, p 0.6/0.575)" % n
+    out = serving_measurement(amr, s, name, isos, seconds, rate, serial_requests)
+    out["resident_cells"] = n
+    out["resident_bytes"] = {"cells": 20 * n, "index": int(s.workspace.numel())}
+    return out
+
+
+def batched_multiset_measurement(amr, n_sets=32, seed=4):
+    """32 independent octree sets of log-uniform sizes 10k..5M cells, each at
+    its own iso (median), in one fused persistent launch replayed from a HIP
+    graph, against the plain path run once per set."""
+    import numpy as np
+    import torch
+
+    import amrgen
+    from paper_2004_08475_amd import autotune
+
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(np.log(1e4), np.log(5e6), n_sets)).astype(int)
+    css, sets = [], []
+    for k, n in enumerate(sizes):
+        cs = amrgen.octree_sized(int(n), seed=200 + k)
+        css.append(cs)
+        sets.append(amr.from_numpy(cs.xyz, cs.level, cs.value))
+    say("batched sets: %d sets, %d cells in all" % (n_sets, sum(c.n for c in css)))
+    dev = sets[0].device
+    b = amr.AmrBatch(sets)
+    isos = np.array([c.iso for c in css], np.float32)
+    counts = torch.zeros(n_sets, dtype=torch.int64, device=dev)
+    probe = b.jobs_tensor(list(range(n_sets)), isos, np.zeros(n_sets), np.zeros(n_sets))
+    b.run_into(probe, n_sets, None, counts)
+    c = counts.cpu().numpy()
+    off = np.concatenate([[0], np.cumsum(c)[:-1]])
+    tris = torch.empty((max(int(c.sum()), 1), 9), dtype=torch.float32, device=dev)
+    jobs = b.jobs_tensor(list(range(n_sets)), isos, off, c)
+    block, per, table = autotune.tune(b, jobs, n_sets, tris, counts)
+    ws = b.workspace(n_sets, block, per)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        b.run_into(jobs, n_sets, tris, counts, block, per, ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.run_into(jobs, n_sets, tris, counts, block, per, ws)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g.replay()
+    e0.record()
+    for _ in range(10):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    fused_ms = e0.elapsed_time(e1) / 10
+    assert counts.cpu().numpy().tolist() == c.tolist()
+    bufs = [torch.empty((max(int(k), 1), 9), dtype=torch.float32, device=dev) for k in c]
+    for k in range(n_sets):
+        sets[k].isosurface_into(float(isos[k]), bufs[k], int(c[k]))
+    e0.record()
+    for _ in range(3):
+        for k in range(n_sets):
+            sets[k].isosurface_into(float(isos[k]), bufs[k], int(c[k]))
+    e1.record()
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1) / 3
+    for k in range(n_sets):
+        assert torch.equal(bufs[k][:int(c[k])], tris[int(off[k]):int(off[k]) + int(c[k])])
+    n_cells = int(sum(cs.n for cs in css))
+    return {"workload": "%d octree sets, log-uniform 10k..5M cells (%d in all), own median iso each, one fused "
+                        "launch replayed from a HIP graph" % (n_sets, n_cells),
+            "set_cells": [int(cs.n) for cs in css], "fused_ms": fused_ms, "plain_ms_for_all_sets": plain_ms,
+            "speedup_vs_plain": plain_ms / fused_ms, "cells_per_s": n_cells / (fused_ms * 1e-3),
+            "triangles": int(c.sum()), "autotuned_shape": {"block": block, "per_thread": per}, "autotune_ms": table}
 
 
 def main():
@@ -177,6 +290,12 @@ def main():
     ap.add_argument("--batch-isos", type=int, default=64, help="isos in the batched (fused) measurement; 0 = skip")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of the serving run; 0 = skip")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the serving run")
+    ap.add_argument("--serve-workload", default="bench", choices=("bench", "large"),
+                    help="resident set of the serving run: the bench workload, or the ~600M-cell octree")
+    ap.add_argument("--serve-serial-requests", type=int, default=0,
+                    help="replay only this many requests through the serial baseline (0 = all)")
+    ap.add_argument("--batch-sets", type=int, default=0,
+                    help="also fuse this many independent octree sets (10k..5M cells) into one launch")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -292,8 +411,16 @@ def main():
         out["batched"] = batched_measurement(amr, s, cs, args.batch_isos)
         say("batched: fused %.3f ms, plain %.3f ms" % (out["batched"]["fused_ms"],
                                                         out["batched"]["plain_ms_for_all_isos"]))
-    if args.serve_seconds > 0:
-        out["serving"] = serving_measurement(amr, s, cs, args.serve_seconds, args.serve_rate)
+    if args.batch_sets:
+        out["batched_sets"] = batched_multiset_measurement(amr, args.batch_sets)
+        say("batched sets: fused %.3f ms, plain %.3f ms" % (out["batched_sets"]["fused_ms"],
+                                                             out["batched_sets"]["plain_ms_for_all_sets"]))
+    if args.serve_seconds > 0 and args.serve_workload == "large":
+        out["serving"] = large_serving(amr, args.serve_seconds, args.serve_rate, args.serve_serial_requests)
+    elif args.serve_seconds > 0:
+        iso_pool = np.quantile(cs.value, np.random.default_rng(5).uniform(0.05, 0.95, 97)).astype(np.float32)
+        out["serving"] = serving_measurement(amr, s, cs.name, iso_pool, args.serve_seconds, args.serve_rate,
+                                             args.serve_serial_requests)
         say("serving: p99 %.2f ms (server) vs %.2f ms (serial)" % (out["serving"]["server"]["p99_ms"],
                                                                   out["serving"]["serial_plain"]["p99_ms"]))
     if not args.no_cpu_baseline:

@@ -95,6 +95,7 @@ struct Ctrl {
     unsigned long long bad_build;
     unsigned long long n_groups;   // written by the compaction's last tile
     unsigned long long n_records;
+    unsigned long long n_leaves;   // cells present in the table
 };
 
 // Scan bookkeeping inside the workspace.
@@ -274,6 +275,7 @@ __global__ void k_ctrl_reset(Ctrl* c) {
         c->bad_build = ~0ull;
         c->n_groups = 0;
         c->n_records = 0;
+        c->n_leaves = 0;
     }
 }
 
@@ -383,17 +385,14 @@ struct Geo {
     uint32_t mask;       // cap - 1
 };
 
-__global__ __launch_bounds__(256) void k_index_init(Record* __restrict__ rec, int32_t* __restrict__ ids, uint32_t cap) {
-    float e = __uint_as_float(kValEmpty);
+__global__ __launch_bounds__(256) void k_index_init(Record* __restrict__ rec, uint32_t cap) {
+    const float e = __uint_as_float(kValEmpty);
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += gridDim.x * blockDim.x) {
         Record r;
         for (int c = 0; c < 8; ++c) r.val[c] = e;
         r.key = kEmpty;
         for (int c = 0; c < 6; ++c) r.pad[c] = 0;
         rec[i] = r;
-        int4* p = reinterpret_cast<int4*>(ids + (size_t)i * 8);
-        p[0] = make_int4(-1, -1, -1, -1);
-        p[1] = make_int4(-1, -1, -1, -1);
     }
 }
 
@@ -414,10 +413,9 @@ __device__ __forceinline__ int find_or_insert(Record* __restrict__ rec, uint64_t
     return -1;
 }
 
-// Every cell stores its value in its group record, then marks its ancestors
-// as refined, level by level, until it meets a mark someone else set.  A
-// leaf exchanged over a refined mark, or a mark set over a leaf, is a nested
-// cell; a leaf exchanged over a leaf is a duplicate.
+// Every cell stores its value and input index in its group record (plain
+// stores: a duplicate cell overwrites its twin and shows up later as a
+// missing leaf in the count of the compaction).
 __global__ __launch_bounds__(256) void k_index_insert(const int32_t* __restrict__ xyz, const int32_t* __restrict__ lvl,
                                                       const float* __restrict__ val, int64_t n, Geo g,
                                                       Record* __restrict__ rec, int32_t* __restrict__ ids, Ctrl* c) {
@@ -431,28 +429,64 @@ __global__ __launch_bounds__(256) void k_index_insert(const int32_t* __restrict_
             continue;
         }
         int child = ((ux >> m) & 1) | (((uy >> m) & 1) << 1) | (((uz >> m) & 1) << 2);
-        uint32_t old = atomicExch(reinterpret_cast<unsigned int*>(&rec[slot].val[child]), __float_as_uint(val[i]));
+        rec[slot].val[child] = val[i];
         ids[(size_t)slot * 8 + child] = (int32_t)i;
-        if (old != kValEmpty) {
-            atomicOr(old == kValRefined ? &c->overlap : &c->dup, 1u);
-            atomicMin(&c->bad_build, (unsigned long long)i);
-        }
+    }
+}
+
+// Every group holding a cell marks its ancestors as refined, level by
+// level, until it meets a mark set by another group.  All leaves are stored
+// before this pass, so a mark that lands on a leaf is a coarser cell
+// containing finer ones.
+__global__ __launch_bounds__(256) void k_index_mark(Record* __restrict__ rec, const int32_t* __restrict__ ids,
+                                                    uint32_t cap, Geo g, Ctrl* c) {
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
+        const uint64_t key = rec[s].key;
+        if (key == kEmpty) continue;
+        const int m = (int)(key >> 57);
+        if (m >= g.lmax) continue;
+        const float4* pv = reinterpret_cast<const float4*>(rec[s].val);
+        const float4 a = pv[0], b = pv[1];
+        const bool leaf = a.x == a.x || a.y == a.y || a.z == a.z || a.w == a.w || b.x == b.x || b.y == b.y ||
+                          b.z == b.z || b.w == b.w;
+        if (!leaf) continue;
+        const uint32_t gx = (uint32_t)(key & 0x7FFFF), gy = (uint32_t)((key >> 19) & 0x7FFFF),
+                       gz = (uint32_t)((key >> 38) & 0x7FFFF);
         for (int L = m + 1; L <= g.lmax; ++L) {
-            int s2 = find_or_insert(rec, group_key(L, ux >> (L + 1), uy >> (L + 1), uz >> (L + 1)), g);
+            // the level-L cell holding this group's block, and its group
+            const int sh = L - m - 1;
+            const uint32_t cx = gx >> sh, cy = gy >> sh, cz = gz >> sh;
+            const int s2 = find_or_insert(rec, group_key(L, cx >> 1, cy >> 1, cz >> 1), g);
             if (s2 < 0) {
                 atomicOr(&c->overflow, 1u);
                 break;
             }
-            int c2 = ((ux >> L) & 1) | (((uy >> L) & 1) << 1) | (((uz >> L) & 1) << 2);
-            uint32_t prev =
+            const int c2 = (cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2);
+            const uint32_t prev =
                 atomicCAS(reinterpret_cast<unsigned int*>(&rec[s2].val[c2]), kValEmpty, kValRefined);
             if (prev == kValEmpty) continue;  // marked here: carry on upwards
-            if (prev != kValRefined) {        // a coarser cell contains this one
+            if (prev != kValRefined) {        // a coarser cell contains this group
                 atomicOr(&c->overlap, 1u);
-                atomicMin(&c->bad_build, (unsigned long long)i);
+                atomicMin(&c->bad_build, (unsigned long long)(uint32_t)ids[(size_t)s2 * 8 + c2]);
             }
             break;
         }
+    }
+}
+
+// Error path only: the lowest input index whose entry was overwritten by a
+// duplicate of the same cell.
+__global__ __launch_bounds__(256) void k_index_find_dup(const int32_t* __restrict__ xyz, const int32_t* __restrict__ lvl,
+                                                        int64_t n, Geo g, const Record* __restrict__ rec,
+                                                        const int32_t* __restrict__ ids, Ctrl* c) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int m = lvl[i];
+        uint32_t ux = (uint32_t)(xyz[3 * i] - g.ox), uy = (uint32_t)(xyz[3 * i + 1] - g.oy),
+                 uz = (uint32_t)(xyz[3 * i + 2] - g.oz);
+        int slot = probe(rec, group_key(m, ux >> (m + 1), uy >> (m + 1), uz >> (m + 1)), g.shift, g.mask);
+        if (slot < 0) continue;
+        int child = ((ux >> m) & 1) | (((uy >> m) & 1) << 1) | (((uz >> m) & 1) << 2);
+        if (ids[(size_t)slot * 8 + child] != (int32_t)i) atomicMin(&c->bad_build, (unsigned long long)i);
     }
 }
 
@@ -474,19 +508,21 @@ __global__ __launch_bounds__(kBlock) void k_index_compact(const Record* __restri
     const uint32_t tile = s_tile;
     // thread t looks at slots base + r*256 + t, r < per (coalesced)
     const uint32_t base = tile * (uint32_t)(kBlock * per);
-    uint32_t grp_bits = 0, n_rec = 0;
+    uint32_t grp_bits = 0;
+    unsigned long long n_rec = 0;
 #pragma unroll 4
     for (int r = 0; r < per; ++r) {
         uint32_t s = base + r * kBlock + t;
         if (s >= cap) continue;
         const Record& R = rec[s];
         if (R.key == kEmpty) continue;
-        ++n_rec;
         const float4* pv = reinterpret_cast<const float4*>(R.val);
         float4 a = pv[0], b = pv[1];
-        bool any = a.x == a.x || a.y == a.y || a.z == a.z || a.w == a.w || b.x == b.x || b.y == b.y ||
-                   b.z == b.z || b.w == b.w;
-        if (any) grp_bits |= 1u << r;
+        uint32_t leaves = (a.x == a.x) + (a.y == a.y) + (a.z == a.z) + (a.w == a.w) + (b.x == b.x) + (b.y == b.y) +
+                          (b.z == b.z) + (b.w == b.w);
+        // records in the low 29 bits, leaves above (cap <= 2^28 keeps them apart)
+        n_rec += 1ull + ((unsigned long long)leaves << 29);
+        if (leaves) grp_bits |= 1u << r;
     }
     for (int r = 0; r < per; ++r) {
         unsigned long long b = __ballot((grp_bits >> r) & 1);
@@ -508,7 +544,8 @@ __global__ __launch_bounds__(kBlock) void k_index_compact(const Record* __restri
             s_pre0 = p0;
             if (tile == n_tiles - 1) {
                 c->n_groups = p0 + total_g;
-                c->n_records = p1 + total_r;
+                c->n_records = (p1 + total_r) & ((1ull << 29) - 1);
+                c->n_leaves = (p1 + total_r) >> 29;
             }
         }
     }
@@ -585,13 +622,6 @@ __host__ __device__ constexpr int edge_lo(int e) {
 }
 __host__ __device__ constexpr int edge_hi(int e) { return edge_lo(e) | (1 << (e >> 2)); }
 
-// LDS cell of slot s of corner k (corner in {0,1,2}^3, slot in {0,1}^3,
-// around the group): neighbour index dd in [0,27) and child in [0,8)
-__device__ __forceinline__ void slot_cell(int kx, int ky, int kz, int s, int& dd, int& child) {
-    int rx = kx + (s & 1) - 1, ry = ky + ((s >> 1) & 1) - 1, rz = kz + ((s >> 2) & 1) - 1;
-    dd = ((rx + 2) >> 1) + 3 * ((ry + 2) >> 1) + 9 * ((rz + 2) >> 1);
-    child = (rx & 1) | ((ry & 1) << 1) | ((rz & 1) << 2);
-}
 
 // Extraction runs as three launches: a count pass (phases 1-2, per-tile
 // totals), a scan of the tile totals, and a write pass that repeats phases
@@ -599,9 +629,12 @@ __device__ __forceinline__ void slot_cell(int kx, int ky, int kz, int s, int& dd
 // scanned positions.  No tile ever waits for another in the heavy passes.
 template <bool kDuals, bool kWrite>
 __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
-    __shared__ float s_val[kGroupsPerTile][27][8];
-    __shared__ int32_t s_ref[kGroupsPerTile][27];
-    __shared__ int8_t s_lvl[kGroupsPerTile][27];
+    // the 4x4x4 cells of level m around each group (offsets -1..2 from its
+    // lower corner, x fastest): value, cell reference, level of the cell that
+    // covers the position (-1: none)
+    __shared__ float s_v[kGroupsPerTile][64];
+    __shared__ int32_t s_r[kGroupsPerTile][64];
+    __shared__ int8_t s_l[kGroupsPerTile][64];
     __shared__ unsigned long long s_tab[256];
     __shared__ unsigned long long s_wave[kBlock / 64];
     __shared__ unsigned long long s_pre_t, s_pre_d;
@@ -688,12 +721,10 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
                     xb = reinterpret_cast<const float4*>(a.rec[h].val)[1];
                 }
             }
-            float* dst = s_val[gi][dd];
-            if (k == want[q]) {
-                reinterpret_cast<float4*>(dst)[0] = xa;
-                reinterpret_cast<float4*>(dst)[1] = xb;
+            float cv = 0.f;
+            const bool hit = k == want[q];
+            if (hit) {
                 lv = m;
-                ref = (int)h;
             } else {
                 // The block holds neither cells of level m nor finer cells (either
                 // would have left a record): it lies inside a coarser cell or in a
@@ -710,13 +741,25 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
                     if (v == v) {
                         lv = L;
                         ref = h2 * 8 + child;
-                        dst[0] = v;
+                        cv = v;
                     }
                     break;
                 }
             }
-            s_ref[gi][dd] = ref;
-            s_lvl[gi][dd] = (int8_t)lv;
+            // the cells of this neighbour that lie in the 4x4x4 block
+            const float v8[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
+            const int dx = dd % 3 - 1, dy = (dd / 3) % 3 - 1, dz = dd / 9 - 1;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int chx = c & 1, chy = (c >> 1) & 1, chz = c >> 2;
+                const bool need = (dx == 0 || (dx < 0) == (chx == 1)) && (dy == 0 || (dy < 0) == (chy == 1)) &&
+                                  (dz == 0 || (dz < 0) == (chz == 1));
+                if (!need) continue;
+                const int p = (2 * dx + chx + 1) + 4 * (2 * dy + chy + 1) + 16 * (2 * dz + chz + 1);
+                s_v[gi][p] = hit ? v8[c] : cv;
+                s_r[gi][p] = hit ? (int)h * 8 + c : ref;
+                s_l[gi][p] = (int8_t)lv;
+            }
         }
     }
     __syncthreads();
@@ -737,17 +780,18 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
         uint32_t same = 0, mine = 0;
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-            int dd, child;
-            slot_cell(kx, ky, kz, s, dd, child);
-            int lv = s_lvl[gi][dd];
-            float v = s_val[gi][dd][lv == m ? child : 0];
-            int r = s_ref[gi][dd];
-            refs[s] = lv == m ? r * 8 + child : r;
+            const int px = kx + (s & 1), py = ky + ((s >> 1) & 1), pz = kz + (s >> 2);
+            const int p = px + 4 * py + 16 * pz;
+            int lv = s_l[gi][p];
+            float v = s_v[gi][p];
+            refs[s] = s_r[gi][p];
             vals[s] = v;
             // rule 1 (hole) and rule 2 (finer cells) both show as lv < 0 or a NaN
             ok = ok && lv >= 0 && v == v;
             same |= (lv == m ? 1u : 0u) << s;
-            mine |= (dd == 13 ? 1u : 0u) << s;
+            // cells of this group sit at positions 1..2 on every axis
+            const bool in = ((px - 1) | (py - 1) | (pz - 1)) >= 0 && px <= 2 && py <= 2 && pz <= 2;
+            mine |= (in ? 1u : 0u) << s;
         }
         // rule 3: the lowest same-level slot must be a cell of this group
         if (!ok || !same || !((mine >> (__ffs(same) - 1)) & 1)) continue;
@@ -825,24 +869,16 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
                 if (a.verts) {
                     int id[8];
 #pragma unroll
-                    for (int s = 0; s < 8; ++s) {
-                        int dd, child;
-                        slot_cell(kx, ky, kz, s, dd, child);
-                        int lv = s_lvl[gi][dd];
-                        int r = s_ref[gi][dd];
-                        id[s] = a.ids[lv == m ? r * 8 + child : r];
-                    }
+                    for (int s = 0; s < 8; ++s)
+                        id[s] = a.ids[s_r[gi][(kx + (s & 1)) + 4 * (ky + ((s >> 1) & 1)) + 16 * (kz + (s >> 2))]];
                     reinterpret_cast<int4*>(a.verts)[2 * out_d] = make_int4(id[0], id[1], id[2], id[3]);
                     reinterpret_cast<int4*>(a.verts)[2 * out_d + 1] = make_int4(id[4], id[5], id[6], id[7]);
                 }
                 if (a.dvals) {
                     float v[8];
 #pragma unroll
-                    for (int s = 0; s < 8; ++s) {
-                        int dd, child;
-                        slot_cell(kx, ky, kz, s, dd, child);
-                        v[s] = s_val[gi][dd][s_lvl[gi][dd] == m ? child : 0];
-                    }
+                    for (int s = 0; s < 8; ++s)
+                        v[s] = s_v[gi][(kx + (s & 1)) + 4 * (ky + ((s >> 1) & 1)) + 16 * (kz + (s >> 2))];
                     reinterpret_cast<float4*>(a.dvals)[2 * out_d] = make_float4(v[0], v[1], v[2], v[3]);
                     reinterpret_cast<float4*>(a.dvals)[2 * out_d + 1] = make_float4(v[4], v[5], v[6], v[7]);
                 }
@@ -903,13 +939,10 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
 #pragma unroll
                     for (int side = 0; side < 2; ++side) {
                         int sl = side ? edge_hi(ed) : edge_lo(ed);
-                        int dd, child;
-                        slot_cell(kx, ky, kz, sl, dd, child);
-                        int lv = s_lvl[og][dd];
-                        int r = s_ref[og][dd];
-                        ev[side] = s_val[og][dd][lv == om ? child : 0];
-                        er[side] = lv == om ? r * 8 + child : r;
-                        el[side] = lv;
+                        const int p = (kx + (sl & 1)) + 4 * (ky + ((sl >> 1) & 1)) + 16 * (kz + (sl >> 2));
+                        ev[side] = s_v[og][p];
+                        er[side] = s_r[og][p];
+                        el[side] = s_l[og][p];
                         epos[side][0] = kx + (sl & 1) - 1;
                         epos[side][1] = ky + ((sl >> 1) & 1) - 1;
                         epos[side][2] = kz + ((sl >> 2) & 1) - 1;
@@ -1837,12 +1870,15 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     s->n_groups = 0;
     Geo g = geo_of(s);
     hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, stream, s->ctrl);
-    hipLaunchKernelGGL(k_index_init, dim3(grid_for(cap, 256)), dim3(256), 0, stream, s->rec, s->ids, cap);
+    hipLaunchKernelGGL(k_index_init, dim3(grid_for(cap, 256)), dim3(256), 0, stream, s->rec, cap);
     hipLaunchKernelGGL(k_sched_reset, dim3(grid_for(L.compact_tiles, 256)), dim3(256), 0, stream, s->sched, s->ct0,
                        s->ct1, L.compact_tiles);
-    if (s->n > 0)
+    if (s->n > 0) {
         hipLaunchKernelGGL(k_index_insert, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->val,
                            s->n, g, s->rec, s->ids, s->ctrl);
+        hipLaunchKernelGGL(k_index_mark, dim3(grid_for(cap, 256)), dim3(256), 0, stream, s->rec, s->ids, cap, g,
+                           s->ctrl);
+    }
     hipLaunchKernelGGL(k_index_compact, dim3(L.compact_tiles), dim3(kBlock), 0, stream, s->rec, cap, s->glist,
                        s->ct0, s->ct1, s->sched, L.compact_tiles, L.compact_per, s->ctrl);
     hipError_t e = hipGetLastError();
@@ -1860,8 +1896,18 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
         return fail(AMR_ENOSPACE, "amr_build_index: hash table too small (%u slots); query amr_index_bytes again",
                     cap);
     }
-    if (c.dup) return fail(AMR_EOVERLAP, "amr_build_index: duplicate cell (index %llu)", c.bad_build);
-    if (c.overlap) return fail(AMR_EOVERLAP, "amr_build_index: cell %llu overlaps a coarser cell", c.bad_build);
+    if (c.overlap) return fail(AMR_EOVERLAP, "amr_build_index: cell %llu contains finer cells", c.bad_build);
+    if (c.n_leaves != (unsigned long long)s->n) {
+        // some cell was stored twice: find the lowest overwritten index
+        hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, stream, s->ctrl);
+        hipLaunchKernelGGL(k_index_find_dup, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->n,
+                           g, s->rec, s->ids, s->ctrl);
+        e = hipMemcpyAsync((char*)s->host_ctrl + tail, (char*)s->ctrl + tail, sizeof(Ctrl) - tail,
+                           hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hipfail(e, "amr_build_index: duplicate search");
+        return fail(AMR_EOVERLAP, "amr_build_index: duplicate cell (index %llu)", s->host_ctrl->bad_build);
+    }
     s->n_groups = (uint32_t)c.n_groups;
     s->built = true;
     g_err[0] = 0;

@@ -125,8 +125,28 @@ class IsoServer:
         return int(2 * max(self.curve_tri[lo], self.curve_tri[hi]) + 4096)
 
     # -- resident iso requests --------------------------------------------
+    def _run_one(self, r, results, stream):
+        """A lone request: the plain single-pass path with the capacity taken
+        from the triangle-count curve (a second pass only if it was short)."""
+        cap = self.iso_cap(r.iso)
+        held = self.mem.acquire(cap * 36 + (1 << 20), self.stop)
+        t_start = time.perf_counter()
+        try:
+            with torch.cuda.stream(stream):
+                tris = torch.empty((cap, 9), dtype=torch.float32, device=self.device)
+                counts = self.resident.isosurface_into(r.iso, tris, cap)
+                c = int(counts[0].item())
+                out = tris[:c] if c <= cap else self.resident.isosurface(r.iso, c)["tris"]
+                stream.synchronize()
+                res = results[r.rid]
+                res.start, res.done, res.triangles, res.tris = t_start, time.perf_counter(), c, out
+        finally:
+            self.mem.release(held)
+
     def _run_batch(self, reqs, results, stream):
         n = len(reqs)
+        if n == 1:
+            return self._run_one(reqs[0], results, stream)
         isos = [r.iso for r in reqs]
         caps = np.array([self.iso_cap(v) for v in isos], np.int64)
         need = int(caps.sum()) * 36 + (1 << 20)
@@ -202,9 +222,10 @@ class IsoServer:
         self._slot_sets.append(s)
 
     # -- driver -----------------------------------------------------------
-    def serve(self, trace, keep_outputs: bool = True):
+    def serve(self, trace, keep_outputs: bool = True, progress=None):
         """Replay `trace` = [(arrival seconds from start, request)] in real
-        time.  Returns the list of Results (one per request, in trace order)."""
+        time.  Returns the list of Results (one per request, in trace order).
+        `progress(k, n)` is called every 100 submitted requests."""
         mk = lambda: {"items": collections.deque(), "cv": threading.Condition(), "closed": False}
         iso_q, up_q = mk(), mk()
         results = {}
@@ -226,6 +247,8 @@ class IsoServer:
             with q["cv"]:
                 q["items"].append(req)
                 q["cv"].notify()
+            if progress and (rid + 1) % 100 == 0:
+                progress(rid + 1, len(trace))
         for q in (iso_q, up_q):
             with q["cv"]:
                 q["closed"] = True
@@ -239,9 +262,10 @@ class IsoServer:
         return out
 
 
-def serve_serial(resident: AmrSet, trace, keep_outputs: bool = False):
+def serve_serial(resident: AmrSet, trace, keep_outputs: bool = False, progress=None):
     """Baseline: the same trace, one request at a time, plain single-iso path
-    (count pass + write pass), in arrival order on one stream."""
+    (count pass + write pass), in arrival order on one stream.  `progress(k,
+    n)` is called every 100 finished requests."""
     results = []
     t0 = time.perf_counter()
     dev = resident.device
@@ -265,6 +289,8 @@ def serve_serial(resident: AmrSet, trace, keep_outputs: bool = False):
         torch.cuda.synchronize(dev)
         r = Result(rid, kind, arrival, start, time.perf_counter(), int(out.shape[0]), out if keep_outputs else None)
         results.append(r)
+        if progress and (rid + 1) % 100 == 0:
+            progress(rid + 1, len(trace))
     return results
 
 
