@@ -62,6 +62,7 @@ constexpr uint32_t kMaxCap = 1u << 28;  // slot * 8 + child fits int32
 constexpr uint32_t kMaxProbe = 1024;    // longer chains mean the table is too full
 constexpr int kCompactMaxPerThread = 16;
 constexpr int kReplicas = 64;           // spread of the upload reduction atomics
+constexpr uint32_t kFusedMaxTiles = 2048;  // sets up to this many tiles extract in one fused pass
 constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
 
 enum : uint32_t { kErrLevel = 1, kErrAlign = 2, kErrValue = 4, kErrCoord = 8 };
@@ -593,10 +594,15 @@ struct ExtractArgs {
     uint32_t n_scan_tiles;
 };
 
-__global__ void k_sched_reset(Sched* sc, unsigned long long* ct0, unsigned long long* ct1, uint32_t nc) {
+__global__ void k_sched_reset(Sched* sc, unsigned long long* ct0, unsigned long long* ct1, uint32_t nc,
+                              unsigned long long* fs0, unsigned long long* fs1) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += gridDim.x * blockDim.x) {
         ct0[i] = 0;
         ct1[i] = 0;
+    }
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < kFusedMaxTiles; i += gridDim.x * blockDim.x) {
+        fs0[i] = 0;
+        fs1[i] = 0;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc->xticket = 0;
@@ -623,11 +629,16 @@ __host__ __device__ constexpr int edge_lo(int e) {
 __host__ __device__ constexpr int edge_hi(int e) { return edge_lo(e) | (1 << (e >> 2)); }
 
 
-// Extraction runs as three launches: a count pass (phases 1-2, per-tile
-// totals), a scan of the tile totals, and a write pass that repeats phases
-// 1-2 for the tiles that have output below the capacity and writes it at the
-// scanned positions.  No tile ever waits for another in the heavy passes.
-template <bool kDuals, bool kWrite>
+// Extraction of a large set runs as three launches: a count pass (phases
+// 1-2, per-tile totals), a scan of the tile totals, and a write pass that
+// repeats phases 1-2 for the tiles that have output below the capacity and
+// writes it at the scanned positions; no tile waits for another in the heavy
+// passes.  A small set (few tiles, where a global ticket per tile is cheap)
+// runs one fused pass: tiles take tickets in start order and find their
+// output position by a decoupled look-back over earlier tickets.
+enum : int { kPassCount = 0, kPassWrite = 1, kPassFused = 2 };
+
+template <bool kDuals, int kPass>
 __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
     // the 4x4x4 cells of level m around each group (offsets -1..2 from its
     // lower corner, x fastest): value, cell reference, level of the cell that
@@ -647,8 +658,13 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
     const int t = threadIdx.x;
     const int gi = t >> 3;  // group within the tile
     const int j = t & 7;    // lane within the group
-    const uint32_t tile = blockIdx.x;
-    if (kWrite) {
+    __shared__ uint32_t s_tile;
+    if (kPass == kPassFused) {
+        if (threadIdx.x == 0) s_tile = (uint32_t)atomicAdd(&a.sched->xticket, 1ull);
+        __syncthreads();
+    }
+    const uint32_t tile = kPass == kPassFused ? s_tile : blockIdx.x;
+    if (kPass == kPassWrite) {
         // nothing of this tile lands below the capacity: done
         const unsigned long long tt = a.tot[tile];
         const unsigned long long mine_n = kDuals ? (tt & 0xFFFFFFFFull) : (tt >> 32);
@@ -658,7 +674,7 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
             s_pre_t = a.pre_t[tile];
             s_pre_d = a.pre_d[tile];
         }
-    } else if (t == 0) {
+    } else if (kPass == kPassCount && t == 0) {
         // the scan that follows starts from clean states
         if (tile < a.n_scan_tiles) {
             a.sc0[tile] = 0;
@@ -844,9 +860,25 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
     }
     unsigned long long excl = wave_pre + incl - mine;
 
-    if (!kWrite) {
+    if (kPass == kPassCount) {
         if (t == 0) a.tot[tile] = total;
         return;
+    }
+    if (kPass == kPassFused) {
+        if (wave == 0) {
+            unsigned long long pre_t, pre_d;
+            const unsigned long long agg_t = total >> 32, agg_d = total & 0xFFFFFFFFull;
+            lookback(a.sc0, a.sc1, tile, 0ull, agg_t, agg_d, pre_t, pre_d);
+            if (lane_id() == 0) {
+                s_pre_t = pre_t;
+                s_pre_d = pre_d;
+                if (tile == a.n_tiles - 1 && a.counts) {
+                    a.counts[0] = kDuals ? (int64_t)(pre_d + agg_d) : (int64_t)(pre_t + agg_t);
+                    a.counts[1] = (int64_t)(pre_d + agg_d);
+                }
+            }
+        }
+        __syncthreads();
     }
 
     // ---- phase 3: write ----
@@ -985,6 +1017,15 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
             }
         }
     }
+}
+
+// After a fused pass: clean look-back states and ticket for the next call.
+__global__ void k_fused_clear(ExtractArgs a) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n_tiles; i += gridDim.x * blockDim.x) {
+        a.sc0[i] = 0;
+        a.sc1[i] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.sched->xticket = 0;
 }
 
 // Exclusive scan of the per-tile (triangles, duals) totals of a count pass:
@@ -1558,6 +1599,8 @@ struct amr_set {
     unsigned long long* st_d = nullptr;
     unsigned long long* xs0 = nullptr;   // extraction scan: look-back states
     unsigned long long* xs1 = nullptr;
+    unsigned long long* fs0 = nullptr;   // fused extraction: look-back states
+    unsigned long long* fs1 = nullptr;
     unsigned long long* ct0 = nullptr;
     unsigned long long* ct1 = nullptr;
     Sched* sched = nullptr;
@@ -1574,7 +1617,7 @@ uint32_t table_cap(const amr_set* s) {
 }
 
 struct Layout {
-    size_t rec, ids, glist, tot, st_t, st_d, xs0, xs1, ct0, ct1, sched, total;
+    size_t rec, ids, glist, tot, st_t, st_d, xs0, xs1, fs0, fs1, ct0, ct1, sched, total;
     uint32_t max_tiles, max_scan_tiles, compact_tiles;
     int compact_per;
 };
@@ -1605,6 +1648,10 @@ Layout layout_for(uint32_t cap) {
     off = align256(off + (size_t)L.max_scan_tiles * 8);
     L.xs1 = off;
     off = align256(off + (size_t)L.max_scan_tiles * 8);
+    L.fs0 = off;
+    off = align256(off + (size_t)kFusedMaxTiles * 8);
+    L.fs1 = off;
+    off = align256(off + (size_t)kFusedMaxTiles * 8);
     L.ct0 = off;
     off = align256(off + (size_t)L.compact_tiles * 8);
     L.ct1 = off;
@@ -1667,18 +1714,29 @@ int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_
     a.sched = s->sched;
     a.n_tiles = n_tiles;
     a.n_scan_tiles = (n_tiles + kBlock * kScanPer - 1) / (kBlock * kScanPer);
-    // count pass, scan, then the write pass only when something is written
-    const bool write = cap > 0 && (duals ? (corner_level || verts || dvals) : (tris || tri_cells || tri_dual));
-    if (duals)
-        hipLaunchKernelGGL((k_extract<true, false>), dim3(n_tiles), dim3(kBlock), 0, stream, a);
-    else
-        hipLaunchKernelGGL((k_extract<false, false>), dim3(n_tiles), dim3(kBlock), 0, stream, a);
-    hipLaunchKernelGGL(k_tile_scan, dim3(a.n_scan_tiles), dim3(kBlock), 0, stream, a, duals ? 1 : 0);
-    if (write) {
+    if (n_tiles <= kFusedMaxTiles) {
+        // one fused pass, then clean its look-back states for the next call
+        a.sc0 = s->fs0;
+        a.sc1 = s->fs1;
         if (duals)
-            hipLaunchKernelGGL((k_extract<true, true>), dim3(n_tiles), dim3(kBlock), 0, stream, a);
+            hipLaunchKernelGGL((k_extract<true, kPassFused>), dim3(n_tiles), dim3(kBlock), 0, stream, a);
         else
-            hipLaunchKernelGGL((k_extract<false, true>), dim3(n_tiles), dim3(kBlock), 0, stream, a);
+            hipLaunchKernelGGL((k_extract<false, kPassFused>), dim3(n_tiles), dim3(kBlock), 0, stream, a);
+        hipLaunchKernelGGL(k_fused_clear, dim3(1), dim3(256), 0, stream, a);
+    } else {
+        // count pass, scan, then the write pass only when something is written
+        const bool write = cap > 0 && (duals ? (corner_level || verts || dvals) : (tris || tri_cells || tri_dual));
+        if (duals)
+            hipLaunchKernelGGL((k_extract<true, kPassCount>), dim3(n_tiles), dim3(kBlock), 0, stream, a);
+        else
+            hipLaunchKernelGGL((k_extract<false, kPassCount>), dim3(n_tiles), dim3(kBlock), 0, stream, a);
+        hipLaunchKernelGGL(k_tile_scan, dim3(a.n_scan_tiles), dim3(kBlock), 0, stream, a, duals ? 1 : 0);
+        if (write) {
+            if (duals)
+                hipLaunchKernelGGL((k_extract<true, kPassWrite>), dim3(n_tiles), dim3(kBlock), 0, stream, a);
+            else
+                hipLaunchKernelGGL((k_extract<false, kPassWrite>), dim3(n_tiles), dim3(kBlock), 0, stream, a);
+        }
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? AMR_OK : hipfail(e, "extract launch");
@@ -1864,6 +1922,8 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     s->st_d = (unsigned long long*)(base + L.st_d);
     s->xs0 = (unsigned long long*)(base + L.xs0);
     s->xs1 = (unsigned long long*)(base + L.xs1);
+    s->fs0 = (unsigned long long*)(base + L.fs0);
+    s->fs1 = (unsigned long long*)(base + L.fs1);
     s->ct0 = (unsigned long long*)(base + L.ct0);
     s->ct1 = (unsigned long long*)(base + L.ct1);
     s->sched = (Sched*)(base + L.sched);
@@ -1872,7 +1932,7 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, stream, s->ctrl);
     hipLaunchKernelGGL(k_index_init, dim3(grid_for(cap, 256)), dim3(256), 0, stream, s->rec, cap);
     hipLaunchKernelGGL(k_sched_reset, dim3(grid_for(L.compact_tiles, 256)), dim3(256), 0, stream, s->sched, s->ct0,
-                       s->ct1, L.compact_tiles);
+                       s->ct1, L.compact_tiles, s->fs0, s->fs1);
     if (s->n > 0) {
         hipLaunchKernelGGL(k_index_insert, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->val,
                            s->n, g, s->rec, s->ids, s->ctrl);

@@ -139,7 +139,7 @@ class IsoServer:
                 out = tris[:c] if c <= cap else self.resident.isosurface(r.iso, c)["tris"]
                 stream.synchronize()
                 res = results[r.rid]
-                res.start, res.done, res.triangles, res.tris = t_start, time.perf_counter(), c, out
+                res.start, res.done, res.triangles, res.tris = t_start, time.perf_counter(), c, self._keep(out)
         finally:
             self.mem.release(held)
 
@@ -167,9 +167,21 @@ class IsoServer:
                         out = self.resident.isosurface(isos[k], int(c[k]))["tris"]
                         stream.synchronize()
                     res = results[r.rid]
-                    res.start, res.done, res.triangles, res.tris = t_start, time.perf_counter(), int(c[k]), out
+                    res.start, res.done, res.triangles, res.tris = t_start, time.perf_counter(), int(c[k]), self._keep(out)
         finally:
             self.mem.release(held)
+
+    def _keep(self, out):
+        # outputs are dropped at once unless the caller keeps them, so that
+        # finished requests do not pin device memory
+        return out if self.keep_outputs else None
+
+    def _guard(self, fn, *args):
+        try:
+            fn(*args)
+        except BaseException as e:  # reported by serve() after the join
+            self.errors.append(e)
+            self.stop.set()
 
     def _batch_worker(self, q, results):
         stream = torch.cuda.Stream(self.device)
@@ -179,9 +191,15 @@ class IsoServer:
                     q["cv"].wait(0.005)
                 if not q["items"] and q["closed"]:
                     return
-                reqs = []
+                # continuous batching: take what is waiting, up to max_batch
+                # requests and a quarter of the memory budget of outputs
+                reqs, est = [], 0
                 while q["items"] and len(reqs) < self.max_batch:
+                    b = 36 * self.iso_cap(q["items"][0].iso)
+                    if reqs and est + b > self.mem.budget // 4:
+                        break
                     reqs.append(q["items"].popleft())
+                    est += b
             self._run_batch(reqs, results, stream)
 
     # -- upload requests --------------------------------------------------
@@ -202,7 +220,8 @@ class IsoServer:
                 out = s.isosurface(r.iso)["tris"]
                 stream.synchronize()
                 res = results[r.rid]
-                res.start, res.done, res.triangles, res.tris = t_start, time.perf_counter(), int(out.shape[0]), out
+                res.start, res.done, res.triangles, res.tris = (t_start, time.perf_counter(), int(out.shape[0]),
+                                                                self._keep(out))
         finally:
             self.mem.release(held)
 
@@ -229,8 +248,10 @@ class IsoServer:
         mk = lambda: {"items": collections.deque(), "cv": threading.Condition(), "closed": False}
         iso_q, up_q = mk(), mk()
         results = {}
-        workers = [threading.Thread(target=self._batch_worker, args=(iso_q, results), daemon=True)]
-        workers += [threading.Thread(target=self._upload_worker, args=(up_q, results), daemon=True)
+        self.keep_outputs = keep_outputs
+        self.errors = []
+        workers = [threading.Thread(target=self._guard, args=(self._batch_worker, iso_q, results), daemon=True)]
+        workers += [threading.Thread(target=self._guard, args=(self._upload_worker, up_q, results), daemon=True)
                     for _ in range(self.upload_slots)]
         for w in workers:
             w.start()
@@ -255,6 +276,8 @@ class IsoServer:
                 q["cv"].notify_all()
         for w in workers:
             w.join()
+        if self.errors:
+            raise RuntimeError("a serving worker failed") from self.errors[0]
         out = [results[i] for i in range(len(trace))]
         if not keep_outputs:
             for r in out:

@@ -80,6 +80,9 @@ CASES = {
                                                         values="random", origin=(0, 0, 0)),
     "grid-33-level1": lambda: amrgen.uniform_grid(33, 1, 3, origin=(-40, 10, 6)),
     "grid-17-level0": lambda: amrgen.uniform_grid(17, 0, 4, origin=(5, -3, 100)),
+    # 92,118 groups = 2,879 tiles: past the fused single-pass limit (2,048
+    # tiles), so this one runs the count / scan / write passes
+    "octree-sized-647k": lambda: amrgen.octree_sized(800_000, seed=9),
 }
 
 
