@@ -279,6 +279,142 @@ def batched_multiset_measurement(amr, n_sets=32, seed=4):
             "triangles": int(c.sum()), "autotuned_shape": {"block": block, "per_thread": per}, "autotune_ms": table}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_extract_traffic.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2004_08475_amd", "csrc", "amriso.hip")
+
+
+def traffic_for(workload):
+    """HBM bytes per amr_isosurface call from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when
+    there is none for this workload or the kernel source changed since."""
+    import hashlib
+
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = [ln.split() for ln in lines if ln and not ln.startswith("#")]
+    recorded = [f[1] for f in fields if f[0] == "source_sha256"]
+    if not recorded or recorded[0] != src:
+        return None
+    for f in fields:
+        if f[0] == "workload" and f[1] == workload:
+            kv = dict(zip(f[2::2], f[3::2]))
+            return float(kv["traffic_bytes"])
+    return None
+
+
+def time_steps(amr, s, xyz, lvl, val, iso, cap, tris, steps, warmup):
+    """Whole-path steps (upload + build + iso) with HIP events per stage on
+    the current stream; returns (ms per step by host clock, stage lists)."""
+    import torch
+
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev:
+            ev[0].record(stream)
+        s.upload(xyz, lvl, val)
+        if ev:
+            ev[1].record(stream)
+        s.build_index()
+        if ev:
+            ev[2].record(stream)
+        s.isosurface_into(iso, tris, cap)
+        if ev:
+            ev[3].record(stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    st = ([e[0].elapsed_time(e[1]) for e in evs], [e[1].elapsed_time(e[2]) for e in evs],
+          [e[2].elapsed_time(e[3]) for e in evs])
+    return ms, st
+
+
+def roofline_of(n_cells, n_tri, iso_ms, traffic):
+    alg = 20.0 * n_cells + 36.0 * n_tri
+    achieved = alg / (iso_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": "k_extract passes of one amr_isosurface call", "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "algorithmic_bytes": alg, "avg_launch_ms": iso_ms}
+
+
+def large_measurement(amr, name, steps):
+    """The same whole-path step on a large set (block-structured, 50.8M
+    cells), where throughput rather than launch latency decides."""
+    import torch
+
+    cs = make_workload(name)
+    dev = torch.device("cuda", 0)
+    xyz, lvl, val = (torch.from_numpy(a).to(dev) for a in (cs.xyz, cs.level, cs.value))
+    s = amr.AmrSet(0)
+    s.upload(xyz, lvl, val)
+    s.build_index()
+    n_tri, n_dual = s.count(cs.iso)
+    tris = torch.empty((max(n_tri, 1), 9), dtype=torch.float32, device=dev)
+    ms, (up, bd, iso) = time_steps(amr, s, xyz, lvl, val, cs.iso, n_tri, tris, steps, 2)
+    assert int(s.counts[0].item()) == n_tri
+    iso_avg = statistics.mean(iso)
+    out = {"workload": name, "cells": cs.n, "triangles": n_tri, "duals": n_dual, "steps": steps,
+           "ms_per_step": ms, "cells_per_s": cs.n / (ms * 1e-3),
+           "stages_ms": {"upload": statistics.mean(up), "build_index": statistics.mean(bd), "isosurface": iso_avg},
+           "iso_only_cells_per_s": cs.n / (iso_avg * 1e-3),
+           "roofline": roofline_of(cs.n, n_tri, iso_avg, traffic_for(name))}
+    del s, xyz, lvl, val, tris
+    torch.cuda.empty_cache()
+    return out
+
+
+def pipeline_measurement(amr, cs, reps=5):
+    """The whole pipeline from host memory and back (the paper's Y column,
+    its sec. 5.2 figure): pinned host cells -> device, validate, index, count
+    and write the triangles, weld them into an indexed mesh, copy vertices
+    and indices back.  PCIe-inclusive, so it is reported beside `value`."""
+    import torch
+
+    dev = torch.device("cuda", 0)
+    hx = torch.from_numpy(cs.xyz).pin_memory()
+    hl = torch.from_numpy(cs.level).pin_memory()
+    hv = torch.from_numpy(cs.value).pin_memory()
+    s = amr.AmrSet(0)
+    times, parts = [], []
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, l, v = hx.to(dev, non_blocking=True), hl.to(dev, non_blocking=True), hv.to(dev, non_blocking=True)
+        s.upload(x, l, v)
+        t1 = time.perf_counter()
+        s.build_index()
+        t2 = time.perf_counter()
+        out = s.isosurface(cs.iso, cells=True)
+        t3 = time.perf_counter()
+        verts, idx = amr.indexed_mesh(out["tris"], out["cells"])
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        hv_out, hi_out = verts.cpu(), idx.cpu()
+        t5 = time.perf_counter()
+        if r:
+            times.append(t5 - t0)
+            parts.append((t1 - t0, t2 - t1, t3 - t2, t4 - t3, t5 - t4))
+    k = sorted(range(reps), key=lambda i: times[i])[reps // 2]
+    p = parts[k]
+    return {"what": "host cells -> device -> amr_upload -> amr_build_index -> amr_isosurface (count + write) -> "
+                    "amr_indexed_mesh -> vertices and indices to host; median of %d, host clock" % reps,
+            "ms": times[k] * 1e3, "cells_per_s": cs.n / times[k],
+            "stages_ms": {"h2d+upload": p[0] * 1e3, "build_index": p[1] * 1e3, "isosurface": p[2] * 1e3,
+                          "indexed_mesh": p[3] * 1e3, "d2h": p[4] * 1e3},
+            "triangles": int(hi_out.shape[0]), "vertices": int(hv_out.shape[0])}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -294,6 +430,10 @@ def main():
                     help="resident set of the serving run: the bench workload, or the ~600M-cell octree")
     ap.add_argument("--serve-serial-requests", type=int, default=0,
                     help="replay only this many requests through the serial baseline (0 = all)")
+    ap.add_argument("--large", default="block-vortex-1024",
+                    help="also time the step on this large workload ('none' to skip)")
+    ap.add_argument("--no-pipeline", action="store_true",
+                    help="skip the host-to-host pipeline timing (transfers, weld, download)")
     ap.add_argument("--batch-sets", type=int, default=0,
                     help="also fuse this many independent octree sets (10k..5M cells) into one launch")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -323,38 +463,8 @@ def main():
     n_tri, n_dual = s.count(cs.iso)
     cap = n_tri
     tris = torch.empty((max(cap, 1), 9), dtype=torch.float32, device=dev)
-    stream = torch.cuda.current_stream(dev)
-
-    def step(ev=None):
-        if ev:
-            ev[0].record(stream)
-        s.upload(xyz, lvl, val)
-        if ev:
-            ev[1].record(stream)
-        s.build_index()
-        if ev:
-            ev[2].record(stream)
-        s.isosurface_into(cs.iso, tris, cap)
-        if ev:
-            ev[3].record(stream)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    got = int(s.counts[0].item())
-    assert got == n_tri, (got, n_tri)
-
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(evs[k])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    up_ms = [e[0].elapsed_time(e[1]) for e in evs]
-    bd_ms = [e[1].elapsed_time(e[2]) for e in evs]
-    iso_ms = [e[2].elapsed_time(e[3]) for e in evs]
+    ms_per_step, (up_ms, bd_ms, iso_ms) = time_steps(amr, s, xyz, lvl, val, cs.iso, cap, tris, args.steps,
+                                                      args.warmup)
     assert int(s.counts[0].item()) == n_tri
 
     # iso requests on the resident set: count pass + write pass, host clock
@@ -379,8 +489,6 @@ def main():
         torch.cuda.synchronize()
 
     iso_avg = statistics.mean(iso_ms)
-    alg_bytes = 20.0 * cs.n + 36.0 * n_tri
-    achieved = alg_bytes / (iso_avg * 1e-3) / 1e9
     out = {
         "metric": METRIC,
         "value": cs.n / (ms_per_step * 1e-3),
@@ -402,11 +510,15 @@ def main():
         "iso_only_cells_per_s": cs.n / (iso_avg * 1e-3),
         "iso_latency_ms": {"p50": percentile(lat, 0.5), "p99": percentile(lat, 0.99), "requests": len(lat),
                            "what": "count pass + write pass on the resident set, host clock"},
-        "roofline": {"bound": "hbm", "kernel": "k_extract (amr_isosurface)", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic_bytes": alg_bytes, "avg_launch_ms": iso_avg},
+        "roofline": roofline_of(cs.n, n_tri, iso_avg, traffic_for(cs.name)),
     }
     say("timed steps done: %.3f ms/step" % ms_per_step)
+    if args.large != "none":
+        out["large_workload"] = large_measurement(amr, args.large, 10)
+        say("large workload %s: %.3f ms/step" % (args.large, out["large_workload"]["ms_per_step"]))
+    if not args.no_pipeline:
+        out["pipeline_pcie_inclusive"] = pipeline_measurement(amr, cs)
+        say("pipeline with host transfers: %.3f ms" % out["pipeline_pcie_inclusive"]["ms"])
     if args.batch_isos:
         out["batched"] = batched_measurement(amr, s, cs, args.batch_isos)
         say("batched: fused %.3f ms, plain %.3f ms" % (out["batched"]["fused_ms"],

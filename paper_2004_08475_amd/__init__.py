@@ -107,6 +107,7 @@ class AmrSet:
         self.counts = torch.zeros(2, dtype=torch.int64, device=self.device)
         self._cells = None
         self.workspace = None
+        self._ws_keep = None  # index workspace kept across uploads for reuse
         self.n = 0
 
     def close(self):
@@ -146,15 +147,20 @@ class AmrSet:
         """Allocate the index workspace (torch) and build the index; grows the
         workspace when the hash table turns out too small."""
         for _ in range(max_attempts):
-            nbytes = self.index_bytes()
-            if self.workspace is None or self.workspace.numel() < nbytes:
-                self.workspace = None
-                self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            if self._ws_keep is not None and self.workspace is None:
+                # a workspace from an earlier upload: the library says if it is short
+                self.workspace = self._ws_keep
+            if self.workspace is None:
+                self.workspace = torch.empty(self.index_bytes(), dtype=torch.uint8, device=self.device)
             code = self.lib.amr_build_index(self._h, _ptr(self.workspace), self.workspace.numel(),
                                             _stream(self.device))
             if code == AMR_ENOSPACE:
+                nbytes = self.index_bytes()
+                self.workspace = self._ws_keep = None
+                self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
                 continue
             _check(code)
+            self._ws_keep = self.workspace
             return self
         raise AmrError(AMR_ENOSPACE, "index workspace kept overflowing")
 

@@ -63,6 +63,7 @@ constexpr uint32_t kMaxProbe = 1024;    // longer chains mean the table is too f
 constexpr int kCompactMaxPerThread = 16;
 constexpr int kReplicas = 64;           // spread of the upload reduction atomics
 constexpr uint32_t kFusedMaxTiles = 2048;  // sets up to this many tiles extract in one fused pass
+constexpr uint32_t kXcds = 8;              // accelerator complex dies of an MI355X
 constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
 
 enum : uint32_t { kErrLevel = 1, kErrAlign = 2, kErrValue = 4, kErrCoord = 8 };
@@ -111,22 +112,30 @@ __device__ __forceinline__ uint64_t group_key(int m, uint32_t gx, uint32_t gy, u
     return ((uint64_t)m << 57) | ((uint64_t)gz << 38) | ((uint64_t)gy << 19) | (uint64_t)gx;
 }
 
-// Home slot of a group.  The table is cut into buckets of 64 slots, one per
-// brick of 4x4x4 groups of one level: the brick's key is hashed (Fibonacci)
-// to a bucket and the group's position inside the brick picks the slot, its
-// 6 bits XORed with 6 more bits of the brick hash so that sparse patterns
-// still spread over all 64 positions.  Spatial neighbours therefore share a
-// 4 KB bucket, and a collision moves on to the same position of the next
-// bucket (probe stride 64).
-constexpr uint32_t kBucket = 64;
+// Home slot of a group.  The table is cut into regions of 4096 slots, one
+// per block of 16x16x16 groups of one level: the block's key is hashed
+// (Fibonacci) to a region and the group's position inside it, as a 12-bit
+// Morton code, picks the slot, XORed with 12 more bits of the block hash so
+// that sparse patterns still spread over all positions.  XOR with a constant
+// keeps every aligned run of 2^k Morton codes together, so 32 consecutive
+// slots hold a 4x4x2 block of groups and consecutive runs are neighbours in
+// space.  A collision moves on to the same position of the next region
+// (probe stride 4096).
+constexpr uint32_t kRegion = 4096;
 
-__device__ __forceinline__ uint32_t slot_of(uint64_t key, int shift) {
-    const uint64_t brick = key & ~((3ull << 38) | (3ull << 19) | 3ull);
-    const uint32_t local = (uint32_t)((key & 3) | (((key >> 19) & 3) << 2) | (((key >> 38) & 3) << 4));
-    return (uint32_t)((brick * kGolden) >> shift) ^ local;
+__device__ __forceinline__ uint32_t spread4(uint32_t v) {
+    // bits 0..3 of v to bits 0, 3, 6, 9
+    return (v & 1u) | ((v & 2u) << 2) | ((v & 4u) << 4) | ((v & 8u) << 6);
 }
 
-__device__ __forceinline__ uint32_t next_slot(uint32_t h, uint32_t mask) { return (h + kBucket) & mask; }
+__device__ __forceinline__ uint32_t slot_of(uint64_t key, int shift) {
+    const uint64_t region = key & ~((15ull << 38) | (15ull << 19) | 15ull);
+    const uint32_t local = spread4((uint32_t)key & 15u) | (spread4((uint32_t)(key >> 19) & 15u) << 1) |
+                           (spread4((uint32_t)(key >> 38) & 15u) << 2);
+    return (uint32_t)((region * kGolden) >> shift) ^ local;
+}
+
+__device__ __forceinline__ uint32_t next_slot(uint32_t h, uint32_t mask) { return (h + kRegion) & mask; }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
@@ -386,14 +395,39 @@ struct Geo {
     uint32_t mask;       // cap - 1
 };
 
-__global__ __launch_bounds__(256) void k_index_init(Record* __restrict__ rec, uint32_t cap) {
+// Start of a build: empty records, clean scan states, zero build results.
+__global__ __launch_bounds__(256) void k_build_reset(Record* __restrict__ rec, uint32_t cap, Sched* sc,
+                                                     unsigned long long* ct0, unsigned long long* ct1, uint32_t nc,
+                                                     unsigned long long* fs0, unsigned long long* fs1, Ctrl* c) {
     const float e = __uint_as_float(kValEmpty);
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += gridDim.x * blockDim.x) {
+    const uint32_t i0 = blockIdx.x * blockDim.x + threadIdx.x, step = gridDim.x * blockDim.x;
+    for (uint32_t i = i0; i < cap; i += step) {
         Record r;
-        for (int c = 0; c < 8; ++c) r.val[c] = e;
+        for (int k = 0; k < 8; ++k) r.val[k] = e;
         r.key = kEmpty;
-        for (int c = 0; c < 6; ++c) r.pad[c] = 0;
+        for (int k = 0; k < 6; ++k) r.pad[k] = 0;
         rec[i] = r;
+    }
+    for (uint32_t i = i0; i < nc; i += step) {
+        ct0[i] = 0;
+        ct1[i] = 0;
+    }
+    for (uint32_t i = i0; i < kFusedMaxTiles; i += step) {
+        fs0[i] = 0;
+        fs1[i] = 0;
+    }
+    if (i0 == 0) {
+        sc->xticket = 0;
+        sc->pad0 = 0;
+        sc->cticket = 0;
+        sc->pad = 0;
+        c->overflow = 0;
+        c->dup = 0;
+        c->overlap = 0;
+        c->bad_build = ~0ull;
+        c->n_groups = 0;
+        c->n_records = 0;
+        c->n_leaves = 0;
     }
 }
 
@@ -414,12 +448,13 @@ __device__ __forceinline__ int find_or_insert(Record* __restrict__ rec, uint64_t
     return -1;
 }
 
-// Every cell stores its value and input index in its group record (plain
-// stores: a duplicate cell overwrites its twin and shows up later as a
-// missing leaf in the count of the compaction).
+// Every cell stores its value in its group record (a plain store: a
+// duplicate cell overwrites its twin and shows up later as a missing leaf in
+// the count of the compaction).  Input indices are filled in later, and only
+// when an output asks for them (k_index_ids).
 __global__ __launch_bounds__(256) void k_index_insert(const int32_t* __restrict__ xyz, const int32_t* __restrict__ lvl,
                                                       const float* __restrict__ val, int64_t n, Geo g,
-                                                      Record* __restrict__ rec, int32_t* __restrict__ ids, Ctrl* c) {
+                                                      Record* __restrict__ rec, Ctrl* c) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         int m = lvl[i];
         uint32_t ux = (uint32_t)(xyz[3 * i] - g.ox), uy = (uint32_t)(xyz[3 * i + 1] - g.oy),
@@ -431,6 +466,20 @@ __global__ __launch_bounds__(256) void k_index_insert(const int32_t* __restrict_
         }
         int child = ((ux >> m) & 1) | (((uy >> m) & 1) << 1) | (((uz >> m) & 1) << 2);
         rec[slot].val[child] = val[i];
+    }
+}
+
+// The input index of every cell, beside its value (slot * 8 + child).
+__global__ __launch_bounds__(256) void k_index_ids(const int32_t* __restrict__ xyz, const int32_t* __restrict__ lvl,
+                                                   int64_t n, Geo g, const Record* __restrict__ rec,
+                                                   int32_t* __restrict__ ids) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int m = lvl[i];
+        uint32_t ux = (uint32_t)(xyz[3 * i] - g.ox), uy = (uint32_t)(xyz[3 * i + 1] - g.oy),
+                 uz = (uint32_t)(xyz[3 * i + 2] - g.oz);
+        int slot = probe(rec, group_key(m, ux >> (m + 1), uy >> (m + 1), uz >> (m + 1)), g.shift, g.mask);
+        if (slot < 0) continue;
+        int child = ((ux >> m) & 1) | (((uy >> m) & 1) << 1) | (((uz >> m) & 1) << 2);
         ids[(size_t)slot * 8 + child] = (int32_t)i;
     }
 }
@@ -439,8 +488,7 @@ __global__ __launch_bounds__(256) void k_index_insert(const int32_t* __restrict_
 // level, until it meets a mark set by another group.  All leaves are stored
 // before this pass, so a mark that lands on a leaf is a coarser cell
 // containing finer ones.
-__global__ __launch_bounds__(256) void k_index_mark(Record* __restrict__ rec, const int32_t* __restrict__ ids,
-                                                    uint32_t cap, Geo g, Ctrl* c) {
+__global__ __launch_bounds__(256) void k_index_mark(Record* __restrict__ rec, uint32_t cap, Geo g, Ctrl* c) {
     for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
         const uint64_t key = rec[s].key;
         if (key == kEmpty) continue;
@@ -463,12 +511,19 @@ __global__ __launch_bounds__(256) void k_index_mark(Record* __restrict__ rec, co
                 break;
             }
             const int c2 = (cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2);
-            const uint32_t prev =
-                atomicCAS(reinterpret_cast<unsigned int*>(&rec[s2].val[c2]), kValEmpty, kValRefined);
+            unsigned int* slot_val = reinterpret_cast<unsigned int*>(&rec[s2].val[c2]);
+            // a mark already seen needs no atomic (a stale read only costs one)
+            uint32_t prev = *slot_val;
+            if (prev == kValEmpty) {
+                // the first level up is this group's own block: finer groups
+                // inside it may mark it too, but only with the same value
+                if (L == m + 1) *slot_val = kValRefined;
+                else prev = atomicCAS(slot_val, kValEmpty, kValRefined);
+            }
             if (prev == kValEmpty) continue;  // marked here: carry on upwards
             if (prev != kValRefined) {        // a coarser cell contains this group
                 atomicOr(&c->overlap, 1u);
-                atomicMin(&c->bad_build, (unsigned long long)(uint32_t)ids[(size_t)s2 * 8 + c2]);
+                atomicMin(&c->bad_build, (unsigned long long)s2 * 8 + c2);  // its slot * 8 + child
             }
             break;
         }
@@ -594,24 +649,6 @@ struct ExtractArgs {
     uint32_t n_scan_tiles;
 };
 
-__global__ void k_sched_reset(Sched* sc, unsigned long long* ct0, unsigned long long* ct1, uint32_t nc,
-                              unsigned long long* fs0, unsigned long long* fs1) {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += gridDim.x * blockDim.x) {
-        ct0[i] = 0;
-        ct1[i] = 0;
-    }
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < kFusedMaxTiles; i += gridDim.x * blockDim.x) {
-        fs0[i] = 0;
-        fs1[i] = 0;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        sc->xticket = 0;
-        sc->pad0 = 0;
-        sc->cticket = 0;
-        sc->pad = 0;
-    }
-}
-
 __global__ void k_counts_zero(int64_t* counts) {
     if (threadIdx.x == 0 && counts) {
         counts[0] = 0;
@@ -627,6 +664,66 @@ __host__ __device__ constexpr int edge_lo(int e) {
     return (((e & 3) >> (e >> 2)) << ((e >> 2) + 1)) | ((e & 3) & ((1 << (e >> 2)) - 1));
 }
 __host__ __device__ constexpr int edge_hi(int e) { return edge_lo(e) | (1 << (e >> 2)); }
+
+// The 27 corners of a group's 2x2x2 block, k = kx + 3 ky + 9 kz with
+// kx, ky, kz in {0, 1, 2}, in the order the eight lanes of a group take them:
+// first the 8 corners whose slot 0 lies inside the group (kx, ky, kz >= 1:
+// the ones the group usually owns), then the other 19 in increasing order,
+// which a dense neighbourhood settles after one look at slot 0.  That keeps
+// whole waves on the same side of that early exit.
+struct CornerOrder {
+    unsigned long long lo = 0, hi = 0;  // 5 bits per corner, 12 + 7 corners
+    constexpr CornerOrder() {
+        int r = 0;
+        for (int k = 0; k < 27; ++k) {
+            const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
+            if (kx >= 1 && ky >= 1 && kz >= 1) continue;
+            if (r < 12) lo |= (unsigned long long)k << (5 * r);
+            else hi |= (unsigned long long)k << (5 * (r - 12));
+            ++r;
+        }
+    }
+};
+constexpr CornerOrder kCornerOrder{};
+
+__device__ __forceinline__ int corner_of(int idx) {
+    if (idx < 8) return 13 + (idx & 1) + 3 * ((idx >> 1) & 1) + 9 * (idx >> 2);
+    const int r = idx - 8;
+    return r < 12 ? (int)((kCornerOrder.lo >> (5 * r)) & 31) : (int)((kCornerOrder.hi >> (5 * (r - 12))) & 31);
+}
+
+// Degenerate duals: a cell may sit at several slots.  A triangle is kept when
+// its three vertices join three different (unordered) cell pairs.  Each slot
+// gets the lowest slot holding the same cell as its class (3 bits per slot);
+// a vertex is the unordered class pair of its edge.
+__device__ __forceinline__ uint32_t slot_classes(const int (&refs)[8]) {
+    uint32_t cls = 0;
+#pragma unroll
+    for (int s1 = 1; s1 < 8; ++s1) {
+        int c = s1;
+#pragma unroll
+        for (int s0 = s1 - 1; s0 >= 0; --s0)
+            if (refs[s0] == refs[s1]) c = s0;
+        cls |= (uint32_t)c << (3 * s1);
+    }
+    return cls;
+}
+
+// Keep mask of the nt triangles in e (three 4-bit edges per 12 bits).
+__device__ __forceinline__ uint32_t keep_by_classes(uint32_t cls, unsigned long long e, int nt) {
+    uint32_t keep = 0;
+    for (int tt = 0; tt < nt; ++tt) {
+        uint32_t pr[3];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            const int ed = (int)((e >> (12 * tt + 4 * v)) & 0xF);
+            const uint32_t a = (cls >> (3 * edge_lo(ed))) & 7u, b = (cls >> (3 * edge_hi(ed))) & 7u;
+            pr[v] = a < b ? (a << 3) | b : (b << 3) | a;
+        }
+        if (pr[0] != pr[1] && pr[1] != pr[2] && pr[0] != pr[2]) keep |= 1u << tt;
+    }
+    return keep;
+}
 
 
 // Extraction of a large set runs as three launches: a count pass (phases
@@ -663,7 +760,12 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
         if (threadIdx.x == 0) s_tile = (uint32_t)atomicAdd(&a.sched->xticket, 1ull);
         __syncthreads();
     }
-    const uint32_t tile = kPass == kPassFused ? s_tile : blockIdx.x;
+    // count and write passes: work-groups go round-robin to the 8 XCDs, so
+    // XCD x is given the contiguous run of tiles [x*T, (x+1)*T) in order and
+    // its L2 sees neighbouring tiles one after another
+    const uint32_t per_xcd = gridDim.x / kXcds;
+    const uint32_t tile = kPass == kPassFused ? s_tile : (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+    if (kPass != kPassFused && tile >= a.n_tiles) return;
     if (kPass == kPassWrite) {
         // nothing of this tile lands below the capacity: done
         const unsigned long long tt = a.tot[tile];
@@ -787,9 +889,14 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         items[q] = 0;
-        int k = j + 8 * q;
-        if (!valid || k >= 27) continue;
+        const int idx = j + 8 * q;
+        if (!valid || idx >= 27) continue;
+        const int k = corner_of(idx);
         int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
+        // Slot 0 decides most corners: a level-m cell there outside this
+        // group is the lowest same-level slot, so the dual belongs to another
+        // group (or is rejected by rule 2 when that cell is refined)
+        if ((kx == 0 || ky == 0 || kz == 0) && s_l[gi][kx + 4 * ky + 16 * kz] == m) continue;
         int refs[8];
         float vals[8];
         bool ok = true;
@@ -819,29 +926,11 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
             unsigned long long e = s_tab[cs];
             int nt = (int)(e >> 60);
             if (nt) {
-                // dup[e]: the lowest edge joining the same two cells as edge e
-                uint64_t dup = 0;
-#pragma unroll
-                for (int e1 = 0; e1 < 12; ++e1) {
-                    int a0 = refs[edge_lo(e1)], a1 = refs[edge_hi(e1)];
-                    int d = e1;
-#pragma unroll
-                    for (int e0 = e1 - 1; e0 >= 0; --e0) {
-                        int b0 = refs[edge_lo(e0)], b1 = refs[edge_hi(e0)];
-                        if ((a0 == b0 && a1 == b1) || (a0 == b1 && a1 == b0)) d = e0;
-                    }
-                    dup |= (uint64_t)d << (4 * e1);
-                }
-                for (int tt = 0; tt < nt; ++tt) {
-                    int ea = (int)((e >> (12 * tt)) & 0xF), eb = (int)((e >> (12 * tt + 4)) & 0xF),
-                        ec = (int)((e >> (12 * tt + 8)) & 0xF);
-                    int da = (int)((dup >> (4 * ea)) & 0xF), db = (int)((dup >> (4 * eb)) & 0xF),
-                        dc = (int)((dup >> (4 * ec)) & 0xF);
-                    if (da != db && db != dc && da != dc) {
-                        keep |= 1u << tt;
-                        ++n_tri;
-                    }
-                }
+                keep = (1u << nt) - 1u;
+                // eight level-m slots are eight different cells: nothing to drop;
+                // otherwise drop triangles whose vertices repeat a cell pair
+                if (same != 0xFFu) keep = keep_by_classes(slot_classes(refs), e, nt);
+                n_tri += __popc(keep);
             }
         }
         items[q] = 0x80000000u | ((uint32_t)k << 20) | (cs << 8) | keep;
@@ -1169,30 +1258,15 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s_w, u
     return pre + (uint32_t)incl - x;
 }
 
-// Triangles of one dual for one iso: case and keep mask (degenerate ones dropped).
+// Triangles of one dual for one iso: case and keep mask (degenerate ones
+// dropped).  The slot classes depend only on the dual, so they are worked
+// out once and reused by every job.
 struct DualMc {
     int32_t id[8];
     float v[8];
-    uint64_t dup;
-    bool dup_ready;
+    uint32_t cls;
+    bool cls_ready;
 };
-
-__device__ __forceinline__ void dual_dup(DualMc& d) {
-    uint64_t dup = 0;
-#pragma unroll
-    for (int e1 = 0; e1 < 12; ++e1) {
-        int a0 = d.id[edge_lo(e1)], a1 = d.id[edge_hi(e1)];
-        int dd = e1;
-#pragma unroll
-        for (int e0 = e1 - 1; e0 >= 0; --e0) {
-            int b0 = d.id[edge_lo(e0)], b1 = d.id[edge_hi(e0)];
-            if ((a0 == b0 && a1 == b1) || (a0 == b1 && a1 == b0)) dd = e0;
-        }
-        dup |= (uint64_t)dd << (4 * e1);
-    }
-    d.dup = dup;
-    d.dup_ready = true;
-}
 
 __device__ __forceinline__ uint32_t dual_case(const DualMc& d, float iso) {
     uint32_t cs = 0;
@@ -1204,16 +1278,11 @@ __device__ __forceinline__ uint32_t dual_case(const DualMc& d, float iso) {
 __device__ __forceinline__ uint32_t dual_keep(DualMc& d, unsigned long long e) {
     int nt = (int)(e >> 60);
     if (!nt) return 0;
-    if (!d.dup_ready) dual_dup(d);
-    uint32_t keep = 0;
-    for (int tt = 0; tt < nt; ++tt) {
-        int ea = (int)((e >> (12 * tt)) & 0xF), eb = (int)((e >> (12 * tt + 4)) & 0xF),
-            ec = (int)((e >> (12 * tt + 8)) & 0xF);
-        int da = (int)((d.dup >> (4 * ea)) & 0xF), db = (int)((d.dup >> (4 * eb)) & 0xF),
-            dc = (int)((d.dup >> (4 * ec)) & 0xF);
-        if (da != db && db != dc && da != dc) keep |= 1u << tt;
+    if (!d.cls_ready) {
+        d.cls = slot_classes(d.id);
+        d.cls_ready = true;
     }
-    return keep;
+    return keep_by_classes(d.cls, e, nt);
 }
 
 template <int PER>
@@ -1258,7 +1327,7 @@ __global__ __launch_bounds__(512) void k_batch(BatchArgs a) {
         for (int p = 0; p < PER; ++p) {
             int64_t di = lt * TS + (int64_t)p * blockDim.x + t;
             live[p] = di < S.n_duals;
-            d[p].dup_ready = false;
+            d[p].cls_ready = false;
             if (!live[p]) continue;
             const int4* vv = reinterpret_cast<const int4*>(S.verts + 8 * di);
             int4 lo = vv[0], hi = vv[1];
@@ -1593,6 +1662,7 @@ struct amr_set {
     uint32_t n_groups = 0;
     Record* rec = nullptr;
     int32_t* ids = nullptr;
+    bool ids_ready = false;  // input indices filled in (on first use)
     int32_t* glist = nullptr;
     unsigned long long* tot = nullptr;   // extraction: per-tile totals
     unsigned long long* st_t = nullptr;  // extraction: per-tile prefixes
@@ -1610,7 +1680,7 @@ namespace {
 
 uint32_t table_cap(const amr_set* s) {
     uint64_t want = s->record_hint * 2;
-    if (want < 1024) want = 1024;
+    if (want < kRegion) want = kRegion;  // slot_of needs at least one whole region
     uint64_t cap = 1;
     while (cap < want) cap <<= 1;
     return cap > kMaxCap ? 0 : (uint32_t)cap;
@@ -1685,6 +1755,14 @@ int grid_for(int64_t n, int block) {
 int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_cells, int32_t* tri_dual,
                    int32_t* corner_level, int32_t* verts, float* dvals, int64_t cap, int64_t* counts,
                    hipStream_t stream) {
+    if ((duals ? verts != nullptr : tri_cells != nullptr) && cap > 0 && !s->ids_ready && s->n > 0) {
+        // outputs name input indices: fill them in once per build
+        hipLaunchKernelGGL(k_index_ids, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->n,
+                           geo_of(s), s->rec, s->ids);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hipfail(e, "extract: cell index map");
+        s->ids_ready = true;
+    }
     uint32_t n_tiles = (s->n_groups + kGroupsPerTile - 1) / kGroupsPerTile;
     if (n_tiles == 0) {
         hipLaunchKernelGGL(k_counts_zero, dim3(1), dim3(64), 0, stream, counts);
@@ -1724,18 +1802,20 @@ int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_
             hipLaunchKernelGGL((k_extract<false, kPassFused>), dim3(n_tiles), dim3(kBlock), 0, stream, a);
         hipLaunchKernelGGL(k_fused_clear, dim3(1), dim3(256), 0, stream, a);
     } else {
-        // count pass, scan, then the write pass only when something is written
+        // count pass, scan, then the write pass only when something is written;
+        // the grid is a multiple of the XCD count (see the tile mapping)
         const bool write = cap > 0 && (duals ? (corner_level || verts || dvals) : (tris || tri_cells || tri_dual));
+        const uint32_t grid = ((n_tiles + kXcds - 1) / kXcds) * kXcds;
         if (duals)
-            hipLaunchKernelGGL((k_extract<true, kPassCount>), dim3(n_tiles), dim3(kBlock), 0, stream, a);
+            hipLaunchKernelGGL((k_extract<true, kPassCount>), dim3(grid), dim3(kBlock), 0, stream, a);
         else
-            hipLaunchKernelGGL((k_extract<false, kPassCount>), dim3(n_tiles), dim3(kBlock), 0, stream, a);
+            hipLaunchKernelGGL((k_extract<false, kPassCount>), dim3(grid), dim3(kBlock), 0, stream, a);
         hipLaunchKernelGGL(k_tile_scan, dim3(a.n_scan_tiles), dim3(kBlock), 0, stream, a, duals ? 1 : 0);
         if (write) {
             if (duals)
-                hipLaunchKernelGGL((k_extract<true, kPassWrite>), dim3(n_tiles), dim3(kBlock), 0, stream, a);
+                hipLaunchKernelGGL((k_extract<true, kPassWrite>), dim3(grid), dim3(kBlock), 0, stream, a);
             else
-                hipLaunchKernelGGL((k_extract<false, kPassWrite>), dim3(n_tiles), dim3(kBlock), 0, stream, a);
+                hipLaunchKernelGGL((k_extract<false, kPassWrite>), dim3(grid), dim3(kBlock), 0, stream, a);
         }
     }
     hipError_t e = hipGetLastError();
@@ -1929,15 +2009,16 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     s->sched = (Sched*)(base + L.sched);
     s->n_groups = 0;
     Geo g = geo_of(s);
-    hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, stream, s->ctrl);
-    hipLaunchKernelGGL(k_index_init, dim3(grid_for(cap, 256)), dim3(256), 0, stream, s->rec, cap);
-    hipLaunchKernelGGL(k_sched_reset, dim3(grid_for(L.compact_tiles, 256)), dim3(256), 0, stream, s->sched, s->ct0,
-                       s->ct1, L.compact_tiles, s->fs0, s->fs1);
+    {
+        uint32_t work = cap > L.compact_tiles ? cap : L.compact_tiles;
+        if (work < kFusedMaxTiles) work = kFusedMaxTiles;
+        hipLaunchKernelGGL(k_build_reset, dim3(grid_for(work, 256)), dim3(256), 0, stream, s->rec, cap, s->sched,
+                           s->ct0, s->ct1, L.compact_tiles, s->fs0, s->fs1, s->ctrl);
+    }
     if (s->n > 0) {
         hipLaunchKernelGGL(k_index_insert, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->val,
-                           s->n, g, s->rec, s->ids, s->ctrl);
-        hipLaunchKernelGGL(k_index_mark, dim3(grid_for(cap, 256)), dim3(256), 0, stream, s->rec, s->ids, cap, g,
-                           s->ctrl);
+                           s->n, g, s->rec, s->ctrl);
+        hipLaunchKernelGGL(k_index_mark, dim3(grid_for(cap, 256)), dim3(256), 0, stream, s->rec, cap, g, s->ctrl);
     }
     hipLaunchKernelGGL(k_index_compact, dim3(L.compact_tiles), dim3(kBlock), 0, stream, s->rec, cap, s->glist,
                        s->ct0, s->ct1, s->sched, L.compact_tiles, L.compact_per, s->ctrl);
@@ -1956,10 +2037,22 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
         return fail(AMR_ENOSPACE, "amr_build_index: hash table too small (%u slots); query amr_index_bytes again",
                     cap);
     }
-    if (c.overlap) return fail(AMR_EOVERLAP, "amr_build_index: cell %llu contains finer cells", c.bad_build);
+    if (c.overlap) {
+        // bad_build holds slot * 8 + child of the coarse cell: name its input index
+        const unsigned long long ref = c.bad_build;
+        int32_t id = -1;
+        hipLaunchKernelGGL(k_index_ids, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->n, g,
+                           s->rec, s->ids);
+        e = hipMemcpyAsync(&id, s->ids + ref, sizeof(id), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hipfail(e, "amr_build_index: overlap report");
+        return fail(AMR_EOVERLAP, "amr_build_index: cell %d contains finer cells", (int)id);
+    }
     if (c.n_leaves != (unsigned long long)s->n) {
         // some cell was stored twice: find the lowest overwritten index
         hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, stream, s->ctrl);
+        hipLaunchKernelGGL(k_index_ids, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->n, g,
+                           s->rec, s->ids);
         hipLaunchKernelGGL(k_index_find_dup, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->n,
                            g, s->rec, s->ids, s->ctrl);
         e = hipMemcpyAsync((char*)s->host_ctrl + tail, (char*)s->ctrl + tail, sizeof(Ctrl) - tail,
@@ -1970,6 +2063,7 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     }
     s->n_groups = (uint32_t)c.n_groups;
     s->built = true;
+    s->ids_ready = false;
     g_err[0] = 0;
     return AMR_OK;
 }
