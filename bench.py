@@ -306,8 +306,11 @@ def traffic_for(workload):
 
 
 def time_steps(amr, s, xyz, lvl, val, iso, cap, tris, steps, warmup):
-    """Whole-path steps (upload + build + iso) with HIP events per stage on
-    the current stream; returns (ms per step by host clock, stage lists)."""
+    """Whole-path steps (upload + build + iso).  The timed run has nothing
+    but the steps between two synchronisations (host clock); a second run of
+    the same steps records HIP events between the stages, on the stream the
+    kernels run on, for the per-stage split.  Returns (ms per step, stage
+    lists from the instrumented run)."""
     import torch
 
     stream = torch.cuda.current_stream()
@@ -328,13 +331,15 @@ def time_steps(amr, s, xyz, lvl, val, iso, cap, tris, steps, warmup):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
     for k in range(steps):
         step(evs[k])
     torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
     st = ([e[0].elapsed_time(e[1]) for e in evs], [e[1].elapsed_time(e[2]) for e in evs],
           [e[2].elapsed_time(e[3]) for e in evs])
     return ms, st

@@ -69,18 +69,21 @@ void amr_destroy(amr_set* set);
      level device int32 [n]     levels
      value device float [n]     cell values
    The arrays must stay alive and unchanged until the set is destroyed or
-   re-uploaded.  Validates every cell on the device (level range, alignment
-   of the corner to 2^level, finite value, coordinate limits) and reduces
-   the bounding box and per-level counts; then synchronises `stream` to read
-   them back.  Returns AMR_EINVAL / AMR_ERANGE for bad cells (message names
-   the first offending index).  n == 0 is allowed (an empty set).
+   re-uploaded.  Enqueues the validation of every cell on the device (level
+   range, alignment of the corner to 2^level, finite value, coordinate
+   limits) and the reduction of the bounding box and per-level counts, and
+   returns without waiting.  The verdict is read by the next
+   amr_index_bytes or amr_build_index, which return AMR_EINVAL / AMR_ERANGE
+   for bad cells (the message names the lowest offending index).  This call
+   itself only rejects bad arguments.  n == 0 is allowed (an empty set).
    Invalidates any index built before. */
 int amr_upload(amr_set* set, const int32_t* xyz, const int32_t* level, const float* value, int64_t n,
                hipStream_t stream);
 
-/* Bytes of device workspace amr_build_index needs for the uploaded set
-   (host-only, no GPU work).  After amr_build_index returned AMR_ENOSPACE
-   the answer grows to fit the set. */
+/* Bytes of device workspace amr_build_index needs for the uploaded set (no
+   GPU work; waits for the upload's verdict if it has not been read yet, and
+   returns its AMR_EINVAL / AMR_ERANGE).  After amr_build_index returned
+   AMR_ENOSPACE the answer grows to fit the set. */
 int amr_index_bytes(const amr_set* set, size_t* bytes);
 
 /* Cell-location index (paper sec. 3.2: the paper sorts the cells by their
@@ -90,10 +93,13 @@ int amr_index_bytes(const amr_set* set, size_t* bytes);
    eight same-level cells).  `workspace` is caller-owned device memory of at
    least amr_index_bytes() bytes, 256-byte aligned; it must stay alive while
    the set is used.  Also checks that no two cells overlap.  Synchronises
-   `stream` to read the result.  Returns AMR_EOVERLAP for duplicate or
-   nested cells, AMR_ENOSPACE if the hash table was too small (query
-   amr_index_bytes again and retry with a larger workspace), AMR_ESTATE
-   before amr_upload. */
+   `stream` once, at the end, to read the result.  When the set has as many
+   cells as at the previous build and the workspace still fits that build's
+   table, the build starts without waiting for the upload's verdict (the
+   kernels read it on the device).  Returns the upload's AMR_EINVAL /
+   AMR_ERANGE for bad cells, AMR_EOVERLAP for duplicate or nested cells,
+   AMR_ENOSPACE if the hash table was too small (query amr_index_bytes again
+   and retry with a larger workspace), AMR_ESTATE before amr_upload. */
 int amr_build_index(amr_set* set, void* workspace, size_t bytes, hipStream_t stream);
 
 /* Dual cells (paper sec. 4.2-4.4).  For every cell and each of its 8

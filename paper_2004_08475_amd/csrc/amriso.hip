@@ -87,6 +87,27 @@ struct alignas(256) Partial {
     unsigned long long level_count[kMaxLevel + 1];
 };
 
+// Index geometry: coordinate origin, coarsest level and hash parameters.
+struct Geo {
+    int32_t ox, oy, oz;  // origin: u = x - ox >= 2^(lmax+1)
+    int lmax;
+    int shift;           // 64 - log2(cap)
+    uint32_t mask;       // cap - 1
+};
+
+// Verdict of an upload, reduced on the device from the 64 replicas.
+struct UpRes {
+    int32_t lo[3], hi[3];
+    int32_t lmin, lmax;
+    int32_t origin[3];
+    int32_t status;  // AMR_OK, AMR_EINVAL or AMR_ERANGE
+    uint32_t err;    // error class bits (kErr*), or 16 + axis for an extent error
+    uint32_t pad;
+    unsigned long long bad;  // lowest offending cell index
+    unsigned long long level_count[kMaxLevel + 1];
+    unsigned long long record_hint;
+};
+
 // Device control block, one per set (library-allocated).
 struct Ctrl {
     Partial part[kReplicas];
@@ -98,6 +119,8 @@ struct Ctrl {
     unsigned long long n_groups;   // written by the compaction's last tile
     unsigned long long n_records;
     unsigned long long n_leaves;   // cells present in the table
+    UpRes res;                     // upload verdict (k_upload_finish)
+    Geo geo;                       // geometry of the index being built (k_build_reset)
 };
 
 // Scan bookkeeping inside the workspace.
@@ -384,19 +407,68 @@ __global__ __launch_bounds__(256) void k_upload(const int32_t* __restrict__ xyz,
     if (t <= kMaxLevel && s_cnt[t]) atomicAdd(&P.level_count[t], s_cnt[t]);
 }
 
+// One wave: combines the 64 replicas into the upload verdict, and derives
+// the index origin (aligned to 2^(lmax+1), one block of margin below the
+// cells) and the expected record count from it.
+__global__ __launch_bounds__(64) void k_upload_finish(Ctrl* c) {
+    const int r = threadIdx.x;
+    const Partial& p = c->part[r];
+    auto mn = [](int a, int b) { return a < b ? a : b; };
+    auto mx = [](int a, int b) { return a > b ? a : b; };
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = wave_reduce(p.lo[a], mn);
+        hi[a] = wave_reduce(p.hi[a], mx);
+    }
+    const int lmin = wave_reduce(p.lmin, mn), lmax = wave_reduce(p.lmax, mx);
+    const uint32_t err = wave_reduce(p.err, [](uint32_t a, uint32_t b) { return a | b; });
+    const unsigned long long bad =
+        wave_reduce(p.bad, [](unsigned long long a, unsigned long long b) { return a < b ? a : b; });
+    unsigned long long hint = 0;
+    for (int l = 0; l <= kMaxLevel; ++l) {
+        const unsigned long long cnt =
+            wave_reduce(p.level_count[l], [](unsigned long long a, unsigned long long b) { return a + b; });
+        if (r == 0) c->res.level_count[l] = cnt;
+        hint += (cnt + 7) / 8;
+    }
+    if (r != 0) return;
+    UpRes& u = c->res;
+    for (int a = 0; a < 3; ++a) {
+        u.lo[a] = lo[a];
+        u.hi[a] = hi[a];
+        u.origin[a] = 0;
+    }
+    u.lmin = lmin;
+    u.lmax = lmax;
+    u.err = err;
+    u.bad = bad;
+    u.status = AMR_OK;
+    // records: one per group of each level, plus refined markers (about one
+    // record per 7 groups for octrees)
+    u.record_hint = hint + hint / 7 + 64;
+    if (err) {
+        u.status = (err & (kErrLevel | kErrAlign | kErrValue)) ? AMR_EINVAL : AMR_ERANGE;
+        return;
+    }
+    const long long blk = 1ll << (lmax + 1);
+    for (int a = 0; a < 3; ++a) {
+        if ((long long)hi[a] - lo[a] + (1ll << (lmax + 3)) > kSpanLimit) {
+            u.status = AMR_ERANGE;
+            u.err = 16u + (uint32_t)a;
+            return;
+        }
+        const long long l0 = lo[a];
+        const long long fl = l0 >= 0 ? (l0 / blk) * blk : -((-l0 + blk - 1) / blk) * blk;
+        u.origin[a] = (int32_t)(fl - blk);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Index build
 // ---------------------------------------------------------------------------
 
-struct Geo {
-    int32_t ox, oy, oz;  // origin: u = x - ox >= 2^(lmax+1)
-    int lmax;
-    int shift;           // 64 - log2(cap)
-    uint32_t mask;       // cap - 1
-};
-
 // Start of a build: empty records, clean scan states, zero build results.
-__global__ __launch_bounds__(256) void k_build_reset(Record* __restrict__ rec, uint32_t cap, Sched* sc,
+__global__ __launch_bounds__(256) void k_build_reset(Record* __restrict__ rec, uint32_t cap, int shift, Sched* sc,
                                                      unsigned long long* ct0, unsigned long long* ct1, uint32_t nc,
                                                      unsigned long long* fs0, unsigned long long* fs1, Ctrl* c) {
     const float e = __uint_as_float(kValEmpty);
@@ -428,6 +500,16 @@ __global__ __launch_bounds__(256) void k_build_reset(Record* __restrict__ rec, u
         c->n_groups = 0;
         c->n_records = 0;
         c->n_leaves = 0;
+        // the geometry comes from the upload verdict, which the host may not
+        // have read yet
+        Geo g;
+        g.ox = c->res.origin[0];
+        g.oy = c->res.origin[1];
+        g.oz = c->res.origin[2];
+        g.lmax = c->res.lmax;
+        g.shift = shift;
+        g.mask = cap - 1;
+        c->geo = g;
     }
 }
 
@@ -453,8 +535,10 @@ __device__ __forceinline__ int find_or_insert(Record* __restrict__ rec, uint64_t
 // the count of the compaction).  Input indices are filled in later, and only
 // when an output asks for them (k_index_ids).
 __global__ __launch_bounds__(256) void k_index_insert(const int32_t* __restrict__ xyz, const int32_t* __restrict__ lvl,
-                                                      const float* __restrict__ val, int64_t n, Geo g,
+                                                      const float* __restrict__ val, int64_t n,
                                                       Record* __restrict__ rec, Ctrl* c) {
+    if (c->res.status != AMR_OK) return;  // invalid cells: nothing to index
+    const Geo g = c->geo;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         int m = lvl[i];
         uint32_t ux = (uint32_t)(xyz[3 * i] - g.ox), uy = (uint32_t)(xyz[3 * i + 1] - g.oy),
@@ -471,8 +555,9 @@ __global__ __launch_bounds__(256) void k_index_insert(const int32_t* __restrict_
 
 // The input index of every cell, beside its value (slot * 8 + child).
 __global__ __launch_bounds__(256) void k_index_ids(const int32_t* __restrict__ xyz, const int32_t* __restrict__ lvl,
-                                                   int64_t n, Geo g, const Record* __restrict__ rec,
+                                                   int64_t n, const Ctrl* c, const Record* __restrict__ rec,
                                                    int32_t* __restrict__ ids) {
+    const Geo g = c->geo;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         int m = lvl[i];
         uint32_t ux = (uint32_t)(xyz[3 * i] - g.ox), uy = (uint32_t)(xyz[3 * i + 1] - g.oy),
@@ -488,7 +573,9 @@ __global__ __launch_bounds__(256) void k_index_ids(const int32_t* __restrict__ x
 // level, until it meets a mark set by another group.  All leaves are stored
 // before this pass, so a mark that lands on a leaf is a coarser cell
 // containing finer ones.
-__global__ __launch_bounds__(256) void k_index_mark(Record* __restrict__ rec, uint32_t cap, Geo g, Ctrl* c) {
+__global__ __launch_bounds__(256) void k_index_mark(Record* __restrict__ rec, uint32_t cap, Ctrl* c) {
+    if (c->res.status != AMR_OK) return;
+    const Geo g = c->geo;
     for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
         const uint64_t key = rec[s].key;
         if (key == kEmpty) continue;
@@ -533,8 +620,9 @@ __global__ __launch_bounds__(256) void k_index_mark(Record* __restrict__ rec, ui
 // Error path only: the lowest input index whose entry was overwritten by a
 // duplicate of the same cell.
 __global__ __launch_bounds__(256) void k_index_find_dup(const int32_t* __restrict__ xyz, const int32_t* __restrict__ lvl,
-                                                        int64_t n, Geo g, const Record* __restrict__ rec,
+                                                        int64_t n, const Record* __restrict__ rec,
                                                         const int32_t* __restrict__ ids, Ctrl* c) {
+    const Geo g = c->geo;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         int m = lvl[i];
         uint32_t ux = (uint32_t)(xyz[3 * i] - g.ox), uy = (uint32_t)(xyz[3 * i + 1] - g.oy),
@@ -1656,6 +1744,11 @@ struct amr_set {
     int32_t origin[3] = {0, 0, 0};
     uint64_t level_count[kMaxLevel + 1] = {};
     uint64_t record_hint = 0;
+    bool up_pending = false;       // upload verdict not read on the host yet
+    int up_status = AMR_OK;
+    hipEvent_t up_event = nullptr;  // recorded after the verdict's copy
+    uint32_t last_cap = 0;          // table size of the last build, and its n
+    int64_t last_n = -1;
     // index
     bool built = false;
     uint32_t cap = 0;
@@ -1758,7 +1851,7 @@ int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_
     if ((duals ? verts != nullptr : tri_cells != nullptr) && cap > 0 && !s->ids_ready && s->n > 0) {
         // outputs name input indices: fill them in once per build
         hipLaunchKernelGGL(k_index_ids, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->n,
-                           geo_of(s), s->rec, s->ids);
+                           s->ctrl, s->rec, s->ids);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hipfail(e, "extract: cell index map");
         s->ids_ready = true;
@@ -1865,14 +1958,18 @@ int amr_create(amr_set** out, int hip_device) {
     amr_set* s = new (std::nothrow) amr_set();
     if (!s) return fail(AMR_ENOMEM, "amr_create: out of host memory");
     s->device = hip_device;
-    s->host_ctrl = (Ctrl*)calloc(1, sizeof(Ctrl));
-    if (!s->host_ctrl) {
-        delete s;
-        return fail(AMR_ENOMEM, "amr_create: out of host memory");
-    }
-    hipError_t e = hipMalloc((void**)&s->ctrl, sizeof(Ctrl));
+    // pinned, so that the read-backs after upload and build are plain DMA
+    hipError_t e = hipHostMalloc((void**)&s->host_ctrl, sizeof(Ctrl), hipHostMallocDefault);
     if (e != hipSuccess) {
-        free(s->host_ctrl);
+        delete s;
+        return hipfail(e, "amr_create: host control block");
+    }
+    memset(s->host_ctrl, 0, sizeof(Ctrl));
+    e = hipMalloc((void**)&s->ctrl, sizeof(Ctrl));
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->up_event, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        if (s->ctrl) (void)hipFree(s->ctrl);
+        (void)hipHostFree(s->host_ctrl);
         delete s;
         return hipfail(e, "amr_create: control block");
     }
@@ -1886,8 +1983,9 @@ void amr_destroy(amr_set* s) {
     {
         DeviceGuard dg(s->device);
         if (s->ctrl) (void)hipFree(s->ctrl);
+        if (s->up_event) (void)hipEventDestroy(s->up_event);
     }
-    free(s->host_ctrl);
+    (void)hipHostFree(s->host_ctrl);
     delete s;
 }
 
@@ -1908,73 +2006,72 @@ int amr_upload(amr_set* s, const int32_t* xyz, const int32_t* level, const float
     s->lmin = s->lmax = 0;
     s->origin[0] = s->origin[1] = s->origin[2] = 0;
     s->record_hint = 0;
+    s->up_pending = false;
+    s->up_status = AMR_OK;
     if (n == 0) {
         s->uploaded = true;
         return AMR_OK;
     }
     hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, stream, s->ctrl);
     hipLaunchKernelGGL(k_upload, dim3(grid_for(n, 256)), dim3(256), 0, stream, xyz, level, value, n, s->ctrl);
+    hipLaunchKernelGGL(k_upload_finish, dim3(1), dim3(kReplicas), 0, stream, s->ctrl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hipfail(e, "amr_upload: launch");
-    e = hipMemcpyAsync(s->host_ctrl, s->ctrl, sizeof(Partial) * kReplicas, hipMemcpyDeviceToHost, stream);
+    // the verdict travels to the host behind the kernels; whoever needs it
+    // first (amr_index_bytes, amr_build_index) waits for this event
+    e = hipMemcpyAsync(&s->host_ctrl->res, &s->ctrl->res, sizeof(UpRes), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipEventRecord(s->up_event, stream);
     if (e != hipSuccess) return hipfail(e, "amr_upload: readback");
-    e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return hipfail(e, "amr_upload: synchronize");
-    Partial c{};
-    for (int a = 0; a < 3; ++a) {
-        c.lo[a] = INT32_MAX;
-        c.hi[a] = INT32_MIN;
-    }
-    c.lmin = INT32_MAX;
-    c.lmax = INT32_MIN;
-    c.bad = ~0ull;
-    for (int r = 0; r < kReplicas; ++r) {
-        const Partial& p = s->host_ctrl->part[r];
-        for (int a = 0; a < 3; ++a) {
-            c.lo[a] = p.lo[a] < c.lo[a] ? p.lo[a] : c.lo[a];
-            c.hi[a] = p.hi[a] > c.hi[a] ? p.hi[a] : c.hi[a];
-        }
-        c.lmin = p.lmin < c.lmin ? p.lmin : c.lmin;
-        c.lmax = p.lmax > c.lmax ? p.lmax : c.lmax;
-        c.err |= p.err;
-        c.bad = p.bad < c.bad ? p.bad : c.bad;
-        for (int l = 0; l <= kMaxLevel; ++l) c.level_count[l] += p.level_count[l];
-    }
-    if (c.err) {
-        const char* why = (c.err & kErrLevel)   ? "level outside [0, 20]"
-                          : (c.err & kErrAlign) ? "lower corner not a multiple of 2^level"
-                          : (c.err & kErrValue) ? "non-finite value"
-                                                : "coordinate outside [-2^23, 2^23]";
-        int code = (c.err & (kErrLevel | kErrAlign | kErrValue)) ? AMR_EINVAL : AMR_ERANGE;
-        return fail(code, "amr_upload: cell %llu: %s", (unsigned long long)c.bad, why);
-    }
-    s->lmin = c.lmin;
-    s->lmax = c.lmax;
-    int64_t blk = (int64_t)1 << (s->lmax + 1);
-    for (int a = 0; a < 3; ++a) {
-        int64_t lo = c.lo[a], hi = c.hi[a];
-        if (hi - lo + ((int64_t)1 << (s->lmax + 3)) > kSpanLimit)
-            return fail(AMR_ERANGE, "amr_upload: extent %lld on axis %d too large for level %d (limit 2^20)",
-                        (long long)(hi - lo), a, s->lmax);
-        int64_t fl = lo >= 0 ? (lo / blk) * blk : -((-lo + blk - 1) / blk) * blk;
-        s->origin[a] = (int32_t)(fl - blk);
-    }
-    // records: one per group of each level, plus refined markers (about one
-    // record per 7 groups for octrees)
-    uint64_t hint = 0;
-    for (int l = 0; l <= kMaxLevel; ++l) {
-        s->level_count[l] = c.level_count[l];
-        hint += (c.level_count[l] + 7) / 8;
-    }
-    s->record_hint = hint + hint / 7 + 64;
+    s->up_pending = true;
     s->uploaded = true;
     g_err[0] = 0;
     return AMR_OK;
 }
 
-int amr_index_bytes(const amr_set* s, size_t* bytes) {
-    if (!s || !bytes) return fail(AMR_EINVAL, "amr_index_bytes: NULL argument");
+namespace {
+
+// Take over an upload verdict that has reached host_ctrl->res.
+int apply_upload(amr_set* s) {
+    const UpRes& u = s->host_ctrl->res;
+    s->up_pending = false;
+    s->up_status = u.status;
+    if (u.status != AMR_OK) {
+        if (u.err >= 16)
+            return fail(AMR_ERANGE, "amr_upload: extent %lld on axis %d too large for level %d (limit 2^20)",
+                        (long long)u.hi[u.err - 16] - u.lo[u.err - 16], (int)(u.err - 16), u.lmax);
+        const char* why = (u.err & kErrLevel)   ? "level outside [0, 20]"
+                          : (u.err & kErrAlign) ? "lower corner not a multiple of 2^level"
+                          : (u.err & kErrValue) ? "non-finite value"
+                                                : "coordinate outside [-2^23, 2^23]";
+        return fail(u.status, "amr_upload: cell %llu: %s", (unsigned long long)u.bad, why);
+    }
+    s->lmin = u.lmin;
+    s->lmax = u.lmax;
+    for (int a = 0; a < 3; ++a) s->origin[a] = u.origin[a];
+    for (int l = 0; l <= kMaxLevel; ++l) s->level_count[l] = u.level_count[l];
+    s->record_hint = u.record_hint;
+    return AMR_OK;
+}
+
+// Wait for the upload verdict if it is still on its way.
+int upload_verdict(amr_set* s) {
+    if (s->up_pending) {
+        hipError_t e = hipEventSynchronize(s->up_event);
+        if (e != hipSuccess) return hipfail(e, "amr_upload: waiting for the verdict");
+        return apply_upload(s);
+    }
+    if (s->up_status != AMR_OK) return apply_upload(s);  // the same error again
+    return AMR_OK;
+}
+
+}  // namespace
+
+int amr_index_bytes(const amr_set* cs, size_t* bytes) {
+    if (!cs || !bytes) return fail(AMR_EINVAL, "amr_index_bytes: NULL argument");
+    amr_set* s = const_cast<amr_set*>(cs);  // reading the upload verdict updates the handle
     if (!s->uploaded) return fail(AMR_ESTATE, "amr_index_bytes: call amr_upload first");
+    int st = upload_verdict(s);
+    if (st != AMR_OK) return st;
     uint32_t cap = table_cap(s);
     if (!cap) return fail(AMR_ERANGE, "amr_index_bytes: more groups than the index supports");
     *bytes = layout_for(cap).total;
@@ -1985,10 +2082,20 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     if (!s) return fail(AMR_EINVAL, "amr_build_index: set is NULL");
     if (!s->uploaded) return fail(AMR_ESTATE, "amr_build_index: call amr_upload first");
     s->built = false;
-    uint32_t cap = table_cap(s);
-    if (!cap) return fail(AMR_ERANGE, "amr_build_index: more groups than the index supports");
-    Layout L = layout_for(cap);
     if (!ws || ((uintptr_t)ws & 255)) return fail(AMR_EINVAL, "amr_build_index: workspace NULL or not 256-B aligned");
+    uint32_t cap;
+    if (s->up_pending && s->n == s->last_n && s->last_cap && bytes >= layout_for(s->last_cap).total) {
+        // a set of the same size as last time: build at once with the same
+        // table; the kernels take the geometry from the upload verdict on the
+        // device, and a table that turns out too small reports AMR_ENOSPACE
+        cap = s->last_cap;
+    } else {
+        int st = upload_verdict(s);
+        if (st != AMR_OK) return st;
+        cap = table_cap(s);
+        if (!cap) return fail(AMR_ERANGE, "amr_build_index: more groups than the index supports");
+    }
+    Layout L = layout_for(cap);
     if (bytes < L.total)
         return fail(AMR_ENOSPACE, "amr_build_index: workspace of %zu bytes, need %zu", bytes, L.total);
     DeviceGuard dg(s->device);
@@ -2008,17 +2115,18 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     s->ct1 = (unsigned long long*)(base + L.ct1);
     s->sched = (Sched*)(base + L.sched);
     s->n_groups = 0;
-    Geo g = geo_of(s);
+    int log2cap = 0;
+    while ((1u << log2cap) < cap) ++log2cap;
     {
         uint32_t work = cap > L.compact_tiles ? cap : L.compact_tiles;
         if (work < kFusedMaxTiles) work = kFusedMaxTiles;
-        hipLaunchKernelGGL(k_build_reset, dim3(grid_for(work, 256)), dim3(256), 0, stream, s->rec, cap, s->sched,
-                           s->ct0, s->ct1, L.compact_tiles, s->fs0, s->fs1, s->ctrl);
+        hipLaunchKernelGGL(k_build_reset, dim3(grid_for(work, 256)), dim3(256), 0, stream, s->rec, cap,
+                           64 - log2cap, s->sched, s->ct0, s->ct1, L.compact_tiles, s->fs0, s->fs1, s->ctrl);
     }
     if (s->n > 0) {
         hipLaunchKernelGGL(k_index_insert, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->val,
-                           s->n, g, s->rec, s->ctrl);
-        hipLaunchKernelGGL(k_index_mark, dim3(grid_for(cap, 256)), dim3(256), 0, stream, s->rec, cap, g, s->ctrl);
+                           s->n, s->rec, s->ctrl);
+        hipLaunchKernelGGL(k_index_mark, dim3(grid_for(cap, 256)), dim3(256), 0, stream, s->rec, cap, s->ctrl);
     }
     hipLaunchKernelGGL(k_index_compact, dim3(L.compact_tiles), dim3(kBlock), 0, stream, s->rec, cap, s->glist,
                        s->ct0, s->ct1, s->sched, L.compact_tiles, L.compact_per, s->ctrl);
@@ -2030,6 +2138,11 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     if (e != hipSuccess) return hipfail(e, "amr_build_index: readback");
     e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hipfail(e, "amr_build_index: synchronize");
+    if (s->up_pending) {
+        // the read-back above carried the upload verdict too
+        int st = apply_upload(s);
+        if (st != AMR_OK) return st;
+    }
     const Ctrl& c = *s->host_ctrl;
     if (c.overflow || c.n_records * 4 > (unsigned long long)cap * 3) {
         uint64_t seen = c.n_records;
@@ -2041,8 +2154,8 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
         // bad_build holds slot * 8 + child of the coarse cell: name its input index
         const unsigned long long ref = c.bad_build;
         int32_t id = -1;
-        hipLaunchKernelGGL(k_index_ids, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->n, g,
-                           s->rec, s->ids);
+        hipLaunchKernelGGL(k_index_ids, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->n,
+                           s->ctrl, s->rec, s->ids);
         e = hipMemcpyAsync(&id, s->ids + ref, sizeof(id), hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return hipfail(e, "amr_build_index: overlap report");
@@ -2051,10 +2164,10 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     if (c.n_leaves != (unsigned long long)s->n) {
         // some cell was stored twice: find the lowest overwritten index
         hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, stream, s->ctrl);
-        hipLaunchKernelGGL(k_index_ids, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->n, g,
-                           s->rec, s->ids);
+        hipLaunchKernelGGL(k_index_ids, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->n,
+                           s->ctrl, s->rec, s->ids);
         hipLaunchKernelGGL(k_index_find_dup, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->n,
-                           g, s->rec, s->ids, s->ctrl);
+                           s->rec, s->ids, s->ctrl);
         e = hipMemcpyAsync((char*)s->host_ctrl + tail, (char*)s->ctrl + tail, sizeof(Ctrl) - tail,
                            hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -2064,6 +2177,8 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     s->n_groups = (uint32_t)c.n_groups;
     s->built = true;
     s->ids_ready = false;
+    s->last_cap = cap;
+    s->last_n = s->n;
     g_err[0] = 0;
     return AMR_OK;
 }

@@ -183,11 +183,14 @@ def test_sparse_set_grows_index(amr):
 
 
 def test_error_codes(amr):
-    def up(xyz, lvl, val):
+    def up(xyz, lvl, val, build=True):
+        # the upload's verdict is read by the build (or amr_index_bytes)
         s = amr.AmrSet()
         s.upload(torch.tensor(np.asarray(xyz), dtype=torch.int32, device="cuda").reshape(-1, 3),
                  torch.tensor(np.asarray(lvl), dtype=torch.int32, device="cuda"),
                  torch.tensor(np.asarray(val), dtype=torch.float32, device="cuda"))
+        if build:
+            s.build_index()
         return s
 
     with pytest.raises(amr.AmrError) as ei:
@@ -205,15 +208,22 @@ def test_error_codes(amr):
     with pytest.raises(amr.AmrError) as ei:
         up([[0, 0, 0], [1 << 20, 0, 0]], [0, 0], [0.0, 0.0])
     assert ei.value.code == amr.AMR_ERANGE
-    s = up([[0, 0, 0], [0, 0, 0]], [0, 0], [0.0, 1.0])
+    with pytest.raises(amr.AmrError) as ei:
+        up([[0, 0, 0], [0, 0, 0]], [0, 0], [0.0, 1.0])
+    assert ei.value.code == amr.AMR_EOVERLAP
+    with pytest.raises(amr.AmrError) as ei:
+        up([[0, 0, 0], [2, 2, 2]], [2, 0], [0.0, 1.0])
+    assert ei.value.code == amr.AMR_EOVERLAP
+    # a bad upload after a good one on the same set and workspace (the build
+    # does not wait for the verdict then) still reports the bad cell
+    s = up([[0, 0, 0], [2, 0, 0]], [1, 1], [0.0, 1.0])
+    s.upload(torch.tensor([[0, 0, 0], [3, 0, 0]], dtype=torch.int32, device="cuda"),
+             torch.tensor([1, 1], dtype=torch.int32, device="cuda"),
+             torch.tensor([0.0, 1.0], dtype=torch.float32, device="cuda"))
     with pytest.raises(amr.AmrError) as ei:
         s.build_index()
-    assert ei.value.code == amr.AMR_EOVERLAP
-    s = up([[0, 0, 0], [2, 2, 2]], [2, 0], [0.0, 1.0])
-    with pytest.raises(amr.AmrError) as ei:
-        s.build_index()
-    assert ei.value.code == amr.AMR_EOVERLAP
-    s = up([[0, 0, 0]], [0], [0.0])
+    assert ei.value.code == amr.AMR_EINVAL
+    s = up([[0, 0, 0]], [0], [0.0], build=False)
     with pytest.raises(amr.AmrError) as ei:
         s.count(0.5)
     assert ei.value.code == amr.AMR_ESTATE
