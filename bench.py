@@ -54,7 +54,7 @@ def cpu_baseline(cs, min_seconds=10.0):
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     reps, t_total = 0, 0.0
     tris = 0
-    while t_total < min_seconds and reps < 50:
+    while t_total < min_seconds and reps < 10000:
         t0 = time.perf_counter()
         o = oracle.Oracle(cs.xyz, cs.level, cs.value, validate=False)
         tris, _ = o.isosurface_threaded(cs.iso, threads)
