@@ -126,9 +126,9 @@ struct Ctrl {
 // Scan bookkeeping inside the workspace.
 struct Sched {
     unsigned long long xticket;  // extraction scan tiles started (reset by each count pass)
-    unsigned long long pad0;
+    unsigned long long fcall;    // fused extraction calls started
     unsigned long long cticket;  // compaction tiles started
-    unsigned long long pad;
+    unsigned long long fticket;  // fused extraction tiles started, over all calls
 };
 
 __device__ __forceinline__ uint64_t group_key(int m, uint32_t gx, uint32_t gy, uint32_t gz) {
@@ -490,9 +490,9 @@ __global__ __launch_bounds__(256) void k_build_reset(Record* __restrict__ rec, u
     }
     if (i0 == 0) {
         sc->xticket = 0;
-        sc->pad0 = 0;
+        sc->fcall = 0;
         sc->cticket = 0;
-        sc->pad = 0;
+        sc->fticket = 0;
         c->overflow = 0;
         c->dup = 0;
         c->overlap = 0;
@@ -638,7 +638,8 @@ __global__ __launch_bounds__(256) void k_index_find_dup(const int32_t* __restric
 // order, by a block scan plus look-back over tiles of 4096 slots.  Also
 // counts all occupied records (groups plus marker-only records).
 __global__ __launch_bounds__(kBlock) void k_index_compact(const Record* __restrict__ rec, uint32_t cap,
-                                                          int32_t* __restrict__ glist, unsigned long long* s0,
+                                                          int32_t* __restrict__ glist,
+                                                          unsigned long long* __restrict__ gkey, unsigned long long* s0,
                                                           unsigned long long* s1, Sched* sc, uint32_t n_tiles,
                                                           int per, Ctrl* c) {
     __shared__ uint32_t s_rcount[kCompactMaxPerThread][kBlock / 64];
@@ -700,8 +701,12 @@ __global__ __launch_bounds__(kBlock) void k_index_compact(const Record* __restri
         unsigned long long b = __ballot((grp_bits >> r) & 1);
         uint32_t before = 0;
         for (int w = 0; w < wave; ++w) before += s_rcount[r][w];
-        if ((grp_bits >> r) & 1)
-            glist[pos + before + (uint32_t)__popcll(b & ((1ull << lane) - 1))] = (int32_t)(base + r * kBlock + t);
+        if ((grp_bits >> r) & 1) {
+            const uint32_t at = pos + before + (uint32_t)__popcll(b & ((1ull << lane) - 1));
+            const uint32_t slot = base + r * kBlock + t;
+            glist[at] = (int32_t)slot;
+            gkey[at] = rec[slot].key;  // beside the slot, so extraction needs no dependent load
+        }
         for (int w = 0; w < kBlock / 64; ++w) pos += s_rcount[r][w];
     }
 }
@@ -714,6 +719,7 @@ struct ExtractArgs {
     const Record* rec;
     const int32_t* ids;
     const int32_t* glist;
+    const unsigned long long* gkey;
     uint32_t n_groups;
     Geo g;
     float iso;
@@ -844,9 +850,25 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
     const int gi = t >> 3;  // group within the tile
     const int j = t & 7;    // lane within the group
     __shared__ uint32_t s_tile;
+    __shared__ unsigned long long s_call;
     if (kPass == kPassFused) {
-        if (threadIdx.x == 0) s_tile = (uint32_t)atomicAdd(&a.sched->xticket, 1ull);
+        if (threadIdx.x == 0) {
+            // Tiles take tickets in start order.  The call number is read
+            // before the ticket: the ticket's address depends on the value
+            // read (call >> 63 is always 0), so the read completes first.  By
+            // the time the last tile of this call holds its ticket every tile
+            // of the call has read the number, and the last tile may advance
+            // it at once for the next call.
+            const unsigned long long call = ld_relaxed(&a.sched->fcall);
+            const unsigned long long tk = atomicAdd(&a.sched->fticket + (call >> 63), 1ull);
+            const unsigned long long tl = tk - call * a.n_tiles;
+            s_call = call;
+            s_tile = tl < a.n_tiles ? (uint32_t)tl : 0xFFFFFFFFu;
+            if (tl == a.n_tiles - 1)
+                __hip_atomic_store(&a.sched->fcall, call + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         __syncthreads();
+        if (s_tile == 0xFFFFFFFFu) return;  // cannot happen while calls on a set do not overlap
     }
     // count and write passes: work-groups go round-robin to the 8 XCDs, so
     // XCD x is given the contiguous run of tiles [x*T, (x+1)*T) in order and
@@ -883,7 +905,7 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
     int own = 0;
     if (valid) {
         own = a.glist[gidx];
-        uint64_t key = a.rec[own].key;
+        uint64_t key = a.gkey[gidx];
         m = (int)(key >> 57);
         gx = (uint32_t)(key & 0x7FFFF);
         gy = (uint32_t)((key >> 19) & 0x7FFFF);
@@ -935,21 +957,64 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
                 // The block holds neither cells of level m nor finer cells (either
                 // would have left a record): it lies inside a coarser cell or in a
                 // hole.  The first record found going up decides.
+                // In the fused pass (small sets, one wave of tiles: latency
+                // bound) the home slots of four levels are read at once, so a
+                // deep walk costs one memory round trip per four levels; the
+                // throughput passes walk one level at a time, which keeps
+                // their register count (and occupancy) down.
+                constexpr int kWalk = kPass == kPassFused ? 4 : 1;
                 int dx = dd % 3 - 1, dy = (dd / 3) % 3 - 1, dz = dd / 9 - 1;
                 uint32_t bx = gx + dx, by = gy + dy, bz = gz + dz;
-                for (int L = m + 1; L <= g.lmax; ++L) {
-                    int sh = L - m - 1;
-                    uint32_t cx = bx >> sh, cy = by >> sh, cz = bz >> sh;
-                    int h2 = probe(a.rec, group_key(L, cx >> 1, cy >> 1, cz >> 1), g.shift, g.mask);
-                    if (h2 < 0) continue;
-                    int child = (cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2);
-                    float v = a.rec[h2].val[child];
-                    if (v == v) {
-                        lv = L;
-                        ref = h2 * 8 + child;
-                        cv = v;
+                // Each level's home slot is read with the one child value the
+                // block would need there (same line), so a record found at its
+                // home slot costs no further round trip.
+                int found_l = -1, found_h = -1, found_c = 0;
+                float found_v = 0.f;
+                for (int L0 = m + 1; L0 <= g.lmax && found_l < 0; L0 += kWalk) {
+                    uint64_t wk[kWalk], kk[kWalk];
+                    uint32_t hh[kWalk];
+                    int ch[kWalk];
+                    float vv[kWalk];
+#pragma unroll
+                    for (int u = 0; u < kWalk; ++u) {
+                        const int L = L0 + u, sh = L - m - 1;
+                        wk[u] = group_key(L, bx >> (sh + 1), by >> (sh + 1), bz >> (sh + 1));
+                        hh[u] = slot_of(wk[u], g.shift);
+                        ch[u] = ((bx >> sh) & 1) | (((by >> sh) & 1) << 1) | (((bz >> sh) & 1) << 2);
+                        kk[u] = kEmpty;
+                        vv[u] = 0.f;
+                        if (L <= g.lmax) {
+                            kk[u] = a.rec[hh[u]].key;
+                            vv[u] = a.rec[hh[u]].val[ch[u]];
+                        }
                     }
-                    break;
+#pragma unroll
+                    for (int u = 0; u < kWalk; ++u) {
+                        if (found_l >= 0 || L0 + u > g.lmax) continue;
+                        uint32_t h2 = hh[u];
+                        uint64_t k2 = kk[u];
+                        float v2 = vv[u];
+                        if (k2 != wk[u] && k2 != kEmpty) {
+                            for (uint32_t step = 0; k2 != wk[u] && k2 != kEmpty && step <= g.mask; ++step) {
+                                h2 = next_slot(h2, g.mask);
+                                k2 = a.rec[h2].key;
+                            }
+                            if (k2 == wk[u]) v2 = a.rec[h2].val[ch[u]];
+                        }
+                        if (k2 == wk[u]) {
+                            found_l = L0 + u;
+                            found_h = (int)h2;
+                            found_c = ch[u];
+                            found_v = v2;
+                        }
+                    }
+                }
+                // the lowest level with a record decides (a NaN there: finer
+                // cells or none at all, either way no cell covers this block)
+                if (found_l >= 0 && found_v == found_v) {
+                    lv = found_l;
+                    ref = found_h * 8 + found_c;
+                    cv = found_v;
                 }
             }
             // the cells of this neighbour that lie in the 4x4x4 block
@@ -1045,7 +1110,9 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
         if (wave == 0) {
             unsigned long long pre_t, pre_d;
             const unsigned long long agg_t = total >> 32, agg_d = total & 0xFFFFFFFFull;
-            lookback(a.sc0, a.sc1, tile, 0ull, agg_t, agg_d, pre_t, pre_d);
+            // states of the previous call carry the other parity
+            const unsigned long long par = (s_call & 1) ? kParityBit : 0ull;
+            lookback(a.sc0, a.sc1, tile, par, agg_t, agg_d, pre_t, pre_d);
             if (lane_id() == 0) {
                 s_pre_t = pre_t;
                 s_pre_d = pre_d;
@@ -1194,15 +1261,6 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
             }
         }
     }
-}
-
-// After a fused pass: clean look-back states and ticket for the next call.
-__global__ void k_fused_clear(ExtractArgs a) {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n_tiles; i += gridDim.x * blockDim.x) {
-        a.sc0[i] = 0;
-        a.sc1[i] = 0;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.sched->xticket = 0;
 }
 
 // Exclusive scan of the per-tile (triangles, duals) totals of a count pass:
@@ -1757,6 +1815,7 @@ struct amr_set {
     int32_t* ids = nullptr;
     bool ids_ready = false;  // input indices filled in (on first use)
     int32_t* glist = nullptr;
+    unsigned long long* gkey = nullptr;
     unsigned long long* tot = nullptr;   // extraction: per-tile totals
     unsigned long long* st_t = nullptr;  // extraction: per-tile prefixes
     unsigned long long* st_d = nullptr;
@@ -1780,7 +1839,7 @@ uint32_t table_cap(const amr_set* s) {
 }
 
 struct Layout {
-    size_t rec, ids, glist, tot, st_t, st_d, xs0, xs1, fs0, fs1, ct0, ct1, sched, total;
+    size_t rec, ids, glist, gkey, tot, st_t, st_d, xs0, xs1, fs0, fs1, ct0, ct1, sched, total;
     uint32_t max_tiles, max_scan_tiles, compact_tiles;
     int compact_per;
 };
@@ -1800,6 +1859,8 @@ Layout layout_for(uint32_t cap) {
     off = align256(off + (size_t)cap * 8 * sizeof(int32_t));
     L.glist = off;
     off = align256(off + (size_t)max_groups * sizeof(int32_t));
+    L.gkey = off;
+    off = align256(off + (size_t)max_groups * sizeof(unsigned long long));
     L.max_scan_tiles = (L.max_tiles + kBlock * kScanPer - 1) / (kBlock * kScanPer);
     L.tot = off;
     off = align256(off + (size_t)L.max_tiles * 8);
@@ -1866,6 +1927,7 @@ int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_
     a.rec = s->rec;
     a.ids = s->ids;
     a.glist = s->glist;
+    a.gkey = s->gkey;
     a.n_groups = s->n_groups;
     a.g = geo_of(s);
     a.iso = iso;
@@ -1886,14 +1948,13 @@ int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_
     a.n_tiles = n_tiles;
     a.n_scan_tiles = (n_tiles + kBlock * kScanPer - 1) / (kBlock * kScanPer);
     if (n_tiles <= kFusedMaxTiles) {
-        // one fused pass, then clean its look-back states for the next call
+        // one fused pass (look-back states alternate parity between calls)
         a.sc0 = s->fs0;
         a.sc1 = s->fs1;
         if (duals)
             hipLaunchKernelGGL((k_extract<true, kPassFused>), dim3(n_tiles), dim3(kBlock), 0, stream, a);
         else
             hipLaunchKernelGGL((k_extract<false, kPassFused>), dim3(n_tiles), dim3(kBlock), 0, stream, a);
-        hipLaunchKernelGGL(k_fused_clear, dim3(1), dim3(256), 0, stream, a);
     } else {
         // count pass, scan, then the write pass only when something is written;
         // the grid is a multiple of the XCD count (see the tile mapping)
@@ -2104,6 +2165,7 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     s->rec = (Record*)(base + L.rec);
     s->ids = (int32_t*)(base + L.ids);
     s->glist = (int32_t*)(base + L.glist);
+    s->gkey = (unsigned long long*)(base + L.gkey);
     s->tot = (unsigned long long*)(base + L.tot);
     s->st_t = (unsigned long long*)(base + L.st_t);
     s->st_d = (unsigned long long*)(base + L.st_d);
@@ -2129,7 +2191,7 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
         hipLaunchKernelGGL(k_index_mark, dim3(grid_for(cap, 256)), dim3(256), 0, stream, s->rec, cap, s->ctrl);
     }
     hipLaunchKernelGGL(k_index_compact, dim3(L.compact_tiles), dim3(kBlock), 0, stream, s->rec, cap, s->glist,
-                       s->ct0, s->ct1, s->sched, L.compact_tiles, L.compact_per, s->ctrl);
+                       s->gkey, s->ct0, s->ct1, s->sched, L.compact_tiles, L.compact_per, s->ctrl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hipfail(e, "amr_build_index: launch");
     const size_t tail = offsetof(Ctrl, overflow);
