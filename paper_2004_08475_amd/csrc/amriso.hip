@@ -119,6 +119,7 @@ struct Ctrl {
     unsigned long long n_groups;   // written by the compaction's last tile
     unsigned long long n_records;
     unsigned long long n_leaves;   // cells present in the table
+    unsigned long long made[kReplicas * 16];  // marker-only records created (one replica per 128 B)
     UpRes res;                     // upload verdict (k_upload_finish)
     Geo geo;                       // geometry of the index being built (k_build_reset)
 };
@@ -488,6 +489,7 @@ __global__ __launch_bounds__(256) void k_build_reset(Record* __restrict__ rec, u
         fs0[i] = 0;
         fs1[i] = 0;
     }
+    if (i0 < (uint32_t)kReplicas) c->made[i0 * 16] = 0;
     if (i0 == 0) {
         sc->xticket = 0;
         sc->fcall = 0;
@@ -515,7 +517,8 @@ __global__ __launch_bounds__(256) void k_build_reset(Record* __restrict__ rec, u
 
 // A key never changes once written, so a plain (possibly stale) read can only
 // show "free" too often; the compare-and-swap then returns the truth.
-__device__ __forceinline__ int find_or_insert(Record* __restrict__ rec, uint64_t key, const Geo& g) {
+__device__ __forceinline__ int find_or_insert(Record* __restrict__ rec, uint64_t key, const Geo& g,
+                                              uint32_t* created = nullptr) {
     uint32_t h = slot_of(key, g.shift);
     for (uint32_t step = 0; step < kMaxProbe && step <= g.mask; ++step) {
         uint64_t k = rec[h].key;
@@ -523,6 +526,7 @@ __device__ __forceinline__ int find_or_insert(Record* __restrict__ rec, uint64_t
         if (k == kEmpty) {
             uint64_t prev = atomicCAS((unsigned long long*)&rec[h].key, (unsigned long long)kEmpty,
                                       (unsigned long long)key);
+            if (prev == kEmpty && created) ++*created;
             if (prev == kEmpty || prev == key) return (int)h;
         }
         h = next_slot(h, g.mask);
@@ -572,27 +576,29 @@ __global__ __launch_bounds__(256) void k_index_ids(const int32_t* __restrict__ x
 // Every group holding a cell marks its ancestors as refined, level by
 // level, until it meets a mark set by another group.  All leaves are stored
 // before this pass, so a mark that lands on a leaf is a coarser cell
-// containing finer ones.
-__global__ __launch_bounds__(256) void k_index_mark(Record* __restrict__ rec, uint32_t cap, Ctrl* c) {
+// containing finer ones.  The pass runs over the compacted group list (the
+// compaction's count is on the device), and counts the marker-only records
+// it creates, one atomic per work-group into one of 64 replicas.
+__global__ __launch_bounds__(256) void k_index_mark(Record* __restrict__ rec,
+                                                    const unsigned long long* __restrict__ gkey, Ctrl* c) {
+    __shared__ uint32_t s_made;
     if (c->res.status != AMR_OK) return;
     const Geo g = c->geo;
-    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
-        const uint64_t key = rec[s].key;
-        if (key == kEmpty) continue;
+    const uint32_t ng = (uint32_t)c->n_groups;
+    if (threadIdx.x == 0) s_made = 0;
+    __syncthreads();
+    uint32_t made = 0;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ng; i += gridDim.x * blockDim.x) {
+        const uint64_t key = gkey[i];
         const int m = (int)(key >> 57);
         if (m >= g.lmax) continue;
-        const float4* pv = reinterpret_cast<const float4*>(rec[s].val);
-        const float4 a = pv[0], b = pv[1];
-        const bool leaf = a.x == a.x || a.y == a.y || a.z == a.z || a.w == a.w || b.x == b.x || b.y == b.y ||
-                          b.z == b.z || b.w == b.w;
-        if (!leaf) continue;
         const uint32_t gx = (uint32_t)(key & 0x7FFFF), gy = (uint32_t)((key >> 19) & 0x7FFFF),
                        gz = (uint32_t)((key >> 38) & 0x7FFFF);
         for (int L = m + 1; L <= g.lmax; ++L) {
             // the level-L cell holding this group's block, and its group
             const int sh = L - m - 1;
             const uint32_t cx = gx >> sh, cy = gy >> sh, cz = gz >> sh;
-            const int s2 = find_or_insert(rec, group_key(L, cx >> 1, cy >> 1, cz >> 1), g);
+            const int s2 = find_or_insert(rec, group_key(L, cx >> 1, cy >> 1, cz >> 1), g, &made);
             if (s2 < 0) {
                 atomicOr(&c->overflow, 1u);
                 break;
@@ -615,6 +621,11 @@ __global__ __launch_bounds__(256) void k_index_mark(Record* __restrict__ rec, ui
             break;
         }
     }
+    made = (uint32_t)wave_reduce((unsigned long long)made,
+                                 [](unsigned long long x, unsigned long long y) { return x + y; });
+    if (lane_id() == 0 && made) atomicAdd(&s_made, made);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_made) atomicAdd(&c->made[(blockIdx.x % kReplicas) * 16], (unsigned long long)s_made);
 }
 
 // Error path only: the lowest input index whose entry was overwritten by a
@@ -2185,13 +2196,18 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
         hipLaunchKernelGGL(k_build_reset, dim3(grid_for(work, 256)), dim3(256), 0, stream, s->rec, cap,
                            64 - log2cap, s->sched, s->ct0, s->ct1, L.compact_tiles, s->fs0, s->fs1, s->ctrl);
     }
-    if (s->n > 0) {
+    if (s->n > 0)
         hipLaunchKernelGGL(k_index_insert, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->val,
                            s->n, s->rec, s->ctrl);
-        hipLaunchKernelGGL(k_index_mark, dim3(grid_for(cap, 256)), dim3(256), 0, stream, s->rec, cap, s->ctrl);
-    }
+    // the group list only depends on the leaves, so it is compacted before
+    // the ancestors are marked, and the marking runs over it
     hipLaunchKernelGGL(k_index_compact, dim3(L.compact_tiles), dim3(kBlock), 0, stream, s->rec, cap, s->glist,
                        s->gkey, s->ct0, s->ct1, s->sched, L.compact_tiles, L.compact_per, s->ctrl);
+    if (s->n > 0) {
+        const int64_t most = s->n < (int64_t)cap ? s->n : (int64_t)cap;  // at least the number of groups
+        hipLaunchKernelGGL(k_index_mark, dim3(grid_for(most, 256)), dim3(256), 0, stream, s->rec, s->gkey,
+                           s->ctrl);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hipfail(e, "amr_build_index: launch");
     const size_t tail = offsetof(Ctrl, overflow);
@@ -2206,8 +2222,10 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
         if (st != AMR_OK) return st;
     }
     const Ctrl& c = *s->host_ctrl;
-    if (c.overflow || c.n_records * 4 > (unsigned long long)cap * 3) {
-        uint64_t seen = c.n_records;
+    unsigned long long n_records = c.n_records;  // records at compaction time: the groups
+    for (int r = 0; r < kReplicas; ++r) n_records += c.made[r * 16];
+    if (c.overflow || n_records * 4 > (unsigned long long)cap * 3) {
+        uint64_t seen = n_records;
         s->record_hint = seen * 2 > s->record_hint * 4 ? seen * 2 : s->record_hint * 4;
         return fail(AMR_ENOSPACE, "amr_build_index: hash table too small (%u slots); query amr_index_bytes again",
                     cap);
