@@ -1369,8 +1369,11 @@ struct BatchArgs {
     float* tris;
     int64_t* counts;
     uint32_t* tcount;  // per (job, tile of its set): count, then exclusive prefix
+    uint32_t* bsum;    // per work-group: sum of its stretch of one job's counts
     GridBar* bar;
 };
+
+constexpr int kMaxBatchGrid = 4096;  // work-groups of a batched launch (bsum entries)
 
 __device__ void grid_barrier(GridBar* bar, unsigned int& sense) {
     __syncthreads();
@@ -1507,12 +1510,24 @@ __global__ __launch_bounds__(512) void k_batch(BatchArgs a) {
     };
 
     // ---- phase A: triangle counts per (job, tile) ----
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        int sidx = set_of(tile);
-        int64_t lt = tile - s_tbase[sidx];
-        DualMc d[PER];
-        bool live[PER];
+    // the duals of a work-group's next tile are loaded before the current
+    // tile is processed, so their latency overlaps the work on this one
+    DualMc d[PER], dn[PER];
+    bool live[PER], ln[PER];
+    int sidx = 0, sn = 0;
+    int64_t lt = 0, ltn = 0;
+    if (blockIdx.x < n_tiles) {
+        sidx = set_of(blockIdx.x);
+        lt = blockIdx.x - s_tbase[sidx];
         load_duals(sidx, lt, d, live);
+    }
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t next = tile + gridDim.x;
+        if (next < n_tiles) {
+            sn = set_of(next);
+            ltn = next - s_tbase[sn];
+            load_duals(sn, ltn, dn, ln);
+        }
         for (int j = 0; j < a.n_jobs; ++j) {
             if (s_job[j].set != sidx) continue;
             float iso = s_job[j].iso;
@@ -1524,33 +1539,85 @@ __global__ __launch_bounds__(512) void k_batch(BatchArgs a) {
             (void)block_excl_scan(c, s_w, &tot);
             if (t == 0) a.tcount[s_jbase[j] + lt] = tot;
         }
+        sidx = sn;
+        lt = ltn;
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            d[p] = dn[p];
+            live[p] = ln[p];
+        }
     }
     grid_barrier(a.bar, sense);
 
     // ---- phase B: exclusive scan over each job's tiles ----
-    for (int j = blockIdx.x; j < a.n_jobs; j += gridDim.x) {
-        int64_t base = s_jbase[j], n = s_jbase[j + 1] - base;
-        uint64_t carry = 0;
-        for (int64_t c0 = 0; c0 < n; c0 += blockDim.x) {
-            int64_t i = c0 + t;
-            uint32_t x = i < n ? a.tcount[base + i] : 0u;
-            uint32_t tot;
-            uint32_t pre = block_excl_scan(x, s_w, &tot);
-            if (i < n) a.tcount[base + i] = (uint32_t)(carry + pre);
-            carry += tot;
+    if (a.n_jobs >= (int)gridDim.x) {
+        // at least as many jobs as work-groups: one work-group per job
+        for (int j = blockIdx.x; j < a.n_jobs; j += gridDim.x) {
+            int64_t base = s_jbase[j], n = s_jbase[j + 1] - base;
+            uint64_t carry = 0;
+            for (int64_t c0 = 0; c0 < n; c0 += blockDim.x) {
+                int64_t i = c0 + t;
+                uint32_t x = i < n ? a.tcount[base + i] : 0u;
+                uint32_t tot;
+                uint32_t pre = block_excl_scan(x, s_w, &tot);
+                if (i < n) a.tcount[base + i] = (uint32_t)(carry + pre);
+                carry += tot;
+            }
+            if (t == 0) a.counts[j] = (int64_t)carry;
         }
-        if (t == 0) a.counts[j] = (int64_t)carry;
+    } else {
+        // fewer jobs than work-groups: each job's counts are split over
+        // gridDim / n_jobs work-groups; every work-group sums its stretch,
+        // then (after a barrier) adds the sums of the stretches before its own
+        // and rewrites its stretch as prefixes
+        const int bj = (int)gridDim.x / a.n_jobs;
+        const int j = blockIdx.x / bj, r = blockIdx.x % bj;
+        int64_t base = 0, c0 = 0, c1 = 0;
+        if (j < a.n_jobs) {
+            base = s_jbase[j];
+            const int64_t n = s_jbase[j + 1] - base, len = (n + bj - 1) / bj;
+            c0 = (int64_t)r * len < n ? (int64_t)r * len : n;
+            c1 = c0 + len < n ? c0 + len : n;
+        }
+        uint32_t mine = 0;
+        for (int64_t c = c0 + t; c < c1; c += blockDim.x) mine += a.tcount[base + c];
+        uint32_t part;
+        (void)block_excl_scan(mine, s_w, &part);
+        if (t == 0 && j < a.n_jobs) a.bsum[blockIdx.x] = part;
+        grid_barrier(a.bar, sense);
+        if (j < a.n_jobs) {
+            uint32_t before = 0;
+            for (int k = t; k < r; k += blockDim.x) before += a.bsum[j * bj + k];
+            uint32_t pre_all;
+            (void)block_excl_scan(before, s_w, &pre_all);
+            if (t == 0 && r == bj - 1) a.counts[j] = (int64_t)pre_all + part;
+            uint64_t carry = pre_all;
+            for (int64_t cc = c0; cc < c1; cc += blockDim.x) {
+                const int64_t i = cc + t;
+                const uint32_t x = i < c1 ? a.tcount[base + i] : 0u;
+                uint32_t tot;
+                const uint32_t pre = block_excl_scan(x, s_w, &tot);
+                if (i < c1) a.tcount[base + i] = (uint32_t)(carry + pre);
+                carry += tot;
+            }
+        }
     }
     grid_barrier(a.bar, sense);
 
-    // ---- phase C: write ----
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        int sidx = set_of(tile);
-        int64_t lt = tile - s_tbase[sidx];
-        const BatchSet& S = a.sets[sidx];
-        DualMc d[PER];
-        bool live[PER];
+    // ---- phase C: write (same prefetch of the next tile) ----
+    if (blockIdx.x < n_tiles) {
+        sidx = set_of(blockIdx.x);
+        lt = blockIdx.x - s_tbase[sidx];
         load_duals(sidx, lt, d, live);
+    }
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t next = tile + gridDim.x;
+        if (next < n_tiles) {
+            sn = set_of(next);
+            ltn = next - s_tbase[sn];
+            load_duals(sn, ltn, dn, ln);
+        }
+        const BatchSet& S = a.sets[sidx];
         for (int j = 0; j < a.n_jobs; ++j) {
             if (s_job[j].set != sidx) continue;
             const float iso = s_job[j].iso;
@@ -1643,6 +1710,13 @@ __global__ __launch_bounds__(512) void k_batch(BatchArgs a) {
                     rel_slice += totp;
                 }
             }
+        }
+        sidx = sn;
+        lt = ltn;
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            d[p] = dn[p];
+            live[p] = ln[p];
         }
     }
 }
@@ -2010,6 +2084,7 @@ int batch_grid(const amr_batch* b, int block, int per, int64_t n_tiles) {
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
     if (per_cu > 2) per_cu = 2;
     int64_t g = (int64_t)b->cu_count * per_cu;
+    if (g > kMaxBatchGrid) g = kMaxBatchGrid;
     if (g > n_tiles) g = n_tiles;
     if (g < 1) g = 1;
     return (int)g;
@@ -2358,7 +2433,8 @@ int amr_batch_workspace_bytes(const amr_batch* b, int max_jobs, int block, int p
         return fail(AMR_EINVAL, "amr_batch_workspace_bytes: per_thread must be 1, 2 or 4");
     int64_t ts = (int64_t)block * per_thread;
     int64_t tiles = (b->max_set_duals + ts - 1) / ts;
-    *bytes = align256(sizeof(GridBar)) + align256((size_t)max_jobs * (size_t)tiles * sizeof(uint32_t));
+    *bytes = align256(sizeof(GridBar)) + align256((size_t)kMaxBatchGrid * sizeof(uint32_t)) +
+             align256((size_t)max_jobs * (size_t)tiles * sizeof(uint32_t));
     return AMR_OK;
 }
 
@@ -2379,7 +2455,8 @@ int amr_batch_isosurface(amr_batch* b, const amr_iso_job* jobs, int n_jobs, floa
     a.tris = tris;
     a.counts = counts;
     a.bar = (GridBar*)ws;
-    a.tcount = (uint32_t*)((char*)ws + align256(sizeof(GridBar)));
+    a.bsum = (uint32_t*)((char*)ws + align256(sizeof(GridBar)));
+    a.tcount = (uint32_t*)((char*)ws + align256(sizeof(GridBar)) + align256((size_t)kMaxBatchGrid * sizeof(uint32_t)));
     int64_t ts = (int64_t)block * per_thread;
     int64_t n_tiles = 0;
     // an upper bound is enough for the grid size: every set's tile count

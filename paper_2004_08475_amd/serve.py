@@ -93,12 +93,12 @@ def upload_bytes(n_cells: int, triangles_guess: int) -> int:
 
 class IsoServer:
     def __init__(self, resident: AmrSet, hbm_budget: int | None = None, upload_slots: int = 4,
-                 max_batch: int = 64, block: int = 256, per_thread: int = 1, curve_points: int = 64):
+                 max_batch: int = 64, block: int | None = None, per_thread: int | None = None,
+                 curve_points: int = 64):
         self.resident = resident
         self.device = resident.device
         self.batch = AmrBatch([resident])
         self.max_batch = max_batch
-        self.block, self.per_thread = block, per_thread
         if hbm_budget is None:
             free, _ = torch.cuda.mem_get_info(self.device)
             hbm_budget = int(free * 0.8)
@@ -112,11 +112,45 @@ class IsoServer:
         counts = torch.zeros(curve_points, dtype=torch.int64, device=self.device)
         jobs = self.batch.jobs_tensor([0] * curve_points, self.curve_iso, np.zeros(curve_points),
                                       np.zeros(curve_points))
+        if block is None or per_thread is None:
+            # launch shape for this set: the autotuner on a counting launch of
+            # a few isos from the middle of the curve (no output memory)
+            from . import autotune
+
+            k = 8
+            mid = self.curve_iso[curve_points // 4:curve_points // 4 + k]
+            tj = self.batch.jobs_tensor([0] * k, mid, np.zeros(k), np.zeros(k))
+            tc = torch.zeros(k, dtype=torch.int64, device=self.device)
+            block, per_thread, _ = autotune.tune(self.batch, tj, k, None, tc, reps=2)
+        self.block, self.per_thread = block, per_thread
         self.batch.run_into(jobs, curve_points, None, counts, block, per_thread)
         self.curve_tri = counts.cpu().numpy()
+        # a lone request goes through whichever is faster on this set: the
+        # plain single pass or a batched launch of one job (timed once here)
+        self.lone_plain = self._plain_is_faster()
         self.upload_slots = upload_slots
         self.stop = threading.Event()
         self._slot_sets = []  # kept until the server is dropped
+
+    def _plain_is_faster(self, reps: int = 3) -> bool:
+        iso = float(self.curve_iso[len(self.curve_iso) // 2])
+        cap = self.iso_cap(iso)
+        tris = torch.empty((cap, 9), dtype=torch.float32, device=self.device)
+        counts = torch.zeros(1, dtype=torch.int64, device=self.device)
+        jobs = self.batch.jobs_tensor([0], [iso], [0], [cap])
+
+        def run(fn):
+            fn()
+            torch.cuda.synchronize(self.device)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize(self.device)
+            return time.perf_counter() - t0
+
+        t_plain = run(lambda: self.resident.isosurface_into(iso, tris, cap))
+        t_batch = run(lambda: self.batch.run_into(jobs, 1, tris, counts, self.block, self.per_thread))
+        return t_plain <= t_batch
 
     # -- sizing -----------------------------------------------------------
     def iso_cap(self, iso: float) -> int:
@@ -145,7 +179,7 @@ class IsoServer:
 
     def _run_batch(self, reqs, results, stream):
         n = len(reqs)
-        if n == 1:
+        if n == 1 and self.lone_plain:
             return self._run_one(reqs[0], results, stream)
         isos = [r.iso for r in reqs]
         caps = np.array([self.iso_cap(v) for v in isos], np.int64)
