@@ -7,7 +7,7 @@
 //
 // Data layout in HBM
 //   input (caller, borrowed): SoA  xyz int32[n][3], level int32[n], value f32[n]
-//   index workspace (caller): records | cell ids | group list | scan states
+//   index workspace (caller): records | cell ids | group list + keys | scan states
 //     record (64 B, one per hash slot): val f32[8] | key u64 | pad
 //       A record belongs to one 2x2x2 block of level-m logical cells (a
 //       "group"): key = (m, block coordinates).  val[c] is the value of
@@ -15,14 +15,16 @@
 //       level m, the NaN "empty" when it is not, or the NaN "refined" when
 //       finer cells exist inside it.  One probe thus returns up to 8 cells,
 //       and the refined markers end a snap as soon as it meets finer cells.
-//     cell ids  int32[slots][8]: input index of the cell in each child slot
-//     group list int32[]: slots of the records that hold at least one cell
-//     scan states: decoupled look-back words of the group-list compaction
-//       and of the extraction
+//       Slots come in regions of 4096, one per 16x16x16 block of groups
+//       (Morton order inside), so neighbours share a few cache lines.
+//     cell ids  int32[slots][8]: input index of the cell in each child slot,
+//       filled in when an output first asks for cell indices
+//     group list int32[] + keys u64[]: the records that hold at least one cell
+//     scan states: look-back words of the compaction and of the extraction
 //
 // Extraction kernel (paper sec. 4.2-5): one work-group processes 32 groups,
-// eight lanes per group.  The lanes fetch the 27 neighbouring groups of
-// their group (same level; absent ones are resolved to the coarser cell that
+// eight lanes per group.  The lanes fetch the level-m cells of the 4x4x4
+// block around their group (absent ones resolved to the coarser cell that
 // covers them) into LDS, then evaluate the 27 corners of the group's 2x2x2
 // cell block.  A corner's logical dual is emitted when its 8 slots are all
 // covered by cells of this level or coarser and the lowest-numbered slot on
@@ -30,9 +32,10 @@
 // "precedes" order of rule 3 read as slot order (= lexicographic (z,y,x)
 // order of the lower corners of same-level cells).  Marching Cubes runs on
 // each emitted dual from a 256-entry table kept in LDS; degenerate triangles
-// are culled by comparing cell references; counts are prefix-summed within
-// the work-group and across work-groups by a decoupled look-back, so output
-// positions are deterministic and no count pass is needed.
+// are culled by comparing cell references.  Small sets run one fused pass
+// whose tiles find their output positions by a decoupled look-back; large
+// sets run a count pass, a scan of the tile totals and a write pass, so no
+// tile waits for another.  Output positions are deterministic either way.
 
 #include <hip/hip_runtime.h>
 
