@@ -1059,32 +1059,34 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
         const int idx = j + 8 * q;
         if (!valid || idx >= 27) continue;
         const int k = corner_of(idx);
-        int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
+        const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
+        const int p0 = kx + 4 * ky + 16 * kz;  // slot 0's cell; slot s adds ex + 4 ey + 16 ez
         // Slot 0 decides most corners: a level-m cell there outside this
         // group is the lowest same-level slot, so the dual belongs to another
         // group (or is rejected by rule 2 when that cell is refined)
-        if ((kx == 0 || ky == 0 || kz == 0) && s_l[gi][kx + 4 * ky + 16 * kz] == m) continue;
+        if ((kx == 0 || ky == 0 || kz == 0) && s_l[gi][p0] == m) continue;
         int refs[8];
         float vals[8];
         bool ok = true;
-        uint32_t same = 0, mine = 0;
+        uint32_t same = 0;
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-            const int px = kx + (s & 1), py = ky + ((s >> 1) & 1), pz = kz + (s >> 2);
-            const int p = px + 4 * py + 16 * pz;
-            int lv = s_l[gi][p];
-            float v = s_v[gi][p];
+            const int p = p0 + (s & 1) + 4 * ((s >> 1) & 1) + 16 * (s >> 2);
+            const int lv = s_l[gi][p];
+            const float v = s_v[gi][p];
             refs[s] = s_r[gi][p];
             vals[s] = v;
             // rule 1 (hole) and rule 2 (finer cells) both show as lv < 0 or a NaN
             ok = ok && lv >= 0 && v == v;
             same |= (lv == m ? 1u : 0u) << s;
-            // cells of this group sit at positions 1..2 on every axis
-            const bool in = ((px - 1) | (py - 1) | (pz - 1)) >= 0 && px <= 2 && py <= 2 && pz <= 2;
-            mine |= (in ? 1u : 0u) << s;
         }
+        // the slots inside this group (cell positions 1..2 on every axis):
+        // on an axis where the corner sits at 0 only e = 1, at 2 only e = 0
+        const uint32_t mine = (kx == 0 ? 0xAAu : kx == 1 ? 0xFFu : 0x55u) &
+                              (ky == 0 ? 0xCCu : ky == 1 ? 0xFFu : 0x33u) &
+                              (kz == 0 ? 0xF0u : kz == 1 ? 0xFFu : 0x0Fu);
         // rule 3: the lowest same-level slot must be a cell of this group
-        if (!ok || !same || !((mine >> (__ffs(same) - 1)) & 1)) continue;
+        if (!ok || !(same & (0u - same) & mine)) continue;
         ++n_dual;
         uint32_t cs = 0, keep = 0;
         if (!kDuals) {
