@@ -127,6 +127,41 @@ def test_deterministic_and_capacity_contract(amr):
     assert s.count(cs.iso)[0] == len(full)
 
 
+@pytest.mark.parametrize("name", ["octree-shell-256", "octree-sized-647k"])
+def test_isosurface_graph_replays(amr, name):
+    # amr_isosurface does no host synchronisation, so it can be captured in a
+    # HIP graph; replays with new isos (eager work in between) must equal the
+    # eager calls.  octree-shell-256 runs the fused pass, the 647k set the
+    # count / scan / write passes.
+    cs = CASES[name]()
+    _say("graph replay %s: %d cells" % (name, cs.n))
+    s = gpu_set(amr, cs)
+    isos = np.quantile(cs.value, [0.3, 0.5, 0.7, 0.5]).astype(np.float32)
+    cap = 2 * max(s.count(float(v))[0] for v in isos) + 64
+    tris = torch.zeros((cap, 9), dtype=torch.float32, device=s.device)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        s.isosurface_into(float(isos[0]), tris, cap)  # warm-up outside the graph
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graphs = []
+    for v in isos[:3]:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            s.isosurface_into(float(v), tris, cap)
+        graphs.append((g, float(v)))
+    torch.cuda.synchronize()
+    for g, v in graphs + graphs[::-1]:
+        g.replay()
+        torch.cuda.synchronize()
+        n = int(s.counts[0].item())
+        got = tris[:n].clone()
+        want = s.isosurface(v)["tris"]  # eager work between the replays
+        assert n == len(want)
+        assert torch.equal(got, want)
+
+
 def test_tri_dual_points_at_generating_dual(amr):
     cs = amrgen.random_octree(9, roots=4, root_level=3, p_split=0.5, p_hole=0.1, values="smooth")
     s = gpu_set(amr, cs)
