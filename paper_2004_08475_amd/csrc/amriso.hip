@@ -430,10 +430,26 @@ __global__ __launch_bounds__(64) void k_upload_finish(Ctrl* c) {
         wave_reduce(p.bad, [](unsigned long long a, unsigned long long b) { return a < b ? a : b; });
     unsigned long long hint = 0;
     for (int l = 0; l <= kMaxLevel; ++l) {
+        // only levels that occur can have cells
         const unsigned long long cnt =
-            wave_reduce(p.level_count[l], [](unsigned long long a, unsigned long long b) { return a + b; });
+            (l >= lmin && l <= lmax)
+                ? wave_reduce(p.level_count[l], [](unsigned long long a, unsigned long long b) { return a + b; })
+                : 0ull;
         if (r == 0) c->res.level_count[l] = cnt;
         hint += (cnt + 7) / 8;
+    }
+    // leave this replica clean for the next upload (every lane has read it)
+    {
+        Partial& q = c->part[r];
+        for (int a = 0; a < 3; ++a) {
+            q.lo[a] = INT32_MAX;
+            q.hi[a] = INT32_MIN;
+        }
+        q.lmin = INT32_MAX;
+        q.lmax = INT32_MIN;
+        q.err = 0;
+        q.bad = ~0ull;
+        for (int l = 0; l <= kMaxLevel; ++l) q.level_count[l] = 0;
     }
     if (r != 0) return;
     UpRes& u = c->res;
@@ -2118,6 +2134,12 @@ int amr_create(amr_set** out, int hip_device) {
     }
     memset(s->host_ctrl, 0, sizeof(Ctrl));
     e = hipMalloc((void**)&s->ctrl, sizeof(Ctrl));
+    if (e == hipSuccess) {
+        // clean replicas for the first upload
+        hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, 0, s->ctrl);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+    }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->up_event, hipEventDisableTiming);
     if (e != hipSuccess) {
         if (s->ctrl) (void)hipFree(s->ctrl);
@@ -2164,7 +2186,7 @@ int amr_upload(amr_set* s, const int32_t* xyz, const int32_t* level, const float
         s->uploaded = true;
         return AMR_OK;
     }
-    hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, stream, s->ctrl);
+    // the replicas are clean: amr_create and every k_upload_finish leave them so
     hipLaunchKernelGGL(k_upload, dim3(grid_for(n, 256)), dim3(256), 0, stream, xyz, level, value, n, s->ctrl);
     hipLaunchKernelGGL(k_upload_finish, dim3(1), dim3(kReplicas), 0, stream, s->ctrl);
     hipError_t e = hipGetLastError();
