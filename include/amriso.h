@@ -219,8 +219,11 @@ int amr_indexed_mesh_bytes(int64_t n_tris, size_t* bytes);
    idx       device int32 [n_tris][3]: vertex index of every corner
    n_verts   device int64 [1]: number of unique vertices (verts past cap_verts
              are not written; idx is always complete)
-   workspace device, >= amr_indexed_mesh_bytes(n_tris), 256-byte aligned.
-   No host synchronisation.  n_tris must be below 2^29. */
+   workspace device, >= amr_indexed_mesh_bytes(n_tris), 256-byte aligned;
+             no initial contents needed.
+   No host synchronisation.  Returns AMR_ERANGE unless 0 <= n_tris < 2^29,
+   AMR_EINVAL for NULL arrays or an unaligned workspace, AMR_ENOSPACE for a
+   workspace below amr_indexed_mesh_bytes. */
 int amr_indexed_mesh(const float* tris, const int32_t* tri_cells, int64_t n_tris, float* verts, int32_t* idx,
                      int64_t cap_verts, int64_t* n_verts, void* workspace, size_t bytes, hipStream_t stream);
 
