@@ -764,6 +764,7 @@ struct ExtractArgs {
     int64_t cap;
     int64_t* counts;
     unsigned long long* tot;    // per tile: triangles << 32 | duals (count pass)
+    unsigned long long* gcnt;   // per group: triangles << 32 | duals (count pass)
     unsigned long long* pre_t;  // per tile: exclusive prefix of triangles (scan)
     unsigned long long* pre_d;  // per tile: exclusive prefix of duals (scan)
     unsigned long long* sc0;    // per scan tile: look-back states
@@ -930,10 +931,23 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
     const bool valid = gidx < a.n_groups;
     const Geo g = a.g;
 
+    // In the write pass a group with nothing to write this time needs no
+    // neighbourhood: it only brings its dual count (from the count pass) to
+    // the scan, through its first lane.
+    bool work = valid;
+    uint32_t carried_duals = 0;
+    if (kPass == kPassWrite && valid) {
+        const unsigned long long gc = a.gcnt[gidx];
+        if ((kDuals ? (gc & 0xFFFFFFFFull) : (gc >> 32)) == 0) {
+            work = false;
+            carried_duals = j == 0 ? (uint32_t)(gc & 0xFFFFFFFFull) : 0u;
+        }
+    }
+
     int m = 0;
     uint32_t gx = 0, gy = 0, gz = 0;
     int own = 0;
-    if (valid) {
+    if (work) {
         own = a.glist[gidx];
         uint64_t key = a.gkey[gidx];
         m = (int)(key >> 57);
@@ -943,7 +957,7 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
     }
 
     // ---- phase 1: the 27 neighbouring groups of this group, into LDS ----
-    if (valid) {
+    if (work) {
         // lane j owns neighbours j, j+8, j+16 (and j+24 for j < 3); the home
         // slots of all of them are loaded before any is examined
         uint64_t want[4], got[4];
@@ -1073,7 +1087,7 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
     for (int q = 0; q < 4; ++q) {
         items[q] = 0;
         const int idx = j + 8 * q;
-        if (!valid || idx >= 27) continue;
+        if (!work || idx >= 27) continue;
         const int k = corner_of(idx);
         const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
         const int p0 = kx + 4 * ky + 16 * kz;  // slot 0's cell; slot s adds ex + 4 ey + 16 ez
@@ -1119,6 +1133,16 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
             }
         }
         items[q] = 0x80000000u | ((uint32_t)k << 20) | (cs << 8) | keep;
+    }
+
+    n_dual += (int)carried_duals;
+    if (kPass == kPassCount) {
+        // the group's totals, for the write pass to skip groups without output
+        unsigned long long gsum = ((unsigned long long)n_tri << 32) | (unsigned long long)n_dual;
+        gsum += __shfl_xor(gsum, 1, 64);
+        gsum += __shfl_xor(gsum, 2, 64);
+        gsum += __shfl_xor(gsum, 4, 64);
+        if (valid && j == 0) a.gcnt[gidx] = gsum;
     }
 
     // ---- block scan of (triangles, duals) ----
@@ -1923,6 +1947,7 @@ struct amr_set {
     int32_t* glist = nullptr;
     unsigned long long* gkey = nullptr;
     unsigned long long* tot = nullptr;   // extraction: per-tile totals
+    unsigned long long* gcnt = nullptr;  // extraction: per-group totals
     unsigned long long* st_t = nullptr;  // extraction: per-tile prefixes
     unsigned long long* st_d = nullptr;
     unsigned long long* xs0 = nullptr;   // extraction scan: look-back states
@@ -1945,7 +1970,7 @@ uint32_t table_cap(const amr_set* s) {
 }
 
 struct Layout {
-    size_t rec, ids, glist, gkey, tot, st_t, st_d, xs0, xs1, fs0, fs1, ct0, ct1, sched, total;
+    size_t rec, ids, glist, gkey, gcnt, tot, st_t, st_d, xs0, xs1, fs0, fs1, ct0, ct1, sched, total;
     uint32_t max_tiles, max_scan_tiles, compact_tiles;
     int compact_per;
 };
@@ -1966,6 +1991,8 @@ Layout layout_for(uint32_t cap) {
     L.glist = off;
     off = align256(off + (size_t)max_groups * sizeof(int32_t));
     L.gkey = off;
+    off = align256(off + (size_t)max_groups * sizeof(unsigned long long));
+    L.gcnt = off;
     off = align256(off + (size_t)max_groups * sizeof(unsigned long long));
     L.max_scan_tiles = (L.max_tiles + kBlock * kScanPer - 1) / (kBlock * kScanPer);
     L.tot = off;
@@ -2046,6 +2073,7 @@ int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_
     a.cap = cap;
     a.counts = counts;
     a.tot = s->tot;
+    a.gcnt = s->gcnt;
     a.pre_t = s->st_t;
     a.pre_d = s->st_d;
     a.sc0 = s->xs0;
@@ -2279,6 +2307,7 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     s->ids = (int32_t*)(base + L.ids);
     s->glist = (int32_t*)(base + L.glist);
     s->gkey = (unsigned long long*)(base + L.gkey);
+    s->gcnt = (unsigned long long*)(base + L.gcnt);
     s->tot = (unsigned long long*)(base + L.tot);
     s->st_t = (unsigned long long*)(base + L.st_t);
     s->st_d = (unsigned long long*)(base + L.st_d);
