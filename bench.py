@@ -353,6 +353,35 @@ def roofline_of(n_cells, n_tri, iso_ms, traffic):
             "algorithmic_bytes": alg, "avg_launch_ms": iso_ms}
 
 
+def resident_iso_measurement(s, cs, reps=3):
+    """Single-pass iso-surfaces at 19 quantiles of the values on the built
+    set (its group value ranges already recorded, so the passes skip groups
+    that cannot hold triangles), HIP events around each call on the stream
+    the kernels run on."""
+    import numpy as np
+    import torch
+
+    stream = torch.cuda.current_stream()
+    isos = np.quantile(cs.value, np.linspace(0.05, 0.95, 19)).astype(np.float32)
+    counts = [s.count(float(v))[0] for v in isos]
+    tris = torch.empty((max(max(counts), 1), 9), dtype=torch.float32, device=s.device)
+    evs = []
+    for _ in range(reps):
+        for v, c in zip(isos, counts):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            s.isosurface_into(float(v), tris, c)
+            e1.record(stream)
+            evs.append((e0, e1))
+    torch.cuda.synchronize()
+    ms = [a.elapsed_time(b) for a, b in evs]
+    mean = statistics.mean(ms)
+    return {"isos": len(isos), "reps": reps, "ms_mean": mean, "ms_min": min(ms), "ms_max": max(ms),
+            "triangles_mean": statistics.mean(counts), "cells_per_s": cs.n / (mean * 1e-3),
+            "what": "amr_isosurface single pass (count, scan, write) at quantiles 0.05..0.95 of the values, "
+                    "group value ranges recorded by an earlier call"}
+
+
 def large_measurement(amr, name, steps):
     """The same whole-path step on a large set (block-structured, 50.8M
     cells), where throughput rather than launch latency decides."""
@@ -369,11 +398,13 @@ def large_measurement(amr, name, steps):
     ms, (up, bd, iso) = time_steps(amr, s, xyz, lvl, val, cs.iso, n_tri, tris, steps, 2)
     assert int(s.counts[0].item()) == n_tri
     iso_avg = statistics.mean(iso)
+    resident = resident_iso_measurement(s, cs)
     out = {"workload": name, "cells": cs.n, "triangles": n_tri, "duals": n_dual, "steps": steps,
            "ms_per_step": ms, "cells_per_s": cs.n / (ms * 1e-3),
            "stages_ms": {"upload": statistics.mean(up), "build_index": statistics.mean(bd), "isosurface": iso_avg},
            "iso_only_cells_per_s": cs.n / (iso_avg * 1e-3),
-           "roofline": roofline_of(cs.n, n_tri, iso_avg, traffic_for(name))}
+           "roofline": roofline_of(cs.n, n_tri, iso_avg, traffic_for(name)),
+           "resident_iso": resident}
     del s, xyz, lvl, val, tris
     torch.cuda.empty_cache()
     return out
@@ -516,6 +547,7 @@ def main():
         "iso_latency_ms": {"p50": percentile(lat, 0.5), "p99": percentile(lat, 0.99), "requests": len(lat),
                            "what": "count pass + write pass on the resident set, host clock"},
         "roofline": roofline_of(cs.n, n_tri, iso_avg, traffic_for(cs.name)),
+        "resident_iso": resident_iso_measurement(s, cs),
     }
     say("timed steps done: %.3f ms/step" % ms_per_step)
     if args.large != "none":

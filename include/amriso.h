@@ -142,8 +142,18 @@ int amr_dual_cells(amr_set* set, int32_t* corner_level, int32_t* verts, float* v
                                   amr_dual_cells writes them
    counts: device int64 [2]; counts[0] = triangles, counts[1] = emitted
    duals.  Triangles past cap are not written.  Asynchronous and free of
-   host synchronisation, so it can be captured in a HIP graph.  Returns
-   AMR_EINVAL for a non-finite iso, AMR_ESTATE before amr_build_index. */
+   host synchronisation, so it can be captured in a HIP graph (a captured
+   call stays valid until the set is built again).  Returns AMR_EINVAL for
+   a non-finite iso, AMR_ESTATE before amr_build_index.
+   Range culling (not part of the paper; outputs are identical with or
+   without it): the second extraction after a build (this call or
+   amr_dual_cells) also records, per 2x2x2 group of cells, the minimum and
+   maximum cell value of the group's 4x4x4 neighbourhood (8 bytes per group,
+   inside the index workspace) and the set's dual count; a set extracted
+   only once never pays for that.  From the third extraction on, calls that
+   pass tri_dual == NULL skip every group whose range lies entirely below
+   iso or entirely at or above it: all its duals have Marching Cubes case 0
+   or 255. */
 int amr_isosurface(amr_set* set, float iso, float* tris, int32_t* tri_cells, int32_t* tri_dual, int64_t cap,
                    int64_t* counts, hipStream_t stream);
 

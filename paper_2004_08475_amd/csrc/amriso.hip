@@ -133,6 +133,7 @@ struct Sched {
     unsigned long long fcall;    // fused extraction calls started
     unsigned long long cticket;  // compaction tiles started
     unsigned long long fticket;  // fused extraction tiles started, over all calls
+    unsigned long long lticket;  // candidate-list work-groups started, over all calls
 };
 
 __device__ __forceinline__ uint64_t group_key(int m, uint32_t gx, uint32_t gy, uint32_t gz) {
@@ -490,7 +491,9 @@ __global__ __launch_bounds__(64) void k_upload_finish(Ctrl* c) {
 // Start of a build: empty records, clean scan states, zero build results.
 __global__ __launch_bounds__(256) void k_build_reset(Record* __restrict__ rec, uint32_t cap, int shift, Sched* sc,
                                                      unsigned long long* ct0, unsigned long long* ct1, uint32_t nc,
-                                                     unsigned long long* fs0, unsigned long long* fs1, Ctrl* c) {
+                                                     unsigned long long* fs0, unsigned long long* fs1,
+                                                     unsigned long long* ls0, unsigned long long* ls1, uint32_t nl,
+                                                     Ctrl* c) {
     const float e = __uint_as_float(kValEmpty);
     const uint32_t i0 = blockIdx.x * blockDim.x + threadIdx.x, step = gridDim.x * blockDim.x;
     for (uint32_t i = i0; i < cap; i += step) {
@@ -508,12 +511,17 @@ __global__ __launch_bounds__(256) void k_build_reset(Record* __restrict__ rec, u
         fs0[i] = 0;
         fs1[i] = 0;
     }
+    for (uint32_t i = i0; i < nl; i += step) {
+        ls0[i] = 0;
+        ls1[i] = 0;
+    }
     if (i0 < (uint32_t)kReplicas) c->made[i0 * 16] = 0;
     if (i0 == 0) {
         sc->xticket = 0;
         sc->fcall = 0;
         sc->cticket = 0;
         sc->fticket = 0;
+        sc->lticket = 0;
         c->overflow = 0;
         c->dup = 0;
         c->overlap = 0;
@@ -772,7 +780,18 @@ struct ExtractArgs {
     Sched* sched;
     uint32_t n_tiles;
     uint32_t n_scan_tiles;
+    // value range of each group's 4x4x4 neighbourhood (min, max over its
+    // cells), recorded by the first full pass after a build and then used to
+    // skip groups in iso-surface passes; the set's dual count goes with it
+    float2* rng;
+    unsigned long long* dual_total;
+    int rng_mode;
+    // candidate list of a culled count / write pass (k_cull_list)
+    const uint32_t* clist;
+    const unsigned long long* n_list;
 };
+
+enum : int { kRngNone = 0, kRngRecord = 1, kRngCull = 2 };
 
 __global__ void k_counts_zero(int64_t* counts) {
     if (threadIdx.x == 0 && counts) {
@@ -860,8 +879,13 @@ __device__ __forceinline__ uint32_t keep_by_classes(uint32_t cls, unsigned long 
 // output position by a decoupled look-back over earlier tickets.
 enum : int { kPassCount = 0, kPassWrite = 1, kPassFused = 2 };
 
-template <bool kDuals, int kPass>
-__global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
+// One tile of 32 groups: all of them (group index = tile * 32 + i) or, with
+// kList, 32 entries of the candidate list of an iso-value (n_list long).
+// `call` is the fused pass's call number.  Every return is taken by the
+// whole work-group.
+template <bool kDuals, int kPass, bool kList>
+__device__ __forceinline__ void extract_tile(const ExtractArgs& a, const uint32_t tile, const uint32_t n_list,
+                                             const unsigned long long call) {
     // the 4x4x4 cells of level m around each group (offsets -1..2 from its
     // lower corner, x fastest): value, cell reference, level of the cell that
     // covers the position (-1: none)
@@ -880,33 +904,6 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
     const int t = threadIdx.x;
     const int gi = t >> 3;  // group within the tile
     const int j = t & 7;    // lane within the group
-    __shared__ uint32_t s_tile;
-    __shared__ unsigned long long s_call;
-    if (kPass == kPassFused) {
-        if (threadIdx.x == 0) {
-            // Tiles take tickets in start order.  The call number is read
-            // before the ticket: the ticket's address depends on the value
-            // read (call >> 63 is always 0), so the read completes first.  By
-            // the time the last tile of this call holds its ticket every tile
-            // of the call has read the number, and the last tile may advance
-            // it at once for the next call.
-            const unsigned long long call = ld_relaxed(&a.sched->fcall);
-            const unsigned long long tk = atomicAdd(&a.sched->fticket + (call >> 63), 1ull);
-            const unsigned long long tl = tk - call * a.n_tiles;
-            s_call = call;
-            s_tile = tl < a.n_tiles ? (uint32_t)tl : 0xFFFFFFFFu;
-            if (tl == a.n_tiles - 1)
-                __hip_atomic_store(&a.sched->fcall, call + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __syncthreads();
-        if (s_tile == 0xFFFFFFFFu) return;  // cannot happen while calls on a set do not overlap
-    }
-    // count and write passes: work-groups go round-robin to the 8 XCDs, so
-    // XCD x is given the contiguous run of tiles [x*T, (x+1)*T) in order and
-    // its L2 sees neighbouring tiles one after another
-    const uint32_t per_xcd = gridDim.x / kXcds;
-    const uint32_t tile = kPass == kPassFused ? s_tile : (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
-    if (kPass != kPassFused && tile >= a.n_tiles) return;
     if (kPass == kPassWrite) {
         // nothing of this tile lands below the capacity: done
         const unsigned long long tt = a.tot[tile];
@@ -917,7 +914,7 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
             s_pre_t = a.pre_t[tile];
             s_pre_d = a.pre_d[tile];
         }
-    } else if (kPass == kPassCount && t == 0) {
+    } else if (kPass == kPassCount && !kList && t == 0) {
         // the scan that follows starts from clean states
         if (tile < a.n_scan_tiles) {
             a.sc0[tile] = 0;
@@ -927,8 +924,16 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
     }
     if (!kDuals) s_tab[t] = kMcTable[t];
     __syncthreads();
-    const uint32_t gidx = tile * kGroupsPerTile + gi;
-    const bool valid = gidx < a.n_groups;
+    uint32_t gidx;
+    bool valid;
+    if (kList) {
+        const uint32_t li = tile * kGroupsPerTile + gi;
+        valid = li < n_list;
+        gidx = valid ? a.clist[li] : 0u;
+    } else {
+        gidx = tile * kGroupsPerTile + gi;
+        valid = gidx < a.n_groups;
+    }
     const Geo g = a.g;
 
     // In the write pass a group with nothing to write this time needs no
@@ -942,6 +947,15 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
             work = false;
             carried_duals = j == 0 ? (uint32_t)(gc & 0xFFFFFFFFull) : 0u;
         }
+    }
+    // A group whose neighbourhood values all lie on one side of iso has only
+    // Marching Cubes cases 0 and 255 at its corners: no triangles.  (Its
+    // duals are not counted here; the set's total was recorded.)  The count
+    // and write passes get such groups filtered out beforehand (kList).
+    const bool cull = !kDuals && kPass == kPassFused && a.rng_mode == kRngCull;
+    if (cull && valid) {
+        const float2 r = a.rng[gidx];
+        work = r.x < a.iso && r.y >= a.iso;
     }
 
     int m = 0;
@@ -1078,6 +1092,28 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
         }
     }
     __syncthreads();
+    if (kPass != kPassWrite && a.rng_mode == kRngRecord) {
+        // the range of the cells in the neighbourhood (holes and the markers
+        // of refined or empty slots excluded); lane j takes 8 of the 64
+        float lo = INFINITY, hi = -INFINITY;
+        if (work) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const float v = s_v[gi][8 * j + c];
+                if (s_l[gi][8 * j + c] >= 0 && v == v) {
+                    lo = fminf(lo, v);
+                    hi = fmaxf(hi, v);
+                }
+            }
+        }
+        lo = fminf(lo, __shfl_xor(lo, 1, 64));
+        hi = fmaxf(hi, __shfl_xor(hi, 1, 64));
+        lo = fminf(lo, __shfl_xor(lo, 2, 64));
+        hi = fmaxf(hi, __shfl_xor(hi, 2, 64));
+        lo = fminf(lo, __shfl_xor(lo, 4, 64));
+        hi = fmaxf(hi, __shfl_xor(hi, 4, 64));
+        if (valid && j == 0) a.rng[gidx] = make_float2(lo, hi);
+    }
 
     // ---- phase 2: the 27 corners of the group's 2x2x2 block ----
     const float iso = a.iso;
@@ -1167,14 +1203,18 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
             unsigned long long pre_t, pre_d;
             const unsigned long long agg_t = total >> 32, agg_d = total & 0xFFFFFFFFull;
             // states of the previous call carry the other parity
-            const unsigned long long par = (s_call & 1) ? kParityBit : 0ull;
+            const unsigned long long par = (call & 1) ? kParityBit : 0ull;
             lookback(a.sc0, a.sc1, tile, par, agg_t, agg_d, pre_t, pre_d);
             if (lane_id() == 0) {
                 s_pre_t = pre_t;
                 s_pre_d = pre_d;
-                if (tile == a.n_tiles - 1 && a.counts) {
-                    a.counts[0] = kDuals ? (int64_t)(pre_d + agg_d) : (int64_t)(pre_t + agg_t);
-                    a.counts[1] = (int64_t)(pre_d + agg_d);
+                if (tile == a.n_tiles - 1) {
+                    const unsigned long long nd = cull ? *a.dual_total : pre_d + agg_d;
+                    if (a.rng_mode == kRngRecord) *a.dual_total = nd;
+                    if (a.counts) {
+                        a.counts[0] = kDuals ? (int64_t)nd : (int64_t)(pre_t + agg_t);
+                        a.counts[1] = (int64_t)nd;
+                    }
                 }
             }
         }
@@ -1319,6 +1359,118 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
     }
 }
 
+template <bool kDuals, int kPass>
+__global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
+    __shared__ uint32_t s_tile;
+    __shared__ unsigned long long s_call;
+    if (kPass == kPassFused) {
+        if (threadIdx.x == 0) {
+            // Tiles take tickets in start order.  The call number is read
+            // before the ticket: the ticket's address depends on the value
+            // read (call >> 63 is always 0), so the read completes first.  By
+            // the time the last tile of this call holds its ticket every tile
+            // of the call has read the number, and the last tile may advance
+            // it at once for the next call.
+            const unsigned long long call = ld_relaxed(&a.sched->fcall);
+            const unsigned long long tk = atomicAdd(&a.sched->fticket + (call >> 63), 1ull);
+            const unsigned long long tl = tk - call * a.n_tiles;
+            s_call = call;
+            s_tile = tl < a.n_tiles ? (uint32_t)tl : 0xFFFFFFFFu;
+            if (tl == a.n_tiles - 1)
+                __hip_atomic_store(&a.sched->fcall, call + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        if (s_tile == 0xFFFFFFFFu) return;  // cannot happen while calls on a set do not overlap
+    }
+    // count and write passes: work-groups go round-robin to the 8 XCDs, so
+    // XCD x is given the contiguous run of tiles [x*T, (x+1)*T) in order and
+    // its L2 sees neighbouring tiles one after another
+    const uint32_t per_xcd = gridDim.x / kXcds;
+    const uint32_t tile = kPass == kPassFused ? s_tile : (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+    if (kPass != kPassFused && tile >= a.n_tiles) return;
+    extract_tile<kDuals, kPass, false>(a, tile, 0u, kPass == kPassFused ? s_call : 0ull);
+}
+
+// Candidate groups of one iso-value: those whose neighbourhood range
+// straddles iso (all others have only Marching Cubes cases 0 and 255), in
+// group order.  The compaction is stable, so passes over the list emit the
+// triangles in the order passes over all groups would.  Work-groups take
+// tickets in start order; each call takes exactly n_wgs of them, so the
+// ticket also gives the call's parity for the look-back states.  The last
+// work-group writes the list's length.
+constexpr int kListPer = 16;  // groups per thread
+
+__global__ __launch_bounds__(kBlock) void k_cull_list(const float2* __restrict__ rng, uint32_t n_groups, float iso,
+                                                      uint32_t n_wgs, uint32_t* __restrict__ clist,
+                                                      unsigned long long* n_list, unsigned long long* ls0,
+                                                      unsigned long long* ls1, Sched* sc) {
+    __shared__ uint32_t s_row[kListPer][kBlock / 64];
+    __shared__ unsigned long long s_tk, s_pre;
+    const int t = threadIdx.x, wave = t >> 6, lane = lane_id();
+    if (t == 0) s_tk = atomicAdd(&sc->lticket, 1ull);
+    __syncthreads();
+    const unsigned long long tk = s_tk;
+    const uint32_t wg = (uint32_t)(tk % n_wgs);
+    const unsigned long long par = ((tk / n_wgs) & 1) ? kParityBit : 0ull;
+    const uint64_t base = (uint64_t)wg * (kBlock * kListPer);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    uint32_t keep = 0, rank[kListPer];
+#pragma unroll
+    for (int r = 0; r < kListPer; ++r) {
+        const uint64_t i = base + (uint64_t)r * kBlock + t;
+        bool c = false;
+        if (i < n_groups) {
+            const float2 g = rng[i];
+            c = g.x < iso && g.y >= iso;
+        }
+        const unsigned long long b = __ballot(c);
+        rank[r] = (uint32_t)__popcll(b & below);
+        keep |= (c ? 1u : 0u) << r;
+        if (lane == 0) s_row[r][wave] = (uint32_t)__popcll(b);
+    }
+    __syncthreads();
+    if (wave == 0) {
+        uint32_t total = 0;
+        for (int r = 0; r < kListPer; ++r)
+            for (int q = 0; q < kBlock / 64; ++q) total += s_row[r][q];
+        unsigned long long p0, p1;
+        lookback(ls0, ls1, wg, par, total, 0ull, p0, p1);
+        if (lane == 0) {
+            s_pre = p0;
+            if (wg == n_wgs - 1) *n_list = p0 + total;
+        }
+    }
+    __syncthreads();
+    unsigned long long carry = s_pre;
+    for (int r = 0; r < kListPer; ++r) {
+        uint32_t wave_pre = 0, row = 0;
+        for (int q = 0; q < kBlock / 64; ++q) {
+            if (q < wave) wave_pre += s_row[r][q];
+            row += s_row[r][q];
+        }
+        if ((keep >> r) & 1) clist[carry + wave_pre + rank[r]] = (uint32_t)(base + (uint64_t)r * kBlock + t);
+        carry += row;
+    }
+}
+
+// Count and write passes over the candidate list of one iso-value.  The
+// list's length is known only on the device: the grid covers every group,
+// and work-groups past the list's last tile leave at once.
+template <int kPass>
+__global__ __launch_bounds__(kBlock) void k_extract_list(ExtractArgs a) {
+    const uint32_t n = (uint32_t)*a.n_list;
+    const uint32_t n_tiles = (n + kGroupsPerTile - 1) / kGroupsPerTile;
+    if (kPass == kPassCount) {
+        // the scan that follows starts from clean states
+        for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < a.n_scan_tiles; i += gridDim.x * kBlock) {
+            a.sc0[i] = 0;
+            a.sc1[i] = 0;
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.sched->xticket = 0;
+    }
+    if (blockIdx.x < n_tiles) extract_tile<false, kPass, true>(a, blockIdx.x, n, 0ull);
+}
+
 // Exclusive scan of the per-tile (triangles, duals) totals of a count pass:
 // 4096 tiles per work-group, decoupled look-back across work-groups (tickets
 // keep the look-back waiting only on work-groups that already run).  The
@@ -1330,6 +1482,9 @@ __global__ __launch_bounds__(kBlock) void k_tile_scan(ExtractArgs a, int duals) 
     __shared__ unsigned long long s_p0, s_p1;
     __shared__ uint32_t s_st;
     const int t = threadIdx.x, wave = t >> 6, lane = lane_id();
+    // over a candidate list the tile count is known on the device only
+    const uint32_t n_tiles =
+        a.n_list ? (uint32_t)((*a.n_list + kGroupsPerTile - 1) / kGroupsPerTile) : a.n_tiles;
     if (t == 0) s_st = (uint32_t)atomicAdd(&a.sched->xticket, 1ull);
     __syncthreads();
     const uint32_t st = s_st;
@@ -1341,7 +1496,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_scan(ExtractArgs a, int duals) 
 #pragma unroll
     for (int r = 0; r < kScanPer; ++r) {
         uint64_t i = base + (uint64_t)r * kBlock + t;
-        v[r] = i < a.n_tiles ? a.tot[i] : 0ull;
+        v[r] = i < n_tiles ? a.tot[i] : 0ull;
         incl[r] = wave_incl_scan(v[r]);
         if (lane == 63) s_row[r][wave] = incl[r];
     }
@@ -1355,9 +1510,15 @@ __global__ __launch_bounds__(kBlock) void k_tile_scan(ExtractArgs a, int duals) 
         if (lane == 0) {
             s_p0 = p0;
             s_p1 = p1;
-            if (st == a.n_scan_tiles - 1 && a.counts) {
-                a.counts[0] = (int64_t)(duals ? p1 + (total & 0xFFFFFFFFull) : p0 + (total >> 32));
-                a.counts[1] = (int64_t)(p1 + (total & 0xFFFFFFFFull));
+            if (st == a.n_scan_tiles - 1) {
+                // a culled pass counts no duals: the set's total stands in
+                const unsigned long long nd =
+                    a.rng_mode == kRngCull && !duals ? *a.dual_total : p1 + (total & 0xFFFFFFFFull);
+                if (a.rng_mode == kRngRecord) *a.dual_total = nd;
+                if (a.counts) {
+                    a.counts[0] = (int64_t)(duals ? nd : p0 + (total >> 32));
+                    a.counts[1] = (int64_t)nd;
+                }
             }
         }
     }
@@ -1371,7 +1532,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_scan(ExtractArgs a, int duals) 
             row += s_row[r][q];
         }
         uint64_t i = base + (uint64_t)r * kBlock + t;
-        if (i < a.n_tiles) {
+        if (i < n_tiles) {
             unsigned long long ex = carry + wave_pre + incl[r] - v[r];
             a.pre_t[i] = p0 + (ex >> 32);
             a.pre_d[i] = p1 + (ex & 0xFFFFFFFFull);
@@ -1944,6 +2105,13 @@ struct amr_set {
     Record* rec = nullptr;
     int32_t* ids = nullptr;
     bool ids_ready = false;  // input indices filled in (on first use)
+    int extractions = 0;     // extraction calls since the build (saturates at 2)
+    float2* rng = nullptr;
+    unsigned long long* dual_total = nullptr;
+    uint32_t* clist = nullptr;              // candidate list of a culled pass
+    unsigned long long* n_list = nullptr;
+    unsigned long long* ls0 = nullptr;      // candidate list: look-back states
+    unsigned long long* ls1 = nullptr;
     int32_t* glist = nullptr;
     unsigned long long* gkey = nullptr;
     unsigned long long* tot = nullptr;   // extraction: per-tile totals
@@ -1970,8 +2138,9 @@ uint32_t table_cap(const amr_set* s) {
 }
 
 struct Layout {
-    size_t rec, ids, glist, gkey, gcnt, tot, st_t, st_d, xs0, xs1, fs0, fs1, ct0, ct1, sched, total;
-    uint32_t max_tiles, max_scan_tiles, compact_tiles;
+    size_t rec, ids, glist, gkey, gcnt, rng, clist, tot, st_t, st_d, xs0, xs1, fs0, fs1, ct0, ct1, ls0, ls1, sched,
+        dual_total, n_list, total;
+    uint32_t max_tiles, max_scan_tiles, compact_tiles, max_list_wgs;
     int compact_per;
 };
 
@@ -1994,6 +2163,10 @@ Layout layout_for(uint32_t cap) {
     off = align256(off + (size_t)max_groups * sizeof(unsigned long long));
     L.gcnt = off;
     off = align256(off + (size_t)max_groups * sizeof(unsigned long long));
+    L.rng = off;
+    off = align256(off + (size_t)max_groups * sizeof(float2));
+    L.clist = off;
+    off = align256(off + (size_t)max_groups * sizeof(uint32_t));
     L.max_scan_tiles = (L.max_tiles + kBlock * kScanPer - 1) / (kBlock * kScanPer);
     L.tot = off;
     off = align256(off + (size_t)L.max_tiles * 8);
@@ -2015,6 +2188,15 @@ Layout layout_for(uint32_t cap) {
     off = align256(off + (size_t)L.compact_tiles * 8);
     L.sched = off;
     off = align256(off + sizeof(Sched));
+    L.dual_total = off;
+    off = align256(off + sizeof(unsigned long long));
+    L.n_list = off;
+    off = align256(off + sizeof(unsigned long long));
+    L.max_list_wgs = (max_groups + kBlock * kListPer - 1) / (kBlock * kListPer);
+    L.ls0 = off;
+    off = align256(off + (size_t)L.max_list_wgs * 8);
+    L.ls1 = off;
+    off = align256(off + (size_t)L.max_list_wgs * 8);
     L.total = off;
     return L;
 }
@@ -2081,6 +2263,17 @@ int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_
     a.sched = s->sched;
     a.n_tiles = n_tiles;
     a.n_scan_tiles = (n_tiles + kBlock * kScanPer - 1) / (kBlock * kScanPer);
+    // The second extraction after a build records the group value ranges
+    // (a set extracted once never pays for them); from the third on,
+    // iso-surfaces use them unless triangles name their duals (whose
+    // numbering needs every group's dual count).
+    a.rng = s->rng;
+    a.dual_total = s->dual_total;
+    a.rng_mode = s->extractions == 0   ? kRngNone
+                 : s->extractions == 1 ? kRngRecord
+                 : (!duals && tri_dual == nullptr ? kRngCull : kRngNone);
+    a.clist = nullptr;
+    a.n_list = nullptr;
     if (n_tiles <= kFusedMaxTiles) {
         // one fused pass (look-back states alternate parity between calls)
         a.sc0 = s->fs0;
@@ -2089,6 +2282,17 @@ int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_
             hipLaunchKernelGGL((k_extract<true, kPassFused>), dim3(n_tiles), dim3(kBlock), 0, stream, a);
         else
             hipLaunchKernelGGL((k_extract<false, kPassFused>), dim3(n_tiles), dim3(kBlock), 0, stream, a);
+    } else if (a.rng_mode == kRngCull) {
+        // list the candidate groups, then count, scan and write over the list
+        const bool write = cap > 0 && (tris || tri_cells);
+        const uint32_t n_wgs = (s->n_groups + kBlock * kListPer - 1) / (kBlock * kListPer);
+        hipLaunchKernelGGL(k_cull_list, dim3(n_wgs), dim3(kBlock), 0, stream, s->rng, s->n_groups, iso, n_wgs,
+                           s->clist, s->n_list, s->ls0, s->ls1, s->sched);
+        a.clist = s->clist;
+        a.n_list = s->n_list;
+        hipLaunchKernelGGL(k_extract_list<kPassCount>, dim3(n_tiles), dim3(kBlock), 0, stream, a);
+        hipLaunchKernelGGL(k_tile_scan, dim3(a.n_scan_tiles), dim3(kBlock), 0, stream, a, 0);
+        if (write) hipLaunchKernelGGL(k_extract_list<kPassWrite>, dim3(n_tiles), dim3(kBlock), 0, stream, a);
     } else {
         // count pass, scan, then the write pass only when something is written;
         // the grid is a multiple of the XCD count (see the tile mapping)
@@ -2107,7 +2311,9 @@ int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_
         }
     }
     hipError_t e = hipGetLastError();
-    return e == hipSuccess ? AMR_OK : hipfail(e, "extract launch");
+    if (e != hipSuccess) return hipfail(e, "extract launch");
+    if (s->extractions < 2) ++s->extractions;
+    return AMR_OK;
 }
 
 }  // namespace
@@ -2308,6 +2514,12 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     s->glist = (int32_t*)(base + L.glist);
     s->gkey = (unsigned long long*)(base + L.gkey);
     s->gcnt = (unsigned long long*)(base + L.gcnt);
+    s->rng = (float2*)(base + L.rng);
+    s->dual_total = (unsigned long long*)(base + L.dual_total);
+    s->clist = (uint32_t*)(base + L.clist);
+    s->n_list = (unsigned long long*)(base + L.n_list);
+    s->ls0 = (unsigned long long*)(base + L.ls0);
+    s->ls1 = (unsigned long long*)(base + L.ls1);
     s->tot = (unsigned long long*)(base + L.tot);
     s->st_t = (unsigned long long*)(base + L.st_t);
     s->st_d = (unsigned long long*)(base + L.st_d);
@@ -2325,7 +2537,8 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
         uint32_t work = cap > L.compact_tiles ? cap : L.compact_tiles;
         if (work < kFusedMaxTiles) work = kFusedMaxTiles;
         hipLaunchKernelGGL(k_build_reset, dim3(grid_for(work, 256)), dim3(256), 0, stream, s->rec, cap,
-                           64 - log2cap, s->sched, s->ct0, s->ct1, L.compact_tiles, s->fs0, s->fs1, s->ctrl);
+                           64 - log2cap, s->sched, s->ct0, s->ct1, L.compact_tiles, s->fs0, s->fs1, s->ls0, s->ls1,
+                           L.max_list_wgs, s->ctrl);
     }
     if (s->n > 0)
         hipLaunchKernelGGL(k_index_insert, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->val,
@@ -2388,6 +2601,7 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     s->n_groups = (uint32_t)c.n_groups;
     s->built = true;
     s->ids_ready = false;
+    s->extractions = 0;
     s->last_cap = cap;
     s->last_n = s->n;
     g_err[0] = 0;
