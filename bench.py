@@ -169,7 +169,11 @@ def serving_measurement(amr, s, name, iso_pool, seconds, rate, serial_requests=0
     out = {"workload": "resident %s + uploads of %s-cell octree sets; Poisson %.0f req/s for %.0f s, 30%% uploads"
                        % (name, "/".join(str(p.n) for p in pool), rate, seconds),
            "server": serve.summarize(res, wall), "serial_plain": serve.summarize(base, wall_b),
-           "hbm_peak_reserved_bytes": srv.mem.peak}
+           "hbm_peak_reserved_bytes": srv.mem.peak,
+           "policy_ms": {"plain_pass": srv.t_plain * 1e3, "batch_fixed": srv.t_batch_fixed * 1e3,
+                         "batch_per_job": srv.t_batch_job * 1e3,
+                         "batch_from_size": next((n for n in range(1, srv.max_batch + 1)
+                                                         if not srv.plain_wins(n)), None)}}
     if serial_requests and serial_requests < len(trace):
         out["serial_plain"]["note"] = ("first %d requests of the same trace only (the serial path is saturated, "
                                        "so its latencies only grow with more requests)" % len(strace))

@@ -125,32 +125,46 @@ class IsoServer:
         self.block, self.per_thread = block, per_thread
         self.batch.run_into(jobs, curve_points, None, counts, block, per_thread)
         self.curve_tri = counts.cpu().numpy()
-        # a lone request goes through whichever is faster on this set: the
-        # plain single pass or a batched launch of one job (timed once here)
-        self.lone_plain = self._plain_is_faster()
+        # per request, the plain single pass against a batched launch (fixed
+        # part + part per job), timed once here; a batch of n waiting
+        # requests takes whichever is cheaper for n
+        self.t_plain, self.t_batch_fixed, self.t_batch_job = self._calibrate()
         self.upload_slots = upload_slots
         self.stop = threading.Event()
         self._slot_sets = []  # kept until the server is dropped
 
-    def _plain_is_faster(self, reps: int = 3) -> bool:
-        iso = float(self.curve_iso[len(self.curve_iso) // 2])
-        cap = self.iso_cap(iso)
-        tris = torch.empty((cap, 9), dtype=torch.float32, device=self.device)
-        counts = torch.zeros(1, dtype=torch.int64, device=self.device)
-        jobs = self.batch.jobs_tensor([0], [iso], [0], [cap])
+    def _calibrate(self, reps: int = 3):
+        """(plain pass, batch fixed part, batch part per job) in seconds, on
+        isos from the middle of the value range.  The plain path is timed
+        after its first two calls on the set (the second records the group
+        value ranges that later calls cull with)."""
+        mid = len(self.curve_iso) // 2
+        isos = [float(self.curve_iso[mid]), float(self.curve_iso[min(mid + 1, len(self.curve_iso) - 1)])]
+        caps = [self.iso_cap(v) for v in isos]
+        tris = torch.empty((sum(caps), 9), dtype=torch.float32, device=self.device)
+        counts = torch.zeros(2, dtype=torch.int64, device=self.device)
+        jobs1 = self.batch.jobs_tensor([0], isos[:1], [0], caps[:1])
+        jobs2 = self.batch.jobs_tensor([0, 0], isos, [0, caps[0]], caps)
 
-        def run(fn):
-            fn()
+        def run(fn, warm=2):
+            for _ in range(warm):
+                fn()
             torch.cuda.synchronize(self.device)
             t0 = time.perf_counter()
             for _ in range(reps):
                 fn()
             torch.cuda.synchronize(self.device)
-            return time.perf_counter() - t0
+            return (time.perf_counter() - t0) / reps
 
-        t_plain = run(lambda: self.resident.isosurface_into(iso, tris, cap))
-        t_batch = run(lambda: self.batch.run_into(jobs, 1, tris, counts, self.block, self.per_thread))
-        return t_plain <= t_batch
+        t_plain = run(lambda: self.resident.isosurface_into(isos[0], tris, caps[0]))
+        t1 = run(lambda: self.batch.run_into(jobs1, 1, tris, counts, self.block, self.per_thread))
+        t2 = run(lambda: self.batch.run_into(jobs2, 2, tris, counts, self.block, self.per_thread))
+        per_job = max(t2 - t1, 0.0)
+        return t_plain, max(t1 - per_job, 0.0), per_job
+
+    def plain_wins(self, n: int) -> bool:
+        """True when n plain passes cost no more than one batched launch of n."""
+        return n * self.t_plain <= self.t_batch_fixed + n * self.t_batch_job
 
     # -- sizing -----------------------------------------------------------
     def iso_cap(self, iso: float) -> int:
@@ -179,8 +193,12 @@ class IsoServer:
 
     def _run_batch(self, reqs, results, stream):
         n = len(reqs)
-        if n == 1 and self.lone_plain:
-            return self._run_one(reqs[0], results, stream)
+        if self.plain_wins(n):
+            # one plain pass after the other: each request completes as soon
+            # as its own pass has
+            for r in reqs:
+                self._run_one(r, results, stream)
+            return
         isos = [r.iso for r in reqs]
         caps = np.array([self.iso_cap(v) for v in isos], np.int64)
         need = int(caps.sum()) * 36 + (1 << 20)
