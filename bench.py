@@ -155,7 +155,7 @@ def serving_measurement(amr, s, name, iso_pool, seconds, rate, serial_requests=0
         say("serving: %d/%d requests" % (k, n))
 
     trace = serve.poisson_trace(rate, seconds, 5, lambda k: isos[k % len(isos)], up, p_upload=0.3)
-    srv = serve.IsoServer(s)
+    srv = serve.IsoServer(s, upload_max_cells=max(p.n for p in pool))
     say("serving: server ready, %d requests in the trace" % len(trace))
     t0 = time.perf_counter()
     res = srv.serve(trace, keep_outputs=False, progress=progress)

@@ -4,13 +4,19 @@ A resident AMR set stays on the device with its index and dual cells.
 Requests arrive over time:
 
   * IsoRequest(iso): an iso-surface of the resident set.  Requests that are
-    waiting when the batch stream becomes free are fused into one batched
-    launch (amr_batch_isosurface over the resident set's dual cells), so
-    the iso-independent topology is never recomputed and new requests join
-    at the next launch instead of waiting for a queue to drain.
+    waiting when the iso stream becomes free are taken together: as one
+    batched launch (amr_batch_isosurface over the resident set's dual
+    cells, the iso-independent topology never recomputed) or as plain
+    passes one after the other (which cull groups by their value ranges),
+    whichever a start-up calibration says is cheaper for that many.  New
+    requests join at the next round instead of waiting for a queue to drain.
   * UploadRequest(xyz, level, value, iso): a new small set; it is copied
     to the GPU, validated, indexed and extracted on one of several upload
-    streams, overlapping on the device with the batched launches.
+    streams, overlapping on the device with the iso work.
+
+Outputs and upload cell buffers live on the device, reused across requests (grown when a
+request needs more), so that allocations, which can stall every stream,
+stop once the sizes have been seen.
 
 Admission is by memory: every request reserves an estimate of the device
 memory it needs against an HBM budget and waits (first come, first served)
@@ -91,10 +97,55 @@ def upload_bytes(n_cells: int, triangles_guess: int) -> int:
     return 20 * n_cells + 64 * n_cells + 36 * triangles_guess + (1 << 20)
 
 
+class _Grow:
+    """A device buffer reused from request to request and grown when a
+    request needs more rows: an allocation, which can stall the other
+    streams, only happens while the sizes still grow.  Used by one thread at
+    a time."""
+
+    def __init__(self, cols, dtype, device):
+        self.cols, self.dtype, self.device = cols, dtype, device
+        self.buf = None
+
+    def rows(self, n: int) -> torch.Tensor:
+        n = max(int(n), 1)
+        if self.buf is None or self.buf.shape[0] < n:
+            m = max(n, int(1.25 * (0 if self.buf is None else self.buf.shape[0])))
+            shape = (m,) if self.cols is None else (m, self.cols)
+            self.buf = torch.empty(shape, dtype=self.dtype, device=self.device)
+        return self.buf[:n]
+
+
+class _UploadSlot:
+    """One upload stream with its set handle and device buffers (cells,
+    output), kept for the server's lifetime (freeing device memory would
+    synchronise the whole device)."""
+
+    def __init__(self, device, max_cells: int = 0):
+        self.stream = torch.cuda.Stream(device)
+        self.set = AmrSet(device.index)
+        self.dev = [_Grow(3, torch.int32, device), _Grow(None, torch.int32, device), _Grow(None, torch.float32, device)]
+        self.out = _Grow(9, torch.float32, device)
+        if max_cells > 0:
+            for g in self.dev:
+                g.rows(max_cells)
+            self.out.rows(max_cells // 2)
+            # index a block of max_cells unit cells once, so that the set
+            # keeps an index workspace of about the size such uploads need
+            k = int(np.ceil(max_cells ** (1.0 / 3.0)))
+            i = torch.arange(max_cells, dtype=torch.int32, device=device)
+            xyz = self.dev[0].rows(max_cells)
+            xyz[:, 0], xyz[:, 1], xyz[:, 2] = i % k, (i // k) % k, i // (k * k)
+            self.dev[1].rows(max_cells).zero_()
+            self.dev[2].rows(max_cells).zero_()
+            self.set.upload(*(d.rows(max_cells) for d in self.dev))
+            self.set.build_index()
+
+
 class IsoServer:
     def __init__(self, resident: AmrSet, hbm_budget: int | None = None, upload_slots: int = 4,
                  max_batch: int = 64, block: int | None = None, per_thread: int | None = None,
-                 curve_points: int = 64):
+                 curve_points: int = 64, upload_max_cells: int = 0):
         self.resident = resident
         self.device = resident.device
         self.batch = AmrBatch([resident])
@@ -131,7 +182,20 @@ class IsoServer:
         self.t_plain, self.t_batch_fixed, self.t_batch_job = self._calibrate()
         self.upload_slots = upload_slots
         self.stop = threading.Event()
-        self._slot_sets = []  # kept until the server is dropped
+        # request outputs live in buffers reused across requests
+        self._iso_stream = torch.cuda.Stream(self.device)
+        self._iso_out = _Grow(9, torch.float32, self.device)
+        self._batch_counts = torch.zeros(max_batch, dtype=torch.int64, device=self.device)
+        # upload_max_cells > 0 sizes the upload buffers and index workspaces
+        # for sets up to that many cells now rather than on first use
+        self._slots = [_UploadSlot(self.device, upload_max_cells) for _ in range(upload_slots)]
+        # warm-up on the iso stream, into the output buffer sized for the
+        # largest lone request on the triangle-count curve
+        with torch.cuda.stream(self._iso_stream):
+            iso = float(self.curve_iso[len(self.curve_iso) // 2])
+            big = max(self.iso_cap(float(v)) for v in self.curve_iso)
+            self.resident.isosurface_into(iso, self._iso_out.rows(big), big)
+        torch.cuda.synchronize(self.device)
 
     def _calibrate(self, reps: int = 3):
         """(plain pass, batch fixed part, batch part per job) in seconds, on
@@ -181,13 +245,16 @@ class IsoServer:
         t_start = time.perf_counter()
         try:
             with torch.cuda.stream(stream):
-                tris = torch.empty((cap, 9), dtype=torch.float32, device=self.device)
+                tris = self._iso_out.rows(cap)
                 counts = self.resident.isosurface_into(r.iso, tris, cap)
                 c = int(counts[0].item())
-                out = tris[:c] if c <= cap else self.resident.isosurface(r.iso, c)["tris"]
+                if c > cap:
+                    tris = self._iso_out.rows(c)
+                    self.resident.isosurface_into(r.iso, tris, c)
+                kept = self._keep(tris[:c])
                 stream.synchronize()
                 res = results[r.rid]
-                res.start, res.done, res.triangles, res.tris = t_start, time.perf_counter(), c, self._keep(out)
+                res.start, res.done, res.triangles, res.tris = t_start, time.perf_counter(), c, kept
         finally:
             self.mem.release(held)
 
@@ -207,26 +274,30 @@ class IsoServer:
         try:
             with torch.cuda.stream(stream):
                 off = np.concatenate([[0], np.cumsum(caps)[:-1]])
-                tris = torch.empty((max(int(caps.sum()), 1), 9), dtype=torch.float32, device=self.device)
-                counts = torch.zeros(n, dtype=torch.int64, device=self.device)
+                tris = self._iso_out.rows(int(caps.sum()))
+                counts = self._batch_counts[:n]
                 jobs = self.batch.jobs_tensor([0] * n, isos, off, caps)
                 self.batch.run_into(jobs, n, tris, counts, self.block, self.per_thread)
-                stream.synchronize()
                 c = counts.cpu().numpy()
-                for k, r in enumerate(reqs):
+                kept = []
+                for k in range(n):
                     out = tris[int(off[k]):int(off[k]) + int(c[k])]
                     if c[k] > caps[k]:  # the estimate was short: exact rerun
                         out = self.resident.isosurface(isos[k], int(c[k]))["tris"]
-                        stream.synchronize()
+                    kept.append(self._keep(out))
+                stream.synchronize()
+                t_done = time.perf_counter()
+                for k, r in enumerate(reqs):
                     res = results[r.rid]
-                    res.start, res.done, res.triangles, res.tris = t_start, time.perf_counter(), int(c[k]), self._keep(out)
+                    res.start, res.done, res.triangles, res.tris = t_start, t_done, int(c[k]), kept[k]
         finally:
             self.mem.release(held)
 
     def _keep(self, out):
         # outputs are dropped at once unless the caller keeps them, so that
-        # finished requests do not pin device memory
-        return out if self.keep_outputs else None
+        # finished requests do not pin device memory; kept ones are copied out
+        # of the reused output buffer
+        return out.clone() if self.keep_outputs else None
 
     def _guard(self, fn, *args):
         try:
@@ -236,7 +307,7 @@ class IsoServer:
             self.stop.set()
 
     def _batch_worker(self, q, results):
-        stream = torch.cuda.Stream(self.device)
+        stream = self._iso_stream
         while True:
             with q["cv"]:
                 while not q["items"] and not q["closed"]:
@@ -255,33 +326,33 @@ class IsoServer:
             self._run_batch(reqs, results, stream)
 
     # -- upload requests --------------------------------------------------
-    def _run_upload(self, r: UploadRequest, results, stream, s: AmrSet):
+    def _run_upload(self, r: UploadRequest, results, slot: _UploadSlot):
         n = len(r.level)
         held = self.mem.acquire(upload_bytes(n, n // 2), self.stop)
         t_start = time.perf_counter()
         try:
-            with torch.cuda.stream(stream):
-                xyz = torch.from_numpy(np.ascontiguousarray(r.xyz, np.int32)).pin_memory().to(self.device,
-                                                                                              non_blocking=True)
-                lvl = torch.from_numpy(np.ascontiguousarray(r.level, np.int32)).pin_memory().to(self.device,
-                                                                                               non_blocking=True)
-                val = torch.from_numpy(np.ascontiguousarray(r.value, np.float32)).pin_memory().to(self.device,
-                                                                                                 non_blocking=True)
-                s.upload(xyz, lvl, val)
+            with torch.cuda.stream(slot.stream):
+                # straight from the caller's arrays (a copy through pinned
+                # staging on the host measured slower for large sets)
+                cells = []
+                for d, a, dt in zip(slot.dev, (r.xyz, r.level, r.value), (np.int32, np.int32, np.float32)):
+                    db = d.rows(n)
+                    db.copy_(torch.from_numpy(np.ascontiguousarray(a, dt)).view(db.shape))
+                    cells.append(db)
+                s = slot.set
+                s.upload(*cells)
                 s.build_index()
-                out = s.isosurface(r.iso)["tris"]
-                stream.synchronize()
+                t, _ = s.count(r.iso)
+                tris = slot.out.rows(t)
+                s.isosurface_into(r.iso, tris, t)
+                kept = self._keep(tris[:t])
+                slot.stream.synchronize()
                 res = results[r.rid]
-                res.start, res.done, res.triangles, res.tris = (t_start, time.perf_counter(), int(out.shape[0]),
-                                                                self._keep(out))
+                res.start, res.done, res.triangles, res.tris = t_start, time.perf_counter(), t, kept
         finally:
             self.mem.release(held)
 
-    def _upload_worker(self, q, results):
-        stream = torch.cuda.Stream(self.device)
-        # one set handle per upload slot, reused: freeing device memory
-        # would synchronise the whole device and stall the other streams
-        s = AmrSet(self.device.index)
+    def _upload_worker(self, q, results, slot: _UploadSlot):
         while True:
             with q["cv"]:
                 while not q["items"] and not q["closed"]:
@@ -289,8 +360,7 @@ class IsoServer:
                 if not q["items"] and q["closed"]:
                     break
                 r = q["items"].popleft()
-            self._run_upload(r, results, stream, s)
-        self._slot_sets.append(s)
+            self._run_upload(r, results, slot)
 
     # -- driver -----------------------------------------------------------
     def serve(self, trace, keep_outputs: bool = True, progress=None):
@@ -303,8 +373,8 @@ class IsoServer:
         self.keep_outputs = keep_outputs
         self.errors = []
         workers = [threading.Thread(target=self._guard, args=(self._batch_worker, iso_q, results), daemon=True)]
-        workers += [threading.Thread(target=self._guard, args=(self._upload_worker, up_q, results), daemon=True)
-                    for _ in range(self.upload_slots)]
+        workers += [threading.Thread(target=self._guard, args=(self._upload_worker, up_q, results, slot), daemon=True)
+                    for slot in self._slots]
         for w in workers:
             w.start()
         t0 = time.perf_counter()
