@@ -386,7 +386,7 @@ def resident_iso_measurement(s, cs, reps=3):
                     "group value ranges recorded by an earlier call"}
 
 
-def large_measurement(amr, name, steps):
+def large_measurement(amr, name, steps, resident=True):
     """The same whole-path step on a large set (block-structured, 50.8M
     cells), where throughput rather than launch latency decides."""
     import torch
@@ -402,7 +402,7 @@ def large_measurement(amr, name, steps):
     ms, (up, bd, iso) = time_steps(amr, s, xyz, lvl, val, cs.iso, n_tri, tris, steps, 2)
     assert int(s.counts[0].item()) == n_tri
     iso_avg = statistics.mean(iso)
-    resident = resident_iso_measurement(s, cs)
+    resident = resident_iso_measurement(s, cs) if resident else None
     out = {"workload": name, "cells": cs.n, "triangles": n_tri, "duals": n_dual, "steps": steps,
            "ms_per_step": ms, "cells_per_s": cs.n / (ms * 1e-3),
            "stages_ms": {"upload": statistics.mean(up), "build_index": statistics.mean(bd), "isosurface": iso_avg},
@@ -476,6 +476,8 @@ def main():
                     help="skip the host-to-host pipeline timing (transfers, weld, download)")
     ap.add_argument("--batch-sets", type=int, default=0,
                     help="also fuse this many independent octree sets (10k..5M cells) into one launch")
+    ap.add_argument("--no-resident", action="store_true",
+                    help="skip the repeated-iso timing on the built set (culled passes), e.g. under a profiler")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -551,11 +553,12 @@ def main():
         "iso_latency_ms": {"p50": percentile(lat, 0.5), "p99": percentile(lat, 0.99), "requests": len(lat),
                            "what": "count pass + write pass on the resident set, host clock"},
         "roofline": roofline_of(cs.n, n_tri, iso_avg, traffic_for(cs.name)),
-        "resident_iso": resident_iso_measurement(s, cs),
     }
+    if not args.no_resident:
+        out["resident_iso"] = resident_iso_measurement(s, cs)
     say("timed steps done: %.3f ms/step" % ms_per_step)
     if args.large != "none":
-        out["large_workload"] = large_measurement(amr, args.large, 10)
+        out["large_workload"] = large_measurement(amr, args.large, 10, resident=not args.no_resident)
         say("large workload %s: %.3f ms/step" % (args.large, out["large_workload"]["ms_per_step"]))
     if not args.no_pipeline:
         out["pipeline_pcie_inclusive"] = pipeline_measurement(amr, cs)
