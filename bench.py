@@ -482,8 +482,8 @@ def main():
                     help="also run a plain device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the method is single-device data-parallel work and this build "
-              "has no multi-GPU path (see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library extracts on a single device and has no multi-GPU "
+              "path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

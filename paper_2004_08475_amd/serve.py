@@ -9,7 +9,7 @@ Requests arrive over time:
     cells, the iso-independent topology never recomputed) or as plain
     passes one after the other (which cull groups by their value ranges),
     whichever a start-up calibration says is cheaper for that many.  New
-    requests join at the next round instead of waiting for a queue to drain.
+    requests join the next batch instead of waiting for a queue to drain.
   * UploadRequest(xyz, level, value, iso): a new small set; it is copied
     to the GPU, validated, indexed and extracted on one of several upload
     streams, overlapping on the device with the iso work.
