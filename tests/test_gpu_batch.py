@@ -106,3 +106,29 @@ def test_batch_graph_replay_with_new_isos(amr, shell):
             assert c[k] == len(want[k])
             assert torch.equal(tris[k * cap:k * cap + c[k]], want[k])
     assert not b.barrier_timed_out(256, 1)
+
+
+def test_batched_configurations_at_full_size(amr, shell):
+    """The two batched workloads bench.py times, at full size, in the launch
+    shapes the autotuner picks for them (512 x 1 and 256 x 2) and the default
+    one: octree-shell-256 with 64 isos at percentiles 5 + 90 k / 63, and 32
+    octree sets of log-uniform sizes in [10k, 5M] cells (seed 4), each at its
+    median iso.  Every job equals the plain path bit for bit."""
+    cs, s = shell
+    isos = np.quantile(cs.value, 0.05 + 0.90 * np.arange(64) / 63).astype(np.float32)
+    b = amr.AmrBatch([s])
+    want = [_plain(s, iso) for iso in isos]
+    for block, per in ((512, 1), (256, 1)):
+        outs = b.isosurface([0] * len(isos), isos, block, per)
+        for w, got in zip(want, outs):
+            assert torch.equal(got, w)
+    sizes = np.exp(np.random.default_rng(4).uniform(np.log(1e4), np.log(5e6), 32)).astype(int)
+    css = [amrgen.octree_sized(int(n), seed=200 + k) for k, n in enumerate(sizes)]
+    print("32 sets, %d cells in all" % sum(c.n for c in css), flush=True)
+    sets = [amr.from_numpy(c.xyz, c.level, c.value) for c in css]
+    b = amr.AmrBatch(sets)
+    want = [_plain(st, c.iso) for st, c in zip(sets, css)]
+    for block, per in ((256, 2), (256, 1)):
+        outs = b.isosurface(list(range(len(sets))), [c.iso for c in css], block, per)
+        for w, got in zip(want, outs):
+            assert torch.equal(got, w)
