@@ -10,7 +10,8 @@ duals and triangles depend on, and the oracle's index stays small.
 
 Bar: dual cells bit-exact (corner, level, 8 global cell indices); triangle
 topology exact (per-vertex cell pairs); positions within
-max(1e-5 * finest width, 2 ulp_f32).
+max(1e-5 * finest width, 2 ulp_f32).  A serving mix against the same resident
+set must give each request's result as it is alone.
 """
 import os
 import sys
@@ -57,7 +58,8 @@ def _owned(pl, ids, level, sample_mask, chunk=1 << 26):
     return out
 
 
-def test_serving_set_sampled(amr):
+@pytest.fixture(scope="module")
+def big(amr):
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     xyz, lv, val, iso = amrgen.octree_shell_torch(2048, 5, (480.0, 560.0), 0.6, 0.575, 5, dev,
@@ -68,6 +70,12 @@ def test_serving_set_sampled(amr):
     s = amr.AmrSet(0)
     s.upload(xyz, lv, val)
     s.build_index()
+    return xyz, lv, val, iso, s
+
+
+def test_serving_set_sampled(amr, big):
+    dev = torch.device("cuda", 0)
+    xyz, lv, val, iso, s = big
 
     # GPU: the whole set
     pl, ids = s.dual_cells()
@@ -122,3 +130,40 @@ def test_serving_set_sampled(amr):
     assert len(A) == len(B) > 0
     assert np.array_equal(AC, BC)
     assert np.all(np.abs(A.astype(np.float64) - B.astype(np.float64)) <= position_tolerance(B))
+
+
+def test_serving_mix_on_the_resident_set(amr, big):
+    """Requests served against the 608.9M-cell resident set, mixed with
+    uploads, give what each gives alone: iso requests the same bits in the
+    same order as the plain path, uploads the same triangles (their index is
+    built afresh, so compared in canonical order)."""
+    from paper_2004_08475_amd import serve
+
+    xyz, lv, val, iso, s = big
+    sample = val[torch.randint(0, val.numel(), (1 << 20,), device=val.device,
+                               generator=torch.Generator(val.device).manual_seed(7))]
+    isos = torch.quantile(sample.double(), torch.linspace(0.1, 0.9, 9, device=val.device,
+                                                          dtype=torch.float64)).float().cpu().numpy()
+    uploads = [amrgen.random_octree(400 + k, roots=3, root_level=3, p_split=0.5, p_hole=0.05, values="smooth")
+               for k in range(3)]
+
+    def up(k):
+        u = uploads[k % len(uploads)]
+        return serve.UploadRequest(u.xyz, u.level, u.value, u.iso)
+
+    trace = serve.poisson_trace(20.0, 2.0, 17, lambda k: isos[k % len(isos)], up, p_upload=0.3)
+    _say("mix on the resident set: %d requests" % len(trace))
+    srv = serve.IsoServer(s, upload_slots=2)
+    out = srv.serve(trace)
+    _say("served; checking each request alone")
+    assert len(out) == len(trace)
+    for (at, req), r in zip(trace, out):
+        if isinstance(req, serve.IsoRequest):
+            want = s.isosurface(req.iso)["tris"]
+            assert r.triangles == want.shape[0]
+            assert torch.equal(r.tris, want)
+        else:
+            alone = amr.from_numpy(req.xyz, req.level, req.value).isosurface(req.iso)["tris"]
+            a = oracle.canonical_triangles(r.tris.cpu().numpy())[0]
+            b = oracle.canonical_triangles(alone.cpu().numpy())[0]
+            assert np.array_equal(a, b)
