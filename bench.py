@@ -309,6 +309,31 @@ def traffic_for(workload):
     return None
 
 
+VALU_FILE = os.path.join(ROOT, "profiles", "k_extract_valu.txt")
+
+
+def valu_for(workload):
+    """Per extraction kernel of this workload: the fraction of the VALU issue
+    peak from the committed rocprofv3 SQ counter summary, or None when there
+    is none or the kernel source changed since."""
+    import hashlib
+
+    try:
+        lines = open(VALU_FILE).read().splitlines()
+        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    recorded = [ln.split()[1] for ln in lines if ln.startswith("source_sha256")]
+    if not recorded or recorded[0] != src:
+        return None
+    out = {}
+    for ln in lines:
+        if ln.startswith(workload + " "):
+            kernel = ln[len(workload) + 1:].split(":")[0]
+            out[kernel] = float(ln.rsplit("|", 1)[1])
+    return out or None
+
+
 def time_steps(amr, s, xyz, lvl, val, iso, cap, tris, steps, warmup):
     """Whole-path steps (upload + build + iso).  The timed run has nothing
     but the steps between two synchronisations (host clock); a second run of
@@ -349,12 +374,12 @@ def time_steps(amr, s, xyz, lvl, val, iso, cap, tris, steps, warmup):
     return ms, st
 
 
-def roofline_of(n_cells, n_tri, iso_ms, traffic):
+def roofline_of(n_cells, n_tri, iso_ms, traffic, valu=None):
     alg = 20.0 * n_cells + 36.0 * n_tri
     achieved = alg / (iso_ms * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": "k_extract passes of one amr_isosurface call", "achieved": achieved,
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "algorithmic_bytes": alg, "avg_launch_ms": iso_ms}
+            "algorithmic_bytes": alg, "avg_launch_ms": iso_ms, "valu_issue_frac": valu}
 
 
 def resident_iso_measurement(s, cs, reps=3):
@@ -407,7 +432,7 @@ def large_measurement(amr, name, steps, resident=True):
            "ms_per_step": ms, "cells_per_s": cs.n / (ms * 1e-3),
            "stages_ms": {"upload": statistics.mean(up), "build_index": statistics.mean(bd), "isosurface": iso_avg},
            "iso_only_cells_per_s": cs.n / (iso_avg * 1e-3),
-           "roofline": roofline_of(cs.n, n_tri, iso_avg, traffic_for(name)),
+           "roofline": roofline_of(cs.n, n_tri, iso_avg, traffic_for(name), valu_for(name)),
            "resident_iso": resident}
     del s, xyz, lvl, val, tris
     torch.cuda.empty_cache()
@@ -552,7 +577,7 @@ def main():
         "iso_only_cells_per_s": cs.n / (iso_avg * 1e-3),
         "iso_latency_ms": {"p50": percentile(lat, 0.5), "p99": percentile(lat, 0.99), "requests": len(lat),
                            "what": "count pass + write pass on the resident set, host clock"},
-        "roofline": roofline_of(cs.n, n_tri, iso_avg, traffic_for(cs.name)),
+        "roofline": roofline_of(cs.n, n_tri, iso_avg, traffic_for(cs.name), valu_for(cs.name)),
     }
     if not args.no_resident:
         out["resident_iso"] = resident_iso_measurement(s, cs)

@@ -31,6 +31,20 @@ def test_traffic_only_for_the_source_it_was_measured_on(tmp_path, monkeypatch):
     assert bench.traffic_for("octree-shell-256") is None
 
 
+def test_valu_issue_only_for_the_source_it_was_measured_on(tmp_path, monkeypatch):
+    have = bench.valu_for("block-vortex-1024")
+    if have is None:
+        # the committed counters belong to another version of the kernels
+        return
+    assert set(have) == {"k_extract<false,0>", "k_extract<false,1>"}
+    assert all(0.0 < v <= 1.0 for v in have.values())
+    assert bench.valu_for("no-such-workload") is None
+    other = tmp_path / "amriso.hip"
+    other.write_bytes(open(bench.KERNEL_SOURCE, "rb").read() + b"\n// changed\n")
+    monkeypatch.setattr(bench, "KERNEL_SOURCE", str(other))
+    assert bench.valu_for("block-vortex-1024") is None
+
+
 def test_roofline_fields():
     r = bench.roofline_of(1000, 10, 0.5, None)
     assert r["algorithmic_bytes"] == 20.0 * 1000 + 36.0 * 10
