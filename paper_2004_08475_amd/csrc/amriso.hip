@@ -786,9 +786,13 @@ struct ExtractArgs {
     float2* rng;
     unsigned long long* dual_total;
     int rng_mode;
-    // candidate list of a culled count / write pass (k_cull_list)
+    // group list of a list count / write pass (k_group_list); with lcnt the
+    // list's triangle counts come from there (no list count pass), and
+    // list_duals holds the set's dual count
     const uint32_t* clist;
     const unsigned long long* n_list;
+    const uint32_t* lcnt;
+    const unsigned long long* list_duals;
 };
 
 enum : int { kRngNone = 0, kRngRecord = 1, kRngCull = 2 };
@@ -1391,20 +1395,28 @@ __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
     extract_tile<kDuals, kPass, false>(a, tile, 0u, kPass == kPassFused ? s_call : 0ull);
 }
 
-// Candidate groups of one iso-value: those whose neighbourhood range
-// straddles iso (all others have only Marching Cubes cases 0 and 255), in
-// group order.  The compaction is stable, so passes over the list emit the
-// triangles in the order passes over all groups would.  Work-groups take
-// tickets in start order; each call takes exactly n_wgs of them, so the
-// ticket also gives the call's parity for the look-back states.  The last
-// work-group writes the list's length.
+// Lists of groups in group order, for passes that need only some of them:
+//  - with `rng`: the candidates of one iso-value, groups whose neighbourhood
+//    range straddles iso (all others have only Marching Cubes cases 0 and
+//    255);
+//  - without: the groups a count pass found triangles in (`gcnt`), with each
+//    entry's triangle count beside it (`lcnt`) and the dual count of all
+//    groups summed on the way (`n_duals`).
+// The compaction is stable, so passes over a list emit the triangles in the
+// order passes over all groups would.  Work-groups take tickets in start
+// order; each call takes exactly n_wgs of them, so the ticket also gives the
+// call's parity for the look-back states.  The last work-group writes the
+// list's length.
 constexpr int kListPer = 16;  // groups per thread
 
-__global__ __launch_bounds__(kBlock) void k_cull_list(const float2* __restrict__ rng, uint32_t n_groups, float iso,
-                                                      uint32_t n_wgs, uint32_t* __restrict__ clist,
-                                                      unsigned long long* n_list, unsigned long long* ls0,
-                                                      unsigned long long* ls1, Sched* sc) {
+__global__ __launch_bounds__(kBlock) void k_group_list(const float2* __restrict__ rng,
+                                                       const unsigned long long* __restrict__ gcnt,
+                                                       uint32_t n_groups, float iso, uint32_t n_wgs,
+                                                       uint32_t* __restrict__ clist, uint32_t* __restrict__ lcnt,
+                                                       unsigned long long* n_list, unsigned long long* n_duals,
+                                                       unsigned long long* ls0, unsigned long long* ls1, Sched* sc) {
     __shared__ uint32_t s_row[kListPer][kBlock / 64];
+    __shared__ unsigned long long s_dual[kBlock / 64];
     __shared__ unsigned long long s_tk, s_pre;
     const int t = threadIdx.x, wave = t >> 6, lane = lane_id();
     if (t == 0) s_tk = atomicAdd(&sc->lticket, 1ull);
@@ -1414,30 +1426,46 @@ __global__ __launch_bounds__(kBlock) void k_cull_list(const float2* __restrict__
     const unsigned long long par = ((tk / n_wgs) & 1) ? kParityBit : 0ull;
     const uint64_t base = (uint64_t)wg * (kBlock * kListPer);
     const unsigned long long below = (1ull << lane) - 1ull;
-    uint32_t keep = 0, rank[kListPer];
+    uint32_t keep = 0, rank[kListPer], tris[kListPer];
+    unsigned long long duals = 0;
 #pragma unroll
     for (int r = 0; r < kListPer; ++r) {
         const uint64_t i = base + (uint64_t)r * kBlock + t;
         bool c = false;
+        tris[r] = 0;
         if (i < n_groups) {
-            const float2 g = rng[i];
-            c = g.x < iso && g.y >= iso;
+            if (rng) {
+                const float2 g = rng[i];
+                c = g.x < iso && g.y >= iso;
+            } else {
+                const unsigned long long gc = gcnt[i];
+                tris[r] = (uint32_t)(gc >> 32);
+                duals += gc & 0xFFFFFFFFull;
+                c = tris[r] != 0;
+            }
         }
         const unsigned long long b = __ballot(c);
         rank[r] = (uint32_t)__popcll(b & below);
         keep |= (c ? 1u : 0u) << r;
         if (lane == 0) s_row[r][wave] = (uint32_t)__popcll(b);
     }
+    duals = wave_reduce(duals, [](unsigned long long x, unsigned long long y) { return x + y; });
+    if (lane == 0) s_dual[wave] = duals;
     __syncthreads();
     if (wave == 0) {
         uint32_t total = 0;
         for (int r = 0; r < kListPer; ++r)
             for (int q = 0; q < kBlock / 64; ++q) total += s_row[r][q];
+        unsigned long long dsum = 0;
+        for (int q = 0; q < kBlock / 64; ++q) dsum += s_dual[q];
         unsigned long long p0, p1;
-        lookback(ls0, ls1, wg, par, total, 0ull, p0, p1);
+        lookback(ls0, ls1, wg, par, total, dsum, p0, p1);
         if (lane == 0) {
             s_pre = p0;
-            if (wg == n_wgs - 1) *n_list = p0 + total;
+            if (wg == n_wgs - 1) {
+                *n_list = p0 + total;
+                if (n_duals) *n_duals = p1 + dsum;
+            }
         }
     }
     __syncthreads();
@@ -1448,18 +1476,26 @@ __global__ __launch_bounds__(kBlock) void k_cull_list(const float2* __restrict__
             if (q < wave) wave_pre += s_row[r][q];
             row += s_row[r][q];
         }
-        if ((keep >> r) & 1) clist[carry + wave_pre + rank[r]] = (uint32_t)(base + (uint64_t)r * kBlock + t);
+        if ((keep >> r) & 1) {
+            const unsigned long long at = carry + wave_pre + rank[r];
+            clist[at] = (uint32_t)(base + (uint64_t)r * kBlock + t);
+            if (lcnt) lcnt[at] = tris[r];
+        }
         carry += row;
     }
 }
 
-// Count and write passes over the candidate list of one iso-value.  The
-// list's length is known only on the device: the grid covers every group,
-// and work-groups past the list's last tile leave at once.
+// Count and write passes over a group list.  The list's length is known
+// only on the device: the grid covers every group, and work-groups past the
+// list's last tile leave at once.  As in the passes over all groups, XCD x
+// (work-groups go round-robin to the 8 XCDs) gets a contiguous run of the
+// list's tiles, so its L2 sees neighbouring groups one after another.
 template <int kPass>
 __global__ __launch_bounds__(kBlock) void k_extract_list(ExtractArgs a) {
     const uint32_t n = (uint32_t)*a.n_list;
     const uint32_t n_tiles = (n + kGroupsPerTile - 1) / kGroupsPerTile;
+    const uint32_t per_xcd = (n_tiles + kXcds - 1) / kXcds;
+    const uint32_t tile = (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
     if (kPass == kPassCount) {
         // the scan that follows starts from clean states
         for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < a.n_scan_tiles; i += gridDim.x * kBlock) {
@@ -1468,7 +1504,7 @@ __global__ __launch_bounds__(kBlock) void k_extract_list(ExtractArgs a) {
         }
         if (blockIdx.x == 0 && threadIdx.x == 0) a.sched->xticket = 0;
     }
-    if (blockIdx.x < n_tiles) extract_tile<false, kPass, true>(a, blockIdx.x, n, 0ull);
+    if (blockIdx.x / kXcds < per_xcd && tile < n_tiles) extract_tile<false, kPass, true>(a, tile, n, 0ull);
 }
 
 // Exclusive scan of the per-tile (triangles, duals) totals of a count pass:
@@ -1493,10 +1529,28 @@ __global__ __launch_bounds__(kBlock) void k_tile_scan(ExtractArgs a, int duals) 
     // triangles << 32 | duals, and no half carries inside one work-group
     // (at most 4096 tiles of at most 4320 triangles each)
     unsigned long long v[kScanPer], incl[kScanPer];
+    const uint32_t n_entries = a.lcnt ? (uint32_t)*a.n_list : 0u;
 #pragma unroll
     for (int r = 0; r < kScanPer; ++r) {
         uint64_t i = base + (uint64_t)r * kBlock + t;
-        v[r] = i < n_tiles ? a.tot[i] : 0ull;
+        if (a.lcnt) {
+            // a list tile's triangles: the counts of its 32 entries
+            unsigned long long tt = 0;
+            if (i < n_tiles) {
+                // 16-byte loads (the buffer has a tile of slack past its end)
+#pragma unroll
+                for (int k = 0; k < kGroupsPerTile; k += 4) {
+                    const uint64_t e = i * kGroupsPerTile + k;
+                    const uint4 c4 = *reinterpret_cast<const uint4*>(a.lcnt + e);
+                    tt += (e < n_entries ? c4.x : 0u) + (e + 1 < n_entries ? c4.y : 0u) +
+                          (e + 2 < n_entries ? c4.z : 0u) + (e + 3 < n_entries ? c4.w : 0u);
+                }
+                a.tot[i] = tt << 32;
+            }
+            v[r] = tt << 32;
+        } else {
+            v[r] = i < n_tiles ? a.tot[i] : 0ull;
+        }
         incl[r] = wave_incl_scan(v[r]);
         if (lane == 63) s_row[r][wave] = incl[r];
     }
@@ -1511,9 +1565,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_scan(ExtractArgs a, int duals) 
             s_p0 = p0;
             s_p1 = p1;
             if (st == a.n_scan_tiles - 1) {
-                // a culled pass counts no duals: the set's total stands in
-                const unsigned long long nd =
-                    a.rng_mode == kRngCull && !duals ? *a.dual_total : p1 + (total & 0xFFFFFFFFull);
+                // a pass over a list counts no duals: the set's total stands in
+                const unsigned long long nd = a.list_duals ? *a.list_duals : p1 + (total & 0xFFFFFFFFull);
                 if (a.rng_mode == kRngRecord) *a.dual_total = nd;
                 if (a.counts) {
                     a.counts[0] = (int64_t)(duals ? nd : p0 + (total >> 32));
@@ -2108,8 +2161,10 @@ struct amr_set {
     int extractions = 0;     // extraction calls since the build (saturates at 2)
     float2* rng = nullptr;
     unsigned long long* dual_total = nullptr;
-    uint32_t* clist = nullptr;              // candidate list of a culled pass
-    unsigned long long* n_list = nullptr;
+    uint32_t* clist = nullptr;              // group list of a list pass, its length,
+    uint32_t* lcnt = nullptr;               // its triangle counts (lists from a count pass)
+    unsigned long long* n_list = nullptr;   // and the dual count summed on the way
+    unsigned long long* list_duals = nullptr;
     unsigned long long* ls0 = nullptr;      // candidate list: look-back states
     unsigned long long* ls1 = nullptr;
     int32_t* glist = nullptr;
@@ -2138,8 +2193,8 @@ uint32_t table_cap(const amr_set* s) {
 }
 
 struct Layout {
-    size_t rec, ids, glist, gkey, gcnt, rng, clist, tot, st_t, st_d, xs0, xs1, fs0, fs1, ct0, ct1, ls0, ls1, sched,
-        dual_total, n_list, total;
+    size_t rec, ids, glist, gkey, gcnt, rng, clist, lcnt, tot, st_t, st_d, xs0, xs1, fs0, fs1, ct0, ct1, ls0, ls1,
+        sched, dual_total, n_list, list_duals, total;
     uint32_t max_tiles, max_scan_tiles, compact_tiles, max_list_wgs;
     int compact_per;
 };
@@ -2167,6 +2222,8 @@ Layout layout_for(uint32_t cap) {
     off = align256(off + (size_t)max_groups * sizeof(float2));
     L.clist = off;
     off = align256(off + (size_t)max_groups * sizeof(uint32_t));
+    L.lcnt = off;
+    off = align256(off + ((size_t)max_groups + kGroupsPerTile) * sizeof(uint32_t));
     L.max_scan_tiles = (L.max_tiles + kBlock * kScanPer - 1) / (kBlock * kScanPer);
     L.tot = off;
     off = align256(off + (size_t)L.max_tiles * 8);
@@ -2191,6 +2248,8 @@ Layout layout_for(uint32_t cap) {
     L.dual_total = off;
     off = align256(off + sizeof(unsigned long long));
     L.n_list = off;
+    off = align256(off + sizeof(unsigned long long));
+    L.list_duals = off;
     off = align256(off + sizeof(unsigned long long));
     L.max_list_wgs = (max_groups + kBlock * kListPer - 1) / (kBlock * kListPer);
     L.ls0 = off;
@@ -2274,6 +2333,9 @@ int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_
                  : (!duals && tri_dual == nullptr ? kRngCull : kRngNone);
     a.clist = nullptr;
     a.n_list = nullptr;
+    a.lcnt = nullptr;
+    a.list_duals = nullptr;
+    const uint32_t n_wgs = (s->n_groups + kBlock * kListPer - 1) / (kBlock * kListPer);
     if (n_tiles <= kFusedMaxTiles) {
         // one fused pass (look-back states alternate parity between calls)
         a.sc0 = s->fs0;
@@ -2285,14 +2347,30 @@ int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_
     } else if (a.rng_mode == kRngCull) {
         // list the candidate groups, then count, scan and write over the list
         const bool write = cap > 0 && (tris || tri_cells);
-        const uint32_t n_wgs = (s->n_groups + kBlock * kListPer - 1) / (kBlock * kListPer);
-        hipLaunchKernelGGL(k_cull_list, dim3(n_wgs), dim3(kBlock), 0, stream, s->rng, s->n_groups, iso, n_wgs,
-                           s->clist, s->n_list, s->ls0, s->ls1, s->sched);
+        hipLaunchKernelGGL(k_group_list, dim3(n_wgs), dim3(kBlock), 0, stream, s->rng, nullptr, s->n_groups, iso,
+                           n_wgs, s->clist, nullptr, s->n_list, nullptr, s->ls0, s->ls1, s->sched);
         a.clist = s->clist;
         a.n_list = s->n_list;
-        hipLaunchKernelGGL(k_extract_list<kPassCount>, dim3(n_tiles), dim3(kBlock), 0, stream, a);
+        a.list_duals = s->dual_total;
+        const uint32_t grid = ((n_tiles + kXcds - 1) / kXcds) * kXcds;
+        hipLaunchKernelGGL(k_extract_list<kPassCount>, dim3(grid), dim3(kBlock), 0, stream, a);
         hipLaunchKernelGGL(k_tile_scan, dim3(a.n_scan_tiles), dim3(kBlock), 0, stream, a, 0);
-        if (write) hipLaunchKernelGGL(k_extract_list<kPassWrite>, dim3(n_tiles), dim3(kBlock), 0, stream, a);
+        if (write) hipLaunchKernelGGL(k_extract_list<kPassWrite>, dim3(grid), dim3(kBlock), 0, stream, a);
+    } else if (!duals && tri_dual == nullptr && cap > 0 && (tris || tri_cells)) {
+        // count pass over all groups, then list the groups with triangles (in
+        // group order, with their counts) and scan and write over that list
+        // only: most groups have none, and the write pass would otherwise
+        // redo their neighbourhoods beside the few that have some
+        const uint32_t grid = ((n_tiles + kXcds - 1) / kXcds) * kXcds;
+        hipLaunchKernelGGL((k_extract<false, kPassCount>), dim3(grid), dim3(kBlock), 0, stream, a);
+        hipLaunchKernelGGL(k_group_list, dim3(n_wgs), dim3(kBlock), 0, stream, nullptr, s->gcnt, s->n_groups, iso,
+                           n_wgs, s->clist, s->lcnt, s->n_list, s->list_duals, s->ls0, s->ls1, s->sched);
+        a.clist = s->clist;
+        a.n_list = s->n_list;
+        a.lcnt = s->lcnt;
+        a.list_duals = s->list_duals;
+        hipLaunchKernelGGL(k_tile_scan, dim3(a.n_scan_tiles), dim3(kBlock), 0, stream, a, 0);
+        hipLaunchKernelGGL(k_extract_list<kPassWrite>, dim3(grid), dim3(kBlock), 0, stream, a);
     } else {
         // count pass, scan, then the write pass only when something is written;
         // the grid is a multiple of the XCD count (see the tile mapping)
@@ -2517,7 +2595,9 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     s->rng = (float2*)(base + L.rng);
     s->dual_total = (unsigned long long*)(base + L.dual_total);
     s->clist = (uint32_t*)(base + L.clist);
+    s->lcnt = (uint32_t*)(base + L.lcnt);
     s->n_list = (unsigned long long*)(base + L.n_list);
+    s->list_duals = (unsigned long long*)(base + L.list_duals);
     s->ls0 = (unsigned long long*)(base + L.ls0);
     s->ls1 = (unsigned long long*)(base + L.ls1);
     s->tot = (unsigned long long*)(base + L.tot);

@@ -123,3 +123,26 @@ def test_rebuild_forgets_ranges(amr, name):
         tb, cb, _ = canon_by_cells(b["tris"].cpu().numpy(), b["cells"].cpu().numpy())
         assert np.array_equal(ca, cb)
         assert np.array_equal(ta.view(np.uint32), tb.view(np.uint32))
+
+
+@pytest.mark.parametrize("name", ["octree-sized-647k"])
+def test_first_writes_over_groups_with_triangles(amr, name):
+    # Right after a build (nothing recorded yet) a write on a set of more
+    # than 2048 tiles counts over all groups, lists the groups with
+    # triangles and writes over that list only: same bits, same order as the
+    # full write pass (the one that also names each triangle's dual).
+    cs = CASES[name]()
+    s = amr.from_numpy(cs.xyz, cs.level, cs.value)
+    for q in (0.1, 0.5, 0.93):
+        iso = float(np.quantile(cs.value, q))
+        s.build_index()  # forget everything recorded
+        n, d = s.count(iso)
+        r = s.isosurface(iso, cap=n + 3, cells=True)  # second extraction: also records
+        f = s.isosurface(iso, cells=True, dual=True)
+        assert r["n_duals"] == f["n_duals"] == d
+        assert torch.equal(r["tris"], f["tris"]) and torch.equal(r["cells"], f["cells"])
+        s.build_index()
+        r1 = s.isosurface(iso, cap=n, cells=True)  # the very first extraction
+        f1 = s.isosurface(iso, cells=True, dual=True)  # same build (a rebuild may order groups differently)
+        assert r1["n_duals"] == f1["n_duals"] == d
+        assert torch.equal(r1["tris"], f1["tris"]) and torch.equal(r1["cells"], f1["cells"])
