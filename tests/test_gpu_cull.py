@@ -146,3 +146,9 @@ def test_first_writes_over_groups_with_triangles(amr, name):
         f1 = s.isosurface(iso, cells=True, dual=True)  # same build (a rebuild may order groups differently)
         assert r1["n_duals"] == f1["n_duals"] == d
         assert torch.equal(r1["tris"], f1["tris"]) and torch.equal(r1["cells"], f1["cells"])
+    # no triangles at all: an empty list, an empty scan, nothing written
+    s.build_index()
+    buf = torch.full((5, 9), -7.0, dtype=torch.float32, device=s.device)
+    counts = s.isosurface_into(float(np.min(cs.value)) - 1.0, buf, 5)
+    assert counts.tolist() == [0, d]
+    assert torch.all(buf == -7.0)
