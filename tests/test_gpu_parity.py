@@ -315,3 +315,27 @@ def test_block_vortex_full_size_sampled(amr, sample):
     # the hole: no dual has a vertex cell inside the obstacle, and the surface
     # is open only where the dual mesh has a boundary (checked on the sample)
     assert len(tg) > 0
+
+
+def _sweep_case(k):
+    """Seeded variety of small AMR sets: root levels 2..5, split and hole
+    rates, smooth or random values, origins with negative coordinates."""
+    rng = np.random.default_rng(1000 + k)
+    root_level = int(rng.integers(2, 6))
+    roots = int(rng.integers(2, 5))
+    origin = tuple(int(v) * (1 << (root_level + 1)) for v in rng.integers(-6, 7, 3))
+    return amrgen.random_octree(2000 + k, roots=roots, root_level=root_level, p_split=float(rng.uniform(0.2, 0.7)),
+                                p_hole=float(rng.choice([0.0, 0.0, 0.1, 0.3])),
+                                values=str(rng.choice(["smooth", "random"])), origin=origin)
+
+
+@pytest.mark.parametrize("k", range(24))
+def test_parity_sweep_random_octrees(amr, k):
+    cs = _sweep_case(k)
+    if cs.n == 0:
+        pytest.skip("empty draw")
+    o = oracle.Oracle(cs.xyz, cs.level, cs.value)
+    s = gpu_set(amr, cs)
+    pl_g, _ = check_duals(s, o)
+    q = float(np.random.default_rng(3000 + k).uniform(0.05, 0.95))
+    check_iso(s, o, float(np.quantile(cs.value, q)), pl_g)
