@@ -61,9 +61,25 @@ def cpu_baseline(cs, min_seconds=10.0):
         t_total += time.perf_counter() - t0
         reps += 1
         del o
+    # the same oracle on one thread, once over the same set
+    t0 = time.perf_counter()
+    o = oracle.Oracle(cs.xyz, cs.level, cs.value, validate=False)
+    o.count_range(cs.iso, 0, cs.n)
+    t_one = time.perf_counter() - t0
+    del o
+    # the brute-force locator (a scan over all cells per snap) on the 960-cell two-level sphere
+    import amrgen
+
+    c1 = amrgen.two_level_sphere()
+    t0 = time.perf_counter()
+    ob = oracle.Oracle(c1.xyz, c1.level, c1.value, locator="brute", validate=False)
+    ob.count_range(c1.iso, 0, c1.n)
+    t_brute = time.perf_counter() - t0
     return {"value": cs.n * reps / t_total, "unit": "cells/s", "cores": threads, "kind": "oracle",
             "sample": "whole %s set (%d cells, %d triangles), sorted-corner index + rules 1-3 + Marching Cubes, "
-                      "%d repetitions, %.1f s" % (cs.name, cs.n, tris, reps, t_total)}
+                      "%d repetitions, %.1f s" % (cs.name, cs.n, tris, reps, t_total),
+            "one_thread": {"value": cs.n / t_one, "seconds": t_one},
+            "brute_force": {"workload": c1.name, "cells": c1.n, "value": c1.n / t_brute, "seconds": t_brute}}
 
 
 def batched_measurement(amr, s, cs, n_isos):

@@ -50,3 +50,12 @@ def test_roofline_fields():
     assert r["algorithmic_bytes"] == 20.0 * 1000 + 36.0 * 10
     assert abs(r["achieved"] - r["algorithmic_bytes"] / 0.5e-3 / 1e9) < 1e-9
     assert r["frac"] == r["achieved"] / r["peak"] and r["unit"] == "GB/s" and r["bound"] == "hbm"
+
+
+def test_cpu_baseline_reports_one_thread_and_brute_force():
+    import amrgen
+
+    r = bench.cpu_baseline(amrgen.two_level_sphere(), min_seconds=0.05)
+    assert r["kind"] == "oracle" and r["unit"] == "cells/s" and r["value"] > 0 and r["cores"] >= 1
+    assert r["one_thread"]["value"] > 0
+    assert r["brute_force"]["cells"] == 960 and r["brute_force"]["value"] > 0
