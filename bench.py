@@ -326,16 +326,17 @@ def traffic_for(workload):
 
 
 VALU_FILE = os.path.join(ROOT, "profiles", "k_extract_valu.txt")
+L2_FILE = os.path.join(ROOT, "profiles", "k_extract_l2.txt")
 
 
-def valu_for(workload):
-    """Per extraction kernel of this workload: the fraction of the VALU issue
-    peak from the committed rocprofv3 SQ counter summary, or None when there
-    is none or the kernel source changed since."""
+def _per_kernel(path, workload):
+    """Per extraction kernel of this workload, the last figure of its line in
+    a committed rocprofv3 counter summary, or None when there is none or the
+    kernel source changed since the counters were taken."""
     import hashlib
 
     try:
-        lines = open(VALU_FILE).read().splitlines()
+        lines = open(path).read().splitlines()
         src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
     except OSError:
         return None
@@ -348,6 +349,16 @@ def valu_for(workload):
             kernel = ln[len(workload) + 1:].split(":")[0]
             out[kernel] = float(ln.rsplit("|", 1)[1])
     return out or None
+
+
+def valu_for(workload):
+    """Fraction of the VALU issue peak per extraction kernel (SQ counters)."""
+    return _per_kernel(VALU_FILE, workload)
+
+
+def l2_hit_for(workload):
+    """L2 hit rate per extraction kernel (TCC counters)."""
+    return _per_kernel(L2_FILE, workload)
 
 
 def time_steps(amr, s, xyz, lvl, val, iso, cap, tris, steps, warmup):
@@ -390,12 +401,12 @@ def time_steps(amr, s, xyz, lvl, val, iso, cap, tris, steps, warmup):
     return ms, st
 
 
-def roofline_of(n_cells, n_tri, iso_ms, traffic, valu=None):
+def roofline_of(n_cells, n_tri, iso_ms, traffic, valu=None, l2_hit=None):
     alg = 20.0 * n_cells + 36.0 * n_tri
     achieved = alg / (iso_ms * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": "k_extract passes of one amr_isosurface call", "achieved": achieved,
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "algorithmic_bytes": alg, "avg_launch_ms": iso_ms, "valu_issue_frac": valu}
+            "algorithmic_bytes": alg, "avg_launch_ms": iso_ms, "valu_issue_frac": valu, "l2_hit_rate": l2_hit}
 
 
 def resident_iso_measurement(s, cs, reps=3):
@@ -448,7 +459,7 @@ def large_measurement(amr, name, steps, resident=True):
            "ms_per_step": ms, "cells_per_s": cs.n / (ms * 1e-3),
            "stages_ms": {"upload": statistics.mean(up), "build_index": statistics.mean(bd), "isosurface": iso_avg},
            "iso_only_cells_per_s": cs.n / (iso_avg * 1e-3),
-           "roofline": roofline_of(cs.n, n_tri, iso_avg, traffic_for(name), valu_for(name)),
+           "roofline": roofline_of(cs.n, n_tri, iso_avg, traffic_for(name), valu_for(name), l2_hit_for(name)),
            "resident_iso": resident}
     del s, xyz, lvl, val, tris
     torch.cuda.empty_cache()
@@ -593,7 +604,8 @@ def main():
         "iso_only_cells_per_s": cs.n / (iso_avg * 1e-3),
         "iso_latency_ms": {"p50": percentile(lat, 0.5), "p99": percentile(lat, 0.99), "requests": len(lat),
                            "what": "count pass + write pass on the resident set, host clock"},
-        "roofline": roofline_of(cs.n, n_tri, iso_avg, traffic_for(cs.name), valu_for(cs.name)),
+        "roofline": roofline_of(cs.n, n_tri, iso_avg, traffic_for(cs.name), valu_for(cs.name),
+                                l2_hit_for(cs.name)),
     }
     if not args.no_resident:
         out["resident_iso"] = resident_iso_measurement(s, cs)
