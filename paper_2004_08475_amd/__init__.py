@@ -94,7 +94,12 @@ class AmrSet:
     """One AMR cell set on one GPU: upload, index, dual cells, iso-surfaces.
 
     Calls on one set are issued on the caller's current torch stream and must
-    not overlap with calls on another stream."""
+    not overlap with calls on another stream.  The second extraction after a
+    build also records each sibling group's neighbourhood value range; from
+    the third on, iso-surfaces that do not ask for dual indices skip groups
+    whose range cannot straddle the iso (same output bits, much less work on
+    a resident set).  A graph captured around an extraction stays valid until
+    the set is built again."""
 
     def __init__(self, device=None):
         self.lib = load_library()
