@@ -7,7 +7,9 @@ Python binding) never imports it, and it imports nothing from the product.
 The arithmetic lives in ``amr_oracle.c`` (plain C, fp32 placement with an
 explicit fma, no fast-math, no FP contraction); this module compiles it with
 gcc, loads it through ctypes and adds numpy conveniences: canonical ordering
-of duals and triangles and a thread-split driver for the CPU baseline.
+of duals and triangles, a thread-split driver for the CPU baseline, the weld
+of an indexed face set, and the dual-mesh interpolant at query points (fp64,
+brute force over the duals).
 """
 from __future__ import annotations
 
@@ -258,3 +260,86 @@ def indexed_mesh(tris: np.ndarray, cells: np.ndarray):
     idx = rank[inv].reshape(-1, 3).astype(np.int32)
     verts = t[np.sort(first)]
     return verts, idx
+
+
+# ---------------------------------------------------------------------------
+# Dual-mesh interpolant (paper sec. 5 names the dual mesh, as Moran et al.
+# use it, as an interpolant for volume rendering; it does not define one).
+# Reading: each emitted dual is the trilinear hexahedron over its 8 vertex
+# cells' centres, slot s = ex + 2 ey + 4 ez at parameter u = (ex, ey, ez),
+# and carries the trilinear interpolant of their values.  A point's value
+# comes from the dual whose map reaches it with u in [0,1]^3 (Newton on the
+# trilinear map, fp64); points no dual reaches get NaN.  Degenerate duals
+# whose map has no volume reach no point.  Brute force over all duals: tiny
+# sets only.
+# ---------------------------------------------------------------------------
+
+def _trilinear(u):
+    """Weights B_s(u) [K,8] and their derivatives dB_s/du_a [K,3,8]."""
+    ux, uy, uz = u[:, 0:1], u[:, 1:2], u[:, 2:3]
+    s = np.arange(8)
+    ex, ey, ez = (s & 1)[None], ((s >> 1) & 1)[None], (s >> 2)[None]
+    fx = np.where(ex, ux, 1 - ux)
+    fy = np.where(ey, uy, 1 - uy)
+    fz = np.where(ez, uz, 1 - uz)
+    dx = np.where(ex, 1.0, -1.0)
+    dy = np.where(ey, 1.0, -1.0)
+    dz = np.where(ez, 1.0, -1.0)
+    w = fx * fy * fz
+    dw = np.stack([dx * fy * fz, fx * dy * fz, fx * fy * dz], 1)
+    return w, dw
+
+
+def _invert(V, p, iters=40):
+    """u [K,3] with X(u) = p for the hexahedra V [K,8,3] (Newton from the
+    centre), and whether it converged."""
+    u = np.full((len(V), 3), 0.5)
+    ok = np.ones(len(V), bool)
+    for _ in range(iters):
+        w, dw = _trilinear(u)
+        x = np.einsum("ks,ksa->ka", w, V)
+        J = np.einsum("kbs,ksa->kab", dw, V)  # J[k, a, b] = dX_a / du_b
+        r = p - x
+        det = np.linalg.det(J)
+        good = np.abs(det) > 1e-14
+        ok &= good
+        step = np.zeros_like(u)
+        if good.any():
+            step[good] = np.linalg.solve(J[good], r[good][:, :, None])[:, :, 0]
+        u = np.clip(u + step, -0.5, 1.5)
+    w, _ = _trilinear(u)
+    resid = np.abs(np.einsum("ks,ksa->ka", w, V) - p).max(1)
+    return u, ok & (resid < 1e-9)
+
+
+def dual_mesh_sample(xyz, level, value, ids, points, eps: float = 1e-9):
+    """Interpolated values at points [Q,3] from the duals ids [M,8] (cell
+    indices per slot) of the cells (xyz, level, value).  Returns (values
+    float64 [Q] (NaN outside the dual mesh), dual index int64 [Q] (the
+    lowest-numbered dual that reaches the point, -1 if none), number of
+    duals that reach it int64 [Q])."""
+    xyz = np.asarray(xyz, np.float64).reshape(-1, 3)
+    lvl = np.asarray(level, np.int64)
+    val = np.asarray(value, np.float64)
+    ids = np.asarray(ids, np.int64).reshape(-1, 8)
+    pts = np.asarray(points, np.float64).reshape(-1, 3)
+    centre = xyz + 0.5 * (1 << lvl)[:, None].astype(np.float64)
+    V = centre[ids]  # [M,8,3]
+    F = val[ids]     # [M,8]
+    lo, hi = V.min(1) - eps, V.max(1) + eps
+    out = np.full(len(pts), np.nan)
+    which = np.full(len(pts), -1, np.int64)
+    hits = np.zeros(len(pts), np.int64)
+    for q, p in enumerate(pts):
+        cand = np.nonzero(np.all((lo <= p) & (p <= hi), 1))[0]
+        if len(cand) == 0:
+            continue
+        u, ok = _invert(V[cand], np.broadcast_to(p, (len(cand), 3)))
+        inside = ok & np.all((u >= -eps) & (u <= 1 + eps), 1)
+        hits[q] = int(inside.sum())
+        if hits[q]:
+            k = int(np.nonzero(inside)[0][0])
+            w, _ = _trilinear(np.clip(u[k:k + 1], 0.0, 1.0))
+            out[q] = float(w[0] @ F[cand[k]])
+            which[q] = int(cand[k])
+    return out, which, hits
