@@ -3,7 +3,12 @@
 One step = the whole hot path over one synthetic AMR set that is already in
 HBM: validate + reduce (amr_upload), build the cell-location index
 (amr_build_index) and extract the iso-surface (amr_isosurface, one pass into
-a buffer sized by the warm-up).  Prints one JSON line.
+a buffer sized by the warm-up).  Prints one JSON line: the step rate of the
+136,935-cell octree (the value), its roofline (HBM; beside it the VALU issue
+fraction and L2 hit rates from the committed counter summaries), iso latency
+and repeated isos on the built set, the same step on the 50.8M-cell
+block-structured set, the host-to-host pipeline, batched launches, a serving
+run and the CPU oracle's rate.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
