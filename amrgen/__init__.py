@@ -178,6 +178,14 @@ def octree_shell(domain: int = 256, root_level: int = 4, shell=(60.0, 70.0), p_i
                  shell=tuple(shell), p_in=p_in, p_out=p_out, **gp)
 
 
+def octree_shell_2m(seed: int = 2) -> CellSet:
+    """The octree-shell recipe on 256^3 (levels 0..4, split probability 0.6
+    for cells meeting the shell 60 < r < 70) with the probability elsewhere
+    raised from 0.1 to 0.565, which gives the ~2M cells the workload states
+    (2,017,464 cells at seed 2; with 0.1 the recipe gives 136,935)."""
+    return octree_shell(p_out=0.565, seed=seed, name="octree-shell-256-2m")
+
+
 def octree_sized(target_cells: int, seed: int) -> CellSet:
     """Octree-shell set whose domain is scaled (shell radii with it) so that the
     cell count lands near `target_cells`; used for batches of uneven sets."""
@@ -249,6 +257,7 @@ def random_octree(seed: int, roots: int = 2, root_level: int = 3, p_split: float
 WORKLOADS = {
     "two-level-sphere-16": two_level_sphere,
     "octree-shell-256": octree_shell,
+    "octree-shell-256-2m": octree_shell_2m,
 }
 
 

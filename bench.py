@@ -1,14 +1,25 @@
 """Benchmark: AMR cells/s to crack-free triangles on one MI355X.
 
-One step = the whole hot path over one synthetic AMR set that is already in
-HBM: validate + reduce (amr_upload), build the cell-location index
-(amr_build_index) and extract the iso-surface (amr_isosurface, one pass into
-a buffer sized by the warm-up).  Prints one JSON line: the step rate of the
-136,935-cell octree (the value), its roofline (HBM; beside it the VALU issue
-fraction and L2 hit rates from the committed counter summaries), iso latency
-and repeated isos on the built set, the same step on the 50.8M-cell
-block-structured set, the host-to-host pipeline, batched launches, a serving
-run and the CPU oracle's rate.
+One step = the whole hot path over one synthetic AMR set already in HBM:
+validate + reduce (amr_upload), build the cell-location index
+(amr_build_index, enqueued without waiting: its verdict stays on the device
+and is read once after the timed steps) and extract the iso-surface
+(amr_isosurface, one pass into a buffer sized beforehand).  The headline is
+the step rate of the ~2M-cell octree (octree-shell-256-2m).  Every kernel of
+the step is timed on its own with HIP events around the kernel (recorded on
+the stream it runs on); the dominant one is timed in every timed step and
+gives the roofline (HBM; counter figures from the committed summary under
+profiles/ while the kernel source is unchanged).
+
+Beside the headline, the JSON line holds: iso latency and repeated isos on
+the built set; the same step on the 137k-cell octree of the literal recipe
+and on the 50.8M-cell block-structured set with holes; the host-to-host
+pipeline (PCIe-inclusive); 64 isos of the headline set in one batched
+launch and 32 uneven sets (10k..5M cells) in one batched launch, each
+against the plain path; serving a Poisson request mix against the
+608.9M-cell resident octree against the serial plain path; and the CPU
+oracle's rate on the headline set, on a sample of the 50.8M-cell set and on
+the 32 sets.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -24,11 +35,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "AMR cells/sec to crack-free triangles (1 GPU, % HBM roofline); p50/p99 iso latency"
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2004_08475_amd", "csrc", "amriso.hip")
 
 
 def make_workload(name):
     import amrgen
 
+    if name == "octree-shell-256-2m":
+        return amrgen.octree_shell_2m()
     if name == "octree-shell-256":
         return amrgen.octree_shell()
     if name == "two-level-sphere-16":
@@ -51,40 +65,330 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def cpu_baseline(cs, min_seconds=10.0):
-    """The oracle as it is, on the host's cores: sorted index + rules + MC
-    over the whole set, repeated until about min_seconds have passed."""
+def host_threads():
+    return len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+
+
+def oracle_rate(cs, threads, sample=None, seed=0):
+    """The oracle as it stands on `threads` host threads: its sorted index over
+    the whole set (timed), then rules 1-3 + Marching Cubes over all cells or
+    over `sample` consecutive cells of the shuffled list (timed); the rate
+    charges the index in full and the extraction scaled to the whole set.
+    Returns (cells/s, seconds spent, cells extracted)."""
     import oracle
 
-    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    reps, t_total = 0, 0.0
-    tris = 0
-    while t_total < min_seconds and reps < 10000:
-        t0 = time.perf_counter()
-        o = oracle.Oracle(cs.xyz, cs.level, cs.value, validate=False)
-        tris, _ = o.isosurface_threaded(cs.iso, threads)
-        t_total += time.perf_counter() - t0
-        reps += 1
-        del o
-    # the same oracle on one thread, once over the same set
     t0 = time.perf_counter()
     o = oracle.Oracle(cs.xyz, cs.level, cs.value, validate=False)
-    o.count_range(cs.iso, 0, cs.n)
-    t_one = time.perf_counter() - t0
+    t_index = time.perf_counter() - t0
+    c0, c1 = 0, cs.n
+    if sample and sample < cs.n:
+        c0 = (seed * 7919) % (cs.n - sample)
+        c1 = c0 + sample
+    t0 = time.perf_counter()
+    o.isosurface_threaded(cs.iso, threads, c0, c1)
+    t_ext = time.perf_counter() - t0
     del o
-    # the brute-force locator (a scan over all cells per snap) on the 960-cell two-level sphere
-    import amrgen
+    t_whole = t_index + t_ext * cs.n / (c1 - c0)
+    return cs.n / t_whole, t_index + t_ext, c1 - c0
 
+
+def cpu_baseline(cs, min_seconds=10.0, large=None, sets=None):
+    """The oracle (never tuned) on the host's cores: the headline set whole,
+    repeated until about min_seconds have passed; one thread on a sample of
+    it; the brute-force locator on the 960-cell two-level sphere; and, when
+    given, a sample of the large set and the batch of uneven sets."""
+    import amrgen
+    import oracle
+
+    threads = host_threads()
+    reps, t_total = 0, 0.0
+    while t_total < min_seconds and reps < 10000:
+        _, dt, _ = oracle_rate(cs, threads)
+        t_total += dt
+        reps += 1
+    one_rate, one_s, one_n = oracle_rate(cs, 1, sample=min(cs.n, 100_000))
     c1 = amrgen.two_level_sphere()
     t0 = time.perf_counter()
     ob = oracle.Oracle(c1.xyz, c1.level, c1.value, locator="brute", validate=False)
     ob.count_range(c1.iso, 0, c1.n)
     t_brute = time.perf_counter() - t0
-    return {"value": cs.n * reps / t_total, "unit": "cells/s", "cores": threads, "kind": "oracle",
-            "sample": "whole %s set (%d cells, %d triangles), sorted-corner index + rules 1-3 + Marching Cubes, "
-                      "%d repetitions, %.1f s" % (cs.name, cs.n, tris, reps, t_total),
-            "one_thread": {"value": cs.n / t_one, "seconds": t_one},
-            "brute_force": {"workload": c1.name, "cells": c1.n, "value": c1.n / t_brute, "seconds": t_brute}}
+    out = {"value": cs.n * reps / t_total, "unit": "cells/s", "cores": threads, "kind": "oracle",
+           "sample": "whole %s set (%d cells): sorted-corner index + rules 1-3 + Marching Cubes on %d threads, "
+                     "%d repetitions, %.1f s" % (cs.name, cs.n, threads, reps, t_total),
+           "one_thread": {"value": one_rate, "seconds": one_s,
+                          "sample": "index over all cells, extraction over %d cells, scaled" % one_n},
+           "brute_force": {"workload": c1.name, "cells": c1.n, "value": c1.n / t_brute, "seconds": t_brute}}
+    if large is not None:
+        rate, dt, k = oracle_rate(large, threads, sample=2_000_000)
+        out["large_workload"] = {"workload": large.name, "cells": large.n, "value": rate, "unit": "cells/s",
+                                 "seconds": dt, "sample": "index over all %d cells (timed), extraction over %d "
+                                 "consecutive cells of the shuffled list, scaled to the set" % (large.n, k)}
+    if sets:
+        t_sum, n_sum, ext = 0.0, 0, 0
+        for k, c in enumerate(sets):
+            _, dt, m = oracle_rate(c, threads, sample=300_000, seed=k)
+            t_sum += dt * c.n / max(m, 1) if m < c.n else dt
+            n_sum += c.n
+            ext += m
+        out["batched_sets"] = {"sets": len(sets), "cells": n_sum, "value": n_sum / t_sum, "unit": "cells/s",
+                               "sample": "each set's index whole, extraction over at most 300,000 cells per set "
+                                         "(%d cells in all), scaled per set" % ext}
+    return out
+
+
+def counters_for(workload, kernel):
+    """rocprofv3 counter figures of one kernel on one workload from the
+    committed summary profiles/<workload>_counters.txt: HBM traffic per
+    launch (FETCH_SIZE + WRITE_SIZE scaled by a plain copy), L2 and MALL hit
+    rates, the VALU issue fraction.  None when there is no summary, no line
+    for the kernel, or the kernel source changed since the counters were
+    taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "%s_counters.txt" % workload)
+    try:
+        lines = open(path).read().splitlines()
+        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    recorded = [ln.split()[1] for ln in lines if ln.startswith("source_sha256")]
+    if not recorded or recorded[0] != src:
+        return None
+    for ln in lines:
+        if ln.startswith("kernel "):
+            name, rest = ln[len("kernel "):].split(" | ", 1)
+            if name.strip() == kernel:
+                f = rest.split()
+                return {k: (None if v == "-" else float(v)) for k, v in zip(f[0::2], f[1::2])}
+    return None
+
+
+def kernel_names(amr):
+    return {amr.KERNEL_UPLOAD: "k_upload", amr.KERNEL_RESET: "k_build_reset", amr.KERNEL_INSERT: "k_index_insert",
+            amr.KERNEL_COMPACT: "k_index_compact", amr.KERNEL_MARK: "k_index_mark",
+            amr.KERNEL_EXTRACT: "extract", amr.KERNEL_WRITE: "write"}
+
+
+def kernel_survey(amr, s, step, reps=3):
+    """Each kernel of a step on its own: HIP events around the kernel itself
+    (recorded on the stream it runs on), `reps` steps per kernel.  Returns
+    {kernel id: mean ms}; a kernel the step does not run (the write pass of
+    a fused call) is left out."""
+    import torch
+
+    out = {}
+    stream = torch.cuda.current_stream()
+    for k in kernel_names(amr):
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            e1.record(stream)
+            s.time_kernel(k, e0, e1)
+            step()
+            torch.cuda.synchronize()
+            s.time_kernel(0, e0, e1)  # disarm, in case the step did not run it
+            ms.append(e0.elapsed_time(e1))
+        if min(ms) > 0.0005:
+            out[k] = statistics.mean(ms)
+    return out
+
+
+def time_steps(amr, s, step, iso_call, steps, warmup, kernel):
+    """`steps` whole-path steps between two synchronisations (host clock),
+    with HIP events around `kernel` in every one of them (its own duration,
+    recorded on the stream it runs on).  A second run of the same steps puts
+    events between the stages for the per-stage split.  Returns (ms per step,
+    kernel ms per step, (upload, build, iso) ms lists)."""
+    import torch
+
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        step()
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in pairs:
+        a.record(stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        s.time_kernel(kernel, *pairs[k])
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    s.build_status()  # the verdict of the last build on the device: raises if it failed
+    kms = [a.elapsed_time(b) for a, b in pairs]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    for e in evs:
+        e[0].record(stream)
+        s.upload(*s._cells)
+        e[1].record(stream)
+        s.build_index(wait=False)
+        e[2].record(stream)
+        iso_call()
+        e[3].record(stream)
+    torch.cuda.synchronize()
+    s.build_status()
+    st = ([e[0].elapsed_time(e[1]) for e in evs], [e[1].elapsed_time(e[2]) for e in evs],
+          [e[2].elapsed_time(e[3]) for e in evs])
+    return ms, kms, st
+
+
+def alg_bytes(amr, kernel, n_cells, n_tri, fused):
+    """Algorithmic bytes of one launch: 20 B per input cell read once (its
+    int3 corner, level and value) and 36 B per triangle written (the per-unit
+    figures of the path); the index insertion also stores each cell's value
+    in its group record (4 B per cell)."""
+    if kernel == amr.KERNEL_UPLOAD:
+        return 20.0 * n_cells
+    if kernel == amr.KERNEL_INSERT:
+        return 24.0 * n_cells
+    if kernel == amr.KERNEL_EXTRACT:
+        return 20.0 * n_cells + (36.0 * n_tri if fused else 0.0)
+    if kernel == amr.KERNEL_WRITE:
+        return 36.0 * n_tri
+    return None
+
+
+def roofline_of(name, alg, kernel_ms, counters, launches):
+    achieved = alg / (kernel_ms * 1e-3) / 1e9
+    c = counters or {}
+    return {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": c.get("traffic_bytes"), "algorithmic_bytes": alg,
+            "avg_launch_ms": kernel_ms, "launches": launches,
+            "l2_hit_rate": c.get("l2_hit"), "mall_hit_rate": c.get("mall_hit"),
+            "valu_issue_frac": c.get("valu_issue")}
+
+
+def step_measurement(amr, cs, xyz, lvl, val, steps, warmup):
+    """The whole-path step on one resident set: throughput, every kernel's
+    own duration, and the roofline of the dominant kernel (timed in every
+    timed step)."""
+    import torch
+
+    dev = xyz.device
+    s = amr.AmrSet(dev.index)
+    s.upload(xyz, lvl, val)
+    s.build_index()
+    n_tri, n_dual = s.count(cs.iso)
+    cap = n_tri
+    tris = torch.empty((max(cap, 1), 9), dtype=torch.float32, device=dev)
+
+    def iso_call():
+        s.isosurface_into(cs.iso, tris, cap)
+
+    def step():
+        s.upload(xyz, lvl, val)
+        s.build_index(wait=False)
+        iso_call()
+
+    for _ in range(warmup):
+        step()
+    survey = kernel_survey(amr, s, step)
+    names = kernel_names(amr)
+    fused = amr.KERNEL_WRITE not in survey
+    names[amr.KERNEL_EXTRACT] = "k_extract<false, 2>" if fused else "k_extract<false, 0>"
+    names[amr.KERNEL_WRITE] = "k_extract_list<1>"
+    dom = max(survey, key=survey.get)
+    ms, kms, (up, bd, iso) = time_steps(amr, s, step, iso_call, steps, warmup, dom)
+    assert int(s.counts[0].item()) == n_tri
+    kernel_ms = statistics.mean(kms)
+    alg = alg_bytes(amr, dom, cs.n, n_tri, fused)
+    return {"set": s, "n_tri": n_tri, "n_dual": n_dual, "ms_per_step": ms, "cells_per_s": cs.n / (ms * 1e-3),
+            "stages_ms": {"upload": statistics.mean(up), "build_index": statistics.mean(bd),
+                          "isosurface": statistics.mean(iso)},
+            "kernels_ms": {names[k]: v for k, v in sorted(survey.items(), key=lambda kv: -kv[1])},
+            "roofline": (roofline_of(names[dom], alg, kernel_ms, counters_for(cs.name, names[dom]), steps)
+                         if alg else {"kernel": names[dom], "avg_launch_ms": kernel_ms})}
+
+
+def large_measurement(amr, cs, steps, resident=True):
+    """The same whole-path step on the 50.8M-cell block-structured set, where
+    throughput rather than launch latency decides."""
+    import torch
+
+    dev = torch.device("cuda", 0)
+    xyz, lvl, val = (torch.from_numpy(a).to(dev) for a in (cs.xyz, cs.level, cs.value))
+    r = step_measurement(amr, cs, xyz, lvl, val, steps, 2)
+    s = r.pop("set")
+    out = {"workload": cs.name, "cells": cs.n, "triangles": r["n_tri"], "duals": r["n_dual"], "steps": steps,
+           "ms_per_step": r["ms_per_step"], "cells_per_s": r["cells_per_s"], "stages_ms": r["stages_ms"],
+           "kernels_ms": r["kernels_ms"], "roofline": r["roofline"],
+           "resident_iso": resident_iso_measurement(s, cs) if resident else None}
+    s.close()
+    del s, xyz, lvl, val
+    torch.cuda.empty_cache()
+    return out
+
+
+def resident_iso_measurement(s, cs, reps=3):
+    """Single-pass iso-surfaces at 19 quantiles of the values on the built
+    set (its group value ranges already recorded, so the passes skip groups
+    that cannot hold triangles), HIP events around each call on the stream
+    the kernels run on."""
+    import numpy as np
+    import torch
+
+    stream = torch.cuda.current_stream()
+    isos = np.quantile(cs.value, np.linspace(0.05, 0.95, 19)).astype(np.float32)
+    counts = [s.count(float(v))[0] for v in isos]
+    tris = torch.empty((max(max(counts), 1), 9), dtype=torch.float32, device=s.device)
+    evs = []
+    for _ in range(reps):
+        for v, c in zip(isos, counts):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            s.isosurface_into(float(v), tris, c)
+            e1.record(stream)
+            evs.append((e0, e1))
+    torch.cuda.synchronize()
+    ms = [a.elapsed_time(b) for a, b in evs]
+    mean = statistics.mean(ms)
+    return {"isos": len(isos), "reps": reps, "ms_mean": mean, "ms_min": min(ms), "ms_max": max(ms),
+            "triangles_mean": statistics.mean(counts), "cells_per_s": cs.n / (mean * 1e-3),
+            "what": "amr_isosurface single pass (count, scan, write) at quantiles 0.05..0.95 of the values, "
+                    "group value ranges recorded by an earlier call"}
+
+
+def pipeline_measurement(amr, cs, reps=5):
+    """The whole pipeline from host memory and back (the paper's Y column,
+    its sec. 5.2 figure): pinned host cells -> device, validate, index, count
+    and write the triangles, weld them into an indexed mesh, copy vertices
+    and indices back.  PCIe-inclusive, so it is reported beside `value`."""
+    import torch
+
+    dev = torch.device("cuda", 0)
+    hx = torch.from_numpy(cs.xyz).pin_memory()
+    hl = torch.from_numpy(cs.level).pin_memory()
+    hv = torch.from_numpy(cs.value).pin_memory()
+    s = amr.AmrSet(0)
+    times, parts = [], []
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, l, v = hx.to(dev, non_blocking=True), hl.to(dev, non_blocking=True), hv.to(dev, non_blocking=True)
+        s.upload(x, l, v)
+        t1 = time.perf_counter()
+        s.build_index()
+        t2 = time.perf_counter()
+        out = s.isosurface(cs.iso, cells=True)
+        t3 = time.perf_counter()
+        verts, idx = amr.indexed_mesh(out["tris"], out["cells"])
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        hv_out, hi_out = verts.cpu(), idx.cpu()
+        t5 = time.perf_counter()
+        if r:
+            times.append(t5 - t0)
+            parts.append((t1 - t0, t2 - t1, t3 - t2, t4 - t3, t5 - t4))
+    k = sorted(range(reps), key=lambda i: times[i])[reps // 2]
+    p = parts[k]
+    return {"what": "host cells -> device -> amr_upload -> amr_build_index -> amr_isosurface (count + write) -> "
+                    "amr_indexed_mesh -> vertices and indices to host; median of %d, host clock" % reps,
+            "ms": times[k] * 1e3, "cells_per_s": cs.n / times[k],
+            "stages_ms": {"h2d+upload": p[0] * 1e3, "build_index": p[1] * 1e3, "isosurface": p[2] * 1e3,
+                          "indexed_mesh": p[3] * 1e3, "d2h": p[4] * 1e3},
+            "triangles": int(hi_out.shape[0]), "vertices": int(hv_out.shape[0])}
 
 
 def batched_measurement(amr, s, cs, n_isos):
@@ -148,6 +452,78 @@ def batched_measurement(amr, s, cs, n_isos):
             "iso_cells_per_s": n_isos * cs.n / (fused_ms * 1e-3), "triangles": int(c.sum()),
             "dual_list_ms": t_duals * 1e3, "autotuned_shape": {"block": block, "per_thread": per},
             "autotune_ms": table}
+
+
+def batched_multiset_measurement(amr, n_sets=32, seed=4):
+    """32 independent octree sets of log-uniform sizes 10k..5M cells, each at
+    its own iso (median), in one fused persistent launch replayed from a HIP
+    graph, against the plain path run once per set."""
+    import numpy as np
+    import torch
+
+    import amrgen
+    from paper_2004_08475_amd import autotune
+
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(np.log(1e4), np.log(5e6), n_sets)).astype(int)
+    css, sets = [], []
+    for k, n in enumerate(sizes):
+        cs = amrgen.octree_sized(int(n), seed=200 + k)
+        css.append(cs)
+        sets.append(amr.from_numpy(cs.xyz, cs.level, cs.value))
+    say("batched sets: %d sets, %d cells in all" % (n_sets, sum(c.n for c in css)))
+    dev = sets[0].device
+    b = amr.AmrBatch(sets)
+    isos = np.array([c.iso for c in css], np.float32)
+    counts = torch.zeros(n_sets, dtype=torch.int64, device=dev)
+    probe = b.jobs_tensor(list(range(n_sets)), isos, np.zeros(n_sets), np.zeros(n_sets))
+    b.run_into(probe, n_sets, None, counts)
+    c = counts.cpu().numpy()
+    off = np.concatenate([[0], np.cumsum(c)[:-1]])
+    tris = torch.empty((max(int(c.sum()), 1), 9), dtype=torch.float32, device=dev)
+    jobs = b.jobs_tensor(list(range(n_sets)), isos, off, c)
+    block, per, table = autotune.tune(b, jobs, n_sets, tris, counts)
+    ws = b.workspace(n_sets, block, per)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        b.run_into(jobs, n_sets, tris, counts, block, per, ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.run_into(jobs, n_sets, tris, counts, block, per, ws)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g.replay()
+    e0.record()
+    for _ in range(10):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    fused_ms = e0.elapsed_time(e1) / 10
+    assert counts.cpu().numpy().tolist() == c.tolist()
+    bufs = [torch.empty((max(int(k), 1), 9), dtype=torch.float32, device=dev) for k in c]
+    for k in range(n_sets):
+        sets[k].isosurface_into(float(isos[k]), bufs[k], int(c[k]))
+    e0.record()
+    for _ in range(3):
+        for k in range(n_sets):
+            sets[k].isosurface_into(float(isos[k]), bufs[k], int(c[k]))
+    e1.record()
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1) / 3
+    for k in range(n_sets):
+        assert torch.equal(bufs[k][:int(c[k])], tris[int(off[k]):int(off[k]) + int(c[k])])
+    n_cells = int(sum(cs.n for cs in css))
+    for st in sets:
+        st.close()
+    b.close()
+    return {"workload": "%d octree sets, log-uniform 10k..5M cells (%d in all), own median iso each, one fused "
+                        "launch replayed from a HIP graph" % (n_sets, n_cells),
+            "set_cells": [int(cs.n) for cs in css], "fused_ms": fused_ms, "plain_ms_for_all_sets": plain_ms,
+            "speedup_vs_plain": plain_ms / fused_ms, "cells_per_s": n_cells / (fused_ms * 1e-3),
+            "triangles": int(c.sum()), "autotuned_shape": {"block": block, "per_thread": per},
+            "autotune_ms": table}, css
 
 
 def serving_measurement(amr, s, name, iso_pool, seconds, rate, serial_requests=0):
@@ -236,303 +612,28 @@ def large_serving(amr, seconds, rate, serial_requests):
     return out
 
 
-def batched_multiset_measurement(amr, n_sets=32, seed=4):
-    """32 independent octree sets of log-uniform sizes 10k..5M cells, each at
-    its own iso (median), in one fused persistent launch replayed from a HIP
-    graph, against the plain path run once per set."""
-    import numpy as np
-    import torch
-
-    import amrgen
-    from paper_2004_08475_amd import autotune
-
-    rng = np.random.default_rng(seed)
-    sizes = np.exp(rng.uniform(np.log(1e4), np.log(5e6), n_sets)).astype(int)
-    css, sets = [], []
-    for k, n in enumerate(sizes):
-        cs = amrgen.octree_sized(int(n), seed=200 + k)
-        css.append(cs)
-        sets.append(amr.from_numpy(cs.xyz, cs.level, cs.value))
-    say("batched sets: %d sets, %d cells in all" % (n_sets, sum(c.n for c in css)))
-    dev = sets[0].device
-    b = amr.AmrBatch(sets)
-    isos = np.array([c.iso for c in css], np.float32)
-    counts = torch.zeros(n_sets, dtype=torch.int64, device=dev)
-    probe = b.jobs_tensor(list(range(n_sets)), isos, np.zeros(n_sets), np.zeros(n_sets))
-    b.run_into(probe, n_sets, None, counts)
-    c = counts.cpu().numpy()
-    off = np.concatenate([[0], np.cumsum(c)[:-1]])
-    tris = torch.empty((max(int(c.sum()), 1), 9), dtype=torch.float32, device=dev)
-    jobs = b.jobs_tensor(list(range(n_sets)), isos, off, c)
-    block, per, table = autotune.tune(b, jobs, n_sets, tris, counts)
-    ws = b.workspace(n_sets, block, per)
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        b.run_into(jobs, n_sets, tris, counts, block, per, ws)
-    torch.cuda.current_stream().wait_stream(side)
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        b.run_into(jobs, n_sets, tris, counts, block, per, ws)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    g.replay()
-    e0.record()
-    for _ in range(10):
-        g.replay()
-    e1.record()
-    torch.cuda.synchronize()
-    fused_ms = e0.elapsed_time(e1) / 10
-    assert counts.cpu().numpy().tolist() == c.tolist()
-    bufs = [torch.empty((max(int(k), 1), 9), dtype=torch.float32, device=dev) for k in c]
-    for k in range(n_sets):
-        sets[k].isosurface_into(float(isos[k]), bufs[k], int(c[k]))
-    e0.record()
-    for _ in range(3):
-        for k in range(n_sets):
-            sets[k].isosurface_into(float(isos[k]), bufs[k], int(c[k]))
-    e1.record()
-    torch.cuda.synchronize()
-    plain_ms = e0.elapsed_time(e1) / 3
-    for k in range(n_sets):
-        assert torch.equal(bufs[k][:int(c[k])], tris[int(off[k]):int(off[k]) + int(c[k])])
-    n_cells = int(sum(cs.n for cs in css))
-    return {"workload": "%d octree sets, log-uniform 10k..5M cells (%d in all), own median iso each, one fused "
-                        "launch replayed from a HIP graph" % (n_sets, n_cells),
-            "set_cells": [int(cs.n) for cs in css], "fused_ms": fused_ms, "plain_ms_for_all_sets": plain_ms,
-            "speedup_vs_plain": plain_ms / fused_ms, "cells_per_s": n_cells / (fused_ms * 1e-3),
-            "triangles": int(c.sum()), "autotuned_shape": {"block": block, "per_thread": per}, "autotune_ms": table}
-
-
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_extract_traffic.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2004_08475_amd", "csrc", "amriso.hip")
-
-
-def traffic_for(workload):
-    """HBM bytes per amr_isosurface call from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when
-    there is none for this workload or the kernel source changed since."""
-    import hashlib
-
-    try:
-        lines = open(TRAFFIC_FILE).read().splitlines()
-        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    except OSError:
-        return None
-    fields = [ln.split() for ln in lines if ln and not ln.startswith("#")]
-    recorded = [f[1] for f in fields if f[0] == "source_sha256"]
-    if not recorded or recorded[0] != src:
-        return None
-    for f in fields:
-        if f[0] == "workload" and f[1] == workload:
-            kv = dict(zip(f[2::2], f[3::2]))
-            return float(kv["traffic_bytes"])
-    return None
-
-
-VALU_FILE = os.path.join(ROOT, "profiles", "k_extract_valu.txt")
-L2_FILE = os.path.join(ROOT, "profiles", "k_extract_l2.txt")
-
-
-def _per_kernel(path, workload):
-    """Per extraction kernel of this workload, the last figure of its line in
-    a committed rocprofv3 counter summary, or None when there is none or the
-    kernel source changed since the counters were taken."""
-    import hashlib
-
-    try:
-        lines = open(path).read().splitlines()
-        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    except OSError:
-        return None
-    recorded = [ln.split()[1] for ln in lines if ln.startswith("source_sha256")]
-    if not recorded or recorded[0] != src:
-        return None
-    out = {}
-    for ln in lines:
-        if ln.startswith(workload + " "):
-            kernel = ln[len(workload) + 1:].split(":")[0]
-            out[kernel] = float(ln.rsplit("|", 1)[1])
-    return out or None
-
-
-def valu_for(workload):
-    """Fraction of the VALU issue peak per extraction kernel (SQ counters)."""
-    return _per_kernel(VALU_FILE, workload)
-
-
-def l2_hit_for(workload):
-    """L2 hit rate per extraction kernel (TCC counters)."""
-    return _per_kernel(L2_FILE, workload)
-
-
-def time_steps(amr, s, xyz, lvl, val, iso, cap, tris, steps, warmup):
-    """Whole-path steps (upload + build + iso).  The timed run has nothing
-    but the steps between two synchronisations (host clock); a second run of
-    the same steps records HIP events between the stages, on the stream the
-    kernels run on, for the per-stage split.  Returns (ms per step, stage
-    lists from the instrumented run)."""
-    import torch
-
-    stream = torch.cuda.current_stream()
-
-    def step(ev=None):
-        if ev:
-            ev[0].record(stream)
-        s.upload(xyz, lvl, val)
-        if ev:
-            ev[1].record(stream)
-        s.build_index()
-        if ev:
-            ev[2].record(stream)
-        s.isosurface_into(iso, tris, cap)
-        if ev:
-            ev[3].record(stream)
-
-    for _ in range(warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
-    for k in range(steps):
-        step(evs[k])
-    torch.cuda.synchronize()
-    st = ([e[0].elapsed_time(e[1]) for e in evs], [e[1].elapsed_time(e[2]) for e in evs],
-          [e[2].elapsed_time(e[3]) for e in evs])
-    return ms, st
-
-
-def roofline_of(n_cells, n_tri, iso_ms, traffic, valu=None, l2_hit=None):
-    alg = 20.0 * n_cells + 36.0 * n_tri
-    achieved = alg / (iso_ms * 1e-3) / 1e9
-    return {"bound": "hbm", "kernel": "k_extract passes of one amr_isosurface call", "achieved": achieved,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "algorithmic_bytes": alg, "avg_launch_ms": iso_ms, "valu_issue_frac": valu, "l2_hit_rate": l2_hit}
-
-
-def resident_iso_measurement(s, cs, reps=3):
-    """Single-pass iso-surfaces at 19 quantiles of the values on the built
-    set (its group value ranges already recorded, so the passes skip groups
-    that cannot hold triangles), HIP events around each call on the stream
-    the kernels run on."""
-    import numpy as np
-    import torch
-
-    stream = torch.cuda.current_stream()
-    isos = np.quantile(cs.value, np.linspace(0.05, 0.95, 19)).astype(np.float32)
-    counts = [s.count(float(v))[0] for v in isos]
-    tris = torch.empty((max(max(counts), 1), 9), dtype=torch.float32, device=s.device)
-    evs = []
-    for _ in range(reps):
-        for v, c in zip(isos, counts):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            s.isosurface_into(float(v), tris, c)
-            e1.record(stream)
-            evs.append((e0, e1))
-    torch.cuda.synchronize()
-    ms = [a.elapsed_time(b) for a, b in evs]
-    mean = statistics.mean(ms)
-    return {"isos": len(isos), "reps": reps, "ms_mean": mean, "ms_min": min(ms), "ms_max": max(ms),
-            "triangles_mean": statistics.mean(counts), "cells_per_s": cs.n / (mean * 1e-3),
-            "what": "amr_isosurface single pass (count, scan, write) at quantiles 0.05..0.95 of the values, "
-                    "group value ranges recorded by an earlier call"}
-
-
-def large_measurement(amr, name, steps, resident=True):
-    """The same whole-path step on a large set (block-structured, 50.8M
-    cells), where throughput rather than launch latency decides."""
-    import torch
-
-    cs = make_workload(name)
-    dev = torch.device("cuda", 0)
-    xyz, lvl, val = (torch.from_numpy(a).to(dev) for a in (cs.xyz, cs.level, cs.value))
-    s = amr.AmrSet(0)
-    s.upload(xyz, lvl, val)
-    s.build_index()
-    n_tri, n_dual = s.count(cs.iso)
-    tris = torch.empty((max(n_tri, 1), 9), dtype=torch.float32, device=dev)
-    ms, (up, bd, iso) = time_steps(amr, s, xyz, lvl, val, cs.iso, n_tri, tris, steps, 2)
-    assert int(s.counts[0].item()) == n_tri
-    iso_avg = statistics.mean(iso)
-    resident = resident_iso_measurement(s, cs) if resident else None
-    out = {"workload": name, "cells": cs.n, "triangles": n_tri, "duals": n_dual, "steps": steps,
-           "ms_per_step": ms, "cells_per_s": cs.n / (ms * 1e-3),
-           "stages_ms": {"upload": statistics.mean(up), "build_index": statistics.mean(bd), "isosurface": iso_avg},
-           "iso_only_cells_per_s": cs.n / (iso_avg * 1e-3),
-           "roofline": roofline_of(cs.n, n_tri, iso_avg, traffic_for(name), valu_for(name), l2_hit_for(name)),
-           "resident_iso": resident}
-    del s, xyz, lvl, val, tris
-    torch.cuda.empty_cache()
-    return out
-
-
-def pipeline_measurement(amr, cs, reps=5):
-    """The whole pipeline from host memory and back (the paper's Y column,
-    its sec. 5.2 figure): pinned host cells -> device, validate, index, count
-    and write the triangles, weld them into an indexed mesh, copy vertices
-    and indices back.  PCIe-inclusive, so it is reported beside `value`."""
-    import torch
-
-    dev = torch.device("cuda", 0)
-    hx = torch.from_numpy(cs.xyz).pin_memory()
-    hl = torch.from_numpy(cs.level).pin_memory()
-    hv = torch.from_numpy(cs.value).pin_memory()
-    s = amr.AmrSet(0)
-    times, parts = [], []
-    for r in range(reps + 1):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        x, l, v = hx.to(dev, non_blocking=True), hl.to(dev, non_blocking=True), hv.to(dev, non_blocking=True)
-        s.upload(x, l, v)
-        t1 = time.perf_counter()
-        s.build_index()
-        t2 = time.perf_counter()
-        out = s.isosurface(cs.iso, cells=True)
-        t3 = time.perf_counter()
-        verts, idx = amr.indexed_mesh(out["tris"], out["cells"])
-        torch.cuda.synchronize()
-        t4 = time.perf_counter()
-        hv_out, hi_out = verts.cpu(), idx.cpu()
-        t5 = time.perf_counter()
-        if r:
-            times.append(t5 - t0)
-            parts.append((t1 - t0, t2 - t1, t3 - t2, t4 - t3, t5 - t4))
-    k = sorted(range(reps), key=lambda i: times[i])[reps // 2]
-    p = parts[k]
-    return {"what": "host cells -> device -> amr_upload -> amr_build_index -> amr_isosurface (count + write) -> "
-                    "amr_indexed_mesh -> vertices and indices to host; median of %d, host clock" % reps,
-            "ms": times[k] * 1e3, "cells_per_s": cs.n / times[k],
-            "stages_ms": {"h2d+upload": p[0] * 1e3, "build_index": p[1] * 1e3, "isosurface": p[2] * 1e3,
-                          "indexed_mesh": p[3] * 1e3, "d2h": p[4] * 1e3},
-            "triangles": int(hi_out.shape[0]), "vertices": int(hv_out.shape[0])}
-
-
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="octree-shell-256")
+    ap.add_argument("--workload", default="octree-shell-256-2m")
+    ap.add_argument("--small", default="octree-shell-256", help="also time the step on this set ('none' to skip)")
+    ap.add_argument("--large", default="block-vortex-1024",
+                    help="also time the step on this large workload ('none' to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-requests", type=int, default=200)
     ap.add_argument("--batch-isos", type=int, default=64, help="isos in the batched (fused) measurement; 0 = skip")
-    ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of the serving run; 0 = skip")
+    ap.add_argument("--batch-sets", type=int, default=32,
+                    help="independent octree sets (10k..5M cells) fused into one launch; 0 = skip")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of the serving run; 0 = skip")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the serving run")
-    ap.add_argument("--serve-workload", default="bench", choices=("bench", "large"),
-                    help="resident set of the serving run: the bench workload, or the ~600M-cell octree")
-    ap.add_argument("--serve-serial-requests", type=int, default=0,
+    ap.add_argument("--serve-workload", default="large", choices=("bench", "large"),
+                    help="resident set of the serving run: the ~600M-cell octree, or the bench workload")
+    ap.add_argument("--serve-serial-requests", type=int, default=300,
                     help="replay only this many requests through the serial baseline (0 = all)")
-    ap.add_argument("--large", default="block-vortex-1024",
-                    help="also time the step on this large workload ('none' to skip)")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="skip the host-to-host pipeline timing (transfers, weld, download)")
-    ap.add_argument("--batch-sets", type=int, default=0,
-                    help="also fuse this many independent octree sets (10k..5M cells) into one launch")
     ap.add_argument("--no-resident", action="store_true",
                     help="skip the repeated-iso timing on the built set (culled passes), e.g. under a profiler")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -556,22 +657,17 @@ def main():
     xyz = torch.from_numpy(cs.xyz).to(dev)
     lvl = torch.from_numpy(cs.level).to(dev)
     val = torch.from_numpy(cs.value).to(dev)
-    s = amr.AmrSet(0)
-    s.upload(xyz, lvl, val)
-    s.build_index()
-    n_tri, n_dual = s.count(cs.iso)
-    cap = n_tri
-    tris = torch.empty((max(cap, 1), 9), dtype=torch.float32, device=dev)
-    ms_per_step, (up_ms, bd_ms, iso_ms) = time_steps(amr, s, xyz, lvl, val, cs.iso, cap, tris, args.steps,
-                                                      args.warmup)
-    assert int(s.counts[0].item()) == n_tri
+    r = step_measurement(amr, cs, xyz, lvl, val, args.steps, args.warmup)
+    s, n_tri, n_dual = r["set"], r["n_tri"], r["n_dual"]
+    say("timed steps done: %.3f ms/step; dominant kernel %s %.3f ms" % (
+        r["ms_per_step"], r["roofline"]["kernel"], r["roofline"]["avg_launch_ms"]))
 
     # iso requests on the resident set: count pass + write pass, host clock
     isos = np.quantile(cs.value, np.linspace(0.05, 0.95, 19)).astype(np.float32)
     lat = []
-    big = torch.empty((max(4 * cap, 1024), 9), dtype=torch.float32, device=dev)
-    for r in range(args.latency_requests):
-        iso = float(isos[r % len(isos)])
+    big = torch.empty((max(4 * n_tri, 1024), 9), dtype=torch.float32, device=dev)
+    for k in range(args.latency_requests):
+        iso = float(isos[k % len(isos)])
         torch.cuda.synchronize()
         ta = time.perf_counter()
         c = s.count(iso)[0]
@@ -587,7 +683,7 @@ def main():
         torch.mul(xa, 1.0, out=ya)
         torch.cuda.synchronize()
 
-    iso_avg = statistics.mean(iso_ms)
+    ms_per_step = r["ms_per_step"]
     out = {
         "metric": METRIC,
         "value": cs.n / (ms_per_step * 1e-3),
@@ -603,20 +699,31 @@ def main():
         "data": "synthetic (seeded generator, shuffled cell order)",
         "config": {"workload": cs.name, "cells": cs.n, "levels": sorted(set(cs.level.tolist())),
                    "iso": cs.iso, "triangles": n_tri, "duals": n_dual,
-                   "step": "amr_upload + amr_build_index + amr_isosurface (single pass)"},
-        "stages_ms": {"upload": statistics.mean(up_ms), "build_index": statistics.mean(bd_ms),
-                      "isosurface": iso_avg},
-        "iso_only_cells_per_s": cs.n / (iso_avg * 1e-3),
+                   "step": "amr_upload + amr_build_index (verdict read after the timed steps) + amr_isosurface "
+                           "(single pass)"},
+        "roofline": r["roofline"],
+        "kernels_ms": r["kernels_ms"],
+        "stages_ms": r["stages_ms"],
         "iso_latency_ms": {"p50": percentile(lat, 0.5), "p99": percentile(lat, 0.99), "requests": len(lat),
                            "what": "count pass + write pass on the resident set, host clock"},
-        "roofline": roofline_of(cs.n, n_tri, iso_avg, traffic_for(cs.name), valu_for(cs.name),
-                                l2_hit_for(cs.name)),
     }
     if not args.no_resident:
         out["resident_iso"] = resident_iso_measurement(s, cs)
-    say("timed steps done: %.3f ms/step" % ms_per_step)
+    if args.small != "none":
+        cs2 = make_workload(args.small)
+        t = [torch.from_numpy(a).to(dev) for a in (cs2.xyz, cs2.level, cs2.value)]
+        r2 = step_measurement(amr, cs2, *t, args.steps, args.warmup)
+        r2["set"].close()
+        out["small_workload"] = {"workload": cs2.name, "cells": cs2.n, "triangles": r2["n_tri"],
+                                 "ms_per_step": r2["ms_per_step"], "cells_per_s": r2["cells_per_s"],
+                                 "stages_ms": r2["stages_ms"], "kernels_ms": r2["kernels_ms"],
+                                 "roofline": r2["roofline"]}
+        say("small workload %s: %.3f ms/step" % (cs2.name, r2["ms_per_step"]))
+        del t, r2
+    large_cs = None
     if args.large != "none":
-        out["large_workload"] = large_measurement(amr, args.large, 10, resident=not args.no_resident)
+        large_cs = make_workload(args.large)
+        out["large_workload"] = large_measurement(amr, large_cs, 10, resident=not args.no_resident)
         say("large workload %s: %.3f ms/step" % (args.large, out["large_workload"]["ms_per_step"]))
     if not args.no_pipeline:
         out["pipeline_pcie_inclusive"] = pipeline_measurement(amr, cs)
@@ -625,8 +732,9 @@ def main():
         out["batched"] = batched_measurement(amr, s, cs, args.batch_isos)
         say("batched: fused %.3f ms, plain %.3f ms" % (out["batched"]["fused_ms"],
                                                         out["batched"]["plain_ms_for_all_isos"]))
+    set_css = None
     if args.batch_sets:
-        out["batched_sets"] = batched_multiset_measurement(amr, args.batch_sets)
+        out["batched_sets"], set_css = batched_multiset_measurement(amr, args.batch_sets)
         say("batched sets: fused %.3f ms, plain %.3f ms" % (out["batched_sets"]["fused_ms"],
                                                              out["batched_sets"]["plain_ms_for_all_sets"]))
     if args.serve_seconds > 0 and args.serve_workload == "large":
@@ -635,10 +743,12 @@ def main():
         iso_pool = np.quantile(cs.value, np.random.default_rng(5).uniform(0.05, 0.95, 97)).astype(np.float32)
         out["serving"] = serving_measurement(amr, s, cs.name, iso_pool, args.serve_seconds, args.serve_rate,
                                              args.serve_serial_requests)
+    if "serving" in out:
         say("serving: p99 %.2f ms (server) vs %.2f ms (serial)" % (out["serving"]["server"]["p99_ms"],
                                                                   out["serving"]["serial_plain"]["p99_ms"]))
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cs)
+        say("cpu baseline: running the oracle on the host")
+        out["cpu_baseline"] = cpu_baseline(cs, large=large_cs, sets=set_css)
         say("cpu baseline: %.3g cells/s on %d threads" % (out["cpu_baseline"]["value"], out["cpu_baseline"]["cores"]))
     print(json.dumps(out), flush=True)
 

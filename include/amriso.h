@@ -22,7 +22,17 @@
  *    on one set must be issued on one stream at a time (they share the
  *    set's scratch space inside the index workspace).
  *  - Errors: functions return an amr_status; they never abort or throw.
- *    amr_last_error() gives a message for the calling thread.
+ *    amr_last_error() gives a message for the calling thread.  Problems
+ *    with the cells themselves (bad fields, overlaps, a hash table too
+ *    small) are found by kernels; they are reported by the next call that
+ *    waits on the host for them (amr_build_status, amr_index_bytes), and
+ *    extractions enqueued after a failed build write -1 into their counts
+ *    and nothing else.
+ *  - Graph capture: amr_upload, amr_build_index (for as many cells as an
+ *    earlier build of the set, or after amr_index_bytes sized the table),
+ *    amr_dual_cells, amr_isosurface, amr_batch_isosurface and
+ *    amr_indexed_mesh do no host synchronisation and can be captured in a
+ *    HIP graph together.
  *  - Limits: 0 <= level <= 20; every coordinate c satisfies
  *    -2^23 <= c and c + 2^level <= 2^23 (cell centres are then exact in
  *    float32); per axis, max(c + 2^level) - min(c) + 2^(Lmax+3) <= 2^20
@@ -72,18 +82,20 @@ void amr_destroy(amr_set* set);
    re-uploaded.  Enqueues the validation of every cell on the device (level
    range, alignment of the corner to 2^level, finite value, coordinate
    limits) and the reduction of the bounding box and per-level counts, and
-   returns without waiting.  The verdict is read by the next
-   amr_index_bytes or amr_build_index, which return AMR_EINVAL / AMR_ERANGE
-   for bad cells (the message names the lowest offending index).  This call
-   itself only rejects bad arguments.  n == 0 is allowed (an empty set).
-   Invalidates any index built before. */
+   returns without waiting.  The verdict stays on the device for the build's
+   kernels; the host reads it in amr_index_bytes, amr_build_index (only
+   when it must size a new table) or amr_build_status, which return
+   AMR_EINVAL / AMR_ERANGE for bad cells (the message names the lowest
+   offending index).  This call itself only rejects bad arguments.  n == 0
+   is allowed (an empty set).  Invalidates any index built before. */
 int amr_upload(amr_set* set, const int32_t* xyz, const int32_t* level, const float* value, int64_t n,
                hipStream_t stream);
 
 /* Bytes of device workspace amr_build_index needs for the uploaded set (no
    GPU work; waits for the upload's verdict if it has not been read yet, and
-   returns its AMR_EINVAL / AMR_ERANGE).  After amr_build_index returned
-   AMR_ENOSPACE the answer grows to fit the set. */
+   returns its AMR_EINVAL / AMR_ERANGE).  It also reads the verdict of a
+   build still unread: after a build that failed with AMR_ENOSPACE the
+   answer grows to fit the set. */
 int amr_index_bytes(const amr_set* set, size_t* bytes);
 
 /* Cell-location index (paper sec. 3.2: the paper sorts the cells by their
@@ -92,15 +104,28 @@ int amr_index_bytes(const amr_set* set, size_t* bytes);
    coordinates of their 2x2x2 sibling block, so one probe returns up to
    eight same-level cells).  `workspace` is caller-owned device memory of at
    least amr_index_bytes() bytes, 256-byte aligned; it must stay alive while
-   the set is used.  Also checks that no two cells overlap.  Synchronises
-   `stream` once, at the end, to read the result.  When the set has as many
-   cells as at the previous build and the workspace still fits that build's
-   table, the build starts without waiting for the upload's verdict (the
-   kernels read it on the device).  Returns the upload's AMR_EINVAL /
-   AMR_ERANGE for bad cells, AMR_EOVERLAP for duplicate or nested cells,
-   AMR_ENOSPACE if the hash table was too small (query amr_index_bytes again
-   and retry with a larger workspace), AMR_ESTATE before amr_upload. */
+   the set is used.  Enqueues the build and returns without waiting: the
+   kernels also check that no two cells overlap and decide the verdict on
+   the device, where the extraction kernels read it.  The host waits only
+   to size a new table: when neither amr_index_bytes nor an earlier build of
+   as many cells (whose table the workspace still fits) has done so, the
+   call waits for the upload's verdict first.  Returns at once the upload's
+   AMR_EINVAL / AMR_ERANGE when that verdict was read and bad, AMR_ENOSPACE
+   for a workspace below the table's size, AMR_ESTATE before amr_upload (or
+   when the table would have to be sized inside a graph capture).  The
+   build's own verdict comes from amr_build_status. */
 int amr_build_index(amr_set* set, void* workspace, size_t bytes, hipStream_t stream);
+
+/* Verdict of the last amr_build_index (paper sec. 3.1 assumes valid,
+   non-overlapping cells; this is where bad ones are reported).  Waits on the
+   host until that build has run, then returns AMR_OK, the upload's
+   AMR_EINVAL / AMR_ERANGE for bad cells, AMR_EOVERLAP for duplicate or
+   nested cells (the message names one of them), AMR_ENOSPACE if the hash
+   table was too small (query amr_index_bytes again and rebuild with a
+   larger workspace), or AMR_ESTATE when no build followed the last upload.
+   A build enqueued inside a graph capture is waited for with a device-wide
+   synchronisation.  Calling it again returns the same verdict. */
+int amr_build_status(amr_set* set);
 
 /* Dual cells (paper sec. 4.2-4.4).  For every cell and each of its 8
    corners, the logical same-level dual centred on that corner is snapped to
@@ -115,8 +140,8 @@ int amr_build_index(amr_set* set, void* workspace, size_t bytes, hipStream_t str
                                   i.e. the cells containing P + (e - 1)*2^l
      vals         float [cap][8]  the values of those cells (so that later
                                   passes over the duals read them in order)
-   counts: device int64 [2]; counts[0] = counts[1] = number of emitted duals.
-   Records past cap are not written.  Asynchronous: the caller reads counts
+   counts: device int64 [2]; counts[0] = counts[1] = number of emitted duals
+   (-1 if the build failed).  Records past cap are not written.  Asynchronous: the caller reads counts
    and re-runs with a larger buffer when counts[0] > cap.  The order of the
    records is fixed for a given index.  Returns AMR_ESTATE before
    amr_build_index. */
@@ -138,13 +163,15 @@ int amr_dual_cells(amr_set* set, int32_t* corner_level, int32_t* verts, float* v
                                   side
      tri_cells int32 [cap][3][2]  per vertex, the (A, B) cell indices of its
                                   edge (a weld key for an indexed mesh)
-     tri_dual  int32 [cap]        index of the generating dual in the order
-                                  amr_dual_cells writes them
+     tri_dual  int64 [cap]        index of the generating dual in the order
+                                  amr_dual_cells writes them (64 bits: a set
+                                  may emit more than 2^31 duals)
    counts: device int64 [2]; counts[0] = triangles, counts[1] = emitted
-   duals.  Triangles past cap are not written.  Asynchronous and free of
-   host synchronisation, so it can be captured in a HIP graph (a captured
-   call stays valid until the set is built again).  Returns AMR_EINVAL for
-   a non-finite iso, AMR_ESTATE before amr_build_index.
+   duals (both -1 if the build failed).  Triangles past cap are not
+   written.  Asynchronous and free of host synchronisation, so it can be
+   captured in a HIP graph (a captured call stays valid until the set is
+   built again).  Returns AMR_EINVAL for a non-finite iso, AMR_ESTATE before
+   amr_build_index.
    Range culling (not part of the paper; outputs are identical with or
    without it): the second extraction after a build (this call or
    amr_dual_cells) also records, per 2x2x2 group of cells, the minimum and
@@ -154,7 +181,7 @@ int amr_dual_cells(amr_set* set, int32_t* corner_level, int32_t* verts, float* v
    pass tri_dual == NULL skip every group whose range lies entirely below
    iso or entirely at or above it: all its duals have Marching Cubes case 0
    or 255. */
-int amr_isosurface(amr_set* set, float iso, float* tris, int32_t* tri_cells, int32_t* tri_dual, int64_t cap,
+int amr_isosurface(amr_set* set, float iso, float* tris, int32_t* tri_cells, int64_t* tri_dual, int64_t cap,
                    int64_t* counts, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
@@ -236,6 +263,26 @@ int amr_indexed_mesh_bytes(int64_t n_tris, size_t* bytes);
    workspace below amr_indexed_mesh_bytes. */
 int amr_indexed_mesh(const float* tris, const int32_t* tri_cells, int64_t n_tris, float* verts, int32_t* idx,
                      int64_t cap_verts, int64_t* n_verts, void* workspace, size_t bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+   Measurement: HIP events around one kernel.  The next launch of the named
+   kernel for this set is made with hipExtLaunchKernelGGL, which records
+   `start` just before the kernel runs and `stop` just after it, on the
+   stream the kernel runs on; hipEventElapsedTime then gives the kernel's own
+   duration, without the gaps between launches.  One-shot: later launches
+   are plain again.  kernel == 0 disarms.  The events are the caller's.
+   --------------------------------------------------------------------------- */
+enum amr_kernel {
+    AMR_KERNEL_UPLOAD = 1,   /* validation and reduction of the cells (amr_upload) */
+    AMR_KERNEL_RESET = 2,    /* clearing of the hash table (amr_build_index) */
+    AMR_KERNEL_INSERT = 3,   /* insertion of every cell into the table (amr_build_index) */
+    AMR_KERNEL_COMPACT = 4,  /* group list of the table (amr_build_index) */
+    AMR_KERNEL_MARK = 5,     /* ancestor marks and the build's verdict (amr_build_index) */
+    AMR_KERNEL_EXTRACT = 6,  /* first extraction pass of a call: the fused pass or the count pass */
+    AMR_KERNEL_WRITE = 7     /* write pass of a call that has one */
+};
+
+int amr_time_kernel(amr_set* set, int kernel, hipEvent_t start, hipEvent_t stop);
 
 /* Message describing the last error on the calling thread ("" if none). */
 const char* amr_last_error(void);

@@ -21,9 +21,14 @@ _NAMES = {0: "AMR_OK", -1: "AMR_EINVAL", -2: "AMR_ERANGE", -3: "AMR_EOVERLAP", -
           -5: "AMR_ESTATE", -6: "AMR_EHIP", -7: "AMR_ENOMEM"}
 
 # Every entry point of the C ABI (include/amriso.h).
-ABI_SYMBOLS = ("amr_create", "amr_destroy", "amr_upload", "amr_index_bytes", "amr_build_index", "amr_dual_cells",
+ABI_SYMBOLS = ("amr_create", "amr_destroy", "amr_upload", "amr_index_bytes", "amr_build_index", "amr_build_status",
+               "amr_dual_cells",
                "amr_isosurface", "amr_batch_create", "amr_batch_destroy", "amr_batch_workspace_bytes",
-               "amr_batch_isosurface", "amr_indexed_mesh_bytes", "amr_indexed_mesh", "amr_last_error")
+               "amr_batch_isosurface", "amr_indexed_mesh_bytes", "amr_indexed_mesh", "amr_time_kernel",
+               "amr_last_error")
+
+# amr_kernel: kernels amr_time_kernel can bracket with events
+KERNEL_UPLOAD, KERNEL_RESET, KERNEL_INSERT, KERNEL_COMPACT, KERNEL_MARK, KERNEL_EXTRACT, KERNEL_WRITE = range(1, 8)
 
 _lib = None
 
@@ -54,6 +59,8 @@ def load_library(path: str = LIB_PATH):
     L.amr_index_bytes.restype = C.c_int
     L.amr_build_index.argtypes = [vp, vp, C.c_size_t, vp]
     L.amr_build_index.restype = C.c_int
+    L.amr_build_status.argtypes = [vp]
+    L.amr_build_status.restype = C.c_int
     L.amr_dual_cells.argtypes = [vp, i32p, i32p, f32p, i64, i64p, vp]
     L.amr_dual_cells.restype = C.c_int
     L.amr_isosurface.argtypes = [vp, C.c_float, f32p, i32p, i32p, i64, i64p, vp]
@@ -71,6 +78,8 @@ def load_library(path: str = LIB_PATH):
     L.amr_indexed_mesh_bytes.restype = C.c_int
     L.amr_indexed_mesh.argtypes = [f32p, i32p, i64, f32p, i32p, i64, i64p, vp, C.c_size_t, vp]
     L.amr_indexed_mesh.restype = C.c_int
+    L.amr_time_kernel.argtypes = [vp, C.c_int, vp, vp]
+    L.amr_time_kernel.restype = C.c_int
     L.amr_last_error.argtypes = []
     L.amr_last_error.restype = C.c_char_p
     _lib = L
@@ -148,9 +157,23 @@ class AmrSet:
         _check(self.lib.amr_index_bytes(self._h, C.byref(b)))
         return int(b.value)
 
-    def build_index(self, max_attempts: int = 6):
+    def build_status(self):
+        """Wait for the last build and raise AmrError if it failed."""
+        _check(self.lib.amr_build_status(self._h))
+        return self
+
+    def build_index(self, max_attempts: int = 6, wait: bool = True):
         """Allocate the index workspace (torch) and build the index; grows the
-        workspace when the hash table turns out too small."""
+        workspace when the hash table turns out too small.  With wait=False
+        the build is only enqueued (no host synchronisation; the set's
+        workspace must already fit, and build_status() reads the verdict)."""
+        if not wait:
+            if self.workspace is None:
+                self.workspace = self._ws_keep if self._ws_keep is not None else torch.empty(
+                    self.index_bytes(), dtype=torch.uint8, device=self.device)
+            _check(self.lib.amr_build_index(self._h, _ptr(self.workspace), self.workspace.numel(),
+                                            _stream(self.device)))
+            return self
         for _ in range(max_attempts):
             if self._ws_keep is not None and self.workspace is None:
                 # a workspace from an earlier upload: the library says if it is short
@@ -159,6 +182,8 @@ class AmrSet:
                 self.workspace = torch.empty(self.index_bytes(), dtype=torch.uint8, device=self.device)
             code = self.lib.amr_build_index(self._h, _ptr(self.workspace), self.workspace.numel(),
                                             _stream(self.device))
+            if code == AMR_OK:
+                code = self.lib.amr_build_status(self._h)
             if code == AMR_ENOSPACE:
                 nbytes = self.index_bytes()
                 self.workspace = self._ws_keep = None
@@ -168,6 +193,18 @@ class AmrSet:
             self._ws_keep = self.workspace
             return self
         raise AmrError(AMR_ENOSPACE, "index workspace kept overflowing")
+
+    def time_kernel(self, kernel: int, start, stop):
+        """Arm torch.cuda.Events `start` and `stop` around the next launch of
+        `kernel` (a KERNEL_* constant) for this set; they are recorded on the
+        stream that kernel runs on, so start.elapsed_time(stop) is its own
+        duration."""
+        stream = torch.cuda.current_stream(self.device)
+        for e in (start, stop):
+            if not e.cuda_event:
+                e.record(stream)  # torch creates the event on first use
+        _check(self.lib.amr_time_kernel(self._h, int(kernel), C.c_void_p(start.cuda_event),
+                                        C.c_void_p(stop.cuda_event)))
 
     # -- extraction -------------------------------------------------------
     def dual_cells_into(self, corner_level, verts, cap: int, vals=None):
@@ -208,7 +245,7 @@ class AmrSet:
         return int(c[0]), int(c[1])
 
     def isosurface(self, iso: float, cap: int | None = None, cells: bool = False, dual: bool = False):
-        """Triangles float32 [T,9] (+ cells int32 [T,6], dual int32 [T]).
+        """Triangles float32 [T,9] (+ cells int32 [T,6], dual int64 [T]).
         Without `cap` a count pass sizes the output first (the paper's
         two-pass scheme); with `cap` a single pass runs and repeats only if
         the capacity was too small."""
@@ -216,7 +253,7 @@ class AmrSet:
             cap = self.count(iso)[0]
         tris = torch.empty((max(cap, 1), 9), dtype=torch.float32, device=self.device)
         tc = torch.empty((max(cap, 1), 6), dtype=torch.int32, device=self.device) if cells else None
-        td = torch.empty((max(cap, 1),), dtype=torch.int32, device=self.device) if dual else None
+        td = torch.empty((max(cap, 1),), dtype=torch.int64, device=self.device) if dual else None
         self.isosurface_into(iso, tris, cap, tc, td)
         t = int(self.counts[0].item())
         if t > cap:
@@ -306,8 +343,17 @@ class AmrBatch:
         return counts
 
     def barrier_timed_out(self, block: int = 256, per_thread: int = 1) -> bool:
+        """True if a grid-barrier wait of a launch with this workspace gave up
+        (bytes 8..11 of the workspace; that launch's results are invalid)."""
         ws = self._ws.get((block, per_thread))
         return ws is not None and bool(ws[8:12].any().item())
+
+    def reset_barrier(self, block: int = 256, per_thread: int = 1):
+        """Clear the grid barrier (arrival count, sense, time-out flag) of this
+        workspace after a time-out, before its next launch."""
+        ws = self._ws.get((block, per_thread))
+        if ws is not None:
+            ws[:16].zero_()
 
     def isosurface(self, set_idx, isos, block: int = 256, per_thread: int = 1):
         """List of float32 [T_j, 9] triangle tensors, one per job: a count

@@ -37,6 +37,7 @@
 // sets run a count pass, a scan of the tile totals and a write pass, so no
 // tile waits for another.  Output positions are deterministic either way.
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -111,13 +112,21 @@ struct UpRes {
     unsigned long long record_hint;
 };
 
-// Device control block, one per set (library-allocated).
+// Device control block, one per set (library-allocated).  The build's
+// verdict (`status`) is decided on the device by the last work-group of the
+// ancestor marking; extraction kernels read it, the group count and the
+// geometry from here, so nothing of the build has to reach the host before
+// the next call is enqueued.
+constexpr int32_t kStatusPending = 1;  // a build is enqueued and has not finished
+
 struct Ctrl {
     Partial part[kReplicas];
     uint32_t overflow;
     uint32_t dup;
     uint32_t overlap;
-    uint32_t pad0;
+    int32_t status;                // AMR_OK or the build's error code (kStatusPending meanwhile)
+    uint32_t mark_done;            // work-groups of the marking pass that have finished
+    uint32_t pad1;
     unsigned long long bad_build;
     unsigned long long n_groups;   // written by the compaction's last tile
     unsigned long long n_records;
@@ -134,6 +143,8 @@ struct Sched {
     unsigned long long cticket;  // compaction tiles started
     unsigned long long fticket;  // fused extraction tiles started, over all calls
     unsigned long long lticket;  // candidate-list work-groups started, over all calls
+    uint32_t rng_ok;             // group value ranges and dual count recorded for this build
+    uint32_t pad;
 };
 
 __device__ __forceinline__ uint64_t group_key(int m, uint32_t gx, uint32_t gy, uint32_t gz) {
@@ -310,6 +321,8 @@ __global__ void k_ctrl_reset(Ctrl* c) {
         c->overflow = 0;
         c->dup = 0;
         c->overlap = 0;
+        c->status = kStatusPending;
+        c->mark_done = 0;
         c->bad_build = ~0ull;
         c->n_groups = 0;
         c->n_records = 0;
@@ -471,6 +484,12 @@ __global__ __launch_bounds__(64) void k_upload_finish(Ctrl* c) {
         u.status = (err & (kErrLevel | kErrAlign | kErrValue)) ? AMR_EINVAL : AMR_ERANGE;
         return;
     }
+    if (lmax < lmin) {
+        // no cells at all (an empty upload): an empty box at the origin
+        for (int a = 0; a < 3; ++a) u.lo[a] = u.hi[a] = 0;
+        u.lmin = u.lmax = 0;
+        return;
+    }
     const long long blk = 1ll << (lmax + 1);
     for (int a = 0; a < 3; ++a) {
         if ((long long)hi[a] - lo[a] + (1ll << (lmax + 3)) > kSpanLimit) {
@@ -522,9 +541,12 @@ __global__ __launch_bounds__(256) void k_build_reset(Record* __restrict__ rec, u
         sc->cticket = 0;
         sc->fticket = 0;
         sc->lticket = 0;
+        sc->rng_ok = 0;
         c->overflow = 0;
         c->dup = 0;
         c->overlap = 0;
+        c->status = kStatusPending;
+        c->mark_done = 0;
         c->bad_build = ~0ull;
         c->n_groups = 0;
         c->n_records = 0;
@@ -588,6 +610,7 @@ __global__ __launch_bounds__(256) void k_index_insert(const int32_t* __restrict_
 __global__ __launch_bounds__(256) void k_index_ids(const int32_t* __restrict__ xyz, const int32_t* __restrict__ lvl,
                                                    int64_t n, const Ctrl* c, const Record* __restrict__ rec,
                                                    int32_t* __restrict__ ids) {
+    if (c->res.status != AMR_OK) return;  // invalid cells: nothing was indexed
     const Geo g = c->geo;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         int m = lvl[i];
@@ -605,13 +628,20 @@ __global__ __launch_bounds__(256) void k_index_ids(const int32_t* __restrict__ x
 // before this pass, so a mark that lands on a leaf is a coarser cell
 // containing finer ones.  The pass runs over the compacted group list (the
 // compaction's count is on the device), and counts the marker-only records
-// it creates, one atomic per work-group into one of 64 replicas.
+// it creates, one atomic per work-group into one of 64 replicas.  The last
+// work-group to finish decides the build's verdict on the device: the
+// upload's error, a table too full (a failed insertion, more than 3/4 of the
+// slots in use, or more groups than the `max_groups` the extraction grids
+// are sized for), a coarser cell containing finer ones, or fewer leaves than
+// cells (a duplicate overwrote its twin).
 __global__ __launch_bounds__(256) void k_index_mark(Record* __restrict__ rec,
-                                                    const unsigned long long* __restrict__ gkey, Ctrl* c) {
+                                                    const unsigned long long* __restrict__ gkey, int64_t n,
+                                                    uint32_t cap, uint32_t max_groups, Ctrl* c) {
     __shared__ uint32_t s_made;
-    if (c->res.status != AMR_OK) return;
+    __shared__ bool s_last;
+    const bool ok = c->res.status == AMR_OK;
     const Geo g = c->geo;
-    const uint32_t ng = (uint32_t)c->n_groups;
+    const uint32_t ng = ok ? (uint32_t)c->n_groups : 0u;
     if (threadIdx.x == 0) s_made = 0;
     __syncthreads();
     uint32_t made = 0;
@@ -651,8 +681,28 @@ __global__ __launch_bounds__(256) void k_index_mark(Record* __restrict__ rec,
     made = (uint32_t)wave_reduce((unsigned long long)made,
                                  [](unsigned long long x, unsigned long long y) { return x + y; });
     if (lane_id() == 0 && made) atomicAdd(&s_made, made);
+    __threadfence();  // every lane's flags and marks have landed before the count below
     __syncthreads();
-    if (threadIdx.x == 0 && s_made) atomicAdd(&c->made[(blockIdx.x % kReplicas) * 16], (unsigned long long)s_made);
+    if (threadIdx.x == 0) {
+        if (s_made) atomicAdd(&c->made[(blockIdx.x % kReplicas) * 16], (unsigned long long)s_made);
+        // everything this work-group did is visible before it counts itself out
+        const uint32_t done =
+            __hip_atomic_fetch_add(&c->mark_done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = done == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last || threadIdx.x != 0) return;
+    int32_t st = c->res.status;
+    if (st == AMR_OK) {
+        auto ld32 = [](const uint32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
+        unsigned long long recs = c->n_records;  // records at compaction time: the groups
+        for (int r = 0; r < kReplicas; ++r) recs += ld_relaxed(&c->made[r * 16]);
+        if (ld32(&c->overflow) || recs * 4 > (unsigned long long)cap * 3 || c->n_groups > max_groups)
+            st = AMR_ENOSPACE;
+        else if (ld32(&c->overlap) || c->n_leaves != (unsigned long long)n) st = AMR_EOVERLAP;
+    }
+    c->mark_done = 0;
+    __hip_atomic_store(&c->status, st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Error path only: the lowest input index whose entry was overwritten by a
@@ -758,13 +808,12 @@ struct ExtractArgs {
     const int32_t* ids;
     const int32_t* glist;
     const unsigned long long* gkey;
-    uint32_t n_groups;
-    Geo g;
+    const Ctrl* ctrl;  // build verdict, group count and geometry (written by the build's kernels)
     float iso;
     // iso-surface outputs
     float* tris;
     int32_t* tri_cells;
-    int32_t* tri_dual;
+    int64_t* tri_dual;
     // dual-cell outputs
     int32_t* corner_level;
     int32_t* verts;
@@ -778,14 +827,16 @@ struct ExtractArgs {
     unsigned long long* sc0;    // per scan tile: look-back states
     unsigned long long* sc1;
     Sched* sched;
-    uint32_t n_tiles;
-    uint32_t n_scan_tiles;
+    uint32_t n_scan_tiles;  // work-groups of the scan launch (their look-back states)
     // value range of each group's 4x4x4 neighbourhood (min, max over its
-    // cells), recorded by the first full pass after a build and then used to
-    // skip groups in iso-surface passes; the set's dual count goes with it
+    // cells), recorded by the second extraction after a build and then used
+    // to skip groups in iso-surface passes; the set's dual count goes with
+    // it, and sched->rng_ok says both are there (the host only asks for
+    // culling; without recorded ranges the kernels run full passes)
     float2* rng;
     unsigned long long* dual_total;
     int rng_mode;
+    int list_from_cull;  // the list passes run over culled candidates (dual count: the recorded one)
     // group list of a list count / write pass (k_group_list); with lcnt the
     // list's triangle counts come from there (no list count pass), and
     // list_duals holds the set's dual count
@@ -796,13 +847,6 @@ struct ExtractArgs {
 };
 
 enum : int { kRngNone = 0, kRngRecord = 1, kRngCull = 2 };
-
-__global__ void k_counts_zero(int64_t* counts) {
-    if (threadIdx.x == 0 && counts) {
-        counts[0] = 0;
-        counts[1] = 0;
-    }
-}
 
 // Hexahedron edge e -> lower slot (upper slot = lower | (1 << axis)).  Edges
 // 0-3 run along x, 4-7 along y, 8-11 along z; the i-th edge of an axis starts
@@ -883,13 +927,15 @@ __device__ __forceinline__ uint32_t keep_by_classes(uint32_t cls, unsigned long 
 // output position by a decoupled look-back over earlier tickets.
 enum : int { kPassCount = 0, kPassWrite = 1, kPassFused = 2 };
 
-// One tile of 32 groups: all of them (group index = tile * 32 + i) or, with
-// kList, 32 entries of the candidate list of an iso-value (n_list long).
-// `call` is the fused pass's call number.  Every return is taken by the
-// whole work-group.
+// One tile of 32 groups: all of them (group index = tile * 32 + i, n_groups
+// in all, n_tiles tiles) or, with kList, 32 entries of the candidate list of
+// an iso-value (n_list long).  `call` is the fused pass's call number and
+// `rng_mode` the effective range mode (culling only when ranges are
+// recorded).  Every return is taken by the whole work-group.
 template <bool kDuals, int kPass, bool kList>
-__device__ __forceinline__ void extract_tile(const ExtractArgs& a, const uint32_t tile, const uint32_t n_list,
-                                             const unsigned long long call) {
+__device__ __forceinline__ void extract_tile(const ExtractArgs& a, const Geo& g, const uint32_t n_groups,
+                                             const uint32_t n_tiles, const uint32_t tile, const uint32_t n_list,
+                                             const unsigned long long call, const int rng_mode) {
     // the 4x4x4 cells of level m around each group (offsets -1..2 from its
     // lower corner, x fastest): value, cell reference, level of the cell that
     // covers the position (-1: none)
@@ -918,13 +964,6 @@ __device__ __forceinline__ void extract_tile(const ExtractArgs& a, const uint32_
             s_pre_t = a.pre_t[tile];
             s_pre_d = a.pre_d[tile];
         }
-    } else if (kPass == kPassCount && !kList && t == 0) {
-        // the scan that follows starts from clean states
-        if (tile < a.n_scan_tiles) {
-            a.sc0[tile] = 0;
-            a.sc1[tile] = 0;
-        }
-        if (tile == 0) a.sched->xticket = 0;
     }
     if (!kDuals) s_tab[t] = kMcTable[t];
     __syncthreads();
@@ -936,9 +975,8 @@ __device__ __forceinline__ void extract_tile(const ExtractArgs& a, const uint32_
         gidx = valid ? a.clist[li] : 0u;
     } else {
         gidx = tile * kGroupsPerTile + gi;
-        valid = gidx < a.n_groups;
+        valid = gidx < n_groups;
     }
-    const Geo g = a.g;
 
     // In the write pass a group with nothing to write this time needs no
     // neighbourhood: it only brings its dual count (from the count pass) to
@@ -956,7 +994,7 @@ __device__ __forceinline__ void extract_tile(const ExtractArgs& a, const uint32_
     // Marching Cubes cases 0 and 255 at its corners: no triangles.  (Its
     // duals are not counted here; the set's total was recorded.)  The count
     // and write passes get such groups filtered out beforehand (kList).
-    const bool cull = !kDuals && kPass == kPassFused && a.rng_mode == kRngCull;
+    const bool cull = !kDuals && kPass == kPassFused && rng_mode == kRngCull;
     if (cull && valid) {
         const float2 r = a.rng[gidx];
         work = r.x < a.iso && r.y >= a.iso;
@@ -1096,7 +1134,7 @@ __device__ __forceinline__ void extract_tile(const ExtractArgs& a, const uint32_
         }
     }
     __syncthreads();
-    if (kPass != kPassWrite && a.rng_mode == kRngRecord) {
+    if (kPass != kPassWrite && rng_mode == kRngRecord) {
         // the range of the cells in the neighbourhood (holes and the markers
         // of refined or empty slots excluded); lane j takes 8 of the 64
         float lo = INFINITY, hi = -INFINITY;
@@ -1212,9 +1250,12 @@ __device__ __forceinline__ void extract_tile(const ExtractArgs& a, const uint32_
             if (lane_id() == 0) {
                 s_pre_t = pre_t;
                 s_pre_d = pre_d;
-                if (tile == a.n_tiles - 1) {
+                if (tile == n_tiles - 1) {
                     const unsigned long long nd = cull ? *a.dual_total : pre_d + agg_d;
-                    if (a.rng_mode == kRngRecord) *a.dual_total = nd;
+                    if (rng_mode == kRngRecord) {
+                        *a.dual_total = nd;
+                        a.sched->rng_ok = 1;
+                    }
                     if (a.counts) {
                         a.counts[0] = kDuals ? (int64_t)nd : (int64_t)(pre_t + agg_t);
                         a.counts[1] = (int64_t)nd;
@@ -1356,43 +1397,112 @@ __device__ __forceinline__ void extract_tile(const ExtractArgs& a, const uint32_
                     // the owner lane's emitted duals before item q
                     uint32_t rank = 0;
                     for (int q2 = 0; q2 < q; ++q2) rank += s_items[owner][q2] >> 31;
-                    a.tri_dual[o_t] = (int32_t)((int64_t)s_pre_d + s_dual[owner] + rank);
+                    a.tri_dual[o_t] = (int64_t)s_pre_d + s_dual[owner] + rank;
                 }
             }
         }
     }
 }
 
+// What every extraction kernel reads first: the build's verdict, the group
+// count and the geometry, written on the device by the build (a failed build
+// extracts nothing), and the range mode the ranges on hand allow.
+struct TileSetup {
+    Geo g;
+    uint32_t n_groups, n_tiles;
+    bool ok;
+    int rng_mode;
+};
+
+// Every lane reads the same words; readfirstlane tells the compiler so, which
+// keeps them (and all that is derived from them) in scalar registers.
+__device__ __forceinline__ int32_t uniform_i32(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+
+__device__ __forceinline__ TileSetup tile_setup(const ExtractArgs& a) {
+    TileSetup u;
+    const Geo g = a.ctrl->geo;
+    u.g.ox = uniform_i32(g.ox);
+    u.g.oy = uniform_i32(g.oy);
+    u.g.oz = uniform_i32(g.oz);
+    u.g.lmax = uniform_i32(g.lmax);
+    u.g.shift = uniform_i32(g.shift);
+    u.g.mask = uniform_u32(g.mask);
+    u.ok = uniform_i32(a.ctrl->status) == AMR_OK;
+    u.n_groups = u.ok ? uniform_u32((uint32_t)a.ctrl->n_groups) : 0u;
+    u.n_tiles = (u.n_groups + kGroupsPerTile - 1) / kGroupsPerTile;
+    u.rng_mode = (a.rng_mode == kRngCull && uniform_u32(a.sched->rng_ok) == 0) ? kRngNone : a.rng_mode;
+    return u;
+}
+
+// Counts of a call that has no tiles: zeros, or -1 after a failed build.
+__device__ __forceinline__ void write_empty_counts(const ExtractArgs& a, const TileSetup& u) {
+    if (a.counts) {
+        a.counts[0] = u.ok ? 0 : -1;
+        a.counts[1] = u.ok ? 0 : -1;
+    }
+    if (u.ok && u.rng_mode == kRngRecord) {
+        *a.dual_total = 0;
+        a.sched->rng_ok = 1;
+    }
+}
+
+// The group count is known on the device only.  The host sizes the grids for
+// a bound it chose at the build (the build fails if the groups exceed it), so
+// every tile has a work-group and work-groups past the last tile leave.
+//  - fused pass: tiles are handed out as tickets in start order (a tile's
+//    look-back then only waits on tiles that running work-groups hold); each
+//    call takes exactly gridDim.x tickets, which numbers the calls and gives
+//    the look-back states their parity;
+//  - count and write passes: work-groups go round-robin to the 8 XCDs, so
+//    XCD x is given the contiguous run of tiles [x*T, (x+1)*T) in order and
+//    its L2 sees neighbouring tiles one after another.
 template <bool kDuals, int kPass>
 __global__ __launch_bounds__(kBlock) void k_extract(ExtractArgs a) {
     __shared__ uint32_t s_tile;
     __shared__ unsigned long long s_call;
+    TileSetup u = tile_setup(a);
     if (kPass == kPassFused) {
+        // the host picks this pass only when the bound fits the look-back
+        // states of kFusedMaxTiles tiles
+        if (u.n_tiles > gridDim.x || u.n_tiles > kFusedMaxTiles) {
+            u.ok = false;
+            u.n_groups = u.n_tiles = 0;
+        }
         if (threadIdx.x == 0) {
-            // Tiles take tickets in start order.  The call number is read
-            // before the ticket: the ticket's address depends on the value
-            // read (call >> 63 is always 0), so the read completes first.  By
-            // the time the last tile of this call holds its ticket every tile
-            // of the call has read the number, and the last tile may advance
-            // it at once for the next call.
+            // The call number is read before the ticket: the ticket's address
+            // depends on the value read (call >> 63 is always 0), so the read
+            // completes first.  By the time the last ticket of this call is
+            // taken every work-group of the call has read the number, and its
+            // holder may advance it at once for the next call.
             const unsigned long long call = ld_relaxed(&a.sched->fcall);
             const unsigned long long tk = atomicAdd(&a.sched->fticket + (call >> 63), 1ull);
-            const unsigned long long tl = tk - call * a.n_tiles;
+            const unsigned long long tl = tk - call * gridDim.x;
             s_call = call;
-            s_tile = tl < a.n_tiles ? (uint32_t)tl : 0xFFFFFFFFu;
-            if (tl == a.n_tiles - 1)
+            s_tile = tl < gridDim.x ? (uint32_t)tl : 0xFFFFFFFFu;
+            if (tl == gridDim.x - 1)
                 __hip_atomic_store(&a.sched->fcall, call + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (tl == 0 && u.n_tiles == 0) write_empty_counts(a, u);
         }
         __syncthreads();
-        if (s_tile == 0xFFFFFFFFu) return;  // cannot happen while calls on a set do not overlap
+        const uint32_t tile = uniform_u32(s_tile);
+        if (tile >= u.n_tiles) return;  // past the last tile (or calls overlapping, which they must not)
+        extract_tile<kDuals, kPass, false>(a, u.g, u.n_groups, u.n_tiles, tile, 0u, s_call, u.rng_mode);
+        return;
     }
-    // count and write passes: work-groups go round-robin to the 8 XCDs, so
-    // XCD x is given the contiguous run of tiles [x*T, (x+1)*T) in order and
-    // its L2 sees neighbouring tiles one after another
-    const uint32_t per_xcd = gridDim.x / kXcds;
-    const uint32_t tile = kPass == kPassFused ? s_tile : (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
-    if (kPass != kPassFused && tile >= a.n_tiles) return;
-    extract_tile<kDuals, kPass, false>(a, tile, 0u, kPass == kPassFused ? s_call : 0ull);
+    if (kPass == kPassCount) {
+        // the scan that follows starts from clean states
+        for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < a.n_scan_tiles; i += gridDim.x * kBlock) {
+            a.sc0[i] = 0;
+            a.sc1[i] = 0;
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.sched->xticket = 0;
+    }
+    const uint32_t per_xcd = (u.n_tiles + kXcds - 1) / kXcds;
+    const uint32_t k = blockIdx.x / kXcds;
+    const uint32_t tile = (blockIdx.x % kXcds) * per_xcd + k;
+    if (k < per_xcd && tile < u.n_tiles)
+        extract_tile<kDuals, kPass, false>(a, u.g, u.n_groups, u.n_tiles, tile, 0u, 0ull, u.rng_mode);
 }
 
 // Lists of groups in group order, for passes that need only some of them:
@@ -1411,7 +1521,7 @@ constexpr int kListPer = 16;  // groups per thread
 
 __global__ __launch_bounds__(kBlock) void k_group_list(const float2* __restrict__ rng,
                                                        const unsigned long long* __restrict__ gcnt,
-                                                       uint32_t n_groups, float iso, uint32_t n_wgs,
+                                                       const Ctrl* ctrl, float iso, uint32_t n_wgs,
                                                        uint32_t* __restrict__ clist, uint32_t* __restrict__ lcnt,
                                                        unsigned long long* n_list, unsigned long long* n_duals,
                                                        unsigned long long* ls0, unsigned long long* ls1, Sched* sc) {
@@ -1419,6 +1529,9 @@ __global__ __launch_bounds__(kBlock) void k_group_list(const float2* __restrict_
     __shared__ unsigned long long s_dual[kBlock / 64];
     __shared__ unsigned long long s_tk, s_pre;
     const int t = threadIdx.x, wave = t >> 6, lane = lane_id();
+    // groups of a good build; without recorded ranges every group is a candidate
+    const uint32_t n_groups = ctrl->status == AMR_OK ? (uint32_t)ctrl->n_groups : 0u;
+    const bool ranged = rng != nullptr && sc->rng_ok != 0;
     if (t == 0) s_tk = atomicAdd(&sc->lticket, 1ull);
     __syncthreads();
     const unsigned long long tk = s_tk;
@@ -1434,9 +1547,11 @@ __global__ __launch_bounds__(kBlock) void k_group_list(const float2* __restrict_
         bool c = false;
         tris[r] = 0;
         if (i < n_groups) {
-            if (rng) {
+            if (ranged) {
                 const float2 g = rng[i];
                 c = g.x < iso && g.y >= iso;
+            } else if (rng) {
+                c = true;
             } else {
                 const unsigned long long gc = gcnt[i];
                 tris[r] = (uint32_t)(gc >> 32);
@@ -1492,10 +1607,10 @@ __global__ __launch_bounds__(kBlock) void k_group_list(const float2* __restrict_
 // list's tiles, so its L2 sees neighbouring groups one after another.
 template <int kPass>
 __global__ __launch_bounds__(kBlock) void k_extract_list(ExtractArgs a) {
+    const TileSetup u = tile_setup(a);
     const uint32_t n = (uint32_t)*a.n_list;
     const uint32_t n_tiles = (n + kGroupsPerTile - 1) / kGroupsPerTile;
     const uint32_t per_xcd = (n_tiles + kXcds - 1) / kXcds;
-    const uint32_t tile = (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
     if (kPass == kPassCount) {
         // the scan that follows starts from clean states
         for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < a.n_scan_tiles; i += gridDim.x * kBlock) {
@@ -1504,7 +1619,10 @@ __global__ __launch_bounds__(kBlock) void k_extract_list(ExtractArgs a) {
         }
         if (blockIdx.x == 0 && threadIdx.x == 0) a.sched->xticket = 0;
     }
-    if (blockIdx.x / kXcds < per_xcd && tile < n_tiles) extract_tile<false, kPass, true>(a, tile, n, 0ull);
+    const uint32_t k = blockIdx.x / kXcds;
+    const uint32_t tile = (blockIdx.x % kXcds) * per_xcd + k;
+    if (k < per_xcd && tile < n_tiles)
+        extract_tile<false, kPass, true>(a, u.g, u.n_groups, n_tiles, tile, n, 0ull, u.rng_mode);
 }
 
 // Exclusive scan of the per-tile (triangles, duals) totals of a count pass:
@@ -1518,9 +1636,9 @@ __global__ __launch_bounds__(kBlock) void k_tile_scan(ExtractArgs a, int duals) 
     __shared__ unsigned long long s_p0, s_p1;
     __shared__ uint32_t s_st;
     const int t = threadIdx.x, wave = t >> 6, lane = lane_id();
-    // over a candidate list the tile count is known on the device only
-    const uint32_t n_tiles =
-        a.n_list ? (uint32_t)((*a.n_list + kGroupsPerTile - 1) / kGroupsPerTile) : a.n_tiles;
+    // tile counts are known on the device only
+    const TileSetup u = tile_setup(a);
+    const uint32_t n_tiles = a.n_list ? (uint32_t)((*a.n_list + kGroupsPerTile - 1) / kGroupsPerTile) : u.n_tiles;
     if (t == 0) s_st = (uint32_t)atomicAdd(&a.sched->xticket, 1ull);
     __syncthreads();
     const uint32_t st = s_st;
@@ -1565,12 +1683,18 @@ __global__ __launch_bounds__(kBlock) void k_tile_scan(ExtractArgs a, int duals) 
             s_p0 = p0;
             s_p1 = p1;
             if (st == a.n_scan_tiles - 1) {
-                // a pass over a list counts no duals: the set's total stands in
-                const unsigned long long nd = a.list_duals ? *a.list_duals : p1 + (total & 0xFFFFFFFFull);
-                if (a.rng_mode == kRngRecord) *a.dual_total = nd;
+                // a pass over a list of candidates counts only their duals: the
+                // set's recorded total stands in (without recorded ranges the
+                // list held every group, and the count is complete)
+                const bool stand_in = a.list_duals && (!a.list_from_cull || u.rng_mode == kRngCull);
+                const unsigned long long nd = stand_in ? *a.list_duals : p1 + (total & 0xFFFFFFFFull);
+                if (u.ok && u.rng_mode == kRngRecord) {
+                    *a.dual_total = nd;
+                    a.sched->rng_ok = 1;
+                }
                 if (a.counts) {
-                    a.counts[0] = (int64_t)(duals ? nd : p0 + (total >> 32));
-                    a.counts[1] = (int64_t)nd;
+                    a.counts[0] = u.ok ? (int64_t)(duals ? nd : p0 + (total >> 32)) : -1;
+                    a.counts[1] = u.ok ? (int64_t)nd : -1;
                 }
             }
         }
@@ -2147,14 +2271,20 @@ struct amr_set {
     uint64_t level_count[kMaxLevel + 1] = {};
     uint64_t record_hint = 0;
     bool up_pending = false;       // upload verdict not read on the host yet
+    bool up_captured = false;      // ... and not on its way either (enqueued inside a graph capture)
     int up_status = AMR_OK;
     hipEvent_t up_event = nullptr;  // recorded after the verdict's copy
     uint32_t last_cap = 0;          // table size of the last build, and its n
     int64_t last_n = -1;
     // index
-    bool built = false;
+    bool built = false;             // a build is enqueued (its verdict may still be on the device)
+    bool build_tried = false;       // a build was enqueued since the last upload
+    bool build_pending = false;     // its verdict has not been read by amr_build_status
+    bool build_captured = false;    // it was enqueued inside a graph capture (no event to wait for)
+    int build_status = AMR_OK;      // the verdict, once read
+    hipEvent_t build_event = nullptr;
     uint32_t cap = 0;
-    uint32_t n_groups = 0;
+    uint32_t grid_groups = 0;       // groups the extraction grids cover (a bound the build enforces)
     Record* rec = nullptr;
     int32_t* ids = nullptr;
     bool ids_ready = false;  // input indices filled in (on first use)
@@ -2180,9 +2310,25 @@ struct amr_set {
     unsigned long long* ct0 = nullptr;
     unsigned long long* ct1 = nullptr;
     Sched* sched = nullptr;
+    // amr_time_kernel: the next launch of this kernel records these events
+    int time_kernel = 0;
+    hipEvent_t time_start = nullptr, time_stop = nullptr;
 };
 
 namespace {
+
+// A launch that records the set's timing events around the kernel itself
+// when amr_time_kernel armed them for `which` (once), else a plain launch.
+template <typename... KArgs, typename... Args>
+void launch(amr_set* s, int which, void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStream_t stream,
+            Args... args) {
+    if (s->time_kernel == which) {
+        s->time_kernel = 0;
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, stream, s->time_start, s->time_stop, 0, args...);
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, 0, stream, args...);
+    }
+}
 
 uint32_t table_cap(const amr_set* s) {
     uint64_t want = s->record_hint * 2;
@@ -2280,7 +2426,11 @@ int grid_for(int64_t n, int block) {
     return (int)g;
 }
 
-int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_cells, int32_t* tri_dual,
+// Most groups a good build can hold: the build fails when more than 3/4 of
+// the slots are in use.
+uint32_t max_groups_of(uint32_t cap) { return cap - cap / 4; }
+
+int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_cells, int64_t* tri_dual,
                    int32_t* corner_level, int32_t* verts, float* dvals, int64_t cap, int64_t* counts,
                    hipStream_t stream) {
     if ((duals ? verts != nullptr : tri_cells != nullptr) && cap > 0 && !s->ids_ready && s->n > 0) {
@@ -2291,19 +2441,17 @@ int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_
         if (e != hipSuccess) return hipfail(e, "extract: cell index map");
         s->ids_ready = true;
     }
-    uint32_t n_tiles = (s->n_groups + kGroupsPerTile - 1) / kGroupsPerTile;
-    if (n_tiles == 0) {
-        hipLaunchKernelGGL(k_counts_zero, dim3(1), dim3(64), 0, stream, counts);
-        hipError_t e = hipGetLastError();
-        return e == hipSuccess ? AMR_OK : hipfail(e, "extract (empty set)");
-    }
+    // The group count lives on the device; the grids cover the bound the
+    // build enforced, and work-groups past the last tile leave at once.
+    const uint32_t max_groups = s->grid_groups;
+    uint32_t max_tiles = (max_groups + kGroupsPerTile - 1) / kGroupsPerTile;
+    if (max_tiles == 0) max_tiles = 1;
     ExtractArgs a;
     a.rec = s->rec;
     a.ids = s->ids;
     a.glist = s->glist;
     a.gkey = s->gkey;
-    a.n_groups = s->n_groups;
-    a.g = geo_of(s);
+    a.ctrl = s->ctrl;
     a.iso = iso;
     a.tris = tris;
     a.tri_cells = tri_cells;
@@ -2320,72 +2468,74 @@ int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_
     a.sc0 = s->xs0;
     a.sc1 = s->xs1;
     a.sched = s->sched;
-    a.n_tiles = n_tiles;
-    a.n_scan_tiles = (n_tiles + kBlock * kScanPer - 1) / (kBlock * kScanPer);
+    a.n_scan_tiles = (max_tiles + kBlock * kScanPer - 1) / (kBlock * kScanPer);
+    if (a.n_scan_tiles == 0) a.n_scan_tiles = 1;
     // The second extraction after a build records the group value ranges
     // (a set extracted once never pays for them); from the third on,
     // iso-surfaces use them unless triangles name their duals (whose
-    // numbering needs every group's dual count).
+    // numbering needs every group's dual count).  The kernels cull only when
+    // the device says the ranges of this build are there (a recording call
+    // captured in a graph and never replayed leaves none).
     a.rng = s->rng;
     a.dual_total = s->dual_total;
     a.rng_mode = s->extractions == 0   ? kRngNone
                  : s->extractions == 1 ? kRngRecord
                  : (!duals && tri_dual == nullptr ? kRngCull : kRngNone);
+    a.list_from_cull = 0;
     a.clist = nullptr;
     a.n_list = nullptr;
     a.lcnt = nullptr;
     a.list_duals = nullptr;
-    const uint32_t n_wgs = (s->n_groups + kBlock * kListPer - 1) / (kBlock * kListPer);
-    if (n_tiles <= kFusedMaxTiles) {
+    const uint32_t n_wgs = (max_groups + kBlock * kListPer - 1) / (kBlock * kListPer);
+    const uint32_t grid = ((max_tiles + kXcds - 1) / kXcds) * kXcds;
+    if (max_tiles <= kFusedMaxTiles) {
         // one fused pass (look-back states alternate parity between calls)
         a.sc0 = s->fs0;
         a.sc1 = s->fs1;
         if (duals)
-            hipLaunchKernelGGL((k_extract<true, kPassFused>), dim3(n_tiles), dim3(kBlock), 0, stream, a);
+            launch(s, AMR_KERNEL_EXTRACT, k_extract<true, kPassFused>, dim3(max_tiles), dim3(kBlock), stream, a);
         else
-            hipLaunchKernelGGL((k_extract<false, kPassFused>), dim3(n_tiles), dim3(kBlock), 0, stream, a);
+            launch(s, AMR_KERNEL_EXTRACT, k_extract<false, kPassFused>, dim3(max_tiles), dim3(kBlock), stream, a);
     } else if (a.rng_mode == kRngCull) {
         // list the candidate groups, then count, scan and write over the list
         const bool write = cap > 0 && (tris || tri_cells);
-        hipLaunchKernelGGL(k_group_list, dim3(n_wgs), dim3(kBlock), 0, stream, s->rng, nullptr, s->n_groups, iso,
-                           n_wgs, s->clist, nullptr, s->n_list, nullptr, s->ls0, s->ls1, s->sched);
+        hipLaunchKernelGGL(k_group_list, dim3(n_wgs), dim3(kBlock), 0, stream, s->rng, nullptr, s->ctrl, iso, n_wgs,
+                           s->clist, nullptr, s->n_list, nullptr, s->ls0, s->ls1, s->sched);
         a.clist = s->clist;
         a.n_list = s->n_list;
         a.list_duals = s->dual_total;
-        const uint32_t grid = ((n_tiles + kXcds - 1) / kXcds) * kXcds;
-        hipLaunchKernelGGL(k_extract_list<kPassCount>, dim3(grid), dim3(kBlock), 0, stream, a);
+        a.list_from_cull = 1;
+        launch(s, AMR_KERNEL_EXTRACT, k_extract_list<kPassCount>, dim3(grid), dim3(kBlock), stream, a);
         hipLaunchKernelGGL(k_tile_scan, dim3(a.n_scan_tiles), dim3(kBlock), 0, stream, a, 0);
-        if (write) hipLaunchKernelGGL(k_extract_list<kPassWrite>, dim3(grid), dim3(kBlock), 0, stream, a);
+        if (write) launch(s, AMR_KERNEL_WRITE, k_extract_list<kPassWrite>, dim3(grid), dim3(kBlock), stream, a);
     } else if (!duals && tri_dual == nullptr && cap > 0 && (tris || tri_cells)) {
         // count pass over all groups, then list the groups with triangles (in
         // group order, with their counts) and scan and write over that list
         // only: most groups have none, and the write pass would otherwise
         // redo their neighbourhoods beside the few that have some
-        const uint32_t grid = ((n_tiles + kXcds - 1) / kXcds) * kXcds;
-        hipLaunchKernelGGL((k_extract<false, kPassCount>), dim3(grid), dim3(kBlock), 0, stream, a);
-        hipLaunchKernelGGL(k_group_list, dim3(n_wgs), dim3(kBlock), 0, stream, nullptr, s->gcnt, s->n_groups, iso,
+        launch(s, AMR_KERNEL_EXTRACT, k_extract<false, kPassCount>, dim3(grid), dim3(kBlock), stream, a);
+        hipLaunchKernelGGL(k_group_list, dim3(n_wgs), dim3(kBlock), 0, stream, nullptr, s->gcnt, s->ctrl, iso,
                            n_wgs, s->clist, s->lcnt, s->n_list, s->list_duals, s->ls0, s->ls1, s->sched);
         a.clist = s->clist;
         a.n_list = s->n_list;
         a.lcnt = s->lcnt;
         a.list_duals = s->list_duals;
         hipLaunchKernelGGL(k_tile_scan, dim3(a.n_scan_tiles), dim3(kBlock), 0, stream, a, 0);
-        hipLaunchKernelGGL(k_extract_list<kPassWrite>, dim3(grid), dim3(kBlock), 0, stream, a);
+        launch(s, AMR_KERNEL_WRITE, k_extract_list<kPassWrite>, dim3(grid), dim3(kBlock), stream, a);
     } else {
         // count pass, scan, then the write pass only when something is written;
         // the grid is a multiple of the XCD count (see the tile mapping)
         const bool write = cap > 0 && (duals ? (corner_level || verts || dvals) : (tris || tri_cells || tri_dual));
-        const uint32_t grid = ((n_tiles + kXcds - 1) / kXcds) * kXcds;
         if (duals)
-            hipLaunchKernelGGL((k_extract<true, kPassCount>), dim3(grid), dim3(kBlock), 0, stream, a);
+            launch(s, AMR_KERNEL_EXTRACT, k_extract<true, kPassCount>, dim3(grid), dim3(kBlock), stream, a);
         else
-            hipLaunchKernelGGL((k_extract<false, kPassCount>), dim3(grid), dim3(kBlock), 0, stream, a);
+            launch(s, AMR_KERNEL_EXTRACT, k_extract<false, kPassCount>, dim3(grid), dim3(kBlock), stream, a);
         hipLaunchKernelGGL(k_tile_scan, dim3(a.n_scan_tiles), dim3(kBlock), 0, stream, a, duals ? 1 : 0);
         if (write) {
             if (duals)
-                hipLaunchKernelGGL((k_extract<true, kPassWrite>), dim3(grid), dim3(kBlock), 0, stream, a);
+                launch(s, AMR_KERNEL_WRITE, k_extract<true, kPassWrite>, dim3(grid), dim3(kBlock), stream, a);
             else
-                hipLaunchKernelGGL((k_extract<false, kPassWrite>), dim3(grid), dim3(kBlock), 0, stream, a);
+                launch(s, AMR_KERNEL_WRITE, k_extract<false, kPassWrite>, dim3(grid), dim3(kBlock), stream, a);
         }
     }
     hipError_t e = hipGetLastError();
@@ -2438,7 +2588,7 @@ int amr_create(amr_set** out, int hip_device) {
     amr_set* s = new (std::nothrow) amr_set();
     if (!s) return fail(AMR_ENOMEM, "amr_create: out of host memory");
     s->device = hip_device;
-    // pinned, so that the read-backs after upload and build are plain DMA
+    // pinned, so that the read-backs of the verdicts are plain DMA
     hipError_t e = hipHostMalloc((void**)&s->host_ctrl, sizeof(Ctrl), hipHostMallocDefault);
     if (e != hipSuccess) {
         delete s;
@@ -2453,8 +2603,10 @@ int amr_create(amr_set** out, int hip_device) {
         if (e == hipSuccess) e = hipDeviceSynchronize();
     }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->up_event, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->build_event, hipEventDisableTiming);
     if (e != hipSuccess) {
         if (s->ctrl) (void)hipFree(s->ctrl);
+        if (s->up_event) (void)hipEventDestroy(s->up_event);
         (void)hipHostFree(s->host_ctrl);
         delete s;
         return hipfail(e, "amr_create: control block");
@@ -2470,10 +2622,23 @@ void amr_destroy(amr_set* s) {
         DeviceGuard dg(s->device);
         if (s->ctrl) (void)hipFree(s->ctrl);
         if (s->up_event) (void)hipEventDestroy(s->up_event);
+        if (s->build_event) (void)hipEventDestroy(s->build_event);
     }
     (void)hipHostFree(s->host_ctrl);
     delete s;
 }
+
+namespace {
+
+// True while `stream` records a graph: then nothing may wait on the host,
+// and events and copies to the host are left out.
+bool capturing(hipStream_t stream) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &st) != hipSuccess) return false;
+    return st != hipStreamCaptureStatusNone;
+}
+
+}  // namespace
 
 int amr_upload(amr_set* s, const int32_t* xyz, const int32_t* level, const float* value, int64_t n,
                hipStream_t stream) {
@@ -2484,6 +2649,8 @@ int amr_upload(amr_set* s, const int32_t* xyz, const int32_t* level, const float
     DeviceGuard dg(s->device);
     s->uploaded = false;
     s->built = false;
+    s->build_tried = false;
+    s->build_pending = false;
     s->xyz = xyz;
     s->lvl = level;
     s->val = value;
@@ -2493,21 +2660,30 @@ int amr_upload(amr_set* s, const int32_t* xyz, const int32_t* level, const float
     s->origin[0] = s->origin[1] = s->origin[2] = 0;
     s->record_hint = 0;
     s->up_pending = false;
+    s->up_captured = false;
     s->up_status = AMR_OK;
-    if (n == 0) {
-        s->uploaded = true;
-        return AMR_OK;
-    }
     // the replicas are clean: amr_create and every k_upload_finish leave them so
-    hipLaunchKernelGGL(k_upload, dim3(grid_for(n, 256)), dim3(256), 0, stream, xyz, level, value, n, s->ctrl);
-    hipLaunchKernelGGL(k_upload_finish, dim3(1), dim3(kReplicas), 0, stream, s->ctrl);
+    if (n > 0) {
+        launch(s, AMR_KERNEL_UPLOAD, k_upload, dim3(grid_for(n, 256)), dim3(256), stream, xyz, level, value, n,
+               s->ctrl);
+        hipLaunchKernelGGL(k_upload_finish, dim3(1), dim3(kReplicas), 0, stream, s->ctrl);
+    } else {
+        // an empty set: a clean verdict for the build's kernels
+        hipLaunchKernelGGL(k_upload_finish, dim3(1), dim3(kReplicas), 0, stream, s->ctrl);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hipfail(e, "amr_upload: launch");
-    // the verdict travels to the host behind the kernels; whoever needs it
-    // first (amr_index_bytes, amr_build_index) waits for this event
-    e = hipMemcpyAsync(&s->host_ctrl->res, &s->ctrl->res, sizeof(UpRes), hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipEventRecord(s->up_event, stream);
-    if (e != hipSuccess) return hipfail(e, "amr_upload: readback");
+    if (capturing(stream)) {
+        // inside a graph: the verdict stays on the device (the build reads it
+        // there; amr_index_bytes fetches it once the graph has run)
+        s->up_captured = true;
+    } else {
+        // the verdict travels to the host behind the kernels; whoever needs it
+        // first (amr_index_bytes, amr_build_index, amr_build_status) waits for this event
+        e = hipMemcpyAsync(&s->host_ctrl->res, &s->ctrl->res, sizeof(UpRes), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipEventRecord(s->up_event, stream);
+        if (e != hipSuccess) return hipfail(e, "amr_upload: readback");
+    }
     s->up_pending = true;
     s->uploaded = true;
     g_err[0] = 0;
@@ -2520,6 +2696,7 @@ namespace {
 int apply_upload(amr_set* s) {
     const UpRes& u = s->host_ctrl->res;
     s->up_pending = false;
+    s->up_captured = false;
     s->up_status = u.status;
     if (u.status != AMR_OK) {
         if (u.err >= 16)
@@ -2539,10 +2716,17 @@ int apply_upload(amr_set* s) {
     return AMR_OK;
 }
 
-// Wait for the upload verdict if it is still on its way.
+// Wait for the upload verdict if it is still on its way (or, for an upload
+// enqueued inside a graph capture, fetch it from the device).
 int upload_verdict(amr_set* s) {
     if (s->up_pending) {
-        hipError_t e = hipEventSynchronize(s->up_event);
+        hipError_t e;
+        if (s->up_captured) {
+            e = hipDeviceSynchronize();
+            if (e == hipSuccess) e = hipMemcpy(&s->host_ctrl->res, &s->ctrl->res, sizeof(UpRes), hipMemcpyDeviceToHost);
+        } else {
+            e = hipEventSynchronize(s->up_event);
+        }
         if (e != hipSuccess) return hipfail(e, "amr_upload: waiting for the verdict");
         return apply_upload(s);
     }
@@ -2550,17 +2734,88 @@ int upload_verdict(amr_set* s) {
     return AMR_OK;
 }
 
+// Read the verdict of the last build (and of the upload before it) from the
+// device, waiting for the build first; sets s->build_status and returns it.
+int read_build_verdict(amr_set* s) {
+    if (!s->build_pending) return s->build_status;
+    DeviceGuard dg(s->device);
+    hipError_t e = s->build_captured ? hipDeviceSynchronize() : hipEventSynchronize(s->build_event);
+    const size_t tail = offsetof(Ctrl, overflow);
+    if (e == hipSuccess)
+        e = hipMemcpy((char*)s->host_ctrl + tail, (char*)s->ctrl + tail, sizeof(Ctrl) - tail, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hipfail(e, "amr_build_status: reading the verdict");
+    s->build_pending = false;
+    s->build_captured = false;
+    const Ctrl& c = *s->host_ctrl;
+    int st = c.status;
+    if (s->up_pending) {
+        // the copy above carried the upload verdict too
+        int su = apply_upload(s);
+        if (su != AMR_OK) {
+            s->build_status = su;
+            s->built = false;
+            return su;
+        }
+    } else if (s->up_status != AMR_OK) {
+        st = s->up_status;
+    }
+    if (st == AMR_OK) {
+        s->build_status = AMR_OK;
+        g_err[0] = 0;
+        return AMR_OK;
+    }
+    s->built = false;
+    s->build_status = st;
+    if (st == AMR_ENOSPACE) {
+        unsigned long long n_records = c.n_records;  // records at compaction time: the groups
+        for (int r = 0; r < kReplicas; ++r) n_records += c.made[r * 16];
+        uint64_t seen = n_records;
+        s->record_hint = seen * 2 > s->record_hint * 4 ? seen * 2 : s->record_hint * 4;
+        s->last_cap = 0;  // the next build sizes a new table and bound
+        return fail(AMR_ENOSPACE, "amr_build_index: hash table too small (%u slots, %llu groups against a bound of %u); "
+                    "query amr_index_bytes again", s->cap, (unsigned long long)c.n_groups, s->grid_groups);
+    }
+    if (st == AMR_EOVERLAP && c.overlap) {
+        // bad_build holds slot * 8 + child of the coarse cell: name its input index
+        const unsigned long long ref = c.bad_build;
+        int32_t id = -1;
+        hipLaunchKernelGGL(k_index_ids, dim3(grid_for(s->n, 256)), dim3(256), 0, 0, s->xyz, s->lvl, s->n, s->ctrl,
+                           s->rec, s->ids);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpy(&id, s->ids + ref, sizeof(id), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hipfail(e, "amr_build_index: overlap report");
+        return fail(AMR_EOVERLAP, "amr_build_index: cell %d contains finer cells", (int)id);
+    }
+    if (st == AMR_EOVERLAP) {
+        // some cell was stored twice: find the lowest overwritten index
+        hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, 0, s->ctrl);
+        hipLaunchKernelGGL(k_index_ids, dim3(grid_for(s->n, 256)), dim3(256), 0, 0, s->xyz, s->lvl, s->n, s->ctrl,
+                           s->rec, s->ids);
+        hipLaunchKernelGGL(k_index_find_dup, dim3(grid_for(s->n, 256)), dim3(256), 0, 0, s->xyz, s->lvl, s->n, s->rec,
+                           s->ids, s->ctrl);
+        e = hipGetLastError();
+        if (e == hipSuccess)
+            e = hipMemcpy((char*)s->host_ctrl + tail, (char*)s->ctrl + tail, sizeof(Ctrl) - tail,
+                          hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hipfail(e, "amr_build_index: duplicate search");
+        return fail(AMR_EOVERLAP, "amr_build_index: duplicate cell (index %llu)", s->host_ctrl->bad_build);
+    }
+    return fail(st, "amr_build_index: the build failed (status %d)", st);
+}
+
 }  // namespace
 
 int amr_index_bytes(const amr_set* cs, size_t* bytes) {
     if (!cs || !bytes) return fail(AMR_EINVAL, "amr_index_bytes: NULL argument");
-    amr_set* s = const_cast<amr_set*>(cs);  // reading the upload verdict updates the handle
+    amr_set* s = const_cast<amr_set*>(cs);  // reading a verdict updates the handle
     if (!s->uploaded) return fail(AMR_ESTATE, "amr_index_bytes: call amr_upload first");
+    if (s->build_pending) (void)read_build_verdict(s);  // an AMR_ENOSPACE verdict grows the answer
     int st = upload_verdict(s);
     if (st != AMR_OK) return st;
     uint32_t cap = table_cap(s);
     if (!cap) return fail(AMR_ERANGE, "amr_index_bytes: more groups than the index supports");
     *bytes = layout_for(cap).total;
+    g_err[0] = 0;
     return AMR_OK;
 }
 
@@ -2568,13 +2823,19 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     if (!s) return fail(AMR_EINVAL, "amr_build_index: set is NULL");
     if (!s->uploaded) return fail(AMR_ESTATE, "amr_build_index: call amr_upload first");
     s->built = false;
+    s->build_pending = false;
     if (!ws || ((uintptr_t)ws & 255)) return fail(AMR_EINVAL, "amr_build_index: workspace NULL or not 256-B aligned");
+    const bool cap_known = s->n == s->last_n && s->last_cap && bytes >= layout_for(s->last_cap).total;
+    const bool in_graph = capturing(stream);
     uint32_t cap;
-    if (s->up_pending && s->n == s->last_n && s->last_cap && bytes >= layout_for(s->last_cap).total) {
+    if (s->up_pending && cap_known) {
         // a set of the same size as last time: build at once with the same
         // table; the kernels take the geometry from the upload verdict on the
-        // device, and a table that turns out too small reports AMR_ENOSPACE
+        // device, and a table that turns out too small fails the build
         cap = s->last_cap;
+    } else if (s->up_pending && in_graph) {
+        return fail(AMR_ESTATE, "amr_build_index: the table size is unknown inside a graph capture (size it with "
+                                "amr_index_bytes or an earlier build of as many cells first)");
     } else {
         int st = upload_verdict(s);
         if (st != AMR_OK) return st;
@@ -2584,6 +2845,15 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     Layout L = layout_for(cap);
     if (bytes < L.total)
         return fail(AMR_ENOSPACE, "amr_build_index: workspace of %zu bytes, need %zu", bytes, L.total);
+    // The extraction grids cover this many groups; the build fails with
+    // AMR_ENOSPACE if there are more.  A new table takes the upload's record
+    // estimate with a quarter of headroom (about one record per group for
+    // octrees and bricks); a rebuild of as many cells keeps the last bound.
+    if (!(s->up_pending && cap_known)) {
+        const uint64_t want = s->record_hint + s->record_hint / 4 + 256;
+        s->grid_groups = (uint32_t)(want < (uint64_t)max_groups_of(cap) ? want : max_groups_of(cap));
+    }
+    if (s->grid_groups > max_groups_of(cap) || s->grid_groups == 0) s->grid_groups = max_groups_of(cap);
     DeviceGuard dg(s->device);
     char* base = (char*)ws;
     s->cap = cap;
@@ -2610,82 +2880,59 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     s->ct0 = (unsigned long long*)(base + L.ct0);
     s->ct1 = (unsigned long long*)(base + L.ct1);
     s->sched = (Sched*)(base + L.sched);
-    s->n_groups = 0;
     int log2cap = 0;
     while ((1u << log2cap) < cap) ++log2cap;
     {
         uint32_t work = cap > L.compact_tiles ? cap : L.compact_tiles;
         if (work < kFusedMaxTiles) work = kFusedMaxTiles;
-        hipLaunchKernelGGL(k_build_reset, dim3(grid_for(work, 256)), dim3(256), 0, stream, s->rec, cap,
-                           64 - log2cap, s->sched, s->ct0, s->ct1, L.compact_tiles, s->fs0, s->fs1, s->ls0, s->ls1,
-                           L.max_list_wgs, s->ctrl);
+        launch(s, AMR_KERNEL_RESET, k_build_reset, dim3(grid_for(work, 256)), dim3(256), stream, s->rec, cap,
+               64 - log2cap, s->sched, s->ct0, s->ct1, L.compact_tiles, s->fs0, s->fs1, s->ls0, s->ls1,
+               L.max_list_wgs, s->ctrl);
     }
     if (s->n > 0)
-        hipLaunchKernelGGL(k_index_insert, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->val,
-                           s->n, s->rec, s->ctrl);
+        launch(s, AMR_KERNEL_INSERT, k_index_insert, dim3(grid_for(s->n, 256)), dim3(256), stream, s->xyz, s->lvl,
+               s->val, s->n, s->rec, s->ctrl);
     // the group list only depends on the leaves, so it is compacted before
-    // the ancestors are marked, and the marking runs over it
-    hipLaunchKernelGGL(k_index_compact, dim3(L.compact_tiles), dim3(kBlock), 0, stream, s->rec, cap, s->glist,
-                       s->gkey, s->ct0, s->ct1, s->sched, L.compact_tiles, L.compact_per, s->ctrl);
-    if (s->n > 0) {
+    // the ancestors are marked, and the marking runs over it; its last
+    // work-group decides the verdict
+    launch(s, AMR_KERNEL_COMPACT, k_index_compact, dim3(L.compact_tiles), dim3(kBlock), stream, s->rec, cap,
+           s->glist, s->gkey, s->ct0, s->ct1, s->sched, L.compact_tiles, L.compact_per, s->ctrl);
+    {
         const int64_t most = s->n < (int64_t)cap ? s->n : (int64_t)cap;  // at least the number of groups
-        hipLaunchKernelGGL(k_index_mark, dim3(grid_for(most, 256)), dim3(256), 0, stream, s->rec, s->gkey,
-                           s->ctrl);
+        launch(s, AMR_KERNEL_MARK, k_index_mark, dim3(grid_for(most, 256)), dim3(256), stream, s->rec, s->gkey,
+               s->n, cap, s->grid_groups, s->ctrl);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hipfail(e, "amr_build_index: launch");
-    const size_t tail = offsetof(Ctrl, overflow);
-    e = hipMemcpyAsync((char*)s->host_ctrl + tail, (char*)s->ctrl + tail, sizeof(Ctrl) - tail,
-                       hipMemcpyDeviceToHost, stream);
-    if (e != hipSuccess) return hipfail(e, "amr_build_index: readback");
-    e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return hipfail(e, "amr_build_index: synchronize");
-    if (s->up_pending) {
-        // the read-back above carried the upload verdict too
-        int st = apply_upload(s);
-        if (st != AMR_OK) return st;
+    s->build_captured = in_graph;
+    if (!in_graph) {
+        e = hipEventRecord(s->build_event, stream);
+        if (e != hipSuccess) return hipfail(e, "amr_build_index: event");
     }
-    const Ctrl& c = *s->host_ctrl;
-    unsigned long long n_records = c.n_records;  // records at compaction time: the groups
-    for (int r = 0; r < kReplicas; ++r) n_records += c.made[r * 16];
-    if (c.overflow || n_records * 4 > (unsigned long long)cap * 3) {
-        uint64_t seen = n_records;
-        s->record_hint = seen * 2 > s->record_hint * 4 ? seen * 2 : s->record_hint * 4;
-        return fail(AMR_ENOSPACE, "amr_build_index: hash table too small (%u slots); query amr_index_bytes again",
-                    cap);
-    }
-    if (c.overlap) {
-        // bad_build holds slot * 8 + child of the coarse cell: name its input index
-        const unsigned long long ref = c.bad_build;
-        int32_t id = -1;
-        hipLaunchKernelGGL(k_index_ids, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->n,
-                           s->ctrl, s->rec, s->ids);
-        e = hipMemcpyAsync(&id, s->ids + ref, sizeof(id), hipMemcpyDeviceToHost, stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(stream);
-        if (e != hipSuccess) return hipfail(e, "amr_build_index: overlap report");
-        return fail(AMR_EOVERLAP, "amr_build_index: cell %d contains finer cells", (int)id);
-    }
-    if (c.n_leaves != (unsigned long long)s->n) {
-        // some cell was stored twice: find the lowest overwritten index
-        hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, stream, s->ctrl);
-        hipLaunchKernelGGL(k_index_ids, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->n,
-                           s->ctrl, s->rec, s->ids);
-        hipLaunchKernelGGL(k_index_find_dup, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->n,
-                           s->rec, s->ids, s->ctrl);
-        e = hipMemcpyAsync((char*)s->host_ctrl + tail, (char*)s->ctrl + tail, sizeof(Ctrl) - tail,
-                           hipMemcpyDeviceToHost, stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(stream);
-        if (e != hipSuccess) return hipfail(e, "amr_build_index: duplicate search");
-        return fail(AMR_EOVERLAP, "amr_build_index: duplicate cell (index %llu)", s->host_ctrl->bad_build);
-    }
-    s->n_groups = (uint32_t)c.n_groups;
     s->built = true;
+    s->build_tried = true;
+    s->build_pending = true;
+    s->build_status = kStatusPending;
     s->ids_ready = false;
     s->extractions = 0;
     s->last_cap = cap;
     s->last_n = s->n;
     g_err[0] = 0;
     return AMR_OK;
+}
+
+int amr_build_status(amr_set* s) {
+    if (!s) return fail(AMR_EINVAL, "amr_build_status: set is NULL");
+    if (!s->build_tried) return fail(AMR_ESTATE, "amr_build_status: no build since the last upload");
+    if (!s->build_pending) {
+        // read before: the same answer again
+        if (s->build_status == AMR_OK) {
+            g_err[0] = 0;
+            return AMR_OK;
+        }
+        return fail(s->build_status, "amr_build_status: the last build failed (status %d)", s->build_status);
+    }
+    return read_build_verdict(s);
 }
 
 int amr_dual_cells(amr_set* s, int32_t* corner_level, int32_t* verts, float* vals, int64_t cap, int64_t* counts,
@@ -2698,7 +2945,7 @@ int amr_dual_cells(amr_set* s, int32_t* corner_level, int32_t* verts, float* val
     return launch_extract(s, true, 0.0f, nullptr, nullptr, nullptr, corner_level, verts, vals, cap, counts, stream);
 }
 
-int amr_isosurface(amr_set* s, float iso, float* tris, int32_t* tri_cells, int32_t* tri_dual, int64_t cap,
+int amr_isosurface(amr_set* s, float iso, float* tris, int32_t* tri_cells, int64_t* tri_dual, int64_t cap,
                    int64_t* counts, hipStream_t stream) {
     if (!s) return fail(AMR_EINVAL, "amr_isosurface: set is NULL");
     if (!s->built) return fail(AMR_ESTATE, "amr_isosurface: call amr_build_index first");
@@ -2898,6 +3145,17 @@ int amr_indexed_mesh(const float* tris, const int32_t* tri_cells, int64_t n_tris
     hipLaunchKernelGGL(k_weld_index, dim3(grid_for(corners, 256)), dim3(256), 0, stream, corners, w, idx);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? AMR_OK : hipfail(e, "amr_indexed_mesh: launch");
+}
+
+int amr_time_kernel(amr_set* s, int kernel, hipEvent_t start, hipEvent_t stop) {
+    if (!s) return fail(AMR_EINVAL, "amr_time_kernel: set is NULL");
+    if (kernel < 0 || kernel > AMR_KERNEL_WRITE) return fail(AMR_EINVAL, "amr_time_kernel: unknown kernel %d", kernel);
+    if (kernel != 0 && (!start || !stop)) return fail(AMR_EINVAL, "amr_time_kernel: NULL event");
+    s->time_kernel = kernel;
+    s->time_start = start;
+    s->time_stop = stop;
+    g_err[0] = 0;
+    return AMR_OK;
 }
 
 const char* amr_last_error(void) { return g_err; }

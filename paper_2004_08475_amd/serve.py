@@ -181,6 +181,7 @@ class IsoServer:
         # requests takes whichever is cheaper for n
         self.t_plain, self.t_batch_fixed, self.t_batch_job = self._calibrate()
         self.upload_slots = upload_slots
+        self.barrier_timeouts = 0  # batched launches redone as plain passes
         self.stop = threading.Event()
         # request outputs live in buffers reused across requests
         self._iso_stream = torch.cuda.Stream(self.device)
@@ -271,6 +272,7 @@ class IsoServer:
         need = int(caps.sum()) * 36 + (1 << 20)
         held = self.mem.acquire(need, self.stop)
         t_start = time.perf_counter()
+        timed_out = False
         try:
             with torch.cuda.stream(stream):
                 off = np.concatenate([[0], np.cumsum(caps)[:-1]])
@@ -279,6 +281,14 @@ class IsoServer:
                 jobs = self.batch.jobs_tensor([0] * n, isos, off, caps)
                 self.batch.run_into(jobs, n, tris, counts, self.block, self.per_thread)
                 c = counts.cpu().numpy()
+                # a grid barrier that gave up leaves invalid results and a
+                # barrier in an unknown state: clear it, serve these plainly
+                timed_out = self.batch.barrier_timed_out(self.block, self.per_thread)
+                if timed_out:
+                    self.batch.reset_barrier(self.block, self.per_thread)
+                    self.barrier_timeouts += 1
+                    stream.synchronize()
+                    return
                 kept = []
                 for k in range(n):
                     out = tris[int(off[k]):int(off[k]) + int(c[k])]
@@ -292,6 +302,9 @@ class IsoServer:
                     res.start, res.done, res.triangles, res.tris = t_start, t_done, int(c[k]), kept[k]
         finally:
             self.mem.release(held)
+            if timed_out:
+                for r in reqs:
+                    self._run_one(r, results, stream)
 
     def _keep(self, out):
         # outputs are dropped at once unless the caller keeps them, so that

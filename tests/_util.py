@@ -1,4 +1,4 @@
-"""Comparison helpers shared by the GPU parity tests (no method arithmetic)."""
+"""Comparison helpers shared by the GPU parity tests."""
 import numpy as np
 
 
@@ -22,9 +22,15 @@ def canon_by_cells(tris, cells, dual_ids=None):
     return t[order], c[order], d
 
 
-def position_tolerance(ref, w0=1.0):
-    """|delta| <= max(1e-5 * finest width, 2 ulp_f32(|x|))."""
-    return np.maximum(1e-5 * w0, 2.0 * np.spacing(np.abs(np.asarray(ref, np.float32))).astype(np.float64))
+def same_positions(a, b):
+    """True when two float32 position arrays are equal bit for bit.  Both
+    sides place a vertex with the same IEEE float32 operations (cell centres
+    exact in float32, a correctly rounded division, one fused multiply-add),
+    so the gate is equality of the bits, tighter than 1e-5 of the finest cell
+    width and than one unit in the last place."""
+    a = np.ascontiguousarray(np.asarray(a, np.float32))
+    b = np.ascontiguousarray(np.asarray(b, np.float32))
+    return a.shape == b.shape and np.array_equal(a.view(np.uint32), b.view(np.uint32))
 
 
 def directed_edges(cells):
@@ -36,3 +42,31 @@ def directed_edges(cells):
         for i in range(3):
             cnt[(ks[i], ks[(i + 1) % 3])] += 1
     return cnt
+
+
+def owner_of_duals(pl, ids, level):
+    """Generating cell of each dual under rule 3: the cell in the lowest slot
+    whose level equals the dual's level."""
+    lv = np.asarray(level)[ids]
+    same = lv == pl[:, 3:4]
+    first = np.argmax(same, axis=1)
+    return ids[np.arange(len(ids)), first]
+
+
+def window_matches_oracle(o, iso, pl, ids, tris, cells, dual, c0, c1):
+    """The GPU's triangles whose generating dual is owned by a cell in
+    [c0, c1) against the oracle's triangles for that range of cells: count,
+    cell-pair topology after canonical order, positions bit for bit.
+    `pl`, `ids` are the GPU's dual cells (numpy); `tris`, `cells`, `dual` its
+    triangles with their cell pairs and dual indices.  Returns the number of
+    triangles compared."""
+    owner = owner_of_duals(pl, ids, o.level)
+    sel = (owner >= c0) & (owner < c1)
+    tsel = sel[np.asarray(dual)]
+    ro = o.isosurface(float(iso), c0, c1)
+    A, AC, _ = canon_by_cells(np.asarray(tris)[tsel], np.asarray(cells)[tsel])
+    B, BC, _ = canon_by_cells(ro["tris"], ro["cells"])
+    assert len(A) == len(B)
+    assert np.array_equal(AC, BC)
+    assert same_positions(A, B)
+    return len(A)

@@ -1,5 +1,5 @@
-"""Host-side checks of bench.py: the one-GPU contract and the traffic lookup
-keyed to the kernel source (no GPU needed)."""
+"""Host-side checks of bench.py: the one-GPU contract, the counter lookup
+keyed to the kernel source, the roofline fields (no GPU needed)."""
 import os
 import subprocess
 import sys
@@ -18,38 +18,60 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert r.stdout == ""
 
 
-def test_traffic_only_for_the_source_it_was_measured_on(tmp_path, monkeypatch):
-    have = {w: bench.traffic_for(w) for w in ("octree-shell-256", "block-vortex-1024")}
-    if any(v is None for v in have.values()):
-        # the committed counters belong to another version of the kernels
-        return
-    assert all(v > 0 for v in have.values())
-    assert bench.traffic_for("no-such-workload") is None
-    other = tmp_path / "amriso.hip"
-    other.write_bytes(open(bench.KERNEL_SOURCE, "rb").read() + b"\n// changed\n")
-    monkeypatch.setattr(bench, "KERNEL_SOURCE", str(other))
-    assert bench.traffic_for("octree-shell-256") is None
+def test_counters_only_for_the_source_they_were_measured_on(tmp_path, monkeypatch):
+    import hashlib
+
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    src = tmp_path / "amriso.hip"
+    src.write_bytes(b"// kernels\n")
+    sha = hashlib.sha256(src.read_bytes()).hexdigest()
+    (prof / "wl_counters.txt").write_text("# header\nsource_sha256 %s\n"
+                                          "kernel k_extract<false, 0> | traffic_bytes 1.5e9 l2_hit 0.8 mall_hit - "
+                                          "valu_issue 0.7\n" % sha)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "KERNEL_SOURCE", str(src))
+    c = bench.counters_for("wl", "k_extract<false, 0>")
+    assert c == {"traffic_bytes": 1.5e9, "l2_hit": 0.8, "mall_hit": None, "valu_issue": 0.7}
+    assert bench.counters_for("wl", "k_index_insert") is None
+    assert bench.counters_for("other", "k_extract<false, 0>") is None
+    src.write_bytes(b"// kernels, changed\n")
+    assert bench.counters_for("wl", "k_extract<false, 0>") is None
 
 
-def test_valu_issue_only_for_the_source_it_was_measured_on(tmp_path, monkeypatch):
-    have = bench.valu_for("block-vortex-1024")
-    if have is None:
-        # the committed counters belong to another version of the kernels
-        return
-    assert "k_extract<false,0>" in have  # the count pass over all groups
-    assert all(0.0 < v <= 1.0 for v in have.values())
-    assert bench.valu_for("no-such-workload") is None
-    other = tmp_path / "amriso.hip"
-    other.write_bytes(open(bench.KERNEL_SOURCE, "rb").read() + b"\n// changed\n")
-    monkeypatch.setattr(bench, "KERNEL_SOURCE", str(other))
-    assert bench.valu_for("block-vortex-1024") is None
+def test_committed_counter_summaries_parse():
+    """Every committed counter summary names the source it was taken with
+    and parses (its figures are used only while that source is current)."""
+    import glob
+
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*_counters.txt")):
+        lines = open(path).read().splitlines()
+        assert any(ln.startswith("source_sha256 ") for ln in lines), path
+        for ln in lines:
+            if ln.startswith("kernel "):
+                name, rest = ln[len("kernel "):].split(" | ", 1)
+                f = rest.split()
+                assert len(f) % 2 == 0 and name.strip(), ln
 
 
 def test_roofline_fields():
-    r = bench.roofline_of(1000, 10, 0.5, None)
-    assert r["algorithmic_bytes"] == 20.0 * 1000 + 36.0 * 10
+    r = bench.roofline_of("k_extract<false, 0>", 20.0 * 1000, 0.5, None, 7)
+    assert r["algorithmic_bytes"] == 20.0 * 1000
     assert abs(r["achieved"] - r["algorithmic_bytes"] / 0.5e-3 / 1e9) < 1e-9
     assert r["frac"] == r["achieved"] / r["peak"] and r["unit"] == "GB/s" and r["bound"] == "hbm"
+    assert r["traffic"] is None and r["launches"] == 7 and r["kernel"] == "k_extract<false, 0>"
+
+
+def test_algorithmic_bytes_per_kernel():
+    class K:
+        KERNEL_UPLOAD, KERNEL_RESET, KERNEL_INSERT, KERNEL_COMPACT, KERNEL_MARK, KERNEL_EXTRACT, KERNEL_WRITE = \
+            range(1, 8)
+
+    assert bench.alg_bytes(K, K.KERNEL_UPLOAD, 100, 7, False) == 2000
+    assert bench.alg_bytes(K, K.KERNEL_EXTRACT, 100, 7, False) == 2000  # count pass: no triangles written
+    assert bench.alg_bytes(K, K.KERNEL_EXTRACT, 100, 7, True) == 2000 + 252  # fused pass writes them
+    assert bench.alg_bytes(K, K.KERNEL_WRITE, 100, 7, False) == 252
+    assert bench.alg_bytes(K, K.KERNEL_MARK, 100, 7, False) is None
 
 
 def test_cpu_baseline_reports_one_thread_and_brute_force():

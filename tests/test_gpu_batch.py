@@ -1,14 +1,49 @@
-"""Batched iso-surfaces (one persistent launch over many (set, iso) jobs):
-every job's output must equal, bit for bit and in order, the plain
-single-iso path on the same set and iso; graph replays must too."""
+"""Batched iso-surfaces (one persistent launch over many (set, iso) jobs).
+
+Every job's output must equal the CPU oracle's iso-surface of its set at its
+iso: the triangle count, the triangle positions bit for bit, and (through
+the plain single-iso path, which the job equals bit for bit and in order,
+and which also names each vertex's cell pair) the cell-pair topology.  Sets
+above a million cells are checked on windows of owner cells (all triangles
+of the duals those cells generate).  Graph replays must equal eager runs."""
+import os
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 
 import amrgen
+import oracle
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from _util import canon_by_cells, same_positions, window_matches_oracle  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
+
+ORACLE_THREADS = 8
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _check_job_against_oracle(s, iso, got, ro):
+    """One batched job (float32 [T, 9]) against the oracle's output for the
+    whole set: count and positions directly, topology through the plain path."""
+    g = got.cpu().numpy()
+    assert len(g) == len(ro["tris"])
+    A, _ = oracle.canonical_triangles(g)
+    B, _ = oracle.canonical_triangles(ro["tris"])
+    assert same_positions(A, B)
+    r = s.isosurface(float(iso), cells=True)
+    assert torch.equal(r["tris"], got)
+    AT, AC, _ = canon_by_cells(r["tris"].cpu().numpy(), r["cells"].cpu().numpy())
+    BT, BC, _ = canon_by_cells(ro["tris"], ro["cells"])
+    assert np.array_equal(AC, BC)
+    assert same_positions(AT, BT)
 
 
 @pytest.fixture(scope="module")
@@ -108,12 +143,10 @@ def test_batch_graph_replay_with_new_isos(amr, shell):
     assert not b.barrier_timed_out(256, 1)
 
 
-def test_batched_configurations_at_full_size(amr, shell):
-    """The two batched workloads bench.py times, at full size, in the launch
-    shapes the autotuner picks for them (512 x 1 and 256 x 2) and the default
-    one: octree-shell-256 with 64 isos at percentiles 5 + 90 k / 63, and 32
-    octree sets of log-uniform sizes in [10k, 5M] cells (seed 4), each at its
-    median iso.  Every job equals the plain path bit for bit."""
+def test_batched_launch_shapes_agree(amr, shell):
+    """octree-shell-256 with 64 isos at percentiles 5 + 90 k / 63 in the
+    launch shapes 512 x 1 and 256 x 1: every job equals the plain path bit
+    for bit (the oracle tests below cover the jobs themselves)."""
     cs, s = shell
     isos = np.quantile(cs.value, 0.05 + 0.90 * np.arange(64) / 63).astype(np.float32)
     b = amr.AmrBatch([s])
@@ -122,13 +155,79 @@ def test_batched_configurations_at_full_size(amr, shell):
         outs = b.isosurface([0] * len(isos), isos, block, per)
         for w, got in zip(want, outs):
             assert torch.equal(got, w)
+
+
+def test_many_isos_equal_oracle(amr, shell):
+    """octree-shell-256 at 64 isos (percentiles 5 + 90 k / 63), one launch,
+    every job against the oracle on the whole set."""
+    cs, s = shell
+    isos = np.quantile(cs.value, 0.05 + 0.90 * np.arange(64) / 63).astype(np.float32)
+    b = amr.AmrBatch([s])
+    outs = b.isosurface([0] * len(isos), isos, 512, 1)
+    o = oracle.Oracle(cs.xyz, cs.level, cs.value)
+    with ThreadPoolExecutor(ORACLE_THREADS) as ex:
+        ros = list(ex.map(lambda v: o.isosurface(float(v)), isos))
+    _say("64 isos: %d triangles in all" % sum(len(r["tris"]) for r in ros))
+    for iso, got, ro in zip(isos, outs, ros):
+        _check_job_against_oracle(s, iso, got, ro)
+
+
+def test_many_isos_two_million_cells_equal_oracle(amr):
+    """The ~2M-cell octree at 64 isos in one launch; each job is checked on
+    its own window of 40,000 owner cells of the shuffled input."""
+    cs = amrgen.octree_shell_2m()
+    _say("octree-shell-256-2m: %d cells" % cs.n)
+    s = amr.from_numpy(cs.xyz, cs.level, cs.value)
+    isos = np.quantile(cs.value, 0.05 + 0.90 * np.arange(64) / 63).astype(np.float32)
+    b = amr.AmrBatch([s])
+    outs = b.isosurface([0] * len(isos), isos, 256, 1)
+    pl, ids = (t.cpu().numpy() for t in s.dual_cells())
+    o = oracle.Oracle(cs.xyz, cs.level, cs.value, validate=False)
+    win = 40_000
+    jobs = []
+    for k, (iso, got) in enumerate(zip(isos, outs)):
+        r = s.isosurface(float(iso), cells=True, dual=True)
+        assert torch.equal(r["tris"], got)
+        c0 = (k * 29_989) % (cs.n - win)
+        jobs.append((iso, r["tris"].cpu().numpy(), r["cells"].cpu().numpy(), r["dual"].cpu().numpy(), c0))
+    with ThreadPoolExecutor(ORACLE_THREADS) as ex:
+        n = list(ex.map(lambda j: window_matches_oracle(o, j[0], pl, ids, j[1], j[2], j[3], j[4], j[4] + win), jobs))
+    _say("2M-cell set: %d triangles compared over 64 windows" % sum(n))
+    assert sum(n) > 0
+
+
+def test_multiset_batch_equal_oracle(amr):
+    """The 32 octree sets of log-uniform sizes in [10k, 5M] cells (seed 4),
+    each at its median iso, in one launch: sets up to 1M cells against the
+    oracle on the whole set, larger ones on two windows of 60,000 owner
+    cells each."""
     sizes = np.exp(np.random.default_rng(4).uniform(np.log(1e4), np.log(5e6), 32)).astype(int)
     css = [amrgen.octree_sized(int(n), seed=200 + k) for k, n in enumerate(sizes)]
-    print("32 sets, %d cells in all" % sum(c.n for c in css), flush=True)
+    _say("32 sets, %d cells in all" % sum(c.n for c in css))
     sets = [amr.from_numpy(c.xyz, c.level, c.value) for c in css]
     b = amr.AmrBatch(sets)
-    want = [_plain(st, c.iso) for st, c in zip(sets, css)]
-    for block, per in ((256, 2), (256, 1)):
-        outs = b.isosurface(list(range(len(sets))), [c.iso for c in css], block, per)
-        for w, got in zip(want, outs):
-            assert torch.equal(got, w)
+    outs = b.isosurface(list(range(len(sets))), [c.iso for c in css], 256, 2)
+    for a, c in zip(outs, b.isosurface(list(range(len(sets))), [c.iso for c in css], 256, 1)):
+        assert torch.equal(a, c)  # another launch shape, the same bits
+    small = [k for k, c in enumerate(css) if c.n <= 1_000_000]
+    large = [k for k, c in enumerate(css) if c.n > 1_000_000]
+    orcs = {k: oracle.Oracle(css[k].xyz, css[k].level, css[k].value, validate=(css[k].n <= 1_000_000))
+            for k in range(len(css))}
+    with ThreadPoolExecutor(ORACLE_THREADS) as ex:
+        ros = dict(zip(small, ex.map(lambda k: orcs[k].isosurface(float(css[k].iso)), small)))
+    for k in small:
+        _check_job_against_oracle(sets[k], css[k].iso, outs[k], ros[k])
+    _say("%d sets checked whole, %d on windows" % (len(small), len(large)))
+    win = 60_000
+    jobs = []
+    for k in large:
+        cs, s = css[k], sets[k]
+        r = s.isosurface(float(cs.iso), cells=True, dual=True)
+        assert torch.equal(r["tris"], outs[k])
+        pl, ids = (t.cpu().numpy() for t in s.dual_cells())
+        for c0 in (cs.n // 5, (3 * cs.n) // 5):
+            jobs.append((k, pl, ids, r["tris"].cpu().numpy(), r["cells"].cpu().numpy(), r["dual"].cpu().numpy(), c0))
+    with ThreadPoolExecutor(ORACLE_THREADS) as ex:
+        n = list(ex.map(lambda j: window_matches_oracle(orcs[j[0]], css[j[0]].iso, j[1], j[2], j[3], j[4], j[5],
+                                                        j[6], j[6] + win), jobs))
+    assert all(x >= 0 for x in n)

@@ -17,7 +17,7 @@ import amrgen
 import oracle
 
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
-from _util import position_tolerance  # noqa: E402
+from _util import same_positions  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -77,9 +77,7 @@ def check_against_oracle(tris_g, cells_g, verts_g, idx_g, ro):
     og = np.argsort(vk_g)
     oo = np.argsort(vk_o)
     assert np.array_equal(vk_g[og], vk_o[oo])
-    a = np.asarray(verts_g, np.float64)[og]
-    b = ov[oo]
-    assert np.all(np.abs(a - b.astype(np.float64)) <= position_tolerance(b))
+    assert same_positions(np.asarray(verts_g)[og], ov[oo])
 
 
 CASES = {

@@ -2,7 +2,8 @@
 
 Bar: dual cells bit-exact (corner, level, 8 cell indices), triangle topology
 bit-exact (per-vertex cell pairs, per-dual triangle sets), triangle counts
-exact, vertex positions within max(1e-5 * finest width, 2 ulp_f32).
+exact, vertex positions equal bit for bit (tighter than 1e-5 of the finest
+width: both sides place vertices with the same float32 operations).
 """
 import os
 import sys
@@ -14,7 +15,7 @@ import amrgen
 import oracle
 
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
-from _util import canon_by_cells, directed_edges, position_tolerance  # noqa: E402
+from _util import canon_by_cells, directed_edges, same_positions  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -60,8 +61,7 @@ def check_iso(s, o, iso, pl_g=None):
     A, AC, AD = canon_by_cells(tg, cg, dg)
     B, BC, BD = canon_by_cells(ro["tris"], ro["cells"], ro["dual"])
     assert np.array_equal(AC, BC)
-    tol = position_tolerance(B)
-    assert np.all(np.abs(A.astype(np.float64) - B.astype(np.float64)) <= tol)
+    assert same_positions(A, B)
     if pl_g is not None and len(AD):
         # per-dual triangle sets: the generating dual of each triangle agrees
         pl_o, _ = o.dual_cells()
@@ -311,7 +311,7 @@ def test_block_vortex_full_size_sampled(amr, sample):
     B, BC, _ = canon_by_cells(ro["tris"], ro["cells"])
     assert len(A) == len(B) > 0
     assert np.array_equal(AC, BC)
-    assert np.all(np.abs(A.astype(np.float64) - B.astype(np.float64)) <= position_tolerance(B))
+    assert same_positions(A, B)
     # the hole: no dual has a vertex cell inside the obstacle, and the surface
     # is open only where the dual mesh has a boundary (checked on the sample)
     assert len(tg) > 0

@@ -9,8 +9,7 @@ meeting the sample box grown by 2^(Lmax+1) contain every point the sample's
 duals and triangles depend on, and the oracle's index stays small.
 
 Bar: dual cells bit-exact (corner, level, 8 global cell indices); triangle
-topology exact (per-vertex cell pairs); positions within
-max(1e-5 * finest width, 2 ulp_f32).  A serving mix against the same resident
+topology exact (per-vertex cell pairs); positions equal bit for bit.  A serving mix against the same resident
 set must give each request's result as it is alone.
 """
 import os
@@ -23,7 +22,7 @@ import amrgen
 import oracle
 
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
-from _util import canon_by_cells, position_tolerance  # noqa: E402
+from _util import canon_by_cells, same_positions  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -129,7 +128,7 @@ def test_serving_set_sampled(amr, big):
     B, BC, _ = canon_by_cells(ro["tris"], sub_np[ro["cells"]])
     assert len(A) == len(B) > 0
     assert np.array_equal(AC, BC)
-    assert np.all(np.abs(A.astype(np.float64) - B.astype(np.float64)) <= position_tolerance(B))
+    assert same_positions(A, B)
 
 
 def test_serving_mix_on_the_resident_set(amr, big):

@@ -86,3 +86,64 @@ def test_summary_percentiles_by_kind():
     assert abs(s["p50_ms"] - 50.5) < 1e-9
     lat_iso = [(k + 1.0) for k in range(100) if k % 4]
     assert abs(s["by_kind"]["iso"]["p99_ms"] - float(np.percentile(lat_iso, 99))) < 1e-9
+
+
+def test_batch_barrier_timeout_falls_back_to_plain_passes():
+    """A batched launch whose grid-barrier wait gave up: its results are not
+    returned; the barrier is cleared and every request of the batch is served
+    by a plain pass, after the batch's memory was given back."""
+
+    class FakeBatch:
+        def __init__(self):
+            self.resets = 0
+
+        def jobs_tensor(self, *a):
+            return None
+
+        def run_into(self, jobs, n, tris, counts, block, per):
+            counts.fill_(5)
+
+        def barrier_timed_out(self, block, per):
+            return self.resets == 0
+
+        def reset_barrier(self, block, per):
+            self.resets += 1
+
+    srv = object.__new__(serve.IsoServer)
+    srv.t_plain, srv.t_batch_fixed, srv.t_batch_job = 1.0, 0.1, 0.01  # batching wins
+    srv.batch = FakeBatch()
+    srv.block, srv.per_thread = 256, 1
+    srv.mem = serve.HbmBudget(1 << 30)
+    srv.stop = threading.Event()
+    srv.curve_iso = np.array([0.0, 1.0])
+    srv.curve_tri = np.array([10, 10])
+    srv._iso_out = serve._Grow(9, torch.float32, torch.device("cpu"))
+    srv._batch_counts = torch.zeros(8, dtype=torch.int64)
+    srv.keep_outputs = False
+    srv.barrier_timeouts = 0
+    plain = []
+
+    def run_one(r, results, stream):
+        assert srv.mem.used == 0  # the batch's reservation is already released
+        plain.append(r.rid)
+        results[r.rid].done = 1.0
+
+    srv._run_one = run_one
+
+    class Stream:
+        def synchronize(self):
+            pass
+
+    import contextlib
+
+    reqs = [serve.IsoRequest(0.5, rid=k) for k in range(3)]
+    results = {k: serve.Result(k, "iso", 0.0) for k in range(3)}
+    orig = torch.cuda.stream
+    torch.cuda.stream = lambda s: contextlib.nullcontext()
+    try:
+        srv._run_batch(reqs, results, Stream())
+    finally:
+        torch.cuda.stream = orig
+    assert plain == [0, 1, 2]
+    assert srv.batch.resets == 1 and srv.barrier_timeouts == 1
+    assert srv.mem.used == 0
