@@ -264,13 +264,18 @@ def indexed_mesh(tris: np.ndarray, cells: np.ndarray):
 
 # ---------------------------------------------------------------------------
 # Dual-mesh interpolant (paper sec. 5 names the dual mesh, as Moran et al.
-# use it, as an interpolant for volume rendering; it does not define one).
+# use it, as an interpolant for volume rendering; sec. 7 lists that as
+# future work; neither defines one).
 # Reading: each emitted dual is the trilinear hexahedron over its 8 vertex
 # cells' centres, slot s = ex + 2 ey + 4 ez at parameter u = (ex, ey, ez),
 # and carries the trilinear interpolant of their values.  A point's value
-# comes from the dual whose map reaches it with u in [0,1]^3 (Newton on the
+# comes from a dual whose map reaches it with u in [0,1]^3 (Newton on the
 # trilinear map, fp64); points no dual reaches get NaN.  Degenerate duals
-# whose map has no volume reach no point.  Brute force over all duals: tiny
+# whose map has no volume reach no point.  Where several duals reach a
+# point (on shared faces, and inside overlapping duals, which exist when
+# the levels of a dual's cells span three or more), the one with the
+# smallest (level, P.z, P.y, P.x) wins: the finest dual, then the lowest
+# centre vertex P in (z, y, x) order.  Brute force over all duals: small
 # sets only.
 # ---------------------------------------------------------------------------
 
@@ -312,15 +317,17 @@ def _invert(V, p, iters=40):
     return u, ok & (resid < 1e-9)
 
 
-def dual_mesh_sample(xyz, level, value, ids, points, eps: float = 1e-9):
-    """Interpolated values at points [Q,3] from the duals ids [M,8] (cell
-    indices per slot) of the cells (xyz, level, value).  Returns (values
-    float64 [Q] (NaN outside the dual mesh), dual index int64 [Q] (the
-    lowest-numbered dual that reaches the point, -1 if none), number of
-    duals that reach it int64 [Q])."""
+def dual_mesh_sample(xyz, level, value, pl, ids, points, eps: float = 1e-9):
+    """Interpolated values at points [Q,3] from the duals (pl [M,4] = centre
+    vertex P and level, ids [M,8] = cell indices per slot) of the cells
+    (xyz, level, value).  Returns (values float64 [Q] (NaN outside the dual
+    mesh), dual index int64 [Q] (the reaching dual with the smallest
+    (level, P.z, P.y, P.x), -1 if none), number of duals that reach the
+    point int64 [Q])."""
     xyz = np.asarray(xyz, np.float64).reshape(-1, 3)
     lvl = np.asarray(level, np.int64)
     val = np.asarray(value, np.float64)
+    pl = np.asarray(pl, np.int64).reshape(-1, 4)
     ids = np.asarray(ids, np.int64).reshape(-1, 8)
     pts = np.asarray(points, np.float64).reshape(-1, 3)
     centre = xyz + 0.5 * (1 << lvl)[:, None].astype(np.float64)
@@ -335,10 +342,12 @@ def dual_mesh_sample(xyz, level, value, ids, points, eps: float = 1e-9):
         if len(cand) == 0:
             continue
         u, ok = _invert(V[cand], np.broadcast_to(p, (len(cand), 3)))
-        inside = ok & np.all((u >= -eps) & (u <= 1 + eps), 1)
-        hits[q] = int(inside.sum())
-        if hits[q]:
-            k = int(np.nonzero(inside)[0][0])
+        inside = np.nonzero(ok & np.all((u >= -eps) & (u <= 1 + eps), 1))[0]
+        hits[q] = len(inside)
+        if len(inside):
+            key = pl[cand[inside]]
+            # smallest (level, z, y, x): lexsort takes its last key as the primary one
+            k = int(inside[np.lexsort((key[:, 0], key[:, 1], key[:, 2], key[:, 3]))[0]])
             w, _ = _trilinear(np.clip(u[k:k + 1], 0.0, 1.0))
             out[q] = float(w[0] @ F[cand[k]])
             which[q] = int(cand[k])

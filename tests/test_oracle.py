@@ -546,7 +546,8 @@ def _centres(cs):
 
 
 def _duals(cs):
-    return oracle.Oracle(cs.xyz, cs.level, cs.value).dual_cells()[1]
+    """(pl, ids) of the oracle's dual cells."""
+    return oracle.Oracle(cs.xyz, cs.level, cs.value).dual_cells()
 
 
 def test_dual_interpolant_is_trilinear_on_single_level_grids():
@@ -560,7 +561,7 @@ def test_dual_interpolant_is_trilinear_on_single_level_grids():
         lattice[ijk[:, 0], ijk[:, 1], ijk[:, 2]] = cs.value
         rng = np.random.default_rng(11 + level)
         pts = c0 + rng.uniform(0, 5 * w, (150, 3))
-        got, _, hits = oracle.dual_mesh_sample(cs.xyz, cs.level, cs.value, _duals(cs), pts)
+        got, _, hits = oracle.dual_mesh_sample(cs.xyz, cs.level, cs.value, *_duals(cs), pts)
         assert np.all(hits == 1)
         # textbook trilinear interpolation on the cell-centre lattice
         g = (pts - c0) / w
@@ -583,7 +584,7 @@ def test_dual_interpolant_reproduces_linear_fields():
         lin = _centres(cs) @ a + b
         ext = cs.xyz.max(0) + (1 << cs.level.max())
         pts = rng.uniform(cs.xyz.min(0), ext, (300, 3))
-        got, _, hits = oracle.dual_mesh_sample(cs.xyz, cs.level, lin, _duals(cs), pts)
+        got, _, hits = oracle.dual_mesh_sample(cs.xyz, cs.level, lin, *_duals(cs), pts)
         inside = hits > 0
         assert inside.sum() > 15
         assert np.all(np.isnan(got[~inside]))
@@ -593,7 +594,7 @@ def test_dual_interpolant_reproduces_linear_fields():
 def test_dual_interpolant_gives_cell_values_at_centres():
     cs = amrgen.random_octree(52, roots=2, root_level=3, p_split=0.5, values="random")
     c = _centres(cs)
-    got, _, hits = oracle.dual_mesh_sample(cs.xyz, cs.level, cs.value, _duals(cs), c)
+    got, _, hits = oracle.dual_mesh_sample(cs.xyz, cs.level, cs.value, *_duals(cs), c)
     inside = hits > 0
     assert inside.sum() > 20
     # at a collapsed vertex of a degenerate dual the inverse map is ill
@@ -605,14 +606,14 @@ def test_dual_mesh_partitions_the_two_level_sphere():
     # the dual volumes sum to 14^3 over [1,15]^3 (pinned above); each point
     # inside lies in exactly one dual, each point outside in none
     cs = amrgen.two_level_sphere()
-    ids = _duals(cs)
+    pl, ids = _duals(cs)
     rng = np.random.default_rng(9)
     inside = rng.uniform(1.0, 15.0, (300, 3))
-    _, _, hits = oracle.dual_mesh_sample(cs.xyz, cs.level, cs.value, ids, inside)
+    _, _, hits = oracle.dual_mesh_sample(cs.xyz, cs.level, cs.value, pl, ids, inside)
     assert np.all(hits == 1)
     outside = rng.uniform(0.0, 16.0, (400, 3))
     outside = outside[np.any((outside < 1.0) | (outside > 15.0), 1)]
-    _, _, hits = oracle.dual_mesh_sample(cs.xyz, cs.level, cs.value, ids, outside)
+    _, _, hits = oracle.dual_mesh_sample(cs.xyz, cs.level, cs.value, pl, ids, outside)
     assert np.all(hits == 0)
 
 
@@ -623,5 +624,50 @@ def test_dual_hexahedra_overlap_under_large_level_jumps():
     # for overlaps.
     cs = amrgen.random_octree(52, roots=2, root_level=4, p_split=0.6, values="smooth")
     p = np.array([[15.68839305, 13.50619197, 16.97884438]])
-    v, _, hits = oracle.dual_mesh_sample(cs.xyz, cs.level, cs.value, _duals(cs), p)
+    pl, ids = _duals(cs)
+    v, which, hits = oracle.dual_mesh_sample(cs.xyz, cs.level, cs.value, pl, ids, p)
     assert hits[0] == 2
+    # each of the two alone: the overlap rule picks the finer dual's value
+    alone = []
+    for d in range(len(ids)):
+        lo = np.min(_centres(cs)[ids[d]], 0)
+        hi = np.max(_centres(cs)[ids[d]], 0)
+        if np.all(lo <= p[0]) and np.all(p[0] <= hi):
+            vd, _, hd = oracle.dual_mesh_sample(cs.xyz, cs.level, cs.value, pl[d:d + 1], ids[d:d + 1], p)
+            if hd[0]:
+                key = (int(pl[d, 3]), int(pl[d, 2]), int(pl[d, 1]), int(pl[d, 0]))
+                alone.append((key, float(vd[0]), d))
+    # two level-0 duals whose cells span levels 0..4 (the rule's tie-break
+    # by centre vertex decides), interpolants 1.3% apart
+    assert len(alone) == 2 and alone[0][0][0] == alone[1][0][0] == 0
+    first = min(alone)
+    assert which[0] == first[2] and v[0] == first[1]
+    assert abs(alone[0][1] - alone[1][1]) > 1e-2 * abs(first[1])
+
+
+def test_dual_interpolant_on_shared_faces_of_a_grid():
+    # points on the faces, edges and vertices shared by the duals of a
+    # single-level grid are reached by 2, 4 or 8 duals, whose interpolants
+    # agree there: the value is the textbook trilinear one whichever wins
+    cs = amrgen.uniform_grid(5, 0, 3, origin=(2, -3, 7))
+    c = _centres(cs)
+    c0 = c.min(0)
+    lattice = np.full((5, 5, 5), np.nan)
+    ijk = np.rint(c - c0).astype(int)
+    lattice[ijk[:, 0], ijk[:, 1], ijk[:, 2]] = cs.value
+    rng = np.random.default_rng(4)
+    g = rng.uniform(0, 4, (120, 3))
+    k = np.arange(len(g))
+    on = rng.integers(1, 4, (len(g), 3)).astype(float)
+    g[k % 3 == 0, 0] = on[k % 3 == 0, 0]                 # faces
+    g[k % 3 == 1, :2] = on[k % 3 == 1, :2]               # edges
+    g[k % 3 == 2] = on[k % 3 == 2]                       # vertices
+    got, _, hits = oracle.dual_mesh_sample(cs.xyz, cs.level, cs.value, *_duals(cs), c0 + g)
+    assert np.all(hits[k % 3 == 0] == 2) and np.all(hits[k % 3 == 1] == 4) and np.all(hits[k % 3 == 2] == 8)
+    i0 = np.minimum(np.floor(g).astype(int), 3)
+    f = g - i0
+    want = np.zeros(len(g))
+    for dx, dy, dz in itertools.product((0, 1), repeat=3):
+        wt = (f[:, 0] if dx else 1 - f[:, 0]) * (f[:, 1] if dy else 1 - f[:, 1]) * (f[:, 2] if dz else 1 - f[:, 2])
+        want += wt * lattice[i0[:, 0] + dx, i0[:, 1] + dy, i0[:, 2] + dz]
+    assert np.max(np.abs(got - want)) < 1e-12
