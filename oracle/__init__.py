@@ -23,7 +23,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "amr_oracle.c")
-LIB = os.path.join(HERE, "liborc.so")
+# ORACLE_LIB names another build of amr_oracle.c to load (the sanitizer
+# test runs the pins against an AddressSanitizer + UBSan build)
+LIB = os.environ.get("ORACLE_LIB") or os.path.join(HERE, "liborc.so")
 
 OK, EINVAL, ERANGE, EOVERLAP, ENOSPACE = 0, -1, -2, -3, -4
 
@@ -47,7 +49,8 @@ def _load():
     with _lock:
         if _lib is not None:
             return _lib
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        if not os.environ.get("ORACLE_LIB") and (not os.path.exists(LIB) or
+                                                  os.path.getmtime(LIB) < os.path.getmtime(SRC)):
             build()
         L = C.CDLL(LIB)
         i64, i32p, f32p, i64p, vp = C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_float), C.POINTER(C.c_int64), C.c_void_p
