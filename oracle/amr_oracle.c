@@ -207,24 +207,34 @@ static int64_t snap(const orc_index* ix, int64_t n, const int32_t* xyz, const in
 /* Dual cells (rules 1-3)                                                    */
 /* ------------------------------------------------------------------------ */
 
-/* The dual centred on corner `delta` (bit 0 = x, 1 = y, 2 = z) of cell c.
-   Returns 1 and fills ids[8] (slot order) if the dual is emitted by c. */
+/* The dual centred on corner `delta` (bit 0 = x, 1 = y, 2 = z) of cell c
+   (paper sec. 4.2-4.4).  Its vertex cells are the cells holding the 8
+   points P + (e - 1) w around the corner P (slot s = ex + 2 ey + 4 ez).
+   Cell c emits the dual when
+     rule 1: every vertex exists (no hole around P),
+     rule 2: no vertex is finer than c (then a finer dual covers P),
+     rule 3: no vertex of c's level comes before c in (z, y, x) order of
+             lower corners (that vertex generates the dual instead).
+   Returns 1 and fills ids[8] (slot order) if c emits it. */
 static int dual_of_cell(const orc_index* ix, int64_t n, const int32_t* xyz, const int32_t* lvl, int64_t c,
                         int delta, int64_t P[3], int64_t ids[8]) {
-    int l = lvl[c];
-    int64_t w = (int64_t)1 << l;
-    int64_t d[3] = {delta & 1, (delta >> 1) & 1, (delta >> 2) & 1};
+    const int l = lvl[c];
+    const int64_t w = (int64_t)1 << l;
+    const int64_t d[3] = {delta & 1, (delta >> 1) & 1, (delta >> 2) & 1};
     for (int a = 0; a < 3; ++a) P[a] = (int64_t)xyz[3 * c + a] + d[a] * w;
+    int64_t v[8];
     for (int s = 0; s < 8; ++s) {
-        int64_t e[3] = {s & 1, (s >> 1) & 1, (s >> 2) & 1};
-        int64_t q[3];
-        for (int a = 0; a < 3; ++a) q[a] = P[a] + (e[a] - 1) * w;
-        int64_t v = snap(ix, n, xyz, lvl, q[0], q[1], q[2]);
-        if (v < 0) return 0;                                   /* rule 1 */
-        if (lvl[v] < l) return 0;                              /* rule 2 */
-        if (lvl[v] == l && cell_before(xyz, v, c)) return 0;   /* rule 3 */
-        ids[s] = v;
+        const int64_t e[3] = {s & 1, (s >> 1) & 1, (s >> 2) & 1};
+        v[s] = snap(ix, n, xyz, lvl, P[0] + (e[0] - 1) * w, P[1] + (e[1] - 1) * w, P[2] + (e[2] - 1) * w);
     }
+    int all_present = 1, none_finer = 1, none_before = 1;
+    for (int s = 0; s < 8; ++s) all_present = all_present && v[s] >= 0;
+    if (!all_present) return 0; /* rule 1 */
+    for (int s = 0; s < 8; ++s) none_finer = none_finer && lvl[v[s]] >= l;
+    if (!none_finer) return 0; /* rule 2 */
+    for (int s = 0; s < 8; ++s) none_before = none_before && !(lvl[v[s]] == l && cell_before(xyz, v[s], c));
+    if (!none_before) return 0; /* rule 3 */
+    for (int s = 0; s < 8; ++s) ids[s] = v[s];
     return 1;
 }
 
