@@ -272,9 +272,14 @@ def indexed_mesh(tris: np.ndarray, cells: np.ndarray):
 # Reading: each emitted dual is the trilinear hexahedron over its 8 vertex
 # cells' centres, slot s = ex + 2 ey + 4 ez at parameter u = (ex, ey, ez),
 # and carries the trilinear interpolant of their values.  A point's value
-# comes from a dual whose map reaches it with u in [0,1]^3 (Newton on the
-# trilinear map, fp64); points no dual reaches get NaN.  Degenerate duals
-# whose map has no volume reach no point.  Where several duals reach a
+# comes from a dual whose map reaches it with u in [0,1]^3; points no dual
+# reaches get NaN.  The map sends each corner of the unit cube to its slot's
+# cell centre exactly, so a dual reaches the centres of its vertex cells
+# (u = that corner, value = that cell's value); elsewhere Newton on the
+# trilinear map (fp64) finds u.  (Newton alone cannot settle a centre where
+# a degenerate dual's map is singular: there its outcome is decided by
+# rounding.)  Degenerate duals whose map has no volume reach no other
+# point.  Where several duals reach a
 # point (on shared faces, and inside overlapping duals, which exist when
 # the levels of a dual's cells span three or more), the one with the
 # smallest (level, P.z, P.y, P.x) wins: the finest dual, then the lowest
@@ -340,11 +345,18 @@ def dual_mesh_sample(xyz, level, value, pl, ids, points, eps: float = 1e-9):
     out = np.full(len(pts), np.nan)
     which = np.full(len(pts), -1, np.int64)
     hits = np.zeros(len(pts), np.int64)
+    corner = np.array([[s & 1, (s >> 1) & 1, s >> 2] for s in range(8)], np.float64)
     for q, p in enumerate(pts):
         cand = np.nonzero(np.all((lo <= p) & (p <= hi), 1))[0]
         if len(cand) == 0:
             continue
         u, ok = _invert(V[cand], np.broadcast_to(p, (len(cand), 3)))
+        # a dual with a vertex cell centred exactly at p reaches it at that
+        # slot's corner (the first such slot)
+        at = np.all(V[cand] == p, axis=2)  # [K, 8]
+        has = at.any(1)
+        u[has] = corner[np.argmax(at[has], axis=1)]
+        ok = ok | has
         inside = np.nonzero(ok & np.all((u >= -eps) & (u <= 1 + eps), 1))[0]
         hits[q] = len(inside)
         if len(inside):
