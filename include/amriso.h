@@ -186,14 +186,16 @@ int amr_isosurface(amr_set* set, float iso, float* tris, int32_t* tri_cells, int
 
 /* ---------------------------------------------------------------------------
    Batched iso-surfaces (many iso-values and/or many sets in one launch).
-   Topology is iso-independent (paper sec. 4: the dual cells do not depend on
-   the field), so each set's dual cells are computed once with amr_dual_cells
-   and every job runs Marching Cubes (paper sec. 5) over that list.  One
-   persistent kernel handles all jobs: a counting phase, a per-job scan over
-   tiles and a writing phase, separated by grid-wide barriers.  For a job on
-   set s with iso v, the triangles, their order and every bit of their
-   positions equal those of amr_isosurface(s, v) (no cell pairs / dual
-   indices are written here).
+   The dual cells do not depend on the field (paper sec. 4), so a batched
+   launch reads each tile of a set's groups and their neighbourhoods once
+   per phase and runs Marching Cubes (paper sec. 5) for every job on that
+   set against them; groups whose neighbourhood value range straddles no
+   job's iso are skipped (before their neighbourhood is read when the set
+   has recorded ranges, see amr_isosurface).  One persistent kernel handles
+   all jobs: a counting phase, a per-job scan over tiles and a writing
+   phase, separated by grid-wide barriers.  For a job on set s with iso v,
+   the triangles, their order and every bit of their positions equal those
+   of amr_isosurface(s, v) (no cell pairs or dual indices are written here).
    --------------------------------------------------------------------------- */
 
 typedef struct amr_batch amr_batch; /* opaque, library-owned host handle */
@@ -201,42 +203,44 @@ typedef struct amr_batch amr_batch; /* opaque, library-owned host handle */
 /* One job of a batch; the array of jobs lives in device memory, so iso-values
    can be changed between launches (e.g. between replays of a HIP graph). */
 typedef struct amr_iso_job {
-    float iso;          /* iso-value (finite) */
-    int32_t set;        /* index into the batch's sets */
+    float iso;          /* iso-value (finite; otherwise the job counts -1) */
+    int32_t set;        /* index into the batch's sets (otherwise the job counts -1) */
     int64_t out_offset; /* first triangle slot of this job in the output */
     int64_t out_cap;    /* triangles this job may write (more are counted only) */
 } amr_iso_job;
 
-/* Create a batch over n_sets indexed sets.  dual_verts[i] and dual_vals[i]
-   are the device int32 / float [n_duals[i]][8] lists written by
-   amr_dual_cells for sets[i] (caller-owned, kept alive and unchanged with
-   the set's input arrays).  Allocates a small device table (freed by
-   amr_batch_destroy); synchronous.  Returns AMR_ESTATE if a set has no
-   index, AMR_EINVAL for bad arguments. */
-int amr_batch_create(amr_batch** out, amr_set* const* sets, const int32_t* const* dual_verts,
-                     const float* const* dual_vals, const int64_t* n_duals, int n_sets);
+/* Create a batch over n_sets (1..256) indexed sets of one device.  The
+   batch reads each set's index in place: the sets must not be uploaded or
+   built again while the batch is used.  Allocates a small device table
+   (freed by amr_batch_destroy); synchronous.  Returns AMR_ESTATE if a set
+   has no index, AMR_EINVAL for bad arguments. */
+int amr_batch_create(amr_batch** out, amr_set* const* sets, int n_sets);
 
 void amr_batch_destroy(amr_batch* batch);
 
 /* Device workspace bytes for up to max_jobs jobs with `block` threads per
-   work-group and `per_thread` duals per thread (tile = block * per_thread). */
-int amr_batch_workspace_bytes(const amr_batch* batch, int max_jobs, int block, int per_thread, size_t* bytes);
+   work-group (128 or 256: tiles of 16 or 32 groups of 2x2x2 cells, eight
+   threads each) and `per_cu` (1..4) work-groups per compute unit (the
+   persistent grid, capped at what the kernel's occupancy allows):
+   2 x 4 bytes per (job, tile of the largest set) plus 16 KB. */
+int amr_batch_workspace_bytes(const amr_batch* batch, int max_jobs, int block, int per_cu, size_t* bytes);
 
 /* Enqueue one persistent launch for n_jobs jobs (1 <= n_jobs <= 256).
      jobs      device amr_iso_job [n_jobs]
      tris      device float [..][3][3]: job j writes triangles
                out_offset .. out_offset + min(count, out_cap) - 1
-     counts    device int64 [n_jobs]: full triangle count of each job
-     workspace device, >= amr_batch_workspace_bytes(n_jobs, block,
-               per_thread), 256-byte aligned, zero-filled before its first
-               use; it holds the grid barrier, so launches that share a
-               workspace, and batched launches on one GPU, must not overlap
-               in time.  Its bytes 8..11 become non-zero if a barrier wait
-               ever gave up (the results of that launch are then invalid).
-     block     64, 128, 256 or 512;  per_thread 1, 2 or 4
+     counts    device int64 [n_jobs]: full triangle count of each job (-1
+               for an invalid job or a set whose build failed)
+     workspace device, >= amr_batch_workspace_bytes(n_jobs, block, per_cu),
+               256-byte aligned, zero-filled before its first use; it holds
+               the grid barrier, so launches that share a workspace, and
+               batched launches on one GPU, must not overlap in time.  Its
+               bytes 8..11 become non-zero if a barrier wait ever gave up
+               (the results of that launch are then invalid).
+     block     128 or 256;  per_cu 1..4
    No host synchronisation: capturable in a HIP graph. */
 int amr_batch_isosurface(amr_batch* batch, const amr_iso_job* jobs, int n_jobs, float* tris, int64_t* counts,
-                         void* workspace, size_t bytes, int block, int per_thread, hipStream_t stream);
+                         void* workspace, size_t bytes, int block, int per_cu, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
    Indexed face set (paper sec. 5.2): the fat triangles share vertices; each
@@ -265,6 +269,60 @@ int amr_indexed_mesh(const float* tris, const int32_t* tri_cells, int64_t n_tris
                      int64_t cap_verts, int64_t* n_verts, void* workspace, size_t bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+   Dual-mesh interpolant.  The paper names the dual mesh as an interpolant of
+   the cell values (sec. 5, after Moran et al.) and leaves volume rendering
+   over it to future work (sec. 7) without defining the interpolant.  Here a
+   dual (from amr_dual_cells) is the trilinear hexahedron over the centres
+   of its 8 vertex cells, slot s = ex + 2*ey + 4*ez at parameter
+   (ex, ey, ez), carrying the trilinear interpolant of their values.  A
+   point takes the value of the dual whose map reaches it; where several
+   reach it (shared faces, and duals that overlap when their cells span
+   three or more levels) the dual with the smallest (level, P.z, P.y, P.x)
+   wins.  The map sends each cube corner to its slot's cell centre exactly,
+   so a dual reaches the centres of its vertex cells (there the value is
+   that cell's).  The candidates of a point are the duals having the point's
+   cell as a vertex; elsewhere the inverse map is Newton's method in float64 from the
+   dual's centre (40 steps, each clamped to [-1/2, 3/2] per axis), and a
+   dual reaches the point when every Jacobian on the way had |det| > 1e-14,
+   the final residual is below 1e-9 and the parameter lies in
+   [-1e-9, 1 + 1e-9] on every axis.
+   --------------------------------------------------------------------------- */
+
+/* Workspace bytes of a sampler over n_duals duals of the set's n cells
+   (host-only): int64 [n+1] list offsets, uint32 [n] counters, uint32
+   [8*n_duals] lists, a few KB of scan sums.  AMR_ERANGE for n_duals outside
+   [0, 2^32). */
+int amr_sampler_bytes(const amr_set* set, int64_t n_duals, size_t* bytes);
+
+/* Build the map from every cell to the duals that have it as a vertex.
+     verts     device int32 [n_duals][8]: vertex cells of the duals, as
+               amr_dual_cells writes them (entries outside [0, n) are ignored)
+     workspace device, >= amr_sampler_bytes(n_duals), 256-byte aligned; no
+               initial contents needed; owned by the caller and read by
+               amr_sample
+   Asynchronous, no host synchronisation.  The sampler stays valid until the
+   set is uploaded or built again.  Returns AMR_ESTATE before
+   amr_build_index, AMR_ENOSPACE for a short workspace. */
+int amr_sampler_build(amr_set* set, const int32_t* verts, int64_t n_duals, void* workspace, size_t bytes,
+                      hipStream_t stream);
+
+/* Interpolated values at n_points points.
+     corner_level, verts  device int32 [n_duals][4], [n_duals][8]: the same
+               dual list the sampler was built over (unchanged since)
+     workspace the sampler's workspace (amr_sampler_build)
+     points    device float [n_points][3], in finest-level units (the
+               coordinates of the cells)
+     values    device float [n_points]: the interpolant evaluated in float64
+               and rounded to float32; NaN where no dual reaches the point
+     dual      device int64 [n_points] or NULL: index of the winning dual in
+               the list, -1 where none
+   Asynchronous, no host synchronisation.  Returns AMR_ESTATE when no
+   sampler was built for the current index, AMR_EINVAL for bad arguments. */
+int amr_sample(amr_set* set, const int32_t* corner_level, const int32_t* verts, int64_t n_duals,
+               const void* workspace, size_t bytes, const float* points, int64_t n_points, float* values,
+               int64_t* dual, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
    Measurement: HIP events around one kernel.  The next launch of the named
    kernel for this set is made with hipExtLaunchKernelGGL, which records
    `start` just before the kernel runs and `stop` just after it, on the
@@ -279,7 +337,8 @@ enum amr_kernel {
     AMR_KERNEL_COMPACT = 4,  /* group list of the table (amr_build_index) */
     AMR_KERNEL_MARK = 5,     /* ancestor marks and the build's verdict (amr_build_index) */
     AMR_KERNEL_EXTRACT = 6,  /* first extraction pass of a call: the fused pass or the count pass */
-    AMR_KERNEL_WRITE = 7     /* write pass of a call that has one */
+    AMR_KERNEL_WRITE = 7,    /* write pass of a call that has one */
+    AMR_KERNEL_SAMPLE = 8    /* point queries of amr_sample */
 };
 
 int amr_time_kernel(amr_set* set, int kernel, hipEvent_t start, hipEvent_t stop);

@@ -24,11 +24,12 @@ _NAMES = {0: "AMR_OK", -1: "AMR_EINVAL", -2: "AMR_ERANGE", -3: "AMR_EOVERLAP", -
 ABI_SYMBOLS = ("amr_create", "amr_destroy", "amr_upload", "amr_index_bytes", "amr_build_index", "amr_build_status",
                "amr_dual_cells",
                "amr_isosurface", "amr_batch_create", "amr_batch_destroy", "amr_batch_workspace_bytes",
-               "amr_batch_isosurface", "amr_indexed_mesh_bytes", "amr_indexed_mesh", "amr_time_kernel",
-               "amr_last_error")
+               "amr_batch_isosurface", "amr_indexed_mesh_bytes", "amr_indexed_mesh", "amr_sampler_bytes",
+               "amr_sampler_build", "amr_sample", "amr_time_kernel", "amr_last_error")
 
 # amr_kernel: kernels amr_time_kernel can bracket with events
-KERNEL_UPLOAD, KERNEL_RESET, KERNEL_INSERT, KERNEL_COMPACT, KERNEL_MARK, KERNEL_EXTRACT, KERNEL_WRITE = range(1, 8)
+(KERNEL_UPLOAD, KERNEL_RESET, KERNEL_INSERT, KERNEL_COMPACT, KERNEL_MARK, KERNEL_EXTRACT, KERNEL_WRITE,
+ KERNEL_SAMPLE) = range(1, 9)
 
 _lib = None
 
@@ -65,8 +66,7 @@ def load_library(path: str = LIB_PATH):
     L.amr_dual_cells.restype = C.c_int
     L.amr_isosurface.argtypes = [vp, C.c_float, f32p, i32p, i32p, i64, i64p, vp]
     L.amr_isosurface.restype = C.c_int
-    L.amr_batch_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
-                                   C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.c_int]
+    L.amr_batch_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int]
     L.amr_batch_create.restype = C.c_int
     L.amr_batch_destroy.argtypes = [vp]
     L.amr_batch_destroy.restype = None
@@ -78,6 +78,12 @@ def load_library(path: str = LIB_PATH):
     L.amr_indexed_mesh_bytes.restype = C.c_int
     L.amr_indexed_mesh.argtypes = [f32p, i32p, i64, f32p, i32p, i64, i64p, vp, C.c_size_t, vp]
     L.amr_indexed_mesh.restype = C.c_int
+    L.amr_sampler_bytes.argtypes = [vp, i64, C.POINTER(C.c_size_t)]
+    L.amr_sampler_bytes.restype = C.c_int
+    L.amr_sampler_build.argtypes = [vp, i32p, i64, vp, C.c_size_t, vp]
+    L.amr_sampler_build.restype = C.c_int
+    L.amr_sample.argtypes = [vp, i32p, i32p, i64, vp, C.c_size_t, f32p, i64, f32p, i64p, vp]
+    L.amr_sample.restype = C.c_int
     L.amr_time_kernel.argtypes = [vp, C.c_int, vp, vp]
     L.amr_time_kernel.restype = C.c_int
     L.amr_last_error.argtypes = []
@@ -266,6 +272,47 @@ class AmrSet:
         return out
 
 
+class DualSampler:
+    """The dual mesh of a set as an interpolant (amr_sampler_build,
+    amr_sample): each dual is the trilinear hexahedron over its cells'
+    centres carrying the trilinear interpolant of their values; a point takes
+    the value of the reaching dual with the smallest (level, P.z, P.y, P.x),
+    NaN where none reaches it.  Valid until the set is uploaded or built
+    again."""
+
+    def __init__(self, s: AmrSet, corner_level=None, verts=None):
+        self.lib = load_library()
+        self.set = s
+        if corner_level is None or verts is None:
+            corner_level, verts = s.dual_cells()
+        self.corner_level = corner_level.contiguous()
+        self.verts = verts.contiguous()
+        self.m = int(self.verts.shape[0])
+        b = C.c_size_t(0)
+        _check(self.lib.amr_sampler_bytes(s._h, self.m, C.byref(b)))
+        self.workspace = torch.empty(max(int(b.value), 256), dtype=torch.uint8, device=s.device)
+        _check(self.lib.amr_sampler_build(s._h, _ptr(self.verts), self.m, _ptr(self.workspace),
+                                          self.workspace.numel(), _stream(s.device)))
+
+    def sample_into(self, points, values, dual=None):
+        """Enqueue the queries of points float32 [Q,3] into values float32
+        [Q] (and dual int64 [Q]); no synchronisation."""
+        n = int(points.shape[0])
+        _check(self.lib.amr_sample(self.set._h, _ptr(self.corner_level), _ptr(self.verts), self.m,
+                                   _ptr(self.workspace), self.workspace.numel(), _ptr(points), n, _ptr(values),
+                                   _ptr(dual), _stream(self.set.device)))
+        return values
+
+    def sample(self, points):
+        """(values float32 [Q], dual int64 [Q]) at points float32 [Q,3]."""
+        points = points.to(device=self.set.device, dtype=torch.float32).contiguous()
+        n = int(points.shape[0])
+        values = torch.empty(max(n, 1), dtype=torch.float32, device=self.set.device)
+        dual = torch.empty(max(n, 1), dtype=torch.int64, device=self.set.device)
+        self.sample_into(points, values, dual)
+        return values[:n], dual[:n]
+
+
 # amr_iso_job: float iso, int32 set, int64 out_offset, int64 out_cap (24 bytes)
 JOB_DTYPE = None
 
@@ -281,26 +328,27 @@ def _job_dtype():
 
 
 class AmrBatch:
-    """Many (set, iso) jobs in one persistent launch over the sets' dual cell
-    lists (computed once per set with amr_dual_cells)."""
+    """Many (set, iso) jobs in one persistent launch (amr_batch_isosurface):
+    each tile of a set's groups reads its neighbourhoods once per phase and
+    runs Marching Cubes for every job on that set.  The sets must not be
+    uploaded or built again while the batch is used.  Launch shape: `block`
+    threads per work-group (128 or 256) and `per_cu` work-groups per
+    compute unit (1..4)."""
 
     def __init__(self, sets):
         self.lib = load_library()
         self.sets = list(sets)
         self.device = self.sets[0].device
-        self.duals = []
-        for s in self.sets:
-            _, vv, va = s.dual_cells(values=True)
-            self.duals.append((vv, va))
         n = len(self.sets)
         hs = (C.c_void_p * n)(*[s._h.value for s in self.sets])
-        dv = (C.c_void_p * n)(*[d[0].data_ptr() for d in self.duals])
-        dw = (C.c_void_p * n)(*[d[1].data_ptr() for d in self.duals])
-        nd = (C.c_int64 * n)(*[int(d[0].shape[0]) for d in self.duals])
         h = C.c_void_p()
-        _check(self.lib.amr_batch_create(C.byref(h), hs, dv, dw, nd, n))
+        _check(self.lib.amr_batch_create(C.byref(h), hs, n))
         self._h = h
         self._ws = {}
+
+    @property
+    def cells(self) -> int:
+        return sum(s.n for s in self.sets)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -314,11 +362,11 @@ class AmrBatch:
         except Exception:
             pass
 
-    def workspace(self, n_jobs: int, block: int = 256, per_thread: int = 1):
+    def workspace(self, n_jobs: int, block: int = 256, per_cu: int = 2):
         """Zero-filled workspace (cached per launch shape)."""
         b = C.c_size_t(0)
-        _check(self.lib.amr_batch_workspace_bytes(self._h, n_jobs, block, per_thread, C.byref(b)))
-        key = (block, per_thread)
+        _check(self.lib.amr_batch_workspace_bytes(self._h, n_jobs, block, per_cu, C.byref(b)))
+        key = (block, per_cu)
         ws = self._ws.get(key)
         if ws is None or ws.numel() < b.value:
             ws = torch.zeros(max(int(b.value), 256), dtype=torch.uint8, device=self.device)
@@ -335,27 +383,27 @@ class AmrBatch:
         arr["out_cap"] = np.asarray(caps, np.int64)
         return torch.from_numpy(arr.view(np.uint8)).to(self.device)
 
-    def run_into(self, jobs, n_jobs: int, tris, counts, block: int = 256, per_thread: int = 1, workspace=None):
+    def run_into(self, jobs, n_jobs: int, tris, counts, block: int = 256, per_cu: int = 2, workspace=None):
         """Enqueue one launch (no synchronisation); capturable in a graph."""
-        ws = workspace if workspace is not None else self.workspace(n_jobs, block, per_thread)
+        ws = workspace if workspace is not None else self.workspace(n_jobs, block, per_cu)
         _check(self.lib.amr_batch_isosurface(self._h, _ptr(jobs), int(n_jobs), _ptr(tris), _ptr(counts), _ptr(ws),
-                                             ws.numel(), int(block), int(per_thread), _stream(self.device)))
+                                             ws.numel(), int(block), int(per_cu), _stream(self.device)))
         return counts
 
-    def barrier_timed_out(self, block: int = 256, per_thread: int = 1) -> bool:
+    def barrier_timed_out(self, block: int = 256, per_cu: int = 2) -> bool:
         """True if a grid-barrier wait of a launch with this workspace gave up
         (bytes 8..11 of the workspace; that launch's results are invalid)."""
-        ws = self._ws.get((block, per_thread))
+        ws = self._ws.get((block, per_cu))
         return ws is not None and bool(ws[8:12].any().item())
 
-    def reset_barrier(self, block: int = 256, per_thread: int = 1):
+    def reset_barrier(self, block: int = 256, per_cu: int = 2):
         """Clear the grid barrier (arrival count, sense, time-out flag) of this
         workspace after a time-out, before its next launch."""
-        ws = self._ws.get((block, per_thread))
+        ws = self._ws.get((block, per_cu))
         if ws is not None:
             ws[:16].zero_()
 
-    def isosurface(self, set_idx, isos, block: int = 256, per_thread: int = 1):
+    def isosurface(self, set_idx, isos, block: int = 256, per_cu: int = 2):
         """List of float32 [T_j, 9] triangle tensors, one per job: a count
         launch sizes the output, a second launch writes it."""
         import numpy as np
@@ -363,14 +411,17 @@ class AmrBatch:
         n = len(isos)
         counts = torch.zeros(n, dtype=torch.int64, device=self.device)
         jobs = self.jobs_tensor(set_idx, isos, np.zeros(n), np.zeros(n))
-        self.run_into(jobs, n, None, counts, block, per_thread)
+        self.run_into(jobs, n, None, counts, block, per_cu)
         c = counts.cpu().numpy()
+        if (c < 0).any():
+            raise AmrError(AMR_EINVAL, "batched launch: job(s) %s are invalid or on a failed build"
+                           % np.nonzero(c < 0)[0].tolist())
         off = np.concatenate([[0], np.cumsum(c)[:-1]])
         tris = torch.empty((max(int(c.sum()), 1), 9), dtype=torch.float32, device=self.device)
         jobs = self.jobs_tensor(set_idx, isos, off, c)
-        self.run_into(jobs, n, tris, counts, block, per_thread)
+        self.run_into(jobs, n, tris, counts, block, per_cu)
         torch.cuda.synchronize(self.device)
-        if self.barrier_timed_out(block, per_thread):
+        if self.barrier_timed_out(block, per_cu):
             raise AmrError(AMR_EHIP, "batched launch: a grid barrier wait gave up")
         return [tris[int(o):int(o) + int(k)] for o, k in zip(off, c)]
 

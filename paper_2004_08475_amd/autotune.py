@@ -1,7 +1,8 @@
 """Launch-shape autotuner for batched iso-surfaces.
 
-Times every (threads per work-group, duals per thread) shape the library
-accepts on the caller's actual batch, keeps the fastest, and caches the
+Times every (threads per work-group, work-groups per compute unit) shape
+the library accepts on the caller's actual batch, keeps the fastest, and
+caches the
 choice in a JSON file keyed by GPU architecture and batch shape, so later
 processes skip the search.  Cache path: $AMRISO_TUNE_CACHE, else
 ~/.cache/amriso/autotune.json.
@@ -15,7 +16,7 @@ import threading
 
 import torch
 
-SHAPES = ((64, 1), (128, 1), (256, 1), (512, 1), (128, 2), (256, 2), (64, 4), (128, 4))
+SHAPES = ((128, 1), (128, 2), (128, 3), (256, 1), (256, 2), (256, 3), (256, 4))
 _lock = threading.Lock()
 
 
@@ -26,9 +27,9 @@ def cache_path() -> str:
 
 def _key(batch, n_jobs: int) -> str:
     arch = torch.cuda.get_device_properties(batch.device).gcnArchName.split(":")[0]
-    duals = sum(int(d[0].shape[0]) for d in batch.duals)
-    bucket = 0 if duals == 0 else int(round(math.log2(duals)))
-    return "%s|sets=%d|duals=2^%d|jobs=%d" % (arch, len(batch.sets), bucket, n_jobs)
+    cells = batch.cells
+    bucket = 0 if cells == 0 else int(round(math.log2(cells)))
+    return "%s|tiles-v2|sets=%d|cells=2^%d|jobs=%d" % (arch, len(batch.sets), bucket, n_jobs)
 
 
 def _load() -> dict:
@@ -65,13 +66,13 @@ def time_shape(batch, jobs, n_jobs, tris, counts, block, per, reps=5):
 
 
 def tune(batch, jobs, n_jobs, tris, counts, reps=5, use_cache=True):
-    """(block, per_thread, table of timings) for this batch and job list."""
+    """(block, per_cu, table of timings) for this batch and job list."""
     key = _key(batch, n_jobs)
     with _lock:
         table = _load() if use_cache else {}
         hit = table.get(key)
     if hit:
-        return int(hit["block"]), int(hit["per_thread"]), hit.get("ms", {})
+        return int(hit["block"]), int(hit["per_cu"]), hit.get("ms", {})
     ms = {}
     for block, per in SHAPES:
         ms["%dx%d" % (block, per)] = time_shape(batch, jobs, n_jobs, tris, counts, block, per, reps)
@@ -80,6 +81,6 @@ def tune(batch, jobs, n_jobs, tris, counts, reps=5, use_cache=True):
     if use_cache:
         with _lock:
             table = _load()
-            table[key] = {"block": block, "per_thread": per, "ms": ms}
+            table[key] = {"block": block, "per_cu": per, "ms": ms}
             _store(table)
     return block, per, ms

@@ -113,7 +113,7 @@ struct UpRes {
 };
 
 // Device control block, one per set (library-allocated).  The build's
-// verdict (`status`) is decided on the device by the last work-group of the
+// verdict (`status`) is decided on the device by a one-lane kernel after the
 // ancestor marking; extraction kernels read it, the group count and the
 // geometry from here, so nothing of the build has to reach the host before
 // the next call is enqueued.
@@ -125,8 +125,7 @@ struct Ctrl {
     uint32_t dup;
     uint32_t overlap;
     int32_t status;                // AMR_OK or the build's error code (kStatusPending meanwhile)
-    uint32_t mark_done;            // work-groups of the marking pass that have finished
-    uint32_t pad1;
+    uint32_t pad1[2];
     unsigned long long bad_build;
     unsigned long long n_groups;   // written by the compaction's last tile
     unsigned long long n_records;
@@ -159,7 +158,12 @@ __device__ __forceinline__ uint64_t group_key(int m, uint32_t gx, uint32_t gy, u
 // keeps every aligned run of 2^k Morton codes together, so 32 consecutive
 // slots hold a 4x4x2 block of groups and consecutive runs are neighbours in
 // space.  A collision moves on to the same position of the next region
-// (probe stride 4096).
+// (probe stride 4096); once every region has been tried at that position
+// (the step count a multiple of cap / 4096), the position moves on by one,
+// so the probe sequence covers the whole table before it repeats.  (With
+// the stride alone a small table has few regions, and a position taken in
+// all of them left keys without a slot and lookups cycling through the same
+// few slots until the step limit.)
 constexpr uint32_t kRegion = 4096;
 
 __device__ __forceinline__ uint32_t spread4(uint32_t v) {
@@ -174,7 +178,12 @@ __device__ __forceinline__ uint32_t slot_of(uint64_t key, int shift) {
     return (uint32_t)((region * kGolden) >> shift) ^ local;
 }
 
-__device__ __forceinline__ uint32_t next_slot(uint32_t h, uint32_t mask) { return (h + kRegion) & mask; }
+// The slot after h, the step-th slot of a probe sequence (step 0 = home).
+__device__ __forceinline__ uint32_t next_slot(uint32_t h, uint32_t step, uint32_t mask) {
+    uint32_t n = (h + kRegion) & mask;
+    if (((step + 1) & (mask >> 12)) == 0) n = (n & ~(kRegion - 1)) | ((n + 1) & (kRegion - 1));
+    return n;
+}
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
@@ -209,7 +218,7 @@ __device__ __forceinline__ int probe(const Record* __restrict__ rec, uint64_t ke
         uint64_t k = rec[h].key;
         if (k == key) return (int)h;
         if (k == kEmpty) return -1;
-        h = next_slot(h, mask);
+        h = next_slot(h, i, mask);
     }
     return -1;
 }
@@ -322,7 +331,6 @@ __global__ void k_ctrl_reset(Ctrl* c) {
         c->dup = 0;
         c->overlap = 0;
         c->status = kStatusPending;
-        c->mark_done = 0;
         c->bad_build = ~0ull;
         c->n_groups = 0;
         c->n_records = 0;
@@ -546,7 +554,6 @@ __global__ __launch_bounds__(256) void k_build_reset(Record* __restrict__ rec, u
         c->dup = 0;
         c->overlap = 0;
         c->status = kStatusPending;
-        c->mark_done = 0;
         c->bad_build = ~0ull;
         c->n_groups = 0;
         c->n_records = 0;
@@ -578,7 +585,7 @@ __device__ __forceinline__ int find_or_insert(Record* __restrict__ rec, uint64_t
             if (prev == kEmpty && created) ++*created;
             if (prev == kEmpty || prev == key) return (int)h;
         }
-        h = next_slot(h, g.mask);
+        h = next_slot(h, step, g.mask);
     }
     return -1;
 }
@@ -628,20 +635,13 @@ __global__ __launch_bounds__(256) void k_index_ids(const int32_t* __restrict__ x
 // before this pass, so a mark that lands on a leaf is a coarser cell
 // containing finer ones.  The pass runs over the compacted group list (the
 // compaction's count is on the device), and counts the marker-only records
-// it creates, one atomic per work-group into one of 64 replicas.  The last
-// work-group to finish decides the build's verdict on the device: the
-// upload's error, a table too full (a failed insertion, more than 3/4 of the
-// slots in use, or more groups than the `max_groups` the extraction grids
-// are sized for), a coarser cell containing finer ones, or fewer leaves than
-// cells (a duplicate overwrote its twin).
+// it creates, one atomic per work-group into one of 64 replicas.
 __global__ __launch_bounds__(256) void k_index_mark(Record* __restrict__ rec,
-                                                    const unsigned long long* __restrict__ gkey, int64_t n,
-                                                    uint32_t cap, uint32_t max_groups, Ctrl* c) {
+                                                    const unsigned long long* __restrict__ gkey, Ctrl* c) {
     __shared__ uint32_t s_made;
-    __shared__ bool s_last;
-    const bool ok = c->res.status == AMR_OK;
+    if (c->res.status != AMR_OK) return;
     const Geo g = c->geo;
-    const uint32_t ng = ok ? (uint32_t)c->n_groups : 0u;
+    const uint32_t ng = (uint32_t)c->n_groups;
     if (threadIdx.x == 0) s_made = 0;
     __syncthreads();
     uint32_t made = 0;
@@ -681,28 +681,30 @@ __global__ __launch_bounds__(256) void k_index_mark(Record* __restrict__ rec,
     made = (uint32_t)wave_reduce((unsigned long long)made,
                                  [](unsigned long long x, unsigned long long y) { return x + y; });
     if (lane_id() == 0 && made) atomicAdd(&s_made, made);
-    __threadfence();  // every lane's flags and marks have landed before the count below
     __syncthreads();
-    if (threadIdx.x == 0) {
-        if (s_made) atomicAdd(&c->made[(blockIdx.x % kReplicas) * 16], (unsigned long long)s_made);
-        // everything this work-group did is visible before it counts itself out
-        const uint32_t done =
-            __hip_atomic_fetch_add(&c->mark_done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = done == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!s_last || threadIdx.x != 0) return;
+    if (threadIdx.x == 0 && s_made) atomicAdd(&c->made[(blockIdx.x % kReplicas) * 16], (unsigned long long)s_made);
+}
+
+// The build's verdict, decided on the device by one lane after the marking:
+// the upload's error, a table too full (a failed insertion, more than 3/4
+// of the slots in use, or more groups than the `max_groups` the extraction
+// grids are sized for), a coarser cell containing finer ones, or fewer
+// leaves than cells (a duplicate overwrote its twin).  A kernel of its own:
+// a last-work-group test inside the marking pass costs one device-scope
+// atomic per work-group on one address, serialised across the XCDs (1.8 ms
+// for the 16384 work-groups of a 50M-cell set).
+__global__ void k_index_verdict(int64_t n, uint32_t cap, uint32_t max_groups, Ctrl* c) {
+    if (threadIdx.x != 0) return;
     int32_t st = c->res.status;
     if (st == AMR_OK) {
-        auto ld32 = [](const uint32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
         unsigned long long recs = c->n_records;  // records at compaction time: the groups
-        for (int r = 0; r < kReplicas; ++r) recs += ld_relaxed(&c->made[r * 16]);
-        if (ld32(&c->overflow) || recs * 4 > (unsigned long long)cap * 3 || c->n_groups > max_groups)
+        for (int r = 0; r < kReplicas; ++r) recs += c->made[r * 16];
+        if (c->overflow || recs * 4 > (unsigned long long)cap * 3 || c->n_groups > max_groups)
             st = AMR_ENOSPACE;
-        else if (ld32(&c->overlap) || c->n_leaves != (unsigned long long)n) st = AMR_EOVERLAP;
+        else if (c->overlap || c->n_leaves != (unsigned long long)n)
+            st = AMR_EOVERLAP;
     }
-    c->mark_done = 0;
-    __hip_atomic_store(&c->status, st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    c->status = st;
 }
 
 // Error path only: the lowest input index whose entry was overwritten by a
@@ -918,6 +920,309 @@ __device__ __forceinline__ uint32_t keep_by_classes(uint32_t cls, unsigned long 
 }
 
 
+// Phase 1 of a tile for one group (called by its eight lanes, j = 0..7):
+// the level-m cells of the 4x4x4 block around the group (offsets -1..2
+// from its lower corner, x fastest) into the group's LDS rows: value, cell
+// reference (slot * 8 + child), level of the cell that covers the position
+// (-1: none).  kWalk home slots of coarser levels are read at once when a
+// neighbour block holds no level-m record.
+template <int kWalk>
+__device__ __forceinline__ void load_neighbourhood(const Record* __restrict__ rec, const Geo& g, const int j,
+                                                   const int m, const uint32_t gx, const uint32_t gy,
+                                                   const uint32_t gz, const int own, float* sv, int32_t* sr,
+                                                   int8_t* sl) {
+    // lane j owns neighbours j, j+8, j+16 (and j+24 for j < 3); the home
+    // slots of all of them are loaded before any is examined
+    uint64_t want[4], got[4];
+    uint32_t home[4];
+    float4 va[4], vb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int dd = j + 8 * q;
+        if (dd >= 27) continue;
+        int dx = dd % 3 - 1, dy = (dd / 3) % 3 - 1, dz = dd / 9 - 1;
+        want[q] = group_key(m, gx + dx, gy + dy, gz + dz);
+        home[q] = dd == 13 ? (uint32_t)own : slot_of(want[q], g.shift);
+        const Record* r = rec + home[q];
+        va[q] = reinterpret_cast<const float4*>(r->val)[0];
+        vb[q] = reinterpret_cast<const float4*>(r->val)[1];
+        got[q] = r->key;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int dd = j + 8 * q;
+        if (dd >= 27) continue;
+        int lv = -1, ref = -1;
+        uint32_t h = home[q];
+        uint64_t k = got[q];
+        float4 xa = va[q], xb = vb[q];
+        if (k != want[q] && k != kEmpty) {
+            for (uint32_t step = 0; k != want[q] && k != kEmpty && step <= g.mask; ++step) {
+                h = next_slot(h, step, g.mask);
+                k = rec[h].key;
+            }
+            if (k == want[q]) {
+                xa = reinterpret_cast<const float4*>(rec[h].val)[0];
+                xb = reinterpret_cast<const float4*>(rec[h].val)[1];
+            }
+        }
+        float cv = 0.f;
+        const bool hit = k == want[q];
+        if (hit) {
+            lv = m;
+        } else {
+            // The block holds neither cells of level m nor finer cells (either
+            // would have left a record): it lies inside a coarser cell or in a
+            // hole.  The first record found going up decides; kWalk levels
+            // are read per memory round trip.
+            int dx = dd % 3 - 1, dy = (dd / 3) % 3 - 1, dz = dd / 9 - 1;
+            uint32_t bx = gx + dx, by = gy + dy, bz = gz + dz;
+            // Each level's home slot is read with the one child value the
+            // block would need there (same line), so a record found at its
+            // home slot costs no further round trip.
+            int found_l = -1, found_h = -1, found_c = 0;
+            float found_v = 0.f;
+            for (int L0 = m + 1; L0 <= g.lmax && found_l < 0; L0 += kWalk) {
+                uint64_t wk[kWalk], kk[kWalk];
+                uint32_t hh[kWalk];
+                int ch[kWalk];
+                float vv[kWalk];
+#pragma unroll
+                for (int u = 0; u < kWalk; ++u) {
+                    const int L = L0 + u, sh = L - m - 1;
+                    wk[u] = group_key(L, bx >> (sh + 1), by >> (sh + 1), bz >> (sh + 1));
+                    hh[u] = slot_of(wk[u], g.shift);
+                    ch[u] = ((bx >> sh) & 1) | (((by >> sh) & 1) << 1) | (((bz >> sh) & 1) << 2);
+                    kk[u] = kEmpty;
+                    vv[u] = 0.f;
+                    if (L <= g.lmax) {
+                        kk[u] = rec[hh[u]].key;
+                        vv[u] = rec[hh[u]].val[ch[u]];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kWalk; ++u) {
+                    if (found_l >= 0 || L0 + u > g.lmax) continue;
+                    uint32_t h2 = hh[u];
+                    uint64_t k2 = kk[u];
+                    float v2 = vv[u];
+                    if (k2 != wk[u] && k2 != kEmpty) {
+                        for (uint32_t step = 0; k2 != wk[u] && k2 != kEmpty && step <= g.mask; ++step) {
+                            h2 = next_slot(h2, step, g.mask);
+                            k2 = rec[h2].key;
+                        }
+                        if (k2 == wk[u]) v2 = rec[h2].val[ch[u]];
+                    }
+                    if (k2 == wk[u]) {
+                        found_l = L0 + u;
+                        found_h = (int)h2;
+                        found_c = ch[u];
+                        found_v = v2;
+                    }
+                }
+            }
+            // the lowest level with a record decides (a NaN there: finer
+            // cells or none at all, either way no cell covers this block)
+            if (found_l >= 0 && found_v == found_v) {
+                lv = found_l;
+                ref = found_h * 8 + found_c;
+                cv = found_v;
+            }
+        }
+        // the cells of this neighbour that lie in the 4x4x4 block
+        const float v8[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
+        const int dx = dd % 3 - 1, dy = (dd / 3) % 3 - 1, dz = dd / 9 - 1;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int chx = c & 1, chy = (c >> 1) & 1, chz = c >> 2;
+            const bool need = (dx == 0 || (dx < 0) == (chx == 1)) && (dy == 0 || (dy < 0) == (chy == 1)) &&
+                              (dz == 0 || (dz < 0) == (chz == 1));
+            if (!need) continue;
+            const int p = (2 * dx + chx + 1) + 4 * (2 * dy + chy + 1) + 16 * (2 * dz + chz + 1);
+            sv[p] = hit ? v8[c] : cv;
+            sr[p] = hit ? (int)h * 8 + c : ref;
+            sl[p] = (int8_t)lv;
+        }
+    }
+}
+
+// Phase 2 of a tile for lane j of one group: the corners j, j+8, j+16 (and
+// j+24) of the group's 27 (order: corner_of).  A corner's dual is emitted
+// when its 8 slots hold cells of level m or coarser (rules 1 and 2) and the
+// lowest same-level slot lies in this group (rule 3); for iso-surfaces its
+// Marching Cubes case and the mask of kept triangles follow.  items[q]:
+// bit 31 emitted | corner << 20 | case << 8 | keep mask.
+template <bool kDuals>
+__device__ __forceinline__ void corner_items(const int j, const int m, const float iso, const float* sv,
+                                             const int32_t* sr, const int8_t* sl,
+                                             const unsigned long long* s_tab, const bool work,
+                                             uint32_t (&items)[4], int& n_dual, int& n_tri) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        items[q] = 0;
+        const int idx = j + 8 * q;
+        if (!work || idx >= 27) continue;
+        const int k = corner_of(idx);
+        const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
+        const int p0 = kx + 4 * ky + 16 * kz;  // slot 0's cell; slot s adds ex + 4 ey + 16 ez
+        // Slot 0 decides most corners: a level-m cell there outside this
+        // group is the lowest same-level slot, so the dual belongs to another
+        // group (or is rejected by rule 2 when that cell is refined)
+        if ((kx == 0 || ky == 0 || kz == 0) && sl[p0] == m) continue;
+        int refs[8];
+        float vals[8];
+        bool ok = true;
+        uint32_t same = 0;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const int p = p0 + (s & 1) + 4 * ((s >> 1) & 1) + 16 * (s >> 2);
+            const int lv = sl[p];
+            const float v = sv[p];
+            refs[s] = sr[p];
+            vals[s] = v;
+            // rule 1 (hole) and rule 2 (finer cells) both show as lv < 0 or a NaN
+            ok = ok && lv >= 0 && v == v;
+            same |= (lv == m ? 1u : 0u) << s;
+        }
+        // the slots inside this group (cell positions 1..2 on every axis):
+        // on an axis where the corner sits at 0 only e = 1, at 2 only e = 0
+        const uint32_t mine = (kx == 0 ? 0xAAu : kx == 1 ? 0xFFu : 0x55u) &
+                              (ky == 0 ? 0xCCu : ky == 1 ? 0xFFu : 0x33u) &
+                              (kz == 0 ? 0xF0u : kz == 1 ? 0xFFu : 0x0Fu);
+        // rule 3: the lowest same-level slot must be a cell of this group
+        if (!ok || !(same & (0u - same) & mine)) continue;
+        ++n_dual;
+        uint32_t cs = 0, keep = 0;
+        if (!kDuals) {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) cs |= (vals[s] >= iso ? 1u : 0u) << s;
+            unsigned long long e = s_tab[cs];
+            int nt = (int)(e >> 60);
+            if (nt) {
+                keep = (1u << nt) - 1u;
+                // eight level-m slots are eight different cells: nothing to drop;
+                // otherwise drop triangles whose vertices repeat a cell pair
+                if (same != 0xFFu) keep = keep_by_classes(slot_classes(refs), e, nt);
+                n_tri += __popc(keep);
+            }
+        }
+        items[q] = 0x80000000u | ((uint32_t)k << 20) | (cs << 8) | keep;
+    }
+}
+
+// Phase 3 of a tile, triangles: every kept triangle gets an entry (owner
+// lane, item, triangle) in an LDS list, in output order, and the block's
+// lanes take entries round-robin; long tiles go through the list in chunks.
+// Called by the whole work-group (kB lanes, eight per group) after the
+// block scan: my_first = the lane's first triangle within the tile,
+// dual_first its first emitted dual, pre_t / pre_d the tile's first output
+// positions.  Triangles at positions >= cap are not written.
+template <int kB>
+__device__ __forceinline__ void write_triangles(const int t, const Geo& g, const float iso, const int gi, const int j,
+                                                const int m,
+                                                const uint32_t gx, const uint32_t gy, const uint32_t gz,
+                                                const uint32_t (&items)[4], const uint32_t tile_tris,
+                                                const uint32_t my_first, const uint32_t dual_first,
+                                                const int64_t pre_t, const int64_t pre_d, const int64_t cap,
+                                                float* tris, int32_t* tri_cells, int64_t* tri_dual,
+                                                const int32_t* ids, const float (*s_v)[64],
+                                                const int32_t (*s_r)[64], const int8_t (*s_l)[64],
+                                                const unsigned long long* s_tab, uint32_t (*s_items)[4],
+                                                uint32_t* s_dual, uint32_t* s_list, int* s_gm,
+                                                uint32_t (*s_gx)[3]) {
+    if (j == 0) {
+        s_gm[gi] = m;
+        s_gx[gi][0] = gx;
+        s_gx[gi][1] = gy;
+        s_gx[gi][2] = gz;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s_items[t][q] = items[q];
+    s_dual[t] = dual_first;
+    for (uint32_t c0 = 0; c0 < tile_tris; c0 += kTriList) {
+        __syncthreads();
+        // publish my triangles that fall into [c0, c0 + kTriList)
+        uint32_t idx = my_first;
+        for (int q = 0; q < 4; ++q) {
+            uint32_t it = items[q];
+            uint32_t keep = it & 0x1F;
+            for (int tt = 0; tt < 5; ++tt) {
+                if (!((keep >> tt) & 1)) continue;
+                if (idx >= c0 && idx < c0 + kTriList) s_list[idx - c0] = ((uint32_t)t << 8) | (q << 4) | tt;
+                ++idx;
+            }
+        }
+        __syncthreads();
+        uint32_t n_here = tile_tris - c0 < (uint32_t)kTriList ? tile_tris - c0 : (uint32_t)kTriList;
+        for (uint32_t w = t; w < n_here; w += kB) {
+            uint32_t en = s_list[w];
+            int owner = (int)(en >> 8), q = (int)((en >> 4) & 3), tt = (int)(en & 15);
+            int og = owner >> 3;
+            uint32_t it = s_items[owner][q];
+            int k = (it >> 20) & 31;
+            int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
+            int om = s_gm[og];
+            uint32_t gg[3] = {s_gx[og][0], s_gx[og][1], s_gx[og][2]};
+            unsigned long long e = s_tab[(it >> 8) & 0xFF];
+            int64_t o_t = pre_t + c0 + w;
+            if (o_t >= cap) continue;
+            float p[9];
+            int cells[6];
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                int ed = (int)((e >> (12 * tt + 4 * v)) & 0xF);
+                float ev[2];
+                int el[2], er[2], epos[2][3];
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+                    int sl = side ? edge_hi(ed) : edge_lo(ed);
+                    const int p = (kx + (sl & 1)) + 4 * (ky + ((sl >> 1) & 1)) + 16 * (kz + (sl >> 2));
+                    ev[side] = s_v[og][p];
+                    er[side] = s_r[og][p];
+                    el[side] = s_l[og][p];
+                    epos[side][0] = kx + (sl & 1) - 1;
+                    epos[side][1] = ky + ((sl >> 1) & 1) - 1;
+                    epos[side][2] = kz + ((sl >> 2) & 1) - 1;
+                }
+                // A = the end below iso, B = the end at or above it
+                const bool swap = ev[0] >= iso;
+                const float va = swap ? ev[1] : ev[0], vb = swap ? ev[0] : ev[1];
+                const int la = swap ? el[1] : el[0], lb = swap ? el[0] : el[1];
+                float tp = (iso - va) / (vb - va);
+                const int oo[3] = {g.ox, g.oy, g.oz};
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) {
+                    int ra = swap ? epos[1][ax] : epos[0][ax], rb = swap ? epos[0][ax] : epos[1][ax];
+                    // finest-unit offset coordinate of the slot position, floored to the cell's level
+                    uint32_t pa = ((2 * gg[ax] + (uint32_t)ra) << om) & ~((1u << la) - 1u);
+                    uint32_t pb = ((2 * gg[ax] + (uint32_t)rb) << om) & ~((1u << lb) - 1u);
+                    float ca = (float)((int)pa + oo[ax]) + 0.5f * (float)(1 << la);
+                    float cb = (float)((int)pb + oo[ax]) + 0.5f * (float)(1 << lb);
+                    p[3 * v + ax] = fmaf(tp, cb - ca, ca);
+                }
+                cells[2 * v] = swap ? er[1] : er[0];
+                cells[2 * v + 1] = swap ? er[0] : er[1];
+            }
+            if (tris) {
+                float* o = tris + 9 * o_t;
+#pragma unroll
+                for (int c = 0; c < 9; ++c) o[c] = p[c];
+            }
+            if (tri_cells) {
+                int32_t* o = tri_cells + 6 * o_t;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) o[c] = ids[cells[c]];
+            }
+            if (tri_dual) {
+                // the owner lane's emitted duals before item q
+                uint32_t rank = 0;
+                for (int q2 = 0; q2 < q; ++q2) rank += s_items[owner][q2] >> 31;
+                tri_dual[o_t] = pre_d + s_dual[owner] + rank;
+            }
+        }
+    }
+}
+
 // Extraction of a large set runs as three launches: a count pass (phases
 // 1-2, per-tile totals), a scan of the tile totals, and a write pass that
 // repeats phases 1-2 for the tiles that have output below the capacity and
@@ -1013,126 +1318,11 @@ __device__ __forceinline__ void extract_tile(const ExtractArgs& a, const Geo& g,
     }
 
     // ---- phase 1: the 27 neighbouring groups of this group, into LDS ----
-    if (work) {
-        // lane j owns neighbours j, j+8, j+16 (and j+24 for j < 3); the home
-        // slots of all of them are loaded before any is examined
-        uint64_t want[4], got[4];
-        uint32_t home[4];
-        float4 va[4], vb[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            int dd = j + 8 * q;
-            if (dd >= 27) continue;
-            int dx = dd % 3 - 1, dy = (dd / 3) % 3 - 1, dz = dd / 9 - 1;
-            want[q] = group_key(m, gx + dx, gy + dy, gz + dz);
-            home[q] = dd == 13 ? (uint32_t)own : slot_of(want[q], g.shift);
-            const Record* r = a.rec + home[q];
-            va[q] = reinterpret_cast<const float4*>(r->val)[0];
-            vb[q] = reinterpret_cast<const float4*>(r->val)[1];
-            got[q] = r->key;
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            int dd = j + 8 * q;
-            if (dd >= 27) continue;
-            int lv = -1, ref = -1;
-            uint32_t h = home[q];
-            uint64_t k = got[q];
-            float4 xa = va[q], xb = vb[q];
-            if (k != want[q] && k != kEmpty) {
-                for (uint32_t step = 0; k != want[q] && k != kEmpty && step <= g.mask; ++step) {
-                    h = next_slot(h, g.mask);
-                    k = a.rec[h].key;
-                }
-                if (k == want[q]) {
-                    xa = reinterpret_cast<const float4*>(a.rec[h].val)[0];
-                    xb = reinterpret_cast<const float4*>(a.rec[h].val)[1];
-                }
-            }
-            float cv = 0.f;
-            const bool hit = k == want[q];
-            if (hit) {
-                lv = m;
-            } else {
-                // The block holds neither cells of level m nor finer cells (either
-                // would have left a record): it lies inside a coarser cell or in a
-                // hole.  The first record found going up decides.
-                // In the fused pass (small sets, one wave of tiles: latency
-                // bound) the home slots of four levels are read at once, so a
-                // deep walk costs one memory round trip per four levels; the
-                // throughput passes walk one level at a time, which keeps
-                // their register count (and occupancy) down.
-                constexpr int kWalk = kPass == kPassFused ? 4 : 1;
-                int dx = dd % 3 - 1, dy = (dd / 3) % 3 - 1, dz = dd / 9 - 1;
-                uint32_t bx = gx + dx, by = gy + dy, bz = gz + dz;
-                // Each level's home slot is read with the one child value the
-                // block would need there (same line), so a record found at its
-                // home slot costs no further round trip.
-                int found_l = -1, found_h = -1, found_c = 0;
-                float found_v = 0.f;
-                for (int L0 = m + 1; L0 <= g.lmax && found_l < 0; L0 += kWalk) {
-                    uint64_t wk[kWalk], kk[kWalk];
-                    uint32_t hh[kWalk];
-                    int ch[kWalk];
-                    float vv[kWalk];
-#pragma unroll
-                    for (int u = 0; u < kWalk; ++u) {
-                        const int L = L0 + u, sh = L - m - 1;
-                        wk[u] = group_key(L, bx >> (sh + 1), by >> (sh + 1), bz >> (sh + 1));
-                        hh[u] = slot_of(wk[u], g.shift);
-                        ch[u] = ((bx >> sh) & 1) | (((by >> sh) & 1) << 1) | (((bz >> sh) & 1) << 2);
-                        kk[u] = kEmpty;
-                        vv[u] = 0.f;
-                        if (L <= g.lmax) {
-                            kk[u] = a.rec[hh[u]].key;
-                            vv[u] = a.rec[hh[u]].val[ch[u]];
-                        }
-                    }
-#pragma unroll
-                    for (int u = 0; u < kWalk; ++u) {
-                        if (found_l >= 0 || L0 + u > g.lmax) continue;
-                        uint32_t h2 = hh[u];
-                        uint64_t k2 = kk[u];
-                        float v2 = vv[u];
-                        if (k2 != wk[u] && k2 != kEmpty) {
-                            for (uint32_t step = 0; k2 != wk[u] && k2 != kEmpty && step <= g.mask; ++step) {
-                                h2 = next_slot(h2, g.mask);
-                                k2 = a.rec[h2].key;
-                            }
-                            if (k2 == wk[u]) v2 = a.rec[h2].val[ch[u]];
-                        }
-                        if (k2 == wk[u]) {
-                            found_l = L0 + u;
-                            found_h = (int)h2;
-                            found_c = ch[u];
-                            found_v = v2;
-                        }
-                    }
-                }
-                // the lowest level with a record decides (a NaN there: finer
-                // cells or none at all, either way no cell covers this block)
-                if (found_l >= 0 && found_v == found_v) {
-                    lv = found_l;
-                    ref = found_h * 8 + found_c;
-                    cv = found_v;
-                }
-            }
-            // the cells of this neighbour that lie in the 4x4x4 block
-            const float v8[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
-            const int dx = dd % 3 - 1, dy = (dd / 3) % 3 - 1, dz = dd / 9 - 1;
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                const int chx = c & 1, chy = (c >> 1) & 1, chz = c >> 2;
-                const bool need = (dx == 0 || (dx < 0) == (chx == 1)) && (dy == 0 || (dy < 0) == (chy == 1)) &&
-                                  (dz == 0 || (dz < 0) == (chz == 1));
-                if (!need) continue;
-                const int p = (2 * dx + chx + 1) + 4 * (2 * dy + chy + 1) + 16 * (2 * dz + chz + 1);
-                s_v[gi][p] = hit ? v8[c] : cv;
-                s_r[gi][p] = hit ? (int)h * 8 + c : ref;
-                s_l[gi][p] = (int8_t)lv;
-            }
-        }
-    }
+    // (in the fused pass -- small sets, one wave of tiles: latency bound --
+    // the home slots of four coarser levels are read at once; the
+    // throughput passes walk one level at a time, which keeps their register
+    // count, and occupancy, down)
+    if (work) load_neighbourhood<kPass == kPassFused ? 4 : 1>(a.rec, g, j, m, gx, gy, gz, own, s_v[gi], s_r[gi], s_l[gi]);
     __syncthreads();
     if (kPass != kPassWrite && rng_mode == kRngRecord) {
         // the range of the cells in the neighbourhood (holes and the markers
@@ -1158,60 +1348,9 @@ __device__ __forceinline__ void extract_tile(const ExtractArgs& a, const Geo& g,
     }
 
     // ---- phase 2: the 27 corners of the group's 2x2x2 block ----
-    const float iso = a.iso;
     uint32_t items[4];  // bit 31 valid | corner k (5 b) << 20 | case << 8 | keep mask (5 b)
     int n_dual = 0, n_tri = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        items[q] = 0;
-        const int idx = j + 8 * q;
-        if (!work || idx >= 27) continue;
-        const int k = corner_of(idx);
-        const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
-        const int p0 = kx + 4 * ky + 16 * kz;  // slot 0's cell; slot s adds ex + 4 ey + 16 ez
-        // Slot 0 decides most corners: a level-m cell there outside this
-        // group is the lowest same-level slot, so the dual belongs to another
-        // group (or is rejected by rule 2 when that cell is refined)
-        if ((kx == 0 || ky == 0 || kz == 0) && s_l[gi][p0] == m) continue;
-        int refs[8];
-        float vals[8];
-        bool ok = true;
-        uint32_t same = 0;
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            const int p = p0 + (s & 1) + 4 * ((s >> 1) & 1) + 16 * (s >> 2);
-            const int lv = s_l[gi][p];
-            const float v = s_v[gi][p];
-            refs[s] = s_r[gi][p];
-            vals[s] = v;
-            // rule 1 (hole) and rule 2 (finer cells) both show as lv < 0 or a NaN
-            ok = ok && lv >= 0 && v == v;
-            same |= (lv == m ? 1u : 0u) << s;
-        }
-        // the slots inside this group (cell positions 1..2 on every axis):
-        // on an axis where the corner sits at 0 only e = 1, at 2 only e = 0
-        const uint32_t mine = (kx == 0 ? 0xAAu : kx == 1 ? 0xFFu : 0x55u) &
-                              (ky == 0 ? 0xCCu : ky == 1 ? 0xFFu : 0x33u) &
-                              (kz == 0 ? 0xF0u : kz == 1 ? 0xFFu : 0x0Fu);
-        // rule 3: the lowest same-level slot must be a cell of this group
-        if (!ok || !(same & (0u - same) & mine)) continue;
-        ++n_dual;
-        uint32_t cs = 0, keep = 0;
-        if (!kDuals) {
-#pragma unroll
-            for (int s = 0; s < 8; ++s) cs |= (vals[s] >= iso ? 1u : 0u) << s;
-            unsigned long long e = s_tab[cs];
-            int nt = (int)(e >> 60);
-            if (nt) {
-                keep = (1u << nt) - 1u;
-                // eight level-m slots are eight different cells: nothing to drop;
-                // otherwise drop triangles whose vertices repeat a cell pair
-                if (same != 0xFFu) keep = keep_by_classes(slot_classes(refs), e, nt);
-                n_tri += __popc(keep);
-            }
-        }
-        items[q] = 0x80000000u | ((uint32_t)k << 20) | (cs << 8) | keep;
-    }
+    corner_items<kDuals>(j, m, a.iso, s_v[gi], s_r[gi], s_l[gi], s_tab, work, items, n_dual, n_tri);
 
     n_dual += (int)carried_duals;
     if (kPass == kPassCount) {
@@ -1304,104 +1443,10 @@ __device__ __forceinline__ void extract_tile(const ExtractArgs& a, const Geo& g,
         }
         return;
     }
-    // Triangles are spread over all lanes: every kept triangle gets an entry
-    // (owner lane, item, triangle) in an LDS list, in output order, and lanes
-    // take entries round-robin.  Long tiles go through the list in chunks.
-    {
-        const uint32_t tile_tris = (uint32_t)(total >> 32);
-        const uint32_t my_first = (uint32_t)(excl >> 32);
-        if (j == 0) {
-            s_gm[gi] = m;
-            s_gx[gi][0] = gx;
-            s_gx[gi][1] = gy;
-            s_gx[gi][2] = gz;
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) s_items[t][q] = items[q];
-        s_dual[t] = (uint32_t)(excl & 0xFFFFFFFFull);
-        for (uint32_t c0 = 0; c0 < tile_tris; c0 += kTriList) {
-            __syncthreads();
-            // publish my triangles that fall into [c0, c0 + kTriList)
-            uint32_t idx = my_first;
-            for (int q = 0; q < 4; ++q) {
-                uint32_t it = items[q];
-                uint32_t keep = it & 0x1F;
-                for (int tt = 0; tt < 5; ++tt) {
-                    if (!((keep >> tt) & 1)) continue;
-                    if (idx >= c0 && idx < c0 + kTriList) s_list[idx - c0] = ((uint32_t)t << 8) | (q << 4) | tt;
-                    ++idx;
-                }
-            }
-            __syncthreads();
-            uint32_t n_here = tile_tris - c0 < (uint32_t)kTriList ? tile_tris - c0 : (uint32_t)kTriList;
-            for (uint32_t w = t; w < n_here; w += kBlock) {
-                uint32_t en = s_list[w];
-                int owner = (int)(en >> 8), q = (int)((en >> 4) & 3), tt = (int)(en & 15);
-                int og = owner >> 3;
-                uint32_t it = s_items[owner][q];
-                int k = (it >> 20) & 31;
-                int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
-                int om = s_gm[og];
-                uint32_t gg[3] = {s_gx[og][0], s_gx[og][1], s_gx[og][2]};
-                unsigned long long e = s_tab[(it >> 8) & 0xFF];
-                int64_t o_t = (int64_t)s_pre_t + c0 + w;
-                if (o_t >= a.cap) continue;
-                float p[9];
-                int cells[6];
-#pragma unroll
-                for (int v = 0; v < 3; ++v) {
-                    int ed = (int)((e >> (12 * tt + 4 * v)) & 0xF);
-                    float ev[2];
-                    int el[2], er[2], epos[2][3];
-#pragma unroll
-                    for (int side = 0; side < 2; ++side) {
-                        int sl = side ? edge_hi(ed) : edge_lo(ed);
-                        const int p = (kx + (sl & 1)) + 4 * (ky + ((sl >> 1) & 1)) + 16 * (kz + (sl >> 2));
-                        ev[side] = s_v[og][p];
-                        er[side] = s_r[og][p];
-                        el[side] = s_l[og][p];
-                        epos[side][0] = kx + (sl & 1) - 1;
-                        epos[side][1] = ky + ((sl >> 1) & 1) - 1;
-                        epos[side][2] = kz + ((sl >> 2) & 1) - 1;
-                    }
-                    // A = the end below iso, B = the end at or above it
-                    const bool swap = ev[0] >= iso;
-                    const float va = swap ? ev[1] : ev[0], vb = swap ? ev[0] : ev[1];
-                    const int la = swap ? el[1] : el[0], lb = swap ? el[0] : el[1];
-                    float tp = (iso - va) / (vb - va);
-                    const int oo[3] = {g.ox, g.oy, g.oz};
-#pragma unroll
-                    for (int ax = 0; ax < 3; ++ax) {
-                        int ra = swap ? epos[1][ax] : epos[0][ax], rb = swap ? epos[0][ax] : epos[1][ax];
-                        // finest-unit offset coordinate of the slot position, floored to the cell's level
-                        uint32_t pa = ((2 * gg[ax] + (uint32_t)ra) << om) & ~((1u << la) - 1u);
-                        uint32_t pb = ((2 * gg[ax] + (uint32_t)rb) << om) & ~((1u << lb) - 1u);
-                        float ca = (float)((int)pa + oo[ax]) + 0.5f * (float)(1 << la);
-                        float cb = (float)((int)pb + oo[ax]) + 0.5f * (float)(1 << lb);
-                        p[3 * v + ax] = fmaf(tp, cb - ca, ca);
-                    }
-                    cells[2 * v] = swap ? er[1] : er[0];
-                    cells[2 * v + 1] = swap ? er[0] : er[1];
-                }
-                if (a.tris) {
-                    float* o = a.tris + 9 * o_t;
-#pragma unroll
-                    for (int c = 0; c < 9; ++c) o[c] = p[c];
-                }
-                if (a.tri_cells) {
-                    int32_t* o = a.tri_cells + 6 * o_t;
-#pragma unroll
-                    for (int c = 0; c < 6; ++c) o[c] = a.ids[cells[c]];
-                }
-                if (a.tri_dual) {
-                    // the owner lane's emitted duals before item q
-                    uint32_t rank = 0;
-                    for (int q2 = 0; q2 < q; ++q2) rank += s_items[owner][q2] >> 31;
-                    a.tri_dual[o_t] = (int64_t)s_pre_d + s_dual[owner] + rank;
-                }
-            }
-        }
-    }
+    write_triangles<kBlock>(t, g, a.iso, gi, j, m, gx, gy, gz, items, (uint32_t)(total >> 32), (uint32_t)(excl >> 32),
+                            (uint32_t)(excl & 0xFFFFFFFFull), (int64_t)s_pre_t, (int64_t)s_pre_d, a.cap, a.tris,
+                            a.tri_cells, a.tri_dual, a.ids, s_v, s_r, s_l, s_tab, s_items, s_dual, s_list, s_gm,
+                            s_gx);
 }
 
 // What every extraction kernel reads first: the build's verdict, the group
@@ -1719,22 +1764,31 @@ __global__ __launch_bounds__(kBlock) void k_tile_scan(ExtractArgs a, int duals) 
 }
 
 // ---------------------------------------------------------------------------
-// Batched iso-surfaces over explicit dual lists (many iso-values and/or many
-// sets in one persistent launch).  Phase A counts triangles per (job, tile),
-// phase B scans each job's tile counts, phase C writes; grid-wide barriers
-// separate them.  The grid never exceeds what the GPU keeps resident, and
-// every wait is bounded, so the kernel always drains.
+// Batched iso-surfaces: many (set, iso) jobs in one persistent launch.  The
+// dual cells do not depend on the field (sec. 4), so a tile of groups loads
+// its neighbourhoods into LDS once and runs Marching Cubes (sec. 5) for every
+// job of its set against them.  Phase A counts each job's triangles per
+// tile, phase B scans each job's tile counts, phase C loads the tiles that
+// have output again and writes; grid-wide barriers separate the phases.  A
+// group whose neighbourhood value range straddles no job's iso is skipped
+// before its neighbourhood is read when the set has recorded ranges (see
+// range culling above), else after.  Every job's triangles come out in the
+// order, and with the bits, of amr_isosurface on its set.  The grid never
+// exceeds what the GPU keeps resident, and every wait is bounded, so the
+// kernel always drains.
 // ---------------------------------------------------------------------------
 
 constexpr int kMaxJobs = 256;
 constexpr int kMaxSets = 256;
 
+// One set of a batch, as the kernel reads it (device table).
 struct BatchSet {
-    const int32_t* verts;  // [n_duals][8] cell indices in slot order
-    const float* dvals;    // [n_duals][8] their values
-    const int32_t* xyz;
-    const int32_t* lvl;
-    int64_t n_duals;
+    const Record* rec;
+    const int32_t* glist;
+    const unsigned long long* gkey;
+    const Ctrl* ctrl;            // verdict, group count, geometry
+    const float2* rng;           // recorded neighbourhood ranges, when *rng_ok
+    const uint32_t* rng_ok;
 };
 
 struct alignas(256) GridBar {
@@ -1751,8 +1805,9 @@ struct BatchArgs {
     int n_jobs;
     float* tris;
     int64_t* counts;
-    uint32_t* tcount;  // per (job, tile of its set): count, then exclusive prefix
-    uint32_t* bsum;    // per work-group: sum of its stretch of one job's counts
+    uint32_t* tcnt;  // per (job, tile of its set): triangles
+    uint32_t* tpre;  // the same, exclusive prefix over the job's tiles
+    uint32_t* bsum;  // per work-group: sum of its stretch of one job's counts
     GridBar* bar;
 };
 
@@ -1801,306 +1856,364 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s_w, u
     return pre + (uint32_t)incl - x;
 }
 
-// Triangles of one dual for one iso: case and keep mask (degenerate ones
-// dropped).  The slot classes depend only on the dual, so they are worked
-// out once and reused by every job.
-struct DualMc {
-    int32_t id[8];
-    float v[8];
-    uint32_t cls;
-    bool cls_ready;
+// One tile of a batched launch: kG groups of one set, eight lanes each.
+// The set's isos are sorted ascending; a group with neighbourhood value
+// range (lo, hi] has triangles only for the isos with lo < iso <= hi, the
+// sorted positions [ia, ib).  The loader reads the neighbourhoods of the
+// groups that have any, leaves each group's [ia, ib) in LDS and returns the
+// union over the tile.
+template <int kG>
+struct BatchTile {
+    float v[kG][64];
+    int32_t r[kG][64];
+    int8_t l[kG][64];
+    int16_t ia[kG], ib[kG];
+    int fa, fb;
 };
 
-__device__ __forceinline__ uint32_t dual_case(const DualMc& d, float iso) {
-    uint32_t cs = 0;
-#pragma unroll
-    for (int s = 0; s < 8; ++s) cs |= (d.v[s] >= iso ? 1u : 0u) << s;
-    return cs;
-}
-
-__device__ __forceinline__ uint32_t dual_keep(DualMc& d, unsigned long long e) {
-    int nt = (int)(e >> 60);
-    if (!nt) return 0;
-    if (!d.cls_ready) {
-        d.cls = slot_classes(d.id);
-        d.cls_ready = true;
+// first sorted position whose iso exceeds x
+__device__ __forceinline__ int iso_upper(const float* iso_sorted, int n_iso, float x) {
+    int a = 0, b = n_iso;
+    while (a < b) {
+        const int c = (a + b) >> 1;
+        if (iso_sorted[c] > x) b = c;
+        else a = c + 1;
     }
-    return keep_by_classes(d.cls, e, nt);
+    return a;
 }
 
-template <int PER>
-__global__ __launch_bounds__(512) void k_batch(BatchArgs a) {
+template <int kG>
+__device__ __forceinline__ void batch_load_tile(const BatchSet& S, const Geo& g, uint32_t ng, int64_t lt, int gi,
+                                                int j, const float* iso_sorted, int n_iso, BatchTile<kG>& T,
+                                                bool& work, int& m, uint32_t& gx, uint32_t& gy, uint32_t& gz) {
+    const int64_t gidx = lt * kG + gi;
+    const bool valid = gidx < (int64_t)ng;
+    const bool ranged = uniform_u32(*S.rng_ok) != 0;
+    if (threadIdx.x == 0) {
+        T.fa = n_iso;
+        T.fb = 0;
+    }
+    int ia = 0, ib = 0;
+    work = valid;
+    if (valid && ranged) {
+        const float2 rg = S.rng[gidx];
+        ia = iso_upper(iso_sorted, n_iso, rg.x);
+        ib = iso_upper(iso_sorted, n_iso, rg.y);
+        work = ia < ib;
+    }
+    m = 0;
+    gx = gy = gz = 0;
+    int own = 0;
+    if (work) {
+        own = S.glist[gidx];
+        const uint64_t key = S.gkey[gidx];
+        m = (int)(key >> 57);
+        gx = (uint32_t)(key & 0x7FFFF);
+        gy = (uint32_t)((key >> 19) & 0x7FFFF);
+        gz = (uint32_t)((key >> 38) & 0x7FFFF);
+        load_neighbourhood<1>(S.rec, g, j, m, gx, gy, gz, own, T.v[gi], T.r[gi], T.l[gi]);
+    }
+    __syncthreads();
+    if (!ranged) {
+        // the range of the cells in the neighbourhood (holes and the markers
+        // of refined or empty slots excluded); lane j takes 8 of the 64
+        float lo = INFINITY, hi = -INFINITY;
+        if (work) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const float v = T.v[gi][8 * j + c];
+                if (T.l[gi][8 * j + c] >= 0 && v == v) {
+                    lo = fminf(lo, v);
+                    hi = fmaxf(hi, v);
+                }
+            }
+        }
+        lo = fminf(lo, __shfl_xor(lo, 1, 64));
+        hi = fmaxf(hi, __shfl_xor(hi, 1, 64));
+        lo = fminf(lo, __shfl_xor(lo, 2, 64));
+        hi = fmaxf(hi, __shfl_xor(hi, 2, 64));
+        lo = fminf(lo, __shfl_xor(lo, 4, 64));
+        hi = fmaxf(hi, __shfl_xor(hi, 4, 64));
+        if (work) {
+            ia = iso_upper(iso_sorted, n_iso, lo);
+            ib = iso_upper(iso_sorted, n_iso, hi);
+        }
+    }
+    if (!work) ia = ib = 0;
+    if (j == 0) {
+        T.ia[gi] = (int16_t)ia;
+        T.ib[gi] = (int16_t)ib;
+        if (ia < ib) {
+            atomicMin(&T.fa, ia);
+            atomicMax(&T.fb, ib);
+        }
+    }
+    __syncthreads();
+}
+
+// Values every lane of a work-group holds alike, kept in scalar registers.
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+    return reinterpret_cast<T*>(uniform_i64((int64_t)reinterpret_cast<uintptr_t>(p)));
+}
+
+__device__ __forceinline__ BatchSet uniform_set(const BatchSet& s) {
+    BatchSet u;
+    u.rec = uniform_ptr(s.rec);
+    u.glist = uniform_ptr(s.glist);
+    u.gkey = uniform_ptr(s.gkey);
+    u.ctrl = uniform_ptr(s.ctrl);
+    u.rng = uniform_ptr(s.rng);
+    u.rng_ok = uniform_ptr(s.rng_ok);
+    return u;
+}
+
+template <int kG>
+__global__ __launch_bounds__(kG * 8, 4) void k_batch(BatchArgs a) {
+    constexpr int kB = kG * 8;
+    __shared__ BatchTile<kG> T;
     __shared__ unsigned long long s_tab[256];
     __shared__ amr_iso_job s_job[kMaxJobs];
-    __shared__ int64_t s_tbase[kMaxSets + 1];  // first global tile of each set
-    __shared__ int64_t s_jbase[kMaxJobs + 1];  // first tcount entry of each job
+    __shared__ uint16_t s_order[kMaxJobs];       // valid jobs by set, then iso (then index)
+    __shared__ float s_iso[kMaxJobs];            // their isos: ascending within each set
+    __shared__ int s_first[kMaxSets + 1];        // first entry of each set in s_order / s_iso
+    __shared__ int64_t s_tbase[kMaxSets + 1];    // first global tile of each set
+    __shared__ int64_t s_jbase[kMaxJobs + 1];    // first tcnt entry of each job
+    __shared__ uint32_t s_ng[kMaxSets];
+    __shared__ uint32_t s_items[kB][4];
+    __shared__ uint32_t s_dual[kB];
+    __shared__ uint32_t s_list[kTriList];
+    __shared__ int s_gm[kG];
+    __shared__ uint32_t s_gx[kG][3];
     __shared__ uint32_t s_w[8];
+    __shared__ uint32_t s_any;
     __shared__ unsigned int s_sense;
     const int t = threadIdx.x;
-    const int64_t TS = (int64_t)blockDim.x * PER;
-    for (int i = t; i < 256; i += blockDim.x) s_tab[i] = kMcTable[i];
-    for (int i = t; i < a.n_jobs; i += blockDim.x) s_job[i] = a.jobs[i];
-    if (t == 0) {
-        int64_t acc = 0;
-        for (int i = 0; i < a.n_sets; ++i) {
-            s_tbase[i] = acc;
-            acc += (a.sets[i].n_duals + TS - 1) / TS;
+    for (int i = t; i < 256; i += kB) s_tab[i] = kMcTable[i];
+    for (int i = t; i < a.n_jobs; i += kB) s_job[i] = a.jobs[i];
+    for (int i = t; i < a.n_sets; i += kB) {
+        const Ctrl* c = a.sets[i].ctrl;
+        s_ng[i] = c->status == AMR_OK ? (uint32_t)c->n_groups : 0u;
+    }
+    __syncthreads();
+    // each valid job's place among the jobs of its set (by set, then iso for
+    // the sorted isos; by set, then job index for the order); a job naming
+    // no set of the batch, or with a non-finite iso, takes part in nothing
+    auto job_ok = [&](int i) { return s_job[i].set >= 0 && s_job[i].set < a.n_sets && isfinite(s_job[i].iso); };
+    for (int i = t; i < a.n_jobs; i += kB) {
+        if (!job_ok(i)) continue;
+        const int si = s_job[i].set;
+        const float vi = s_job[i].iso;
+        int rank = 0;
+        for (int k = 0; k < a.n_jobs; ++k) {
+            if (!job_ok(k)) continue;
+            const int sk = s_job[k].set;
+            const float vk = s_job[k].iso;
+            rank += sk < si || (sk == si && (vk < vi || (vk == vi && k < i)));
         }
-        s_tbase[a.n_sets] = acc;
-        s_sense = __hip_atomic_load(&a.bar->sense, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_order[rank] = (uint16_t)i;
+        s_iso[rank] = vi;
     }
     __syncthreads();
     if (t == 0) {
+        int n_valid = 0;
+        for (int i = 0; i < a.n_jobs; ++i) n_valid += job_ok(i) ? 1 : 0;
         int64_t acc = 0;
-        for (int j = 0; j < a.n_jobs; ++j) {
-            s_jbase[j] = acc;
-            int sj = s_job[j].set;
-            acc += s_tbase[sj + 1] - s_tbase[sj];
+        int k = 0;
+        for (int s = 0; s < a.n_sets; ++s) {
+            s_tbase[s] = acc;
+            acc += (s_ng[s] + kG - 1) / kG;
+            s_first[s] = k;
+            while (k < n_valid && s_job[s_order[k]].set == s) ++k;
         }
-        s_jbase[a.n_jobs] = acc;
+        s_tbase[a.n_sets] = acc;
+        s_first[a.n_sets] = k;
+        int64_t jb = 0;
+        for (int i = 0; i < a.n_jobs; ++i) {
+            s_jbase[i] = jb;
+            const int sj = s_job[i].set;
+            if (job_ok(i)) jb += s_tbase[sj + 1] - s_tbase[sj];
+        }
+        s_jbase[a.n_jobs] = jb;
+        s_sense = __hip_atomic_load(&a.bar->sense, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
     const int64_t n_tiles = s_tbase[a.n_sets];
     unsigned int sense = s_sense;
-
-    // loads the duals of one tile for this thread
-    auto load_duals = [&](int sidx, int64_t lt, DualMc* d, bool* live) {
-        const BatchSet& S = a.sets[sidx];
-#pragma unroll
-        for (int p = 0; p < PER; ++p) {
-            int64_t di = lt * TS + (int64_t)p * blockDim.x + t;
-            live[p] = di < S.n_duals;
-            d[p].cls_ready = false;
-            if (!live[p]) continue;
-            const int4* vv = reinterpret_cast<const int4*>(S.verts + 8 * di);
-            int4 lo = vv[0], hi = vv[1];
-            d[p].id[0] = lo.x; d[p].id[1] = lo.y; d[p].id[2] = lo.z; d[p].id[3] = lo.w;
-            d[p].id[4] = hi.x; d[p].id[5] = hi.y; d[p].id[6] = hi.z; d[p].id[7] = hi.w;
-            const float4* pv = reinterpret_cast<const float4*>(S.dvals + 8 * di);
-            float4 v0 = pv[0], v1 = pv[1];
-            d[p].v[0] = v0.x; d[p].v[1] = v0.y; d[p].v[2] = v0.z; d[p].v[3] = v0.w;
-            d[p].v[4] = v1.x; d[p].v[5] = v1.y; d[p].v[6] = v1.z; d[p].v[7] = v1.w;
-        }
-    };
     auto set_of = [&](int64_t tile) {
         int lo = 0, hi = a.n_sets;  // s_tbase[lo] <= tile < s_tbase[hi]
         while (hi - lo > 1) {
-            int mid = (lo + hi) >> 1;
+            const int mid = (lo + hi) >> 1;
             if (s_tbase[mid] <= tile) lo = mid;
             else hi = mid;
         }
         return lo;
     };
+    auto geo_of = [&](const BatchSet& S) {
+        Geo g = S.ctrl->geo;
+        g.ox = uniform_i32(g.ox);
+        g.oy = uniform_i32(g.oy);
+        g.oz = uniform_i32(g.oz);
+        g.lmax = uniform_i32(g.lmax);
+        g.shift = uniform_i32(g.shift);
+        g.mask = uniform_u32(g.mask);
+        return g;
+    };
 
     // ---- phase A: triangle counts per (job, tile) ----
-    // the duals of a work-group's next tile are loaded before the current
-    // tile is processed, so their latency overlaps the work on this one
-    DualMc d[PER], dn[PER];
-    bool live[PER], ln[PER];
-    int sidx = 0, sn = 0;
-    int64_t lt = 0, ltn = 0;
-    if (blockIdx.x < n_tiles) {
-        sidx = set_of(blockIdx.x);
-        lt = blockIdx.x - s_tbase[sidx];
-        load_duals(sidx, lt, d, live);
-    }
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const int64_t next = tile + gridDim.x;
-        if (next < n_tiles) {
-            sn = set_of(next);
-            ltn = next - s_tbase[sn];
-            load_duals(sn, ltn, dn, ln);
-        }
-        for (int j = 0; j < a.n_jobs; ++j) {
-            if (s_job[j].set != sidx) continue;
-            float iso = s_job[j].iso;
-            uint32_t c = 0;
-#pragma unroll
-            for (int p = 0; p < PER; ++p)
-                if (live[p]) c += __popc(dual_keep(d[p], s_tab[dual_case(d[p], iso)]));
+        // the lane's place, opaque to the compiler in every iteration: what
+        // derives from it is recomputed per tile instead of being hoisted
+        // out of the loop into registers held across it
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const int gi = tid >> 3, j = tid & 7;
+        const int si = uniform_i32(set_of(tile));
+        const int64_t lt = uniform_i64(tile - s_tbase[si]);
+        const BatchSet S = uniform_set(a.sets[si]);
+        const Geo g = geo_of(S);
+        const int f0 = uniform_i32(s_first[si]), f1 = uniform_i32(s_first[si + 1]);
+        bool work;
+        int m;
+        uint32_t gx, gy, gz;
+        batch_load_tile<kG>(S, g, uniform_u32(s_ng[si]), lt, gi, j, s_iso + f0, f1 - f0, T, work, m, gx, gy, gz);
+        const int fa = uniform_i32(T.fa), fb = uniform_i32(T.fb);
+        const int ia = T.ia[gi], ib = T.ib[gi];
+        // jobs no group of the tile straddles: no triangles here
+        for (int f = t; f < f1 - f0; f += kB)
+            if (f < fa || f >= fb) a.tcnt[s_jbase[s_order[f0 + f]] + lt] = 0;
+        for (int f = fa; f < fb; ++f) {
+            const int jb = uniform_i32(s_order[f0 + f]);
+            const float iso = __int_as_float(uniform_i32(__float_as_int(s_job[jb].iso)));
+            int tid2 = threadIdx.x;
+            asm volatile("" : "+v"(tid2));
+            const int gi2 = tid2 >> 3, j2 = tid2 & 7;
+            const bool on = ia <= f && f < ib;
+            uint32_t items[4];
+            int n_dual = 0, n_tri = 0;
+            corner_items<false>(j2, m, iso, T.v[gi2], T.r[gi2], T.l[gi2], s_tab, on, items, n_dual, n_tri);
             uint32_t tot;
-            (void)block_excl_scan(c, s_w, &tot);
-            if (t == 0) a.tcount[s_jbase[j] + lt] = tot;
+            (void)block_excl_scan((uint32_t)n_tri, s_w, &tot);
+            if (t == 0) a.tcnt[s_jbase[jb] + lt] = tot;
         }
-        sidx = sn;
-        lt = ltn;
-#pragma unroll
-        for (int p = 0; p < PER; ++p) {
-            d[p] = dn[p];
-            live[p] = ln[p];
-        }
+        __syncthreads();  // the tile's LDS is reused by the next tile
     }
     grid_barrier(a.bar, sense);
 
     // ---- phase B: exclusive scan over each job's tiles ----
     if (a.n_jobs >= (int)gridDim.x) {
         // at least as many jobs as work-groups: one work-group per job
-        for (int j = blockIdx.x; j < a.n_jobs; j += gridDim.x) {
-            int64_t base = s_jbase[j], n = s_jbase[j + 1] - base;
+        for (int jb = blockIdx.x; jb < a.n_jobs; jb += gridDim.x) {
+            const int64_t base = s_jbase[jb], n = s_jbase[jb + 1] - base;
             uint64_t carry = 0;
-            for (int64_t c0 = 0; c0 < n; c0 += blockDim.x) {
-                int64_t i = c0 + t;
-                uint32_t x = i < n ? a.tcount[base + i] : 0u;
+            for (int64_t c0 = 0; c0 < n; c0 += kB) {
+                const int64_t i = c0 + t;
+                const uint32_t x = i < n ? a.tcnt[base + i] : 0u;
                 uint32_t tot;
-                uint32_t pre = block_excl_scan(x, s_w, &tot);
-                if (i < n) a.tcount[base + i] = (uint32_t)(carry + pre);
+                const uint32_t pre = block_excl_scan(x, s_w, &tot);
+                if (i < n) a.tpre[base + i] = (uint32_t)(carry + pre);
                 carry += tot;
             }
-            if (t == 0) a.counts[j] = (int64_t)carry;
+            if (t == 0) a.counts[jb] = (int64_t)carry;
         }
     } else {
         // fewer jobs than work-groups: each job's counts are split over
         // gridDim / n_jobs work-groups; every work-group sums its stretch,
         // then (after a barrier) adds the sums of the stretches before its own
-        // and rewrites its stretch as prefixes
+        // and writes its stretch's prefixes
         const int bj = (int)gridDim.x / a.n_jobs;
-        const int j = blockIdx.x / bj, r = blockIdx.x % bj;
+        const int jb = blockIdx.x / bj, r = blockIdx.x % bj;
         int64_t base = 0, c0 = 0, c1 = 0;
-        if (j < a.n_jobs) {
-            base = s_jbase[j];
-            const int64_t n = s_jbase[j + 1] - base, len = (n + bj - 1) / bj;
+        if (jb < a.n_jobs) {
+            base = s_jbase[jb];
+            const int64_t n = s_jbase[jb + 1] - base, len = (n + bj - 1) / bj;
             c0 = (int64_t)r * len < n ? (int64_t)r * len : n;
             c1 = c0 + len < n ? c0 + len : n;
         }
         uint32_t mine = 0;
-        for (int64_t c = c0 + t; c < c1; c += blockDim.x) mine += a.tcount[base + c];
+        for (int64_t c = c0 + t; c < c1; c += kB) mine += a.tcnt[base + c];
         uint32_t part;
         (void)block_excl_scan(mine, s_w, &part);
-        if (t == 0 && j < a.n_jobs) a.bsum[blockIdx.x] = part;
+        if (t == 0 && jb < a.n_jobs) a.bsum[blockIdx.x] = part;
         grid_barrier(a.bar, sense);
-        if (j < a.n_jobs) {
+        if (jb < a.n_jobs) {
             uint32_t before = 0;
-            for (int k = t; k < r; k += blockDim.x) before += a.bsum[j * bj + k];
+            for (int k = t; k < r; k += kB) before += a.bsum[jb * bj + k];
             uint32_t pre_all;
             (void)block_excl_scan(before, s_w, &pre_all);
-            if (t == 0 && r == bj - 1) a.counts[j] = (int64_t)pre_all + part;
+            if (t == 0 && r == bj - 1) a.counts[jb] = (int64_t)pre_all + part;
             uint64_t carry = pre_all;
-            for (int64_t cc = c0; cc < c1; cc += blockDim.x) {
+            for (int64_t cc = c0; cc < c1; cc += kB) {
                 const int64_t i = cc + t;
-                const uint32_t x = i < c1 ? a.tcount[base + i] : 0u;
+                const uint32_t x = i < c1 ? a.tcnt[base + i] : 0u;
                 uint32_t tot;
                 const uint32_t pre = block_excl_scan(x, s_w, &tot);
-                if (i < c1) a.tcount[base + i] = (uint32_t)(carry + pre);
+                if (i < c1) a.tpre[base + i] = (uint32_t)(carry + pre);
                 carry += tot;
             }
         }
     }
     grid_barrier(a.bar, sense);
 
-    // ---- phase C: write (same prefetch of the next tile) ----
-    if (blockIdx.x < n_tiles) {
-        sidx = set_of(blockIdx.x);
-        lt = blockIdx.x - s_tbase[sidx];
-        load_duals(sidx, lt, d, live);
-    }
+    // ---- phase C: write ----
+    // invalid jobs, and jobs on a set whose build failed, count -1
+    for (int jb = blockIdx.x * kB + t; jb < a.n_jobs; jb += gridDim.x * kB)
+        if (!job_ok(jb) || a.sets[s_job[jb].set].ctrl->status != AMR_OK) a.counts[jb] = -1;
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const int64_t next = tile + gridDim.x;
-        if (next < n_tiles) {
-            sn = set_of(next);
-            ltn = next - s_tbase[sn];
-            load_duals(sn, ltn, dn, ln);
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const int gi = tid >> 3, j = tid & 7;
+        const int si = uniform_i32(set_of(tile));
+        const int64_t lt = uniform_i64(tile - s_tbase[si]);
+        const int f0 = uniform_i32(s_first[si]), f1 = uniform_i32(s_first[si + 1]);
+        // the tile is loaded again only if some job has output below its capacity here
+        if (t == 0) s_any = 0;
+        __syncthreads();
+        for (int f = f0 + t; f < f1; f += kB) {
+            const int jb = s_order[f];
+            const int64_t e = s_jbase[jb] + lt;
+            if (a.tcnt[e] && (int64_t)a.tpre[e] < s_job[jb].out_cap) s_any = 1;
         }
-        const BatchSet& S = a.sets[sidx];
-        for (int j = 0; j < a.n_jobs; ++j) {
-            if (s_job[j].set != sidx) continue;
-            const float iso = s_job[j].iso;
-            uint32_t keep[PER], cs[PER];
-            uint32_t c = 0;
-#pragma unroll
-            for (int p = 0; p < PER; ++p) {
-                cs[p] = live[p] ? dual_case(d[p], iso) : 0u;
-                keep[p] = live[p] ? dual_keep(d[p], s_tab[cs[p]]) : 0u;
-                c += __popc(keep[p]);
-            }
+        __syncthreads();
+        const bool any = uniform_u32(s_any) != 0;
+        __syncthreads();  // every wave has read the flag before the next tile clears it
+        if (!any) continue;
+        const BatchSet S = uniform_set(a.sets[si]);
+        const Geo g = geo_of(S);
+        bool work;
+        int m;
+        uint32_t gx, gy, gz;
+        batch_load_tile<kG>(S, g, uniform_u32(s_ng[si]), lt, gi, j, s_iso + f0, f1 - f0, T, work, m, gx, gy, gz);
+        const int fa = uniform_i32(T.fa), fb = uniform_i32(T.fb);
+        const int ia = T.ia[gi], ib = T.ib[gi];
+        for (int f = fa; f < fb; ++f) {
+            const int jb = uniform_i32(s_order[f0 + f]);
+            const int64_t e = uniform_i64(s_jbase[jb] + lt);
+            const uint32_t n_out = uniform_u32(a.tcnt[e]);
+            const int64_t pre = (int64_t)uniform_u32(a.tpre[e]);
+            const float iso = __int_as_float(uniform_i32(__float_as_int(s_job[jb].iso)));
+            const int64_t out_offset = uniform_i64(s_job[jb].out_offset), out_cap = uniform_i64(s_job[jb].out_cap);
+            if (n_out == 0 || pre >= out_cap) continue;  // uniform over the work-group
+            int tid2 = threadIdx.x;
+            asm volatile("" : "+v"(tid2));
+            const int gi2 = tid2 >> 3, j2 = tid2 & 7;
+            const bool on = ia <= f && f < ib;
+            uint32_t items[4];
+            int n_dual = 0, n_tri = 0;
+            corner_items<false>(j2, m, iso, T.v[gi2], T.r[gi2], T.l[gi2], s_tab, on, items, n_dual, n_tri);
             uint32_t tot;
-            uint32_t pre = block_excl_scan(c, s_w, &tot);
-            // the thread's triangles in dual order: p = 0..PER-1 is not dual
-            // order within the tile when PER > 1 (duals are strided), so the
-            // rank of each triangle is recomputed per p
-            int64_t rel0 = (int64_t)a.tcount[s_jbase[j] + lt];
-            if (PER == 1) {
-                if (!c) continue;
-                int64_t rel = rel0 + pre;
-                int64_t di = lt * TS + t;
-                unsigned long long e = s_tab[cs[0]];
-                for (int tt = 0; tt < 5; ++tt) {
-                    if (!((keep[0] >> tt) & 1)) continue;
-                    if (rel < s_job[j].out_cap) {
-                        float* o = a.tris + 9 * (s_job[j].out_offset + rel);
-                        for (int v = 0; v < 3; ++v) {
-                            int ed = (int)((e >> (12 * tt + 4 * v)) & 0xF);
-                            int sa = edge_lo(ed), sb = edge_hi(ed);
-                            int ia = S.verts[8 * di + sa], ib = S.verts[8 * di + sb];
-                            float va = S.dvals[8 * di + sa], vb = S.dvals[8 * di + sb];
-                            if (va >= iso) {
-                                int tmp = ia;
-                                ia = ib;
-                                ib = tmp;
-                                float tv = va;
-                                va = vb;
-                                vb = tv;
-                            }
-                            float tp = (iso - va) / (vb - va);
-                            int la = S.lvl[ia], lb = S.lvl[ib];
-                            for (int ax = 0; ax < 3; ++ax) {
-                                float ca = (float)S.xyz[3 * ia + ax] + 0.5f * (float)(1 << la);
-                                float cb = (float)S.xyz[3 * ib + ax] + 0.5f * (float)(1 << lb);
-                                o[3 * v + ax] = fmaf(tp, cb - ca, ca);
-                            }
-                        }
-                    }
-                    ++rel;
-                }
-            } else {
-                // PER > 1: per slice p, a block scan keeps dual order
-                int64_t rel_slice = rel0;
-                (void)pre;
-                for (int p = 0; p < PER; ++p) {
-                    uint32_t cp = __popc(keep[p]);
-                    uint32_t totp;
-                    uint32_t prep = block_excl_scan(cp, s_w, &totp);
-                    int64_t rel = rel_slice + prep;
-                    int64_t di = lt * TS + (int64_t)p * blockDim.x + t;
-                    unsigned long long e = s_tab[cs[p]];
-                    for (int tt = 0; tt < 5 && cp; ++tt) {
-                        if (!((keep[p] >> tt) & 1)) continue;
-                        if (rel < s_job[j].out_cap) {
-                            float* o = a.tris + 9 * (s_job[j].out_offset + rel);
-                            for (int v = 0; v < 3; ++v) {
-                                int ed = (int)((e >> (12 * tt + 4 * v)) & 0xF);
-                                int sa = edge_lo(ed), sb = edge_hi(ed);
-                                int ia = S.verts[8 * di + sa], ib = S.verts[8 * di + sb];
-                                float va = S.dvals[8 * di + sa], vb = S.dvals[8 * di + sb];
-                                if (va >= iso) {
-                                    int tmp = ia;
-                                    ia = ib;
-                                    ib = tmp;
-                                    float tv = va;
-                                    va = vb;
-                                    vb = tv;
-                                }
-                                float tp = (iso - va) / (vb - va);
-                                int la = S.lvl[ia], lb = S.lvl[ib];
-                                for (int ax = 0; ax < 3; ++ax) {
-                                    float ca = (float)S.xyz[3 * ia + ax] + 0.5f * (float)(1 << la);
-                                    float cb = (float)S.xyz[3 * ib + ax] + 0.5f * (float)(1 << lb);
-                                    o[3 * v + ax] = fmaf(tp, cb - ca, ca);
-                                }
-                            }
-                        }
-                        ++rel;
-                    }
-                    rel_slice += totp;
-                }
-            }
+            const uint32_t first = block_excl_scan((uint32_t)n_tri, s_w, &tot);
+            write_triangles<kB>(tid2, g, iso, gi2, j2, m, gx, gy, gz, items, tot, first, 0u, out_offset + pre, 0,
+                                out_offset + out_cap, a.tris, nullptr, nullptr, nullptr, T.v, T.r, T.l, s_tab,
+                                s_items, s_dual, s_list, s_gm, s_gx);
+            __syncthreads();  // s_items / s_list are reused by the next job
         }
-        sidx = sn;
-        lt = ltn;
-#pragma unroll
-        for (int p = 0; p < PER; ++p) {
-            d[p] = dn[p];
-            live[p] = ln[p];
-        }
+        __syncthreads();
     }
 }
 
@@ -2222,6 +2335,363 @@ __global__ __launch_bounds__(256) void k_weld_index(int64_t n_corners, WeldWs w,
 }
 
 // ---------------------------------------------------------------------------
+// Dual-mesh interpolant.  The paper names the dual mesh as an interpolant
+// of the cell values (sec. 5, after Moran et al.) and leaves its use for
+// volume rendering to future work (sec. 7); it defines no interpolant.
+// Reading taken: a dual is the trilinear hexahedron over the centres of its
+// 8 vertex cells (slot s = ex + 2 ey + 4 ez at parameter (ex, ey, ez)) and
+// carries the trilinear interpolant of their values; a point takes the
+// value of the dual whose map reaches it, and where several do (shared
+// faces, and the duals that overlap when their cells span three or more
+// levels) the one with the smallest (level, P.z, P.y, P.x) wins.  The map
+// sends each corner of the unit cube to its slot's cell centre exactly, so
+// a dual reaches the centres of its vertex cells (with that cell's value);
+// Newton alone would leave those points to rounding where a degenerate
+// dual's map is singular.
+// Candidates for a point are the duals that have the point's cell as a
+// vertex: a map from every cell to its duals (CSR: offsets per cell, dual
+// indices) is built once per dual list.  The inverse map is Newton's method
+// from the centre in float64, 40 steps, each clamped to [-1/2, 3/2]; a dual
+// reaches the point when every Jacobian on the way was regular
+// (|det| > 1e-14), the final residual is below 1e-9 and the parameter lies
+// in [-1e-9, 1 + 1e-9] on every axis.
+// ---------------------------------------------------------------------------
+
+constexpr int kSmpPer = 16;  // cells per thread in the offset scan (4096 per work-group)
+constexpr int kSmpNewton = 40;
+constexpr double kSmpEps = 1e-9;
+constexpr double kSmpDet = 1e-14;
+
+// the dual's distinct vertex cells: slot s counts unless an earlier slot
+// holds the same cell (degenerate duals repeat cells); ids outside [0, n)
+// are skipped
+__device__ __forceinline__ uint32_t smp_distinct(const int32_t (&v)[8], int64_t n) {
+    uint32_t keep = 0;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        bool first = v[s] >= 0 && (int64_t)v[s] < n;
+#pragma unroll
+        for (int r = 0; r < s; ++r) first = first && v[r] != v[s];
+        keep |= (first ? 1u : 0u) << s;
+    }
+    return keep;
+}
+
+__device__ __forceinline__ void smp_load_verts(const int32_t* __restrict__ verts, int64_t d, int32_t (&v)[8]) {
+    const int4 a = reinterpret_cast<const int4*>(verts)[2 * d], b = reinterpret_cast<const int4*>(verts)[2 * d + 1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+
+__global__ __launch_bounds__(256) void k_smp_clear(uint32_t* __restrict__ cur, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        cur[i] = 0;
+}
+
+// duals per cell, and every dual's bounding box (the box of its vertex
+// cells' centres, exact in float32; a dual with a vertex outside [0, n) gets
+// an empty box)
+__global__ __launch_bounds__(256) void k_smp_count(const int32_t* __restrict__ verts, int64_t m, int64_t n,
+                                                   const int32_t* __restrict__ xyz, const int32_t* __restrict__ lvl,
+                                                   uint32_t* __restrict__ cur, float4* __restrict__ box) {
+    for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < m; d += (int64_t)gridDim.x * blockDim.x) {
+        int32_t v[8];
+        smp_load_verts(verts, d, v);
+        const uint32_t keep = smp_distinct(v, n);
+        float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        bool good = true;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            if ((keep >> s) & 1) atomicAdd(&cur[v[s]], 1u);
+            good = good && v[s] >= 0 && (int64_t)v[s] < n;
+            const int64_t c = good ? v[s] : 0;
+            const float h = 0.5f * (float)(1 << lvl[c]);
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                const float x = (float)xyz[3 * c + ax] + h;
+                lo[ax] = fminf(lo[ax], x);
+                hi[ax] = fmaxf(hi[ax], x);
+            }
+        }
+        if (!good) {
+            lo[0] = lo[1] = lo[2] = INFINITY;
+            hi[0] = hi[1] = hi[2] = -INFINITY;
+        }
+        box[2 * d] = make_float4(lo[0], lo[1], lo[2], 0.f);
+        box[2 * d + 1] = make_float4(hi[0], hi[1], hi[2], 0.f);
+    }
+}
+
+// sum of each work-group's 4096 counts
+__global__ __launch_bounds__(256) void k_smp_block_sums(const uint32_t* __restrict__ cur, int64_t n,
+                                                        int64_t* __restrict__ bsum) {
+    __shared__ unsigned long long s_w[4];
+    const int64_t base = (int64_t)blockIdx.x * (256 * kSmpPer);
+    unsigned long long x = 0;
+    for (int r = 0; r < kSmpPer; ++r) {
+        const int64_t i = base + r * 256 + threadIdx.x;
+        if (i < n) x += cur[i];
+    }
+    x = wave_reduce(x, [](unsigned long long p, unsigned long long q) { return p + q; });
+    if (lane_id() == 0) s_w[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) bsum[blockIdx.x] = (int64_t)(s_w[0] + s_w[1] + s_w[2] + s_w[3]);
+}
+
+// exclusive scan of the nb work-group sums in place (one work-group);
+// bsum[nb] receives the total
+__global__ __launch_bounds__(256) void k_smp_scan_sums(int64_t* __restrict__ bsum, int64_t nb) {
+    __shared__ unsigned long long s_w[4];
+    unsigned long long carry = 0;
+    for (int64_t c0 = 0; c0 < nb; c0 += 256) {
+        const int64_t i = c0 + threadIdx.x;
+        const unsigned long long x = i < nb ? (unsigned long long)bsum[i] : 0ull;
+        const unsigned long long incl = wave_incl_scan(x);
+        if (lane_id() == 63) s_w[threadIdx.x >> 6] = incl;
+        __syncthreads();
+        unsigned long long pre = 0, tot = 0;
+        for (int w = 0; w < 4; ++w) {
+            if (w < (int)(threadIdx.x >> 6)) pre += s_w[w];
+            tot += s_w[w];
+        }
+        if (i < nb) bsum[i] = (int64_t)(carry + pre + incl - x);
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bsum[nb] = (int64_t)carry;
+}
+
+// offsets of every cell's list; the counters restart at zero as fill cursors
+__global__ __launch_bounds__(256) void k_smp_offsets(uint32_t* __restrict__ cur, int64_t n,
+                                                     const int64_t* __restrict__ bsum, int64_t nb,
+                                                     int64_t* __restrict__ off) {
+    __shared__ unsigned long long s_w[kSmpPer][4];
+    const int t = threadIdx.x, wave = t >> 6, lane = lane_id();
+    const int64_t base = (int64_t)blockIdx.x * (256 * kSmpPer);
+    unsigned long long v[kSmpPer], incl[kSmpPer];
+#pragma unroll
+    for (int r = 0; r < kSmpPer; ++r) {
+        const int64_t i = base + r * 256 + t;
+        v[r] = i < n ? cur[i] : 0u;
+        incl[r] = wave_incl_scan(v[r]);
+        if (lane == 63) s_w[r][wave] = incl[r];
+    }
+    __syncthreads();
+    unsigned long long carry = (unsigned long long)bsum[blockIdx.x];
+    for (int r = 0; r < kSmpPer; ++r) {
+        unsigned long long pre = 0, row = 0;
+        for (int w = 0; w < 4; ++w) {
+            if (w < wave) pre += s_w[r][w];
+            row += s_w[r][w];
+        }
+        const int64_t i = base + r * 256 + t;
+        if (i < n) {
+            off[i] = (int64_t)(carry + pre + incl[r] - v[r]);
+            cur[i] = 0;
+        }
+        carry += row;
+    }
+    if (blockIdx.x == 0 && t == 0) off[n] = bsum[nb];
+}
+
+// every dual into the lists of its distinct vertex cells
+__global__ __launch_bounds__(256) void k_smp_fill(const int32_t* __restrict__ verts, int64_t m, int64_t n,
+                                                  const int64_t* __restrict__ off, uint32_t* __restrict__ cur,
+                                                  uint32_t* __restrict__ ent) {
+    for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < m; d += (int64_t)gridDim.x * blockDim.x) {
+        int32_t v[8];
+        smp_load_verts(verts, d, v);
+        const uint32_t keep = smp_distinct(v, n);
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+            if ((keep >> s) & 1) ent[off[v[s]] + atomicAdd(&cur[v[s]], 1u)] = (uint32_t)d;
+    }
+}
+
+struct SampleArgs {
+    const Record* rec;
+    const int32_t* ids;
+    const Ctrl* ctrl;
+    const int32_t* xyz;
+    const int32_t* lvl;
+    const float* val;
+    int64_t n;
+    const int32_t* corner_level;
+    const int32_t* verts;
+    const int64_t* off;
+    const uint32_t* ent;
+    const float4* box;
+    const float* pts;
+    int64_t n_pts;
+    float* out;
+    int64_t* dual;
+};
+
+// (level, z, y, x) of a dual, compared lexicographically
+__device__ __forceinline__ bool smp_key_less(const int4& a, const int4& b) {
+    if (a.w != b.w) return a.w < b.w;
+    if (a.z != b.z) return a.z < b.z;
+    if (a.y != b.y) return a.y < b.y;
+    return a.x < b.x;
+}
+
+// The cell containing the finest-level position (ix, iy, iz), or -1: from
+// the coarsest level down, the record of the block holding the position
+// says "a cell" (done), "refined" (finer cells inside: go down) or nothing
+// (no cell covers the position).
+__device__ __forceinline__ int64_t smp_locate(const SampleArgs& a, const Geo& g, int64_t ix, int64_t iy,
+                                              int64_t iz) {
+    const int64_t ux = ix - g.ox, uy = iy - g.oy, uz = iz - g.oz;
+    if (ux < 0 || uy < 0 || uz < 0 || ux >= kSpanLimit || uy >= kSpanLimit || uz >= kSpanLimit) return -1;
+    for (int L = g.lmax; L >= 0; --L) {
+        const int slot = probe(a.rec, group_key(L, (uint32_t)ux >> (L + 1), (uint32_t)uy >> (L + 1),
+                                                (uint32_t)uz >> (L + 1)),
+                               g.shift, g.mask);
+        if (slot < 0) return -1;
+        const int c = (int)(((ux >> L) & 1) | (((uy >> L) & 1) << 1) | (((uz >> L) & 1) << 2));
+        const uint32_t bits = __float_as_uint(a.rec[slot].val[c]);
+        if (bits == kValRefined) continue;
+        if (bits == kValEmpty) return -1;
+        return a.ids[(size_t)slot * 8 + c];
+    }
+    return -1;
+}
+
+__device__ __forceinline__ double smp_det3(const double (&J)[3][3]) {
+    return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+// Does the trilinear map of the hexahedron V reach p?  On success u is the
+// parameter of p.
+__device__ bool smp_invert(const double (&V)[8][3], const double (&p)[3], double (&u)[3]) {
+    u[0] = u[1] = u[2] = 0.5;
+    for (int it = 0; it < kSmpNewton; ++it) {
+        double x[3] = {0.0, 0.0, 0.0}, J[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const double fx = (s & 1) ? u[0] : 1.0 - u[0], fy = (s & 2) ? u[1] : 1.0 - u[1],
+                         fz = (s & 4) ? u[2] : 1.0 - u[2];
+            const double dx = (s & 1) ? 1.0 : -1.0, dy = (s & 2) ? 1.0 : -1.0, dz = (s & 4) ? 1.0 : -1.0;
+            const double w = fx * fy * fz, d0 = dx * fy * fz, d1 = fx * dy * fz, d2 = fx * fy * dz;
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                x[ax] += w * V[s][ax];
+                J[ax][0] += d0 * V[s][ax];
+                J[ax][1] += d1 * V[s][ax];
+                J[ax][2] += d2 * V[s][ax];
+            }
+        }
+        const double det = smp_det3(J);
+        if (!(fabs(det) > kSmpDet)) return false;  // a singular step: this dual does not take the point
+        const double r[3] = {p[0] - x[0], p[1] - x[1], p[2] - x[2]};
+        // Cramer's rule: step_b = det(J with column b replaced by r) / det
+        double st[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            double M[3][3];
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) M[ax][c] = c == b ? r[ax] : J[ax][c];
+            st[b] = smp_det3(M) / det;
+        }
+#pragma unroll
+        for (int b = 0; b < 3; ++b) u[b] = fmin(fmax(u[b] + st[b], -0.5), 1.5);
+        // converged: the remaining steps would only move u by rounding
+        if (fmax(fabs(st[0]), fmax(fabs(st[1]), fabs(st[2]))) < 1e-15) break;
+    }
+    double x[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const double w = ((s & 1) ? u[0] : 1.0 - u[0]) * ((s & 2) ? u[1] : 1.0 - u[1]) * ((s & 4) ? u[2] : 1.0 - u[2]);
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) x[ax] += w * V[s][ax];
+    }
+    double res = 0.0;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) res = fmax(res, fabs(x[ax] - p[ax]));
+    if (!(res < kSmpEps)) return false;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax)
+        if (!(u[ax] >= -kSmpEps && u[ax] <= 1.0 + kSmpEps)) return false;
+    return true;
+}
+
+// One thread per point.
+__global__ __launch_bounds__(256) void k_smp_query(SampleArgs a) {
+    const bool ok = a.ctrl->status == AMR_OK;
+    const Geo g = a.ctrl->geo;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < a.n_pts;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const double p[3] = {(double)a.pts[3 * q], (double)a.pts[3 * q + 1], (double)a.pts[3 * q + 2]};
+        float value = __uint_as_float(0x7fc00000u);
+        int64_t best = -1;
+        int64_t c = -1;
+        // finest-level position of the point (floor), inside the coordinate limits
+        if (ok && fabs(p[0]) < (double)kCoordLimit && fabs(p[1]) < (double)kCoordLimit &&
+            fabs(p[2]) < (double)kCoordLimit)
+            c = smp_locate(a, g, (int64_t)floor(p[0]), (int64_t)floor(p[1]), (int64_t)floor(p[2]));
+        if (c >= 0) {
+            int4 bkey = make_int4(0, 0, 0, 0x7fffffff);
+            const int64_t e1 = a.off[c + 1];
+            for (int64_t e = a.off[c]; e < e1; ++e) {
+                const int64_t d = a.ent[e];
+                const int4 key = reinterpret_cast<const int4*>(a.corner_level)[d];
+                if (best >= 0 && !smp_key_less(key, bkey)) continue;
+                // the dual's box, then its cells
+                const float4 b0 = a.box[2 * d], b1 = a.box[2 * d + 1];
+                if (!(p[0] >= (double)b0.x - kSmpEps && p[0] <= (double)b1.x + kSmpEps &&
+                      p[1] >= (double)b0.y - kSmpEps && p[1] <= (double)b1.y + kSmpEps &&
+                      p[2] >= (double)b0.z - kSmpEps && p[2] <= (double)b1.z + kSmpEps))
+                    continue;
+                int32_t v[8];
+                smp_load_verts(a.verts, d, v);
+                double V[8][3];
+                bool good = true;
+#pragma unroll
+                for (int s = 0; s < 8; ++s) {
+                    const int64_t id = v[s];
+                    good = good && id >= 0 && id < a.n;
+                    const int64_t ci = good ? id : 0;
+                    const double h = 0.5 * (double)(1 << a.lvl[ci]);
+#pragma unroll
+                    for (int ax = 0; ax < 3; ++ax) V[s][ax] = (double)a.xyz[3 * ci + ax] + h;
+                }
+                if (!good) continue;
+                // the map sends each cube corner to its slot's cell centre
+                // exactly: a vertex cell centred at p settles it (first slot)
+                int at = -1;
+#pragma unroll
+                for (int s = 7; s >= 0; --s)
+                    if (V[s][0] == p[0] && V[s][1] == p[1] && V[s][2] == p[2]) at = s;
+                if (at >= 0) {
+                    best = d;
+                    bkey = key;
+                    value = a.val[v[at]];
+                    continue;
+                }
+                double u[3];
+                if (!smp_invert(V, p, u)) continue;
+                double f = 0.0;
+#pragma unroll
+                for (int s = 0; s < 8; ++s) {
+                    const double ux = fmin(fmax(u[0], 0.0), 1.0), uy = fmin(fmax(u[1], 0.0), 1.0),
+                                 uz = fmin(fmax(u[2], 0.0), 1.0);
+                    const double w = ((s & 1) ? ux : 1.0 - ux) * ((s & 2) ? uy : 1.0 - uy) * ((s & 4) ? uz : 1.0 - uz);
+                    f += w * (double)a.val[v[s]];
+                }
+                best = d;
+                bkey = key;
+                value = (float)f;
+            }
+        }
+        a.out[q] = value;
+        if (a.dual) a.dual[q] = best;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 
@@ -2289,6 +2759,8 @@ struct amr_set {
     int32_t* ids = nullptr;
     bool ids_ready = false;  // input indices filled in (on first use)
     int extractions = 0;     // extraction calls since the build (saturates at 2)
+    uint64_t build_gen = 0;  // builds so far
+    uint64_t smp_gen = ~0ull;  // the build a dual-mesh sampler was made for
     float2* rng = nullptr;
     unsigned long long* dual_total = nullptr;
     uint32_t* clist = nullptr;              // group list of a list pass, its length,
@@ -2430,16 +2902,25 @@ int grid_for(int64_t n, int block) {
 // the slots are in use.
 uint32_t max_groups_of(uint32_t cap) { return cap - cap / 4; }
 
+// The input index of every cell beside its value in the table, filled in
+// once per build, when a call first needs it.
+int ensure_ids(amr_set* s, hipStream_t stream) {
+    if (s->ids_ready || s->n == 0) return AMR_OK;
+    hipLaunchKernelGGL(k_index_ids, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->n, s->ctrl,
+                       s->rec, s->ids);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hipfail(e, "cell index map");
+    s->ids_ready = true;
+    return AMR_OK;
+}
+
 int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_cells, int64_t* tri_dual,
                    int32_t* corner_level, int32_t* verts, float* dvals, int64_t cap, int64_t* counts,
                    hipStream_t stream) {
-    if ((duals ? verts != nullptr : tri_cells != nullptr) && cap > 0 && !s->ids_ready && s->n > 0) {
-        // outputs name input indices: fill them in once per build
-        hipLaunchKernelGGL(k_index_ids, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->n,
-                           s->ctrl, s->rec, s->ids);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return hipfail(e, "extract: cell index map");
-        s->ids_ready = true;
+    if ((duals ? verts != nullptr : tri_cells != nullptr) && cap > 0) {
+        // outputs name input indices
+        const int st = ensure_ids(s, stream);
+        if (st != AMR_OK) return st;
     }
     // The group count lives on the device; the grids cover the bound the
     // build enforced, and work-groups past the last tile leave at once.
@@ -2550,22 +3031,31 @@ struct amr_batch {
     int device = 0;
     int n_sets = 0;
     BatchSet* d_sets = nullptr;  // device table
-    int64_t max_set_duals = 0;
+    uint32_t max_groups = 0;     // the largest group bound of the sets (their extraction grids)
     int cu_count = 0;
 };
 
 namespace {
 
-int batch_grid(const amr_batch* b, int block, int per, int64_t n_tiles) {
-    // at most two resident work-groups per compute unit (the barrier needs
-    // every work-group of the grid on the GPU at once)
-    int per_cu = 0;
-    hipError_t e;
-    if (per == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<1>, block, 0);
-    else if (per == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<2>, block, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<4>, block, 0);
-    if (e != hipSuccess || per_cu < 1) per_cu = 1;
-    if (per_cu > 2) per_cu = 2;
+int batch_check_shape(int block, int per_cu) {
+    if (block != 128 && block != 256) return fail(AMR_EINVAL, "batched launch: block must be 128 or 256");
+    if (per_cu < 1 || per_cu > 4) return fail(AMR_EINVAL, "batched launch: 1..4 work-groups per compute unit");
+    return AMR_OK;
+}
+
+int64_t batch_tiles(const amr_batch* b, int block) {
+    const int64_t g = block / 8;
+    const int64_t t = ((int64_t)b->max_groups + g - 1) / g;
+    return t > 0 ? t : 1;
+}
+
+int batch_grid(const amr_batch* b, int block, int per_cu, int64_t n_tiles) {
+    // every work-group of the grid must be on the GPU at once (grid barriers)
+    int occ = 0;
+    hipError_t e = block == 128 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch<16>, 128, 0)
+                                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch<32>, 256, 0);
+    if (e != hipSuccess || occ < 1) occ = 1;
+    if (per_cu > occ) per_cu = occ;
     int64_t g = (int64_t)b->cu_count * per_cu;
     if (g > kMaxBatchGrid) g = kMaxBatchGrid;
     if (g > n_tiles) g = n_tiles;
@@ -2900,8 +3390,9 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     {
         const int64_t most = s->n < (int64_t)cap ? s->n : (int64_t)cap;  // at least the number of groups
         launch(s, AMR_KERNEL_MARK, k_index_mark, dim3(grid_for(most, 256)), dim3(256), stream, s->rec, s->gkey,
-               s->n, cap, s->grid_groups, s->ctrl);
+               s->ctrl);
     }
+    hipLaunchKernelGGL(k_index_verdict, dim3(1), dim3(64), 0, stream, s->n, cap, s->grid_groups, s->ctrl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hipfail(e, "amr_build_index: launch");
     s->build_captured = in_graph;
@@ -2915,6 +3406,7 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     s->build_status = kStatusPending;
     s->ids_ready = false;
     s->extractions = 0;
+    ++s->build_gen;
     s->last_cap = cap;
     s->last_n = s->n;
     g_err[0] = 0;
@@ -2956,16 +3448,14 @@ int amr_isosurface(amr_set* s, float iso, float* tris, int32_t* tri_cells, int64
 }
 
 
-int amr_batch_create(amr_batch** out, amr_set* const* sets, const int32_t* const* dual_verts,
-                     const float* const* dual_vals, const int64_t* n_duals, int n_sets) {
+int amr_batch_create(amr_batch** out, amr_set* const* sets, int n_sets) {
     if (!out) return fail(AMR_EINVAL, "amr_batch_create: out is NULL");
     *out = nullptr;
-    if (!sets || !dual_verts || !dual_vals || !n_duals || n_sets < 1 || n_sets > kMaxSets)
-        return fail(AMR_EINVAL, "amr_batch_create: need 1..%d sets", kMaxSets);
+    if (!sets || n_sets < 1 || n_sets > kMaxSets) return fail(AMR_EINVAL, "amr_batch_create: need 1..%d sets", kMaxSets);
     int dev = sets[0] ? sets[0]->device : -1;
     BatchSet* host = (BatchSet*)calloc((size_t)n_sets, sizeof(BatchSet));
     if (!host) return fail(AMR_ENOMEM, "amr_batch_create: out of host memory");
-    int64_t mx = 0;
+    uint32_t mg = 0;
     for (int i = 0; i < n_sets; ++i) {
         const amr_set* s = sets[i];
         if (!s || s->device != dev) {
@@ -2976,16 +3466,13 @@ int amr_batch_create(amr_batch** out, amr_set* const* sets, const int32_t* const
             free(host);
             return fail(AMR_ESTATE, "amr_batch_create: set %d has no index", i);
         }
-        if (n_duals[i] < 0 || (n_duals[i] > 0 && (!dual_verts[i] || !dual_vals[i]))) {
-            free(host);
-            return fail(AMR_EINVAL, "amr_batch_create: bad dual list for set %d", i);
-        }
-        host[i].verts = dual_verts[i];
-        host[i].dvals = dual_vals[i];
-        host[i].xyz = s->xyz;
-        host[i].lvl = s->lvl;
-        host[i].n_duals = n_duals[i];
-        if (n_duals[i] > mx) mx = n_duals[i];
+        host[i].rec = s->rec;
+        host[i].glist = s->glist;
+        host[i].gkey = s->gkey;
+        host[i].ctrl = s->ctrl;
+        host[i].rng = s->rng;
+        host[i].rng_ok = &s->sched->rng_ok;
+        if (s->grid_groups > mg) mg = s->grid_groups;
     }
     DeviceGuard dg(dev);
     amr_batch* b = new (std::nothrow) amr_batch();
@@ -2995,7 +3482,7 @@ int amr_batch_create(amr_batch** out, amr_set* const* sets, const int32_t* const
     }
     b->device = dev;
     b->n_sets = n_sets;
-    b->max_set_duals = mx;
+    b->max_groups = mg;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) prop.multiProcessorCount = 1;
     b->cu_count = prop.multiProcessorCount;
@@ -3021,29 +3508,29 @@ void amr_batch_destroy(amr_batch* b) {
     delete b;
 }
 
-int amr_batch_workspace_bytes(const amr_batch* b, int max_jobs, int block, int per_thread, size_t* bytes) {
+int amr_batch_workspace_bytes(const amr_batch* b, int max_jobs, int block, int per_cu, size_t* bytes) {
     if (!b || !bytes) return fail(AMR_EINVAL, "amr_batch_workspace_bytes: NULL argument");
     if (max_jobs < 1 || max_jobs > kMaxJobs) return fail(AMR_EINVAL, "amr_batch_workspace_bytes: 1..%d jobs", kMaxJobs);
-    if (block != 64 && block != 128 && block != 256 && block != 512)
-        return fail(AMR_EINVAL, "amr_batch_workspace_bytes: block must be 64, 128, 256 or 512");
-    if (per_thread != 1 && per_thread != 2 && per_thread != 4)
-        return fail(AMR_EINVAL, "amr_batch_workspace_bytes: per_thread must be 1, 2 or 4");
-    int64_t ts = (int64_t)block * per_thread;
-    int64_t tiles = (b->max_set_duals + ts - 1) / ts;
-    *bytes = align256(sizeof(GridBar)) + align256((size_t)kMaxBatchGrid * sizeof(uint32_t)) +
-             align256((size_t)max_jobs * (size_t)tiles * sizeof(uint32_t));
+    const int st = batch_check_shape(block, per_cu);
+    if (st != AMR_OK) return st;
+    const size_t per = (size_t)max_jobs * (size_t)batch_tiles(b, block) * sizeof(uint32_t);
+    *bytes = align256(sizeof(GridBar)) + align256((size_t)kMaxBatchGrid * sizeof(uint32_t)) + 2 * align256(per);
+    g_err[0] = 0;
     return AMR_OK;
 }
 
 int amr_batch_isosurface(amr_batch* b, const amr_iso_job* jobs, int n_jobs, float* tris, int64_t* counts, void* ws,
-                         size_t bytes, int block, int per_thread, hipStream_t stream) {
+                         size_t bytes, int block, int per_cu, hipStream_t stream) {
     if (!b || !jobs || !counts) return fail(AMR_EINVAL, "amr_batch_isosurface: NULL argument");
     size_t need = 0;
-    int st = amr_batch_workspace_bytes(b, n_jobs, block, per_thread, &need);
+    int st = amr_batch_workspace_bytes(b, n_jobs, block, per_cu, &need);
     if (st != AMR_OK) return st;
     if (!ws || ((uintptr_t)ws & 255)) return fail(AMR_EINVAL, "amr_batch_isosurface: workspace NULL or unaligned");
     if (bytes < need) return fail(AMR_ENOSPACE, "amr_batch_isosurface: workspace %zu bytes, need %zu", bytes, need);
     DeviceGuard dg(b->device);
+    const int64_t tiles = batch_tiles(b, block);
+    const size_t per = align256((size_t)n_jobs * (size_t)tiles * sizeof(uint32_t));
+    char* w = (char*)ws;
     BatchArgs a;
     a.sets = b->d_sets;
     a.n_sets = b->n_sets;
@@ -3051,20 +3538,16 @@ int amr_batch_isosurface(amr_batch* b, const amr_iso_job* jobs, int n_jobs, floa
     a.n_jobs = n_jobs;
     a.tris = tris;
     a.counts = counts;
-    a.bar = (GridBar*)ws;
-    a.bsum = (uint32_t*)((char*)ws + align256(sizeof(GridBar)));
-    a.tcount = (uint32_t*)((char*)ws + align256(sizeof(GridBar)) + align256((size_t)kMaxBatchGrid * sizeof(uint32_t)));
-    int64_t ts = (int64_t)block * per_thread;
-    int64_t n_tiles = 0;
-    // an upper bound is enough for the grid size: every set's tile count
-    n_tiles = ((b->max_set_duals + ts - 1) / ts) * b->n_sets;
-    int grid = batch_grid(b, block, per_thread, n_tiles);
-    if (per_thread == 1)
-        hipLaunchKernelGGL(k_batch<1>, dim3(grid), dim3(block), 0, stream, a);
-    else if (per_thread == 2)
-        hipLaunchKernelGGL(k_batch<2>, dim3(grid), dim3(block), 0, stream, a);
+    a.bar = (GridBar*)w;
+    a.bsum = (uint32_t*)(w + align256(sizeof(GridBar)));
+    a.tcnt = (uint32_t*)(w + align256(sizeof(GridBar)) + align256((size_t)kMaxBatchGrid * sizeof(uint32_t)));
+    a.tpre = (uint32_t*)((char*)a.tcnt + per);
+    // the grid for an upper bound of the tiles (group counts are on the device)
+    const int grid = batch_grid(b, block, per_cu, tiles * b->n_sets);
+    if (block == 128)
+        hipLaunchKernelGGL(k_batch<16>, dim3(grid), dim3(128), 0, stream, a);
     else
-        hipLaunchKernelGGL(k_batch<4>, dim3(grid), dim3(block), 0, stream, a);
+        hipLaunchKernelGGL(k_batch<32>, dim3(grid), dim3(256), 0, stream, a);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? AMR_OK : hipfail(e, "amr_batch_isosurface: launch");
 }
@@ -3147,9 +3630,127 @@ int amr_indexed_mesh(const float* tris, const int32_t* tri_cells, int64_t n_tris
     return e == hipSuccess ? AMR_OK : hipfail(e, "amr_indexed_mesh: launch");
 }
 
+namespace {
+// Sampler workspace: per cell the offset of its dual list (int64, n + 1),
+// per cell a counter (uint32), the lists (uint32 dual indices, at most 8 per
+// dual), per dual its bounding box (2 x float4) and the work-group sums of
+// the offset scan.
+struct SmpLayout {
+    int64_t nb;
+    size_t off, cur, ent, box, bsum, total;
+};
+
+bool smp_layout(int64_t n, int64_t m, SmpLayout& L) {
+    if (n < 0 || m < 0 || m > (int64_t)0xFFFFFFFFll) return false;
+    L.nb = (n + 256 * kSmpPer - 1) / (256 * kSmpPer);
+    if (L.nb < 1) L.nb = 1;
+    size_t o = 0;
+    L.off = o;
+    o = align256(o + (size_t)(n + 1) * 8);
+    L.cur = o;
+    o = align256(o + (size_t)n * 4 + 4);
+    L.ent = o;
+    o = align256(o + (size_t)m * 8 * 4 + 4);
+    L.box = o;
+    o = align256(o + (size_t)m * 32 + 32);
+    L.bsum = o;
+    o = align256(o + (size_t)(L.nb + 1) * 8);
+    L.total = o;
+    return true;
+}
+}  // namespace
+
+int amr_sampler_bytes(const amr_set* s, int64_t n_duals, size_t* bytes) {
+    if (!s || !bytes) return fail(AMR_EINVAL, "amr_sampler_bytes: NULL argument");
+    SmpLayout L;
+    if (!smp_layout(s->n, n_duals, L)) return fail(AMR_ERANGE, "amr_sampler_bytes: n_duals out of range");
+    *bytes = L.total;
+    g_err[0] = 0;
+    return AMR_OK;
+}
+
+int amr_sampler_build(amr_set* s, const int32_t* verts, int64_t n_duals, void* ws, size_t bytes,
+                      hipStream_t stream) {
+    if (!s) return fail(AMR_EINVAL, "amr_sampler_build: set is NULL");
+    if (!s->built) return fail(AMR_ESTATE, "amr_sampler_build: call amr_build_index first");
+    SmpLayout L;
+    if (!smp_layout(s->n, n_duals, L)) return fail(AMR_ERANGE, "amr_sampler_build: n_duals out of range");
+    if (n_duals > 0 && !verts) return fail(AMR_EINVAL, "amr_sampler_build: verts is NULL");
+    if (!ws || ((uintptr_t)ws & 255)) return fail(AMR_EINVAL, "amr_sampler_build: workspace NULL or not 256-B aligned");
+    if (bytes < L.total)
+        return fail(AMR_ENOSPACE, "amr_sampler_build: workspace of %zu bytes, need %zu", bytes, L.total);
+    DeviceGuard dg(s->device);
+    int st = ensure_ids(s, stream);
+    if (st != AMR_OK) return st;
+    char* b = (char*)ws;
+    int64_t* off = (int64_t*)(b + L.off);
+    uint32_t* cur = (uint32_t*)(b + L.cur);
+    uint32_t* ent = (uint32_t*)(b + L.ent);
+    int64_t* bsum = (int64_t*)(b + L.bsum);
+    const int64_t n = s->n;
+    hipLaunchKernelGGL(k_smp_clear, dim3(grid_for(n, 256)), dim3(256), 0, stream, cur, n);
+    if (n_duals > 0)
+        hipLaunchKernelGGL(k_smp_count, dim3(grid_for(n_duals, 256)), dim3(256), 0, stream, verts, n_duals, n, s->xyz,
+                           s->lvl, cur, (float4*)(b + L.box));
+    hipLaunchKernelGGL(k_smp_block_sums, dim3(L.nb), dim3(256), 0, stream, cur, n, bsum);
+    hipLaunchKernelGGL(k_smp_scan_sums, dim3(1), dim3(256), 0, stream, bsum, L.nb);
+    hipLaunchKernelGGL(k_smp_offsets, dim3(L.nb), dim3(256), 0, stream, cur, n, bsum, L.nb, off);
+    if (n_duals > 0)
+        hipLaunchKernelGGL(k_smp_fill, dim3(grid_for(n_duals, 256)), dim3(256), 0, stream, verts, n_duals, n, off,
+                           cur, ent);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hipfail(e, "amr_sampler_build: launch");
+    s->smp_gen = s->build_gen;
+    g_err[0] = 0;
+    return AMR_OK;
+}
+
+int amr_sample(amr_set* s, const int32_t* corner_level, const int32_t* verts, int64_t n_duals, const void* ws,
+               size_t bytes, const float* points, int64_t n_points, float* values, int64_t* dual,
+               hipStream_t stream) {
+    if (!s) return fail(AMR_EINVAL, "amr_sample: set is NULL");
+    if (!s->built || s->smp_gen != s->build_gen)
+        return fail(AMR_ESTATE, "amr_sample: no sampler built for the current index (amr_sampler_build)");
+    SmpLayout L;
+    if (!smp_layout(s->n, n_duals, L)) return fail(AMR_ERANGE, "amr_sample: n_duals out of range");
+    if (n_points < 0) return fail(AMR_EINVAL, "amr_sample: negative n_points");
+    if (n_points > 0 && (!points || !values)) return fail(AMR_EINVAL, "amr_sample: NULL points or values");
+    if (n_duals > 0 && (!corner_level || !verts)) return fail(AMR_EINVAL, "amr_sample: NULL dual arrays");
+    if (!ws || ((uintptr_t)ws & 255)) return fail(AMR_EINVAL, "amr_sample: workspace NULL or not 256-B aligned");
+    if (bytes < L.total) return fail(AMR_ENOSPACE, "amr_sample: workspace of %zu bytes, need %zu", bytes, L.total);
+    if (n_points == 0) {
+        g_err[0] = 0;
+        return AMR_OK;
+    }
+    DeviceGuard dg(s->device);
+    const char* b = (const char*)ws;
+    SampleArgs a;
+    a.rec = s->rec;
+    a.ids = s->ids;
+    a.ctrl = s->ctrl;
+    a.xyz = s->xyz;
+    a.lvl = s->lvl;
+    a.val = s->val;
+    a.n = s->n;
+    a.corner_level = corner_level;
+    a.verts = verts;
+    a.off = (const int64_t*)(b + L.off);
+    a.ent = (const uint32_t*)(b + L.ent);
+    a.box = (const float4*)(b + L.box);
+    a.pts = points;
+    a.n_pts = n_points;
+    a.out = values;
+    a.dual = dual;
+    launch(s, AMR_KERNEL_SAMPLE, k_smp_query, dim3(grid_for(n_points, 256)), dim3(256), stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hipfail(e, "amr_sample: launch");
+    g_err[0] = 0;
+    return AMR_OK;
+}
+
 int amr_time_kernel(amr_set* s, int kernel, hipEvent_t start, hipEvent_t stop) {
     if (!s) return fail(AMR_EINVAL, "amr_time_kernel: set is NULL");
-    if (kernel < 0 || kernel > AMR_KERNEL_WRITE) return fail(AMR_EINVAL, "amr_time_kernel: unknown kernel %d", kernel);
+    if (kernel < 0 || kernel > AMR_KERNEL_SAMPLE) return fail(AMR_EINVAL, "amr_time_kernel: unknown kernel %d", kernel);
     if (kernel != 0 && (!start || !stop)) return fail(AMR_EINVAL, "amr_time_kernel: NULL event");
     s->time_kernel = kernel;
     s->time_start = start;

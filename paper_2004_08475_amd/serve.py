@@ -1,15 +1,15 @@
 """Continuous-batching iso-surface server on one GPU.
 
-A resident AMR set stays on the device with its index and dual cells.
-Requests arrive over time:
+A resident AMR set stays on the device with its index.  Requests arrive
+over time:
 
   * IsoRequest(iso): an iso-surface of the resident set.  Requests that are
     waiting when the iso stream becomes free are taken together: as one
-    batched launch (amr_batch_isosurface over the resident set's dual
-    cells, the iso-independent topology never recomputed) or as plain
-    passes one after the other (which cull groups by their value ranges),
-    whichever a start-up calibration says is cheaper for that many.  New
-    requests join the next batch instead of waiting for a queue to drain.
+    batched launch (amr_batch_isosurface: each tile's neighbourhoods read
+    once, every waiting iso run against them) or as plain passes one after
+    the other, whichever a start-up calibration says is cheaper for that
+    many; both skip groups by their recorded value ranges.  New requests
+    join the next batch instead of waiting for a queue to drain.
   * UploadRequest(xyz, level, value, iso): a new small set; it is copied
     to the GPU, validated, indexed and extracted on one of several upload
     streams, overlapping on the device with the iso work.
@@ -144,7 +144,7 @@ class _UploadSlot:
 
 class IsoServer:
     def __init__(self, resident: AmrSet, hbm_budget: int | None = None, upload_slots: int = 4,
-                 max_batch: int = 64, block: int | None = None, per_thread: int | None = None,
+                 max_batch: int = 64, block: int | None = None, per_cu: int | None = None,
                  curve_points: int = 64, upload_max_cells: int = 0):
         self.resident = resident
         self.device = resident.device
@@ -163,7 +163,7 @@ class IsoServer:
         counts = torch.zeros(curve_points, dtype=torch.int64, device=self.device)
         jobs = self.batch.jobs_tensor([0] * curve_points, self.curve_iso, np.zeros(curve_points),
                                       np.zeros(curve_points))
-        if block is None or per_thread is None:
+        if block is None or per_cu is None:
             # launch shape for this set: the autotuner on a counting launch of
             # a few isos from the middle of the curve (no output memory)
             from . import autotune
@@ -172,9 +172,9 @@ class IsoServer:
             mid = self.curve_iso[curve_points // 4:curve_points // 4 + k]
             tj = self.batch.jobs_tensor([0] * k, mid, np.zeros(k), np.zeros(k))
             tc = torch.zeros(k, dtype=torch.int64, device=self.device)
-            block, per_thread, _ = autotune.tune(self.batch, tj, k, None, tc, reps=2)
-        self.block, self.per_thread = block, per_thread
-        self.batch.run_into(jobs, curve_points, None, counts, block, per_thread)
+            block, per_cu, _ = autotune.tune(self.batch, tj, k, None, tc, reps=2)
+        self.block, self.per_cu = block, per_cu
+        self.batch.run_into(jobs, curve_points, None, counts, block, per_cu)
         self.curve_tri = counts.cpu().numpy()
         # per request, the plain single pass against a batched launch (fixed
         # part + part per job), timed once here; a batch of n waiting
@@ -222,8 +222,8 @@ class IsoServer:
             return (time.perf_counter() - t0) / reps
 
         t_plain = run(lambda: self.resident.isosurface_into(isos[0], tris, caps[0]))
-        t1 = run(lambda: self.batch.run_into(jobs1, 1, tris, counts, self.block, self.per_thread))
-        t2 = run(lambda: self.batch.run_into(jobs2, 2, tris, counts, self.block, self.per_thread))
+        t1 = run(lambda: self.batch.run_into(jobs1, 1, tris, counts, self.block, self.per_cu))
+        t2 = run(lambda: self.batch.run_into(jobs2, 2, tris, counts, self.block, self.per_cu))
         per_job = max(t2 - t1, 0.0)
         return t_plain, max(t1 - per_job, 0.0), per_job
 
@@ -279,13 +279,13 @@ class IsoServer:
                 tris = self._iso_out.rows(int(caps.sum()))
                 counts = self._batch_counts[:n]
                 jobs = self.batch.jobs_tensor([0] * n, isos, off, caps)
-                self.batch.run_into(jobs, n, tris, counts, self.block, self.per_thread)
+                self.batch.run_into(jobs, n, tris, counts, self.block, self.per_cu)
                 c = counts.cpu().numpy()
                 # a grid barrier that gave up leaves invalid results and a
                 # barrier in an unknown state: clear it, serve these plainly
-                timed_out = self.batch.barrier_timed_out(self.block, self.per_thread)
+                timed_out = self.batch.barrier_timed_out(self.block, self.per_cu)
                 if timed_out:
-                    self.batch.reset_barrier(self.block, self.per_thread)
+                    self.batch.reset_barrier(self.block, self.per_cu)
                     self.barrier_timeouts += 1
                     stream.synchronize()
                     return

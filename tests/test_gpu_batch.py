@@ -65,7 +65,7 @@ def shell(amr):
     return cs, amr.from_numpy(cs.xyz, cs.level, cs.value)
 
 
-@pytest.mark.parametrize("block,per", [(256, 1), (128, 2), (512, 1), (64, 4)])
+@pytest.mark.parametrize("block,per", [(256, 1), (128, 2), (256, 4), (128, 3)])
 def test_many_isos_one_set_equal_plain(amr, shell, block, per):
     cs, s = shell
     isos = np.quantile(cs.value, np.linspace(0.05, 0.95, 16)).astype(np.float32)
@@ -145,13 +145,13 @@ def test_batch_graph_replay_with_new_isos(amr, shell):
 
 def test_batched_launch_shapes_agree(amr, shell):
     """octree-shell-256 with 64 isos at percentiles 5 + 90 k / 63 in the
-    launch shapes 512 x 1 and 256 x 1: every job equals the plain path bit
+    launch shapes 256 x 2 and 128 x 1: every job equals the plain path bit
     for bit (the oracle tests below cover the jobs themselves)."""
     cs, s = shell
     isos = np.quantile(cs.value, 0.05 + 0.90 * np.arange(64) / 63).astype(np.float32)
     b = amr.AmrBatch([s])
     want = [_plain(s, iso) for iso in isos]
-    for block, per in ((512, 1), (256, 1)):
+    for block, per in ((256, 2), (128, 1)):
         outs = b.isosurface([0] * len(isos), isos, block, per)
         for w, got in zip(want, outs):
             assert torch.equal(got, w)
@@ -163,7 +163,7 @@ def test_many_isos_equal_oracle(amr, shell):
     cs, s = shell
     isos = np.quantile(cs.value, 0.05 + 0.90 * np.arange(64) / 63).astype(np.float32)
     b = amr.AmrBatch([s])
-    outs = b.isosurface([0] * len(isos), isos, 512, 1)
+    outs = b.isosurface([0] * len(isos), isos, 256, 2)
     o = oracle.Oracle(cs.xyz, cs.level, cs.value)
     with ThreadPoolExecutor(ORACLE_THREADS) as ex:
         ros = list(ex.map(lambda v: o.isosurface(float(v)), isos))
@@ -207,7 +207,7 @@ def test_multiset_batch_equal_oracle(amr):
     sets = [amr.from_numpy(c.xyz, c.level, c.value) for c in css]
     b = amr.AmrBatch(sets)
     outs = b.isosurface(list(range(len(sets))), [c.iso for c in css], 256, 2)
-    for a, c in zip(outs, b.isosurface(list(range(len(sets))), [c.iso for c in css], 256, 1)):
+    for a, c in zip(outs, b.isosurface(list(range(len(sets))), [c.iso for c in css], 128, 1)):
         assert torch.equal(a, c)  # another launch shape, the same bits
     small = [k for k, c in enumerate(css) if c.n <= 1_000_000]
     large = [k for k, c in enumerate(css) if c.n > 1_000_000]

@@ -112,7 +112,7 @@ def test_batch_barrier_timeout_falls_back_to_plain_passes():
     srv = object.__new__(serve.IsoServer)
     srv.t_plain, srv.t_batch_fixed, srv.t_batch_job = 1.0, 0.1, 0.01  # batching wins
     srv.batch = FakeBatch()
-    srv.block, srv.per_thread = 256, 1
+    srv.block, srv.per_cu = 256, 1
     srv.mem = serve.HbmBudget(1 << 30)
     srv.stop = threading.Event()
     srv.curve_iso = np.array([0.0, 1.0])
