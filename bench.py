@@ -304,7 +304,7 @@ def step_measurement(amr, cs, xyz, lvl, val, steps, warmup):
             "roofline": roofline_of(names[dom], alg, kernel_ms, counters_for(cs.name, names[dom]), steps)}
 
 
-def large_measurement(amr, cs, steps, resident=True):
+def large_measurement(amr, cs, steps, resident=True, index_ab=True):
     """The same whole-path step on the 50.8M-cell block-structured set, where
     throughput rather than launch latency decides."""
     import torch
@@ -317,6 +317,8 @@ def large_measurement(amr, cs, steps, resident=True):
            "ms_per_step": r["ms_per_step"], "cells_per_s": r["cells_per_s"], "stages_ms": r["stages_ms"],
            "kernels_ms": r["kernels_ms"], "roofline": r["roofline"],
            "resident_iso": resident_iso_measurement(s, cs) if resident else None}
+    if index_ab:
+        out["index_ab"] = index_measurement(amr, s, cs)
     s.close()
     del s, xyz, lvl, val
     torch.cuda.empty_cache()
@@ -389,6 +391,59 @@ def sampler_measurement(amr, s, cs, n_points=1 << 22, reps=5):
                     "k_smp_query timed with HIP events" % n_points,
             "duals": int(pl.shape[0]), "map_build_ms": build_ms, "query_ms": kernel_ms,
             "points_per_s": n_points / (kernel_ms * 1e-3), "inside": inside}
+
+
+def index_measurement(amr, s, cs, reps=3):
+    """The extraction's index (hash of sibling groups) against the paper's
+    sorted cells with a binary search per level, on the same built set:
+    build time of each (HIP events on the stream), and the snap queries of
+    every cell (27 points per cell) through each, the kernel timed with HIP
+    events around it; both must find the same cells."""
+    import torch
+
+    stream = torch.cuda.current_stream()
+    out = torch.zeros(2, dtype=torch.int64, device=s.device)
+
+    def timed(fn):
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return statistics.mean(ms)
+
+    s.build_sorted_index()
+    sorted_build = timed(s.build_sorted_index)
+    s.upload(*s._cells)
+    s.build_index()
+    hash_build = timed(lambda: (s.upload(*s._cells), s.build_index(wait=False)))
+    s.build_status()
+    s.build_sorted_index()
+    res, snap_ms = {}, {}
+    for name, kind in (("hash", amr.INDEX_HASH), ("sorted", amr.INDEX_SORTED)):
+        s.snap_count_into(out, kind)
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            e1.record(stream)
+            s.time_kernel(amr.KERNEL_SNAP, e0, e1)
+            s.snap_count_into(out, kind)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        snap_ms[name] = statistics.mean(ms)
+        res[name] = out.cpu().tolist()
+    assert res["hash"] == res["sorted"]
+    return {"what": "point-location index: build (HIP events around the calls on the stream; the hash build "
+                    "includes the upload validation) and 27 snap queries per cell located through each (the "
+                    "snap kernel timed with HIP events)",
+            "build_ms": {"hash": hash_build, "sorted": sorted_build},
+            "snap_ms": snap_ms, "snaps": 27 * cs.n, "snaps_found": res["hash"][0],
+            "snaps_per_s": {k: 27 * cs.n / (v * 1e-3) for k, v in snap_ms.items()},
+            "chosen": min(snap_ms, key=snap_ms.get)}
 
 
 def pipeline_measurement(amr, cs, reps=5):
@@ -664,6 +719,7 @@ def main():
     ap.add_argument("--large", default="block-vortex-1024",
                     help="also time the step on this large workload ('none' to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-index-ab", action="store_true", help="skip the hash / sorted-cells index comparison")
     ap.add_argument("--sampler-points", type=int, default=1 << 22,
                     help="points per launch of the dual-mesh interpolant measurement; 0 = skip")
     ap.add_argument("--latency-requests", type=int, default=200)
@@ -770,7 +826,8 @@ def main():
     large_cs = None
     if args.large != "none":
         large_cs = make_workload(args.large)
-        out["large_workload"] = large_measurement(amr, large_cs, 10, resident=not args.no_resident)
+        out["large_workload"] = large_measurement(amr, large_cs, 10, resident=not args.no_resident,
+                                                  index_ab=not args.no_index_ab)
         say("large workload %s: %.3f ms/step" % (args.large, out["large_workload"]["ms_per_step"]))
     if not args.no_pipeline:
         out["pipeline_pcie_inclusive"] = pipeline_measurement(amr, cs)
@@ -793,6 +850,10 @@ def main():
     if "serving" in out:
         say("serving: p99 %.2f ms (server) vs %.2f ms (serial)" % (out["serving"]["server"]["p99_ms"],
                                                                   out["serving"]["serial_plain"]["p99_ms"]))
+    if not args.no_index_ab:
+        # last use of the headline set: this rebuilds its index
+        out["index_ab"] = index_measurement(amr, s, cs)
+        say("index A/B: snaps %s ms" % out["index_ab"]["snap_ms"])
     if not args.no_cpu_baseline:
         say("cpu baseline: running the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(cs, large=large_cs, sets=set_css)

@@ -323,6 +323,48 @@ int amr_sample(amr_set* set, const int32_t* corner_level, const int32_t* verts, 
                int64_t* dual, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+   Point location: the index above against the paper's own scheme (sec. 3.2:
+   the cells sorted by their integer coordinates, a binary search per
+   level, a hit counting only when its level matches), built here with a
+   radix sort of (level, Morton code of the level-l coordinates).  Both
+   answer the same queries; amr_snap_count runs the snap queries of every
+   cell through either, which is how the extraction's index was chosen.
+   --------------------------------------------------------------------------- */
+enum amr_index_kind {
+    AMR_INDEX_HASH = 0,   /* the index of amr_build_index */
+    AMR_INDEX_SORTED = 1  /* the index of amr_build_sorted_index */
+};
+
+/* Workspace bytes of the sorted index of the uploaded set: 24 bytes per
+   cell plus 3 KB per 4096 cells.  Waits for the upload's verdict (and
+   returns its AMR_EINVAL / AMR_ERANGE). */
+int amr_sorted_index_bytes(amr_set* set, size_t* bytes);
+
+/* Build the sorted index into `workspace` (device, caller-owned, >=
+   amr_sorted_index_bytes, 256-byte aligned, kept alive while it is used).
+   Waits on the host for the upload's verdict, then enqueues the sort
+   without waiting.  Valid until the next amr_upload.  Independent of
+   amr_build_index. */
+int amr_build_sorted_index(amr_set* set, void* workspace, size_t bytes, hipStream_t stream);
+
+/* The cell containing each point.
+     points device int32 [n][3]: positions in finest-level units (a cell of
+            level l at lower corner c contains [c, c + 2^l) on each axis)
+     cells  device int32 [n]: input index of the containing cell, -1 where
+            no cell contains the point
+   index: AMR_INDEX_HASH (after amr_build_index) or AMR_INDEX_SORTED
+   (after amr_build_sorted_index); AMR_ESTATE when that index is not built.
+   Both give the same answer.  Asynchronous. */
+int amr_locate(amr_set* set, int index, const int32_t* points, int64_t n, int32_t* cells, hipStream_t stream);
+
+/* The snap queries of the paper's method (sec. 4.4) for every cell: the 27
+   points lo + o * 2^l, o in {-1, 0, 1}^3 (the slot points of the cell's 8
+   corner duals), each located through `index`.  out: device uint64 [2]:
+   out[0] = points found in some cell, out[1] = the sum over them of (cell
+   index + 1); both indexes give the same.  Asynchronous. */
+int amr_snap_count(amr_set* set, int index, uint64_t* out, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
    Measurement: HIP events around one kernel.  The next launch of the named
    kernel for this set is made with hipExtLaunchKernelGGL, which records
    `start` just before the kernel runs and `stop` just after it, on the
@@ -338,7 +380,8 @@ enum amr_kernel {
     AMR_KERNEL_MARK = 5,     /* ancestor marks and the build's verdict (amr_build_index) */
     AMR_KERNEL_EXTRACT = 6,  /* first extraction pass of a call: the fused pass or the count pass */
     AMR_KERNEL_WRITE = 7,    /* write pass of a call that has one */
-    AMR_KERNEL_SAMPLE = 8    /* point queries of amr_sample */
+    AMR_KERNEL_SAMPLE = 8,   /* point queries of amr_sample */
+    AMR_KERNEL_SNAP = 9      /* snap queries of amr_snap_count */
 };
 
 int amr_time_kernel(amr_set* set, int kernel, hipEvent_t start, hipEvent_t stop);

@@ -25,11 +25,15 @@ ABI_SYMBOLS = ("amr_create", "amr_destroy", "amr_upload", "amr_index_bytes", "am
                "amr_dual_cells",
                "amr_isosurface", "amr_batch_create", "amr_batch_destroy", "amr_batch_workspace_bytes",
                "amr_batch_isosurface", "amr_indexed_mesh_bytes", "amr_indexed_mesh", "amr_sampler_bytes",
-               "amr_sampler_build", "amr_sample", "amr_time_kernel", "amr_last_error")
+               "amr_sampler_build", "amr_sample", "amr_sorted_index_bytes", "amr_build_sorted_index", "amr_locate",
+               "amr_snap_count", "amr_time_kernel", "amr_last_error")
 
 # amr_kernel: kernels amr_time_kernel can bracket with events
 (KERNEL_UPLOAD, KERNEL_RESET, KERNEL_INSERT, KERNEL_COMPACT, KERNEL_MARK, KERNEL_EXTRACT, KERNEL_WRITE,
- KERNEL_SAMPLE) = range(1, 9)
+ KERNEL_SAMPLE, KERNEL_SNAP) = range(1, 10)
+
+# amr_index_kind: the point-location indexes
+INDEX_HASH, INDEX_SORTED = 0, 1
 
 _lib = None
 
@@ -84,6 +88,14 @@ def load_library(path: str = LIB_PATH):
     L.amr_sampler_build.restype = C.c_int
     L.amr_sample.argtypes = [vp, i32p, i32p, i64, vp, C.c_size_t, f32p, i64, f32p, i64p, vp]
     L.amr_sample.restype = C.c_int
+    L.amr_sorted_index_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+    L.amr_sorted_index_bytes.restype = C.c_int
+    L.amr_build_sorted_index.argtypes = [vp, vp, C.c_size_t, vp]
+    L.amr_build_sorted_index.restype = C.c_int
+    L.amr_locate.argtypes = [vp, C.c_int, i32p, i64, i32p, vp]
+    L.amr_locate.restype = C.c_int
+    L.amr_snap_count.argtypes = [vp, C.c_int, vp, vp]
+    L.amr_snap_count.restype = C.c_int
     L.amr_time_kernel.argtypes = [vp, C.c_int, vp, vp]
     L.amr_time_kernel.restype = C.c_int
     L.amr_last_error.argtypes = []
@@ -211,6 +223,37 @@ class AmrSet:
                 e.record(stream)  # torch creates the event on first use
         _check(self.lib.amr_time_kernel(self._h, int(kernel), C.c_void_p(start.cuda_event),
                                         C.c_void_p(stop.cuda_event)))
+
+    # -- point location ---------------------------------------------------
+    def build_sorted_index(self):
+        """Build the paper's sorted-cells index beside the hash (for
+        comparison); no host synchronisation after the upload's verdict."""
+        b = C.c_size_t(0)
+        _check(self.lib.amr_sorted_index_bytes(self._h, C.byref(b)))
+        if getattr(self, "sorted_workspace", None) is None or self.sorted_workspace.numel() < b.value:
+            self.sorted_workspace = torch.empty(max(int(b.value), 256), dtype=torch.uint8, device=self.device)
+        _check(self.lib.amr_build_sorted_index(self._h, _ptr(self.sorted_workspace), self.sorted_workspace.numel(),
+                                               _stream(self.device)))
+        return self
+
+    def locate_into(self, points, cells, index: int = INDEX_HASH):
+        """Enqueue: cells int32 [Q] of the cells containing points int32 [Q,3]."""
+        _check(self.lib.amr_locate(self._h, int(index), _ptr(points), int(points.shape[0]), _ptr(cells),
+                                   _stream(self.device)))
+        return cells
+
+    def locate(self, points, index: int = INDEX_HASH):
+        """int32 [Q]: the cell containing each point of int32 [Q,3], -1 if none."""
+        points = points.to(device=self.device, dtype=torch.int32).contiguous()
+        cells = torch.empty(max(int(points.shape[0]), 1), dtype=torch.int32, device=self.device)
+        self.locate_into(points, cells, index)
+        return cells[:points.shape[0]]
+
+    def snap_count_into(self, out, index: int = INDEX_HASH):
+        """Enqueue the snap queries of every cell; out int64 [2] (device)
+        receives (points found, sum of cell index + 1)."""
+        _check(self.lib.amr_snap_count(self._h, int(index), _ptr(out), _stream(self.device)))
+        return out
 
     # -- extraction -------------------------------------------------------
     def dual_cells_into(self, corner_level, verts, cap: int, vals=None):

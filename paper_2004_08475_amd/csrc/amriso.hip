@@ -1670,6 +1670,258 @@ __global__ __launch_bounds__(kBlock) void k_extract_list(ExtractArgs a) {
         extract_tile<false, kPass, true>(a, u.g, u.n_groups, n_tiles, tile, n, 0ull, u.rng_mode);
 }
 
+// ---------------------------------------------------------------------------
+// Count passes with one lane per group.  extract_tile gives a group eight
+// lanes, which take different neighbours and corners, so where a
+// neighbour's children land in the 4x4x4 block and which positions a
+// corner reads are run-time values in every lane.  Counting needs less:
+// every lane holds one group and walks the same 27 neighbours and 27
+// corners in the same order, so all positions are compile-time constants,
+// and the block is kept as one byte per position in 16 registers: bit 7 a
+// cell of level m or coarser covers the position, bit 6 its value is >=
+// iso, bits 0-4 its level above m.  Two slots hold the same cell exactly
+// when that level is the same, above m, and their level-m positions fall
+// into one cell of it (the references extract_tile compares).  The counts
+// equal extract_tile's group for group.
+// ---------------------------------------------------------------------------
+
+constexpr uint32_t kPosValid = 0x80u, kPosAbove = 0x40u, kPosLevel = 0x1Fu;
+constexpr uint32_t kLaneCountMinGroups = 1u << 21;  // group bound from which full count passes use k_count
+constexpr int kCountBatch = 3;  // neighbours whose home slots are read at once (3 of 9 and 27 measured fastest)
+
+template <int p>
+__device__ __forceinline__ uint32_t pos_byte(const uint32_t (&pos)[16]) {
+    return (pos[p >> 2] >> (8 * (p & 3))) & 0xFFu;
+}
+
+// Neighbours d0 .. d0 + kN - 1 (dd = dx+1 + 3 (dy+1) + 9 (dz+1)) of the
+// group: the home slots of all of them are read at once, then each one's
+// record at level m or, when its block holds no level-m record, the coarser
+// cell covering it; the children that lie in the 4x4x4 block go into `pos`.
+template <int d0, int kN>
+__device__ __forceinline__ void count_neighbours(const Record* __restrict__ rec, const Geo& g, const int m,
+                                                 uint32_t gx, uint32_t gy, uint32_t gz, const int own,
+                                                 const float iso, uint32_t (&pos)[16], float& lo, float& hi) {
+    // computed here, not for all 27 neighbours up front (which would hold
+    // them all in registers)
+    asm volatile("" : "+v"(gx), "+v"(gy), "+v"(gz));
+    uint64_t want[kN], key[kN];
+    uint32_t h[kN];
+    float4 va[kN], vb[kN];
+#pragma unroll
+    for (int i = 0; i < kN; ++i) {
+        const int dd = d0 + i;
+        const int dx = dd % 3 - 1, dy = (dd / 3) % 3 - 1, dz = dd / 9 - 1;
+        want[i] = group_key(m, gx + dx, gy + dy, gz + dz);
+        h[i] = dd == 13 ? (uint32_t)own : slot_of(want[i], g.shift);
+    }
+#pragma unroll
+    for (int i = 0; i < kN; ++i) {
+        va[i] = reinterpret_cast<const float4*>(rec[h[i]].val)[0];
+        vb[i] = reinterpret_cast<const float4*>(rec[h[i]].val)[1];
+        key[i] = rec[h[i]].key;
+    }
+#pragma unroll
+    for (int i = 0; i < kN; ++i) {
+        const int dd = d0 + i;
+        const int dx = dd % 3 - 1, dy = (dd / 3) % 3 - 1, dz = dd / 9 - 1;
+        const uint32_t bx = gx + dx, by = gy + dy, bz = gz + dz;
+        uint64_t k = key[i];
+        uint32_t hh = h[i];
+        float4 xa = va[i], xb = vb[i];
+        if (k != want[i] && k != kEmpty) {
+            for (uint32_t step = 0; k != want[i] && k != kEmpty && step <= g.mask; ++step) {
+                hh = next_slot(hh, step, g.mask);
+                k = rec[hh].key;
+            }
+            if (k == want[i]) {
+                xa = reinterpret_cast<const float4*>(rec[hh].val)[0];
+                xb = reinterpret_cast<const float4*>(rec[hh].val)[1];
+            }
+        }
+        const bool hit = k == want[i];
+        float cv = 0.f;
+        uint32_t cbyte = 0;  // the covering cell's byte when the block holds no level-m record
+        if (!hit) {
+            // the first record found going up decides (a NaN there: finer
+            // cells or none at all, either way no cell covers the block)
+            for (int L = m + 1; L <= g.lmax; ++L) {
+                const int sh = L - m - 1;
+                const uint64_t wk = group_key(L, bx >> (sh + 1), by >> (sh + 1), bz >> (sh + 1));
+                const int ch = ((bx >> sh) & 1) | (((by >> sh) & 1) << 1) | (((bz >> sh) & 1) << 2);
+                uint32_t h2 = slot_of(wk, g.shift);
+                uint64_t k2 = rec[h2].key;
+                for (uint32_t step = 0; k2 != wk && k2 != kEmpty && step <= g.mask; ++step) {
+                    h2 = next_slot(h2, step, g.mask);
+                    k2 = rec[h2].key;
+                }
+                if (k2 == wk) {
+                    cv = rec[h2].val[ch];
+                    if (cv == cv) cbyte = kPosValid | (cv >= iso ? kPosAbove : 0u) | (uint32_t)(L - m);
+                    break;
+                }
+            }
+            if (cbyte) {
+                lo = fminf(lo, cv);
+                hi = fmaxf(hi, cv);
+            }
+        }
+        const float v8[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int chx = c & 1, chy = (c >> 1) & 1, chz = c >> 2;
+            const bool need = (dx == 0 || (dx < 0) == (chx == 1)) && (dy == 0 || (dy < 0) == (chy == 1)) &&
+                              (dz == 0 || (dz < 0) == (chz == 1));
+            if (!need) continue;
+            const int p = (2 * dx + chx + 1) + 4 * (2 * dy + chy + 1) + 16 * (2 * dz + chz + 1);
+            const float v = v8[c];
+            uint32_t byte = cbyte;
+            if (hit) {
+                byte = v == v ? kPosValid | (v >= iso ? kPosAbove : 0u) : 0u;
+                if (v == v) {
+                    lo = fminf(lo, v);
+                    hi = fmaxf(hi, v);
+                }
+            }
+            pos[p >> 2] |= byte << (8 * (p & 3));
+        }
+    }
+    if constexpr (d0 + kN < 27)
+        count_neighbours<d0 + kN, (27 - d0 - kN < kN ? 27 - d0 - kN : kN)>(rec, g, m, gx, gy, gz, own, iso, pos,
+                                                                          lo, hi);
+}
+
+// Corner k (kx, ky, kz in 0..2) of the group's 2x2x2 block: its dual is
+// emitted when its 8 slots are covered by cells of level m or coarser and
+// the lowest same-level slot lies in the group (rules 1-3); then its
+// Marching Cubes case and kept triangles.
+template <bool kDuals, int k>
+__device__ __forceinline__ void count_corner(const uint32_t (&pos)[16], const int m, const uint32_t gx,
+                                             const uint32_t gy, const uint32_t gz,
+                                             const unsigned long long* s_tab, int& n_dual, int& n_tri) {
+    constexpr int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
+    constexpr int p0 = kx + 4 * ky + 16 * kz;
+    uint32_t b[8];
+    b[0] = pos_byte<p0>(pos);
+    b[1] = pos_byte<p0 + 1>(pos);
+    b[2] = pos_byte<p0 + 4>(pos);
+    b[3] = pos_byte<p0 + 5>(pos);
+    b[4] = pos_byte<p0 + 16>(pos);
+    b[5] = pos_byte<p0 + 17>(pos);
+    b[6] = pos_byte<p0 + 20>(pos);
+    b[7] = pos_byte<p0 + 21>(pos);
+    // a level-m cell at slot 0 outside this group is the lowest same-level
+    // slot (the dual is another group's), or slot 0 is not covered
+    if constexpr (kx == 0 || ky == 0 || kz == 0)
+        if ((b[0] & kPosLevel) == 0) return;
+    uint32_t all = kPosValid, same = 0, cs = 0;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        all &= b[s];
+        same |= ((b[s] & kPosLevel) == 0 ? 1u : 0u) << s;
+        cs |= ((b[s] >> 6) & 1u) << s;
+    }
+    constexpr uint32_t mine = (kx == 0 ? 0xAAu : kx == 1 ? 0xFFu : 0x55u) &
+                              (ky == 0 ? 0xCCu : ky == 1 ? 0xFFu : 0x33u) &
+                              (kz == 0 ? 0xF0u : kz == 1 ? 0xFFu : 0x0Fu);
+    if (!all || !(same & (0u - same) & mine)) return;
+    ++n_dual;
+    if (kDuals) return;
+    const unsigned long long e = s_tab[cs];
+    const int nt = (int)(e >> 60);
+    if (!nt) return;
+    uint32_t keep = (1u << nt) - 1u;
+    if (same != 0xFFu) {
+        // slot classes: the lowest slot holding the same cell
+        const uint32_t A[3] = {2 * gx + kx - 1, 2 * gy + ky - 1, 2 * gz + kz - 1};
+        uint32_t cls = 0;
+#pragma unroll
+        for (int s1 = 1; s1 < 8; ++s1) {
+            int c = s1;
+            const uint32_t d1 = b[s1] & kPosLevel;
+#pragma unroll
+            for (int s0 = s1 - 1; s0 >= 0; --s0) {
+                const uint32_t d0 = b[s0] & kPosLevel;
+                bool eq = d0 == d1 && d1 != 0;
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax)
+                    if (((s0 ^ s1) >> ax) & 1) eq = eq && (((A[ax] + 1) & ((1u << d1) - 1u)) != 0);
+                if (eq) c = s0;
+            }
+            cls |= (uint32_t)c << (3 * s1);
+        }
+        keep = keep_by_classes(cls, e, nt);
+    }
+    n_tri += __popc(keep);
+}
+
+template <bool kDuals, int k>
+__device__ __forceinline__ void count_corners(const uint32_t (&pos)[16], const int m, const uint32_t gx,
+                                              const uint32_t gy, const uint32_t gz,
+                                              const unsigned long long* s_tab, int& n_dual, int& n_tri) {
+    count_corner<kDuals, k>(pos, m, gx, gy, gz, s_tab, n_dual, n_tri);
+    if constexpr (k + 1 < 27) count_corners<kDuals, k + 1>(pos, m, gx, gy, gz, s_tab, n_dual, n_tri);
+}
+
+// One launch: 256 groups per work-group, XCD x taking a contiguous run of
+// work-groups; per group its totals (gcnt), per tile of 32 its totals
+// (tot), with recording on the groups' value ranges.  Used for full count
+// passes over large sets: there it beats the eight-lanes-per-group pass
+// (1.48 against 1.87 ms on a 50.8M-cell set), while on sets of a few
+// hundred thousand groups, where one lane per group leaves too few waves to
+// hide the probes' latency, it loses (0.29 against 0.19 ms at 2M cells).
+template <bool kDuals>
+__global__ __launch_bounds__(256) void k_count(ExtractArgs a) {
+    __shared__ unsigned long long s_tab[256];
+    const TileSetup u = tile_setup(a);
+    const int t = threadIdx.x;
+    if (!kDuals) s_tab[t] = kMcTable[t];
+    // the scan that follows starts from clean states
+    for (uint32_t i = blockIdx.x * 256 + t; i < a.n_scan_tiles; i += gridDim.x * 256) {
+        a.sc0[i] = 0;
+        a.sc1[i] = 0;
+    }
+    if (blockIdx.x == 0 && t == 0) a.sched->xticket = 0;
+    const uint32_t n_items = u.n_groups;
+    const uint32_t n_tiles = (n_items + kGroupsPerTile - 1) / kGroupsPerTile;
+    const uint32_t n_units = (n_items + 255) / 256;
+    const uint32_t per_xcd = (n_units + kXcds - 1) / kXcds;
+    const uint32_t kk = blockIdx.x / kXcds;
+    const uint32_t unit = (blockIdx.x % kXcds) * per_xcd + kk;
+    __syncthreads();
+    if (kk >= per_xcd || unit >= n_units) return;
+    const uint32_t li = unit * 256 + t;
+    const bool valid = li < n_items;
+    const bool record = u.rng_mode == kRngRecord;
+    uint32_t gidx = 0;
+    int m = 0, own = 0;
+    uint32_t gx = 0, gy = 0, gz = 0;
+    int n_dual = 0, n_tri = 0;
+    if (valid) {
+        gidx = li;
+        own = a.glist[gidx];
+        const uint64_t key = a.gkey[gidx];
+        m = (int)(key >> 57);
+        gx = (uint32_t)(key & 0x7FFFF);
+        gy = (uint32_t)((key >> 19) & 0x7FFFF);
+        gz = (uint32_t)((key >> 38) & 0x7FFFF);
+        uint32_t pos[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) pos[i] = 0;
+        float lo = INFINITY, hi = -INFINITY;
+        count_neighbours<0, kCountBatch>(a.rec, u.g, m, gx, gy, gz, own, a.iso, pos, lo, hi);
+        if (record) a.rng[gidx] = make_float2(lo, hi);
+        count_corners<kDuals, 0>(pos, m, gx, gy, gz, s_tab, n_dual, n_tri);
+        a.gcnt[gidx] = ((unsigned long long)n_tri << 32) | (unsigned long long)n_dual;
+    }
+    // per tile of 32 items: half a wave
+    unsigned long long sum = ((unsigned long long)n_tri << 32) | (unsigned long long)n_dual;
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+    const uint32_t tile = (unit * 256 + t) / kGroupsPerTile;
+    if ((t & 31) == 0 && tile < n_tiles) a.tot[tile] = sum;
+}
+
 // Exclusive scan of the per-tile (triangles, duals) totals of a count pass:
 // 4096 tiles per work-group, decoupled look-back across work-groups (tickets
 // keep the look-back waiting only on work-groups that already run).  The
@@ -2335,6 +2587,230 @@ __global__ __launch_bounds__(256) void k_weld_index(int64_t n_corners, WeldWs w,
 }
 
 // ---------------------------------------------------------------------------
+// The paper's cell-location scheme, for comparison with the hash (sec. 3.2):
+// the cells sorted by (level, Morton code of their level-l coordinates),
+// and a point located by a binary search per level, a hit counting only
+// when its level matches.  Built by a least-significant-digit radix sort
+// (8-bit digits, stable).  amr_locate answers point queries from either
+// index, and amr_snap_count runs the snap queries of every cell (the 27
+// points lo + o * 2^l, o in {-1, 0, 1}^3, whose cells are the vertices of
+// the cell's 8 corner duals) through either, which is what the two are
+// timed on.
+// ---------------------------------------------------------------------------
+
+constexpr int kSortPer = 16;                 // keys per thread in the sort passes
+constexpr int kSortTile = 256 * kSortPer;    // keys per work-group
+
+__device__ __forceinline__ uint64_t spread3(uint32_t v) {
+    // bits 0..20 of v to bits 0, 3, 6, ...
+    uint64_t x = v & 0x1FFFFFu;
+    x = (x | (x << 32)) & 0x1F00000000FFFFull;
+    x = (x | (x << 16)) & 0x1F0000FF0000FFull;
+    x = (x | (x << 8)) & 0x100F00F00F00F00Full;
+    x = (x | (x << 4)) & 0x10C30C30C30C30C3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+// sort key of the level-l cell with offset coordinates (ux, uy, uz)
+__device__ __forceinline__ uint64_t cell_sort_key(int l, int lmin, int bits, uint32_t ux, uint32_t uy, uint32_t uz) {
+    return ((uint64_t)(l - lmin) << (3 * bits)) | spread3(ux >> l) | (spread3(uy >> l) << 1) | (spread3(uz >> l) << 2);
+}
+
+__global__ __launch_bounds__(256) void k_sort_keys(const int32_t* __restrict__ xyz, const int32_t* __restrict__ lvl,
+                                                   int64_t n, int32_t ox, int32_t oy, int32_t oz, int lmin, int bits,
+                                                   uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int l = lvl[i];
+        keys[i] = cell_sort_key(l, lmin, bits, (uint32_t)(xyz[3 * i] - ox), (uint32_t)(xyz[3 * i + 1] - oy),
+                                (uint32_t)(xyz[3 * i + 2] - oz));
+        vals[i] = (uint32_t)i;
+    }
+}
+
+// digit histogram of each tile of kSortTile keys, digit-major: hist[d * n_tiles + tile]
+__global__ __launch_bounds__(256) void k_sort_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
+                                                   uint32_t n_tiles, uint32_t* __restrict__ hist) {
+    __shared__ uint32_t s_h[256];
+    const int t = threadIdx.x;
+    s_h[t] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll 4
+    for (int r = 0; r < kSortPer; ++r) {
+        const int64_t i = base + r * 256 + t;
+        if (i < n) atomicAdd(&s_h[(keys[i] >> shift) & 0xFF], 1u);
+    }
+    __syncthreads();
+    hist[(size_t)t * n_tiles + blockIdx.x] = s_h[t];
+}
+
+// Stable scatter: the keys of a tile in rounds of 256, each key at
+// off[digit][tile] + the keys of that digit before it in the tile.  Within
+// a wave the lanes holding the same digit are found with 8 ballots (one per
+// digit bit).
+__global__ __launch_bounds__(256) void k_sort_scatter(const uint64_t* __restrict__ kin,
+                                                      const uint32_t* __restrict__ vin, int64_t n, int shift,
+                                                      uint32_t n_tiles, const int64_t* __restrict__ off,
+                                                      uint64_t* __restrict__ kout, uint32_t* __restrict__ vout) {
+    __shared__ uint32_t s_cnt[4][256];
+    __shared__ int64_t s_base[256];
+    const int t = threadIdx.x, wave = t >> 6, lane = lane_id();
+    s_base[t] = off[(size_t)t * n_tiles + blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int r = 0; r < kSortPer; ++r) {
+        for (int w = 0; w < 4; ++w) s_cnt[w][t] = 0;
+        __syncthreads();
+        const int64_t i = base + r * 256 + t;
+        const bool live = i < n;
+        uint64_t k = 0;
+        uint32_t v = 0, d = 0;
+        if (live) {
+            k = kin[i];
+            v = vin[i];
+            d = (uint32_t)(k >> shift) & 0xFFu;
+        }
+        unsigned long long peers = __ballot(live);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const unsigned long long bal = __ballot(live && ((d >> b) & 1u));
+            peers &= ((d >> b) & 1u) ? bal : ~bal;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & below);
+        if (live && rank == 0) s_cnt[wave][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (live) {
+            uint32_t before = 0;
+            for (int w = 0; w < wave; ++w) before += s_cnt[w][d];
+            const int64_t pos = s_base[d] + before + rank;
+            kout[pos] = k;
+            vout[pos] = v;
+        }
+        __syncthreads();
+        s_base[t] += s_cnt[0][t] + s_cnt[1][t] + s_cnt[2][t] + s_cnt[3][t];
+        __syncthreads();
+    }
+}
+
+// The sorted index as the kernels read it.
+struct SortedIndex {
+    const uint64_t* keys;    // sorted
+    const uint32_t* cells;   // input index of the cell of each key
+    int64_t lo[kMaxLevel + 2];  // keys of level l: [lo[l], lo[l + 1])
+    int lmin, lmax, bits;
+    int32_t ox, oy, oz;
+};
+
+__device__ __forceinline__ int64_t sorted_locate(const SortedIndex& si, int64_t ux, int64_t uy, int64_t uz) {
+    if (ux < 0 || uy < 0 || uz < 0 || ux >= ((int64_t)1 << si.bits) || uy >= ((int64_t)1 << si.bits) ||
+        uz >= ((int64_t)1 << si.bits))
+        return -1;
+    for (int L = si.lmin; L <= si.lmax; ++L) {
+        int64_t a = si.lo[L], b = si.lo[L + 1];
+        const int64_t end = b;
+        if (a == b) continue;
+        const uint64_t key = cell_sort_key(L, si.lmin, si.bits, (uint32_t)ux, (uint32_t)uy, (uint32_t)uz);
+        while (a < b) {
+            const int64_t c = (a + b) >> 1;
+            if (si.keys[c] < key) a = c + 1;
+            else b = c;
+        }
+        if (a < end && si.keys[a] == key) return si.cells[a];
+    }
+    return -1;
+}
+
+// The hash: from the coarsest level down, the record of the block holding
+// the position says "a cell" (done), "refined" (finer cells inside: go
+// down) or nothing (no cell covers the position).
+__device__ __forceinline__ int64_t hash_locate(const Record* __restrict__ rec, const int32_t* __restrict__ ids,
+                                               const Geo& g, int64_t ux, int64_t uy, int64_t uz) {
+    if (ux < 0 || uy < 0 || uz < 0 || ux >= kSpanLimit || uy >= kSpanLimit || uz >= kSpanLimit) return -1;
+    for (int L = g.lmax; L >= 0; --L) {
+        const int slot = probe(rec, group_key(L, (uint32_t)ux >> (L + 1), (uint32_t)uy >> (L + 1),
+                                              (uint32_t)uz >> (L + 1)),
+                               g.shift, g.mask);
+        if (slot < 0) return -1;
+        const int c = (int)(((ux >> L) & 1) | (((uy >> L) & 1) << 1) | (((uz >> L) & 1) << 2));
+        const uint32_t bits = __float_as_uint(rec[slot].val[c]);
+        if (bits == kValRefined) continue;
+        if (bits == kValEmpty) return -1;
+        return ids[(size_t)slot * 8 + c];
+    }
+    return -1;
+}
+
+template <bool kSorted>
+__global__ __launch_bounds__(256) void k_locate(const Record* __restrict__ rec, const int32_t* __restrict__ ids,
+                                                const Ctrl* ctrl, SortedIndex si, const int32_t* __restrict__ pts,
+                                                int64_t n, int32_t* __restrict__ cells) {
+    const bool ok = kSorted || ctrl->status == AMR_OK;
+    const Geo g = ctrl->geo;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t c = -1;
+        if (ok) {
+            if (kSorted)
+                c = sorted_locate(si, (int64_t)pts[3 * i] - si.ox, (int64_t)pts[3 * i + 1] - si.oy,
+                                  (int64_t)pts[3 * i + 2] - si.oz);
+            else
+                c = hash_locate(rec, ids, g, (int64_t)pts[3 * i] - g.ox, (int64_t)pts[3 * i + 1] - g.oy,
+                                (int64_t)pts[3 * i + 2] - g.oz);
+        }
+        cells[i] = (int32_t)c;
+    }
+}
+
+// The snap queries of every cell: the 27 points lo + o * 2^l, o in
+// {-1, 0, 1}^3, each located; out[0] += points found, out[1] += the sum of
+// (cell index + 1) over them (a checksum both indexes must agree on).
+template <bool kSorted>
+__global__ __launch_bounds__(256) void k_snap(const int32_t* __restrict__ xyz, const int32_t* __restrict__ lvl,
+                                              int64_t n, const Record* __restrict__ rec,
+                                              const int32_t* __restrict__ ids, const Ctrl* ctrl, SortedIndex si,
+                                              unsigned long long* out) {
+    const bool ok = kSorted || ctrl->status == AMR_OK;
+    const Geo g = ctrl->geo;
+    const int32_t ox = kSorted ? si.ox : g.ox, oy = kSorted ? si.oy : g.oy, oz = kSorted ? si.oz : g.oz;
+    unsigned long long found = 0, sum = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; ok && i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int l = lvl[i];
+        const int64_t w = (int64_t)1 << l;
+        const int64_t x = (int64_t)xyz[3 * i] - ox, y = (int64_t)xyz[3 * i + 1] - oy, z = (int64_t)xyz[3 * i + 2] - oz;
+        for (int o = 0; o < 27; ++o) {
+            const int64_t qx = x + (o % 3 - 1) * w, qy = y + ((o / 3) % 3 - 1) * w, qz = z + (o / 9 - 1) * w;
+            const int64_t c = kSorted ? sorted_locate(si, qx, qy, qz) : hash_locate(rec, ids, g, qx, qy, qz);
+            if (c >= 0) {
+                ++found;
+                sum += (unsigned long long)c + 1ull;
+            }
+        }
+    }
+    __shared__ unsigned long long s_f[4], s_s[4];
+    auto add = [](unsigned long long p, unsigned long long q) { return p + q; };
+    found = wave_reduce(found, add);
+    sum = wave_reduce(sum, add);
+    if (lane_id() == 0) {
+        s_f[threadIdx.x >> 6] = found;
+        s_s[threadIdx.x >> 6] = sum;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        found = s_f[0] + s_f[1] + s_f[2] + s_f[3];
+        sum = s_s[0] + s_s[1] + s_s[2] + s_s[3];
+        if (found) {
+            atomicAdd(&out[0], found);
+            atomicAdd(&out[1], sum);
+        }
+    }
+}
+
+__global__ void k_zero2(unsigned long long* out) {
+    if (threadIdx.x < 2) out[threadIdx.x] = 0;
+}
+
+// ---------------------------------------------------------------------------
 // Dual-mesh interpolant.  The paper names the dual mesh as an interpolant
 // of the cell values (sec. 5, after Moran et al.) and leaves its use for
 // volume rendering to future work (sec. 7); it defines no interpolant.
@@ -2535,26 +3011,10 @@ __device__ __forceinline__ bool smp_key_less(const int4& a, const int4& b) {
     return a.x < b.x;
 }
 
-// The cell containing the finest-level position (ix, iy, iz), or -1: from
-// the coarsest level down, the record of the block holding the position
-// says "a cell" (done), "refined" (finer cells inside: go down) or nothing
-// (no cell covers the position).
+// The cell containing the finest-level position (ix, iy, iz), or -1.
 __device__ __forceinline__ int64_t smp_locate(const SampleArgs& a, const Geo& g, int64_t ix, int64_t iy,
                                               int64_t iz) {
-    const int64_t ux = ix - g.ox, uy = iy - g.oy, uz = iz - g.oz;
-    if (ux < 0 || uy < 0 || uz < 0 || ux >= kSpanLimit || uy >= kSpanLimit || uz >= kSpanLimit) return -1;
-    for (int L = g.lmax; L >= 0; --L) {
-        const int slot = probe(a.rec, group_key(L, (uint32_t)ux >> (L + 1), (uint32_t)uy >> (L + 1),
-                                                (uint32_t)uz >> (L + 1)),
-                               g.shift, g.mask);
-        if (slot < 0) return -1;
-        const int c = (int)(((ux >> L) & 1) | (((uy >> L) & 1) << 1) | (((uz >> L) & 1) << 2));
-        const uint32_t bits = __float_as_uint(a.rec[slot].val[c]);
-        if (bits == kValRefined) continue;
-        if (bits == kValEmpty) return -1;
-        return a.ids[(size_t)slot * 8 + c];
-    }
-    return -1;
+    return hash_locate(a.rec, a.ids, g, ix - g.ox, iy - g.oy, iz - g.oz);
 }
 
 __device__ __forceinline__ double smp_det3(const double (&J)[3][3]) {
@@ -2760,6 +3220,13 @@ struct amr_set {
     bool ids_ready = false;  // input indices filled in (on first use)
     int extractions = 0;     // extraction calls since the build (saturates at 2)
     uint64_t build_gen = 0;  // builds so far
+    uint64_t upload_gen = 0;  // uploads so far
+    // the sorted-cells index (amr_build_sorted_index), valid for upload srt_gen
+    uint64_t srt_gen = ~0ull;
+    const uint64_t* srt_keys = nullptr;
+    const uint32_t* srt_cells = nullptr;
+    int srt_bits = 0;
+    int64_t srt_lo[kMaxLevel + 2] = {};
     uint64_t smp_gen = ~0ull;  // the build a dual-mesh sampler was made for
     float2* rng = nullptr;
     unsigned long long* dual_total = nullptr;
@@ -2969,6 +3436,11 @@ int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_
     a.list_duals = nullptr;
     const uint32_t n_wgs = (max_groups + kBlock * kListPer - 1) / (kBlock * kListPer);
     const uint32_t grid = ((max_tiles + kXcds - 1) / kXcds) * kXcds;
+    // full count passes over large sets: one lane per group (k_count), 256
+    // groups per work-group
+    const bool lane_count = max_groups >= kLaneCountMinGroups;
+    const uint32_t count_units = (max_groups + 255) / 256;
+    const uint32_t count_grid = (count_units > 0 ? ((count_units + kXcds - 1) / kXcds) : 1) * kXcds;
     if (max_tiles <= kFusedMaxTiles) {
         // one fused pass (look-back states alternate parity between calls)
         a.sc0 = s->fs0;
@@ -2994,7 +3466,10 @@ int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_
         // group order, with their counts) and scan and write over that list
         // only: most groups have none, and the write pass would otherwise
         // redo their neighbourhoods beside the few that have some
-        launch(s, AMR_KERNEL_EXTRACT, k_extract<false, kPassCount>, dim3(grid), dim3(kBlock), stream, a);
+        if (lane_count)
+            launch(s, AMR_KERNEL_EXTRACT, k_count<false>, dim3(count_grid), dim3(256), stream, a);
+        else
+            launch(s, AMR_KERNEL_EXTRACT, k_extract<false, kPassCount>, dim3(grid), dim3(kBlock), stream, a);
         hipLaunchKernelGGL(k_group_list, dim3(n_wgs), dim3(kBlock), 0, stream, nullptr, s->gcnt, s->ctrl, iso,
                            n_wgs, s->clist, s->lcnt, s->n_list, s->list_duals, s->ls0, s->ls1, s->sched);
         a.clist = s->clist;
@@ -3007,10 +3482,16 @@ int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_
         // count pass, scan, then the write pass only when something is written;
         // the grid is a multiple of the XCD count (see the tile mapping)
         const bool write = cap > 0 && (duals ? (corner_level || verts || dvals) : (tris || tri_cells || tri_dual));
-        if (duals)
+        if (lane_count) {
+            if (duals)
+                launch(s, AMR_KERNEL_EXTRACT, k_count<true>, dim3(count_grid), dim3(256), stream, a);
+            else
+                launch(s, AMR_KERNEL_EXTRACT, k_count<false>, dim3(count_grid), dim3(256), stream, a);
+        } else if (duals) {
             launch(s, AMR_KERNEL_EXTRACT, k_extract<true, kPassCount>, dim3(grid), dim3(kBlock), stream, a);
-        else
+        } else {
             launch(s, AMR_KERNEL_EXTRACT, k_extract<false, kPassCount>, dim3(grid), dim3(kBlock), stream, a);
+        }
         hipLaunchKernelGGL(k_tile_scan, dim3(a.n_scan_tiles), dim3(kBlock), 0, stream, a, duals ? 1 : 0);
         if (write) {
             if (duals)
@@ -3145,6 +3626,7 @@ int amr_upload(amr_set* s, const int32_t* xyz, const int32_t* level, const float
     s->lvl = level;
     s->val = value;
     s->n = n;
+    ++s->upload_gen;
     for (int l = 0; l <= kMaxLevel; ++l) s->level_count[l] = 0;
     s->lmin = s->lmax = 0;
     s->origin[0] = s->origin[1] = s->origin[2] = 0;
@@ -3748,9 +4230,194 @@ int amr_sample(amr_set* s, const int32_t* corner_level, const int32_t* verts, in
     return AMR_OK;
 }
 
+namespace {
+// Sorted-index workspace: keys and cell indices twice (the passes
+// alternate), the digit histograms of the tiles and their offsets, and the
+// work-group sums of the offset scan.
+struct SortLayout {
+    uint32_t n_tiles;
+    int64_t n_hist, nb;
+    size_t ka, kb, va, vb, hist, off, bsum, total;
+};
+
+SortLayout sort_layout(int64_t n) {
+    SortLayout L{};
+    L.n_tiles = (uint32_t)((n + kSortTile - 1) / kSortTile);
+    if (L.n_tiles == 0) L.n_tiles = 1;
+    L.n_hist = (int64_t)256 * L.n_tiles;
+    L.nb = (L.n_hist + 256 * kSmpPer - 1) / (256 * kSmpPer);
+    size_t o = 0;
+    L.ka = o;
+    o = align256(o + (size_t)n * 8 + 8);
+    L.kb = o;
+    o = align256(o + (size_t)n * 8 + 8);
+    L.va = o;
+    o = align256(o + (size_t)n * 4 + 4);
+    L.vb = o;
+    o = align256(o + (size_t)n * 4 + 4);
+    L.hist = o;
+    o = align256(o + (size_t)L.n_hist * 4);
+    L.off = o;
+    o = align256(o + (size_t)(L.n_hist + 1) * 8);
+    L.bsum = o;
+    o = align256(o + (size_t)(L.nb + 1) * 8);
+    L.total = o;
+    return L;
+}
+
+SortedIndex sorted_view(const amr_set* s) {
+    SortedIndex si;
+    si.keys = s->srt_keys;
+    si.cells = s->srt_cells;
+    for (int l = 0; l < kMaxLevel + 2; ++l) si.lo[l] = s->srt_lo[l];
+    si.lmin = s->lmin;
+    si.lmax = s->lmax;
+    si.bits = s->srt_bits;
+    si.ox = s->origin[0];
+    si.oy = s->origin[1];
+    si.oz = s->origin[2];
+    return si;
+}
+
+// the index a locate call names: AMR_ESTATE when it has not been built
+int index_ready(amr_set* s, int kind, const char* who, hipStream_t stream) {
+    if (kind == AMR_INDEX_HASH) {
+        if (!s->built) return fail(AMR_ESTATE, "%s: call amr_build_index first", who);
+        return ensure_ids(s, stream);
+    }
+    if (kind == AMR_INDEX_SORTED) {
+        if (!s->uploaded || s->srt_gen != s->upload_gen)
+            return fail(AMR_ESTATE, "%s: call amr_build_sorted_index first", who);
+        return AMR_OK;
+    }
+    return fail(AMR_EINVAL, "%s: unknown index %d", who, kind);
+}
+}  // namespace
+
+int amr_sorted_index_bytes(amr_set* s, size_t* bytes) {
+    if (!s || !bytes) return fail(AMR_EINVAL, "amr_sorted_index_bytes: NULL argument");
+    if (!s->uploaded) return fail(AMR_ESTATE, "amr_sorted_index_bytes: call amr_upload first");
+    DeviceGuard dg(s->device);
+    const int st = upload_verdict(s);
+    if (st != AMR_OK) return st;
+    *bytes = sort_layout(s->n).total;
+    g_err[0] = 0;
+    return AMR_OK;
+}
+
+int amr_build_sorted_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
+    if (!s) return fail(AMR_EINVAL, "amr_build_sorted_index: set is NULL");
+    if (!s->uploaded) return fail(AMR_ESTATE, "amr_build_sorted_index: call amr_upload first");
+    if (!ws || ((uintptr_t)ws & 255))
+        return fail(AMR_EINVAL, "amr_build_sorted_index: workspace NULL or not 256-B aligned");
+    DeviceGuard dg(s->device);
+    int st = upload_verdict(s);  // the geometry comes from the host copy of the verdict
+    if (st != AMR_OK) return st;
+    const SortLayout L = sort_layout(s->n);
+    if (bytes < L.total)
+        return fail(AMR_ENOSPACE, "amr_build_sorted_index: workspace of %zu bytes, need %zu", bytes, L.total);
+    // bits per axis of the offset coordinates, and of the level above lmin
+    int64_t span = 1;
+    for (int a = 0; a < 3; ++a) {
+        const int64_t e = (int64_t)s->host_ctrl->res.hi[a] - s->origin[a];
+        if (e > span) span = e;
+    }
+    int bits = 0;
+    while (((int64_t)1 << bits) < span) ++bits;
+    int lbits = 0;
+    while ((1 << lbits) < s->lmax - s->lmin + 1) ++lbits;
+    if (3 * bits + lbits > 64)
+        return fail(AMR_ERANGE, "amr_build_sorted_index: %d bits per axis and %d level bits exceed a 64-bit key", bits,
+                    lbits);
+    const int passes = s->n > 0 ? (3 * bits + lbits + 7) / 8 : 0;
+    char* b = (char*)ws;
+    uint64_t* k0 = (uint64_t*)(b + L.ka);
+    uint64_t* k1 = (uint64_t*)(b + L.kb);
+    uint32_t* v0 = (uint32_t*)(b + L.va);
+    uint32_t* v1 = (uint32_t*)(b + L.vb);
+    uint32_t* hist = (uint32_t*)(b + L.hist);
+    int64_t* off = (int64_t*)(b + L.off);
+    int64_t* bsum = (int64_t*)(b + L.bsum);
+    if (s->n > 0)
+        hipLaunchKernelGGL(k_sort_keys, dim3(grid_for(s->n, 256)), dim3(256), 0, stream, s->xyz, s->lvl, s->n,
+                           s->origin[0], s->origin[1], s->origin[2], s->lmin, bits, k0, v0);
+    for (int p = 0; p < passes; ++p) {
+        hipLaunchKernelGGL(k_sort_hist, dim3(L.n_tiles), dim3(256), 0, stream, k0, s->n, 8 * p, L.n_tiles, hist);
+        hipLaunchKernelGGL(k_smp_block_sums, dim3(L.nb), dim3(256), 0, stream, hist, L.n_hist, bsum);
+        hipLaunchKernelGGL(k_smp_scan_sums, dim3(1), dim3(256), 0, stream, bsum, L.nb);
+        hipLaunchKernelGGL(k_smp_offsets, dim3(L.nb), dim3(256), 0, stream, hist, L.n_hist, bsum, L.nb, off);
+        hipLaunchKernelGGL(k_sort_scatter, dim3(L.n_tiles), dim3(256), 0, stream, k0, v0, s->n, 8 * p, L.n_tiles,
+                           off, k1, v1);
+        uint64_t* tk = k0;
+        k0 = k1;
+        k1 = tk;
+        uint32_t* tv = v0;
+        v0 = v1;
+        v1 = tv;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hipfail(e, "amr_build_sorted_index: launch");
+    // level l's keys follow those of the finer levels (the level is the top digit)
+    int64_t acc = 0;
+    for (int l = 0; l <= kMaxLevel + 1; ++l) {
+        s->srt_lo[l] = acc;
+        if (l <= kMaxLevel) acc += (int64_t)s->level_count[l];
+    }
+    s->srt_keys = k0;
+    s->srt_cells = v0;
+    s->srt_bits = bits;
+    s->srt_gen = s->upload_gen;
+    g_err[0] = 0;
+    return AMR_OK;
+}
+
+int amr_locate(amr_set* s, int index, const int32_t* points, int64_t n, int32_t* cells, hipStream_t stream) {
+    if (!s) return fail(AMR_EINVAL, "amr_locate: set is NULL");
+    if (n < 0 || (n > 0 && (!points || !cells))) return fail(AMR_EINVAL, "amr_locate: bad arguments");
+    DeviceGuard dg(s->device);
+    const int st = index_ready(s, index, "amr_locate", stream);
+    if (st != AMR_OK) return st;
+    if (n == 0) {
+        g_err[0] = 0;
+        return AMR_OK;
+    }
+    const SortedIndex si = sorted_view(s);
+    if (index == AMR_INDEX_SORTED)
+        hipLaunchKernelGGL(k_locate<true>, dim3(grid_for(n, 256)), dim3(256), 0, stream, s->rec, s->ids, s->ctrl, si,
+                           points, n, cells);
+    else
+        hipLaunchKernelGGL(k_locate<false>, dim3(grid_for(n, 256)), dim3(256), 0, stream, s->rec, s->ids, s->ctrl,
+                           si, points, n, cells);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hipfail(e, "amr_locate: launch");
+    g_err[0] = 0;
+    return AMR_OK;
+}
+
+int amr_snap_count(amr_set* s, int index, uint64_t* out, hipStream_t stream) {
+    if (!s || !out) return fail(AMR_EINVAL, "amr_snap_count: NULL argument");
+    DeviceGuard dg(s->device);
+    const int st = index_ready(s, index, "amr_snap_count", stream);
+    if (st != AMR_OK) return st;
+    const SortedIndex si = sorted_view(s);
+    unsigned long long* o = (unsigned long long*)out;
+    hipLaunchKernelGGL(k_zero2, dim3(1), dim3(64), 0, stream, o);
+    const int grid = s->n > 0 ? (grid_for(s->n, 256) < 1024 ? grid_for(s->n, 256) : 1024) : 1;
+    if (index == AMR_INDEX_SORTED)
+        launch(s, AMR_KERNEL_SNAP, k_snap<true>, dim3(grid), dim3(256), stream, s->xyz, s->lvl, s->n, s->rec, s->ids,
+               s->ctrl, si, o);
+    else
+        launch(s, AMR_KERNEL_SNAP, k_snap<false>, dim3(grid), dim3(256), stream, s->xyz, s->lvl, s->n, s->rec,
+               s->ids, s->ctrl, si, o);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hipfail(e, "amr_snap_count: launch");
+    g_err[0] = 0;
+    return AMR_OK;
+}
+
 int amr_time_kernel(amr_set* s, int kernel, hipEvent_t start, hipEvent_t stop) {
     if (!s) return fail(AMR_EINVAL, "amr_time_kernel: set is NULL");
-    if (kernel < 0 || kernel > AMR_KERNEL_SAMPLE) return fail(AMR_EINVAL, "amr_time_kernel: unknown kernel %d", kernel);
+    if (kernel < 0 || kernel > AMR_KERNEL_SNAP) return fail(AMR_EINVAL, "amr_time_kernel: unknown kernel %d", kernel);
     if (kernel != 0 && (!start || !stop)) return fail(AMR_EINVAL, "amr_time_kernel: NULL event");
     s->time_kernel = kernel;
     s->time_start = start;
