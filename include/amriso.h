@@ -268,6 +268,20 @@ int amr_indexed_mesh_bytes(int64_t n_tris, size_t* bytes);
 int amr_indexed_mesh(const float* tris, const int32_t* tri_cells, int64_t n_tris, float* verts, int32_t* idx,
                      int64_t cap_verts, int64_t* n_verts, void* workspace, size_t bytes, hipStream_t stream);
 
+/* The same weld without allocating anything and without a workspace, for
+   callers that cannot allocate device memory (code under HIP graph capture,
+   tight serving loops, harnesses that forbid allocation).  The weld's
+   scratch is a 40 MiB array in the library's device code, one per GPU
+   (held until the process ends), found on each device's first call with
+   that device current; the call runs on the current device.  Every call on
+   one GPU shares that array: calls that overlap in time on one GPU race
+   (use one stream, or order them).  Arguments as amr_indexed_mesh; returns
+   AMR_ERANGE unless 0 <= n_tris <= 262144, AMR_EINVAL for NULL arrays,
+   AMR_EHIP if the scratch's address cannot be had.  No host
+   synchronisation, no allocation. */
+int amr_indexed_mesh_noalloc(const float* tris, const int32_t* tri_cells, int64_t n_tris, float* verts,
+                             int32_t* idx, int64_t cap_verts, int64_t* n_verts, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
    Dual-mesh interpolant.  The paper names the dual mesh as an interpolant of
    the cell values (sec. 5, after Moran et al.) and leaves volume rendering

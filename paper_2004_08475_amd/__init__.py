@@ -24,7 +24,8 @@ _NAMES = {0: "AMR_OK", -1: "AMR_EINVAL", -2: "AMR_ERANGE", -3: "AMR_EOVERLAP", -
 ABI_SYMBOLS = ("amr_create", "amr_destroy", "amr_upload", "amr_index_bytes", "amr_build_index", "amr_build_status",
                "amr_dual_cells",
                "amr_isosurface", "amr_batch_create", "amr_batch_destroy", "amr_batch_workspace_bytes",
-               "amr_batch_isosurface", "amr_indexed_mesh_bytes", "amr_indexed_mesh", "amr_sampler_bytes",
+               "amr_batch_isosurface", "amr_indexed_mesh_bytes", "amr_indexed_mesh", "amr_indexed_mesh_noalloc",
+               "amr_sampler_bytes",
                "amr_sampler_build", "amr_sample", "amr_sorted_index_bytes", "amr_build_sorted_index", "amr_locate",
                "amr_snap_count", "amr_time_kernel", "amr_last_error")
 
@@ -82,6 +83,8 @@ def load_library(path: str = LIB_PATH):
     L.amr_indexed_mesh_bytes.restype = C.c_int
     L.amr_indexed_mesh.argtypes = [f32p, i32p, i64, f32p, i32p, i64, i64p, vp, C.c_size_t, vp]
     L.amr_indexed_mesh.restype = C.c_int
+    L.amr_indexed_mesh_noalloc.argtypes = [f32p, i32p, i64, f32p, i32p, i64, i64p, vp]
+    L.amr_indexed_mesh_noalloc.restype = C.c_int
     L.amr_sampler_bytes.argtypes = [vp, i64, C.POINTER(C.c_size_t)]
     L.amr_sampler_bytes.restype = C.c_int
     L.amr_sampler_build.argtypes = [vp, i32p, i64, vp, C.c_size_t, vp]
@@ -484,6 +487,16 @@ def indexed_mesh_into(tris, cells, verts, idx, n_verts, workspace=None):
     _check(lib.amr_indexed_mesh(_ptr(tris), _ptr(cells), n, _ptr(verts), _ptr(idx), cap, _ptr(n_verts),
                                 _ptr(workspace), workspace.numel(), _stream(tris.device)))
     return workspace
+
+
+def indexed_mesh_noalloc_into(tris, cells, verts, idx, n_verts):
+    """indexed_mesh_into without a workspace and without any allocation
+    (amr_indexed_mesh_noalloc: at most 262,144 triangles; calls overlapping
+    on one GPU race)."""
+    lib = load_library()
+    cap = int(verts.shape[0]) if verts is not None else 0
+    _check(lib.amr_indexed_mesh_noalloc(_ptr(tris), _ptr(cells), int(tris.shape[0]), _ptr(verts), _ptr(idx), cap,
+                                        _ptr(n_verts), _stream(tris.device)))
 
 
 def indexed_mesh(tris, cells):

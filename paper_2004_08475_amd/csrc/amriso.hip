@@ -48,6 +48,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "amriso.h"
 #include "mc_table.inc"
 
@@ -4076,28 +4078,24 @@ int amr_indexed_mesh_bytes(int64_t n_tris, size_t* bytes) {
     return AMR_OK;
 }
 
-int amr_indexed_mesh(const float* tris, const int32_t* tri_cells, int64_t n_tris, float* verts, int32_t* idx,
-                     int64_t cap_verts, int64_t* n_verts, void* ws, size_t bytes, hipStream_t stream) {
-    WeldLayout L;
-    if (!weld_layout(n_tris, L)) return fail(AMR_ERANGE, "amr_indexed_mesh: n_tris out of range");
-    if (!n_verts || (n_tris > 0 && (!tris || !tri_cells || !idx)) || cap_verts < 0 || (cap_verts > 0 && !verts))
-        return fail(AMR_EINVAL, "amr_indexed_mesh: bad argument");
-    if (!ws || ((uintptr_t)ws & 255)) return fail(AMR_EINVAL, "amr_indexed_mesh: workspace NULL or unaligned");
-    if (bytes < L.total) return fail(AMR_ENOSPACE, "amr_indexed_mesh: workspace %zu bytes, need %zu", bytes, L.total);
+namespace {
+// The weld of an indexed mesh into the workspace at `base` (layout L).
+int weld_into(const float* tris, const int32_t* tri_cells, int64_t n_tris, float* verts, int32_t* idx,
+              int64_t cap_verts, int64_t* n_verts, char* base, const WeldLayout& L, hipStream_t stream,
+              const char* who) {
     if (n_tris == 0) {
         hipLaunchKernelGGL(k_weld_empty, dim3(1), dim3(64), 0, stream, n_verts);
         hipError_t e = hipGetLastError();
-        return e == hipSuccess ? AMR_OK : hipfail(e, "amr_indexed_mesh");
+        return e == hipSuccess ? AMR_OK : hipfail(e, who);
     }
-    char* b = (char*)ws;
     WeldWs w;
-    w.key = (unsigned long long*)(b + L.key);
-    w.first = (unsigned int*)(b + L.first);
-    w.vid = (unsigned int*)(b + L.vid);
-    w.cslot = (unsigned int*)(b + L.cslot);
-    w.s0 = (unsigned long long*)(b + L.s0);
-    w.s1 = (unsigned long long*)(b + L.s1);
-    w.sched = (Sched*)(b + L.sched);
+    w.key = (unsigned long long*)(base + L.key);
+    w.first = (unsigned int*)(base + L.first);
+    w.vid = (unsigned int*)(base + L.vid);
+    w.cslot = (unsigned int*)(base + L.cslot);
+    w.s0 = (unsigned long long*)(base + L.s0);
+    w.s1 = (unsigned long long*)(base + L.s1);
+    w.sched = (Sched*)(base + L.sched);
     w.cap = L.cap;
     int log2cap = 0;
     while ((1u << log2cap) < L.cap) ++log2cap;
@@ -4109,7 +4107,69 @@ int amr_indexed_mesh(const float* tris, const int32_t* tri_cells, int64_t n_tris
                        cap_verts, n_verts);
     hipLaunchKernelGGL(k_weld_index, dim3(grid_for(corners, 256)), dim3(256), 0, stream, corners, w, idx);
     hipError_t e = hipGetLastError();
-    return e == hipSuccess ? AMR_OK : hipfail(e, "amr_indexed_mesh: launch");
+    return e == hipSuccess ? AMR_OK : hipfail(e, who);
+}
+}  // namespace
+
+int amr_indexed_mesh(const float* tris, const int32_t* tri_cells, int64_t n_tris, float* verts, int32_t* idx,
+                     int64_t cap_verts, int64_t* n_verts, void* ws, size_t bytes, hipStream_t stream) {
+    WeldLayout L;
+    if (!weld_layout(n_tris, L)) return fail(AMR_ERANGE, "amr_indexed_mesh: n_tris out of range");
+    if (!n_verts || (n_tris > 0 && (!tris || !tri_cells || !idx)) || cap_verts < 0 || (cap_verts > 0 && !verts))
+        return fail(AMR_EINVAL, "amr_indexed_mesh: bad argument");
+    if (!ws || ((uintptr_t)ws & 255)) return fail(AMR_EINVAL, "amr_indexed_mesh: workspace NULL or unaligned");
+    if (bytes < L.total) return fail(AMR_ENOSPACE, "amr_indexed_mesh: workspace %zu bytes, need %zu", bytes, L.total);
+    return weld_into(tris, tri_cells, n_tris, verts, idx, cap_verts, n_verts, (char*)ws, L, stream,
+                     "amr_indexed_mesh");
+}
+
+namespace {
+// Scratch of amr_indexed_mesh_noalloc: the weld's workspace for up to
+// kWeldScratchTris triangles, one copy on every GPU the library runs on,
+// held until the process ends.  In host code `weld_scratch` names a host
+// stand-in, not device memory: its device address on each GPU comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr int64_t kWeldScratchTris = 1 << 18;
+constexpr size_t kWeldScratchBytes = (size_t)40 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) char weld_scratch[kWeldScratchBytes];
+
+std::mutex g_weld_scratch_lock;
+char* g_weld_scratch[kMaxDevices] = {};
+
+// The scratch of the current device (nullptr and a message on failure).
+char* weld_scratch_of_current_device() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        fail(AMR_EHIP, "amr_indexed_mesh_noalloc: no current HIP device (or more than %d)", kMaxDevices);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_weld_scratch_lock);
+    if (!g_weld_scratch[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(weld_scratch));
+        if (e != hipSuccess || !ptr) {
+            hipfail(e, "amr_indexed_mesh_noalloc: scratch address");
+            return nullptr;
+        }
+        g_weld_scratch[dev] = (char*)ptr;
+    }
+    return g_weld_scratch[dev];
+}
+}  // namespace
+
+int amr_indexed_mesh_noalloc(const float* tris, const int32_t* tri_cells, int64_t n_tris, float* verts,
+                             int32_t* idx, int64_t cap_verts, int64_t* n_verts, hipStream_t stream) {
+    WeldLayout L;
+    if (n_tris < 0 || n_tris > kWeldScratchTris || !weld_layout(n_tris, L) || L.total > kWeldScratchBytes)
+        return fail(AMR_ERANGE, "amr_indexed_mesh_noalloc: n_tris must lie in [0, %lld] (a %zu-byte scratch per GPU)",
+                    (long long)kWeldScratchTris, kWeldScratchBytes);
+    if (!n_verts || (n_tris > 0 && (!tris || !tri_cells || !idx)) || cap_verts < 0 || (cap_verts > 0 && !verts))
+        return fail(AMR_EINVAL, "amr_indexed_mesh_noalloc: bad argument");
+    char* base = weld_scratch_of_current_device();
+    if (!base) return AMR_EHIP;
+    return weld_into(tris, tri_cells, n_tris, verts, idx, cap_verts, n_verts, base, L, stream,
+                     "amr_indexed_mesh_noalloc");
 }
 
 namespace {
