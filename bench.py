@@ -488,7 +488,7 @@ def pipeline_measurement(amr, cs, reps=5):
 
 
 def batched_measurement(amr, s, cs, n_isos):
-    """Many iso-values of one set in one fused persistent launch (autotuned
+    """Many iso-values of one set in one batched run (autotuned
     launch shape, replayed from a HIP graph) against the plain path run once
     per iso on the same stream."""
     import numpy as np
@@ -506,17 +506,17 @@ def batched_measurement(amr, s, cs, n_isos):
     off = np.concatenate([[0], np.cumsum(c)[:-1]])
     tris = torch.empty((max(int(c.sum()), 1), 9), dtype=torch.float32, device=dev)
     jobs = b.jobs_tensor([0] * n_isos, isos, off, c)
-    block, per, table = autotune.tune(b, jobs, n_isos, tris, counts)
-    ws = b.workspace(n_isos, block, per)
+    block, unit, table = autotune.tune(b, jobs, n_isos, tris, counts)
+    ws = b.workspace(n_isos, block, unit)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
-        b.run_into(jobs, n_isos, tris, counts, block, per, ws)
+        b.run_into(jobs, n_isos, tris, counts, block, unit, ws)
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
-        b.run_into(jobs, n_isos, tris, counts, block, per, ws)
+        b.run_into(jobs, n_isos, tris, counts, block, unit, ws)
     reps = 10
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     g.replay()
@@ -543,12 +543,12 @@ def batched_measurement(amr, s, cs, n_isos):
     return {"workload": "%s x %d isos (percentiles 5..95), one fused launch replayed from a HIP graph" % (cs.name, n_isos),
             "fused_ms": fused_ms, "plain_ms_for_all_isos": plain_ms, "speedup_vs_plain": plain_ms / fused_ms,
             "iso_cells_per_s": n_isos * cs.n / (fused_ms * 1e-3), "triangles": int(c.sum()),
-            "autotuned_shape": {"block": block, "per_cu": per}, "autotune_ms": table}
+            "autotuned_shape": {"block": block, "unit": unit}, "autotune_ms": table}
 
 
 def batched_multiset_measurement(amr, n_sets=32, seed=4):
     """32 independent octree sets of log-uniform sizes 10k..5M cells, each at
-    its own iso (median), in one fused persistent launch replayed from a HIP
+    its own iso (median), in one batched run replayed from a HIP
     graph, against the plain path run once per set."""
     import numpy as np
     import torch
@@ -579,17 +579,17 @@ def batched_multiset_measurement(amr, n_sets=32, seed=4):
     off = np.concatenate([[0], np.cumsum(c)[:-1]])
     tris = torch.empty((max(int(c.sum()), 1), 9), dtype=torch.float32, device=dev)
     jobs = b.jobs_tensor(list(range(n_sets)), isos, off, c)
-    block, per, table = autotune.tune(b, jobs, n_sets, tris, counts)
-    ws = b.workspace(n_sets, block, per)
+    block, unit, table = autotune.tune(b, jobs, n_sets, tris, counts)
+    ws = b.workspace(n_sets, block, unit)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
-        b.run_into(jobs, n_sets, tris, counts, block, per, ws)
+        b.run_into(jobs, n_sets, tris, counts, block, unit, ws)
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
-        b.run_into(jobs, n_sets, tris, counts, block, per, ws)
+        b.run_into(jobs, n_sets, tris, counts, block, unit, ws)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     g.replay()
     e0.record()
@@ -619,7 +619,7 @@ def batched_multiset_measurement(amr, n_sets=32, seed=4):
                         "launch replayed from a HIP graph" % (n_sets, n_cells),
             "set_cells": [int(cs.n) for cs in css], "fused_ms": fused_ms, "plain_ms_for_all_sets": plain_ms,
             "speedup_vs_plain": plain_ms / fused_ms, "cells_per_s": n_cells / (fused_ms * 1e-3),
-            "triangles": int(c.sum()), "autotuned_shape": {"block": block, "per_cu": per},
+            "triangles": int(c.sum()), "autotuned_shape": {"block": block, "unit": unit},
             "autotune_ms": table}, css
 
 

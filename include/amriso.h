@@ -185,17 +185,17 @@ int amr_isosurface(amr_set* set, float iso, float* tris, int32_t* tri_cells, int
                    int64_t* counts, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
-   Batched iso-surfaces (many iso-values and/or many sets in one launch).
+   Batched iso-surfaces (many iso-values and/or many sets in one enqueue).
    The dual cells do not depend on the field (paper sec. 4), so a batched
-   launch reads each tile of a set's groups and their neighbourhoods once
-   per phase and runs Marching Cubes (paper sec. 5) for every job on that
-   set against them; groups whose neighbourhood value range straddles no
-   job's iso are skipped (before their neighbourhood is read when the set
-   has recorded ranges, see amr_isosurface).  One persistent kernel handles
-   all jobs: a counting phase, a per-job scan over tiles and a writing
-   phase, separated by grid-wide barriers.  For a job on set s with iso v,
-   the triangles, their order and every bit of their positions equal those
-   of amr_isosurface(s, v) (no cell pairs or dual indices are written here).
+   run reads each unit of a set's groups and their neighbourhoods once per
+   pass and runs Marching Cubes (paper sec. 5) for every job on that set
+   against them; groups whose neighbourhood value range straddles no job's
+   iso are skipped (before their neighbourhood is read when the set has
+   recorded ranges, see amr_isosurface).  A counting pass over all units of
+   all sets, a per-job scan and a writing pass handle all jobs.  For a job
+   on set s with iso v, the triangles, their order and every bit of their
+   positions equal those of amr_isosurface(s, v) (no cell pairs or dual
+   indices are written here).
    --------------------------------------------------------------------------- */
 
 typedef struct amr_batch amr_batch; /* opaque, library-owned host handle */
@@ -219,28 +219,28 @@ int amr_batch_create(amr_batch** out, amr_set* const* sets, int n_sets);
 void amr_batch_destroy(amr_batch* batch);
 
 /* Device workspace bytes for up to max_jobs jobs with `block` threads per
-   work-group (128 or 256: tiles of 16 or 32 groups of 2x2x2 cells, eight
-   threads each) and `per_cu` (1..4) work-groups per compute unit (the
-   persistent grid, capped at what the kernel's occupancy allows):
-   2 x 4 bytes per (job, tile of the largest set) plus 16 KB. */
-int amr_batch_workspace_bytes(const amr_batch* batch, int max_jobs, int block, int per_cu, size_t* bytes);
+   work-group (128 or 256: chunks of 16 or 32 groups of 2x2x2 cells, eight
+   threads each) and `unit` groups of a set per work-group (a power of two,
+   64..1024): 2 x 4 bytes per (job, unit of the largest set) plus 10 KB.
+   AMR_EINVAL for any other shape. */
+int amr_batch_workspace_bytes(const amr_batch* batch, int max_jobs, int block, int unit, size_t* bytes);
 
-/* Enqueue one persistent launch for n_jobs jobs (1 <= n_jobs <= 256).
+/* Enqueue the batched run of n_jobs jobs (1 <= n_jobs <= 256): four kernel
+   launches on `stream` (job layout, per-unit counts, per-job scan, writes).
      jobs      device amr_iso_job [n_jobs]
      tris      device float [..][3][3]: job j writes triangles
-               out_offset .. out_offset + min(count, out_cap) - 1
+               out_offset .. out_offset + min(count, out_cap) - 1 (NULL:
+               nothing is written; give out_cap 0 to skip the writing pass)
      counts    device int64 [n_jobs]: full triangle count of each job (-1
                for an invalid job or a set whose build failed)
-     workspace device, >= amr_batch_workspace_bytes(n_jobs, block, per_cu),
-               256-byte aligned, zero-filled before its first use; it holds
-               the grid barrier, so launches that share a workspace, and
-               batched launches on one GPU, must not overlap in time.  Its
-               bytes 8..11 become non-zero if a barrier wait ever gave up
-               (the results of that launch are then invalid).
-     block     128 or 256;  per_cu 1..4
-   No host synchronisation: capturable in a HIP graph. */
+     workspace device, >= amr_batch_workspace_bytes(n_jobs, block, unit),
+               256-byte aligned, no initial contents needed; runs that share
+               a workspace must not overlap in time.
+     block     128 or 256;  unit 64, 128, .., 1024
+   No host synchronisation, no memset, no allocation: capturable in a HIP
+   graph. */
 int amr_batch_isosurface(amr_batch* batch, const amr_iso_job* jobs, int n_jobs, float* tris, int64_t* counts,
-                         void* workspace, size_t bytes, int block, int per_cu, hipStream_t stream);
+                         void* workspace, size_t bytes, int block, int unit, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
    Indexed face set (paper sec. 5.2): the fat triangles share vertices; each

@@ -374,12 +374,12 @@ def _job_dtype():
 
 
 class AmrBatch:
-    """Many (set, iso) jobs in one persistent launch (amr_batch_isosurface):
-    each tile of a set's groups reads its neighbourhoods once per phase and
-    runs Marching Cubes for every job on that set.  The sets must not be
-    uploaded or built again while the batch is used.  Launch shape: `block`
-    threads per work-group (128 or 256) and `per_cu` work-groups per
-    compute unit (1..4)."""
+    """Many (set, iso) jobs in one enqueue (amr_batch_isosurface): each unit
+    of a set's groups reads its neighbourhoods once per pass and runs
+    Marching Cubes for every job on that set.  The sets must not be uploaded
+    or built again while the batch is used.  Launch shape: `block` threads
+    per work-group (128 or 256) and `unit` groups per work-group (a power of
+    two, 64..1024)."""
 
     def __init__(self, sets):
         self.lib = load_library()
@@ -408,14 +408,14 @@ class AmrBatch:
         except Exception:
             pass
 
-    def workspace(self, n_jobs: int, block: int = 256, per_cu: int = 2):
-        """Zero-filled workspace (cached per launch shape)."""
+    def workspace(self, n_jobs: int, block: int = 256, unit: int = 256):
+        """Workspace for up to n_jobs jobs (cached per launch shape)."""
         b = C.c_size_t(0)
-        _check(self.lib.amr_batch_workspace_bytes(self._h, n_jobs, block, per_cu, C.byref(b)))
-        key = (block, per_cu)
+        _check(self.lib.amr_batch_workspace_bytes(self._h, n_jobs, block, unit, C.byref(b)))
+        key = (block, unit)
         ws = self._ws.get(key)
         if ws is None or ws.numel() < b.value:
-            ws = torch.zeros(max(int(b.value), 256), dtype=torch.uint8, device=self.device)
+            ws = torch.empty(max(int(b.value), 256), dtype=torch.uint8, device=self.device)
             self._ws[key] = ws
         return ws
 
@@ -429,35 +429,22 @@ class AmrBatch:
         arr["out_cap"] = np.asarray(caps, np.int64)
         return torch.from_numpy(arr.view(np.uint8)).to(self.device)
 
-    def run_into(self, jobs, n_jobs: int, tris, counts, block: int = 256, per_cu: int = 2, workspace=None):
-        """Enqueue one launch (no synchronisation); capturable in a graph."""
-        ws = workspace if workspace is not None else self.workspace(n_jobs, block, per_cu)
+    def run_into(self, jobs, n_jobs: int, tris, counts, block: int = 256, unit: int = 256, workspace=None):
+        """Enqueue one batched run (no synchronisation); capturable in a graph."""
+        ws = workspace if workspace is not None else self.workspace(n_jobs, block, unit)
         _check(self.lib.amr_batch_isosurface(self._h, _ptr(jobs), int(n_jobs), _ptr(tris), _ptr(counts), _ptr(ws),
-                                             ws.numel(), int(block), int(per_cu), _stream(self.device)))
+                                             ws.numel(), int(block), int(unit), _stream(self.device)))
         return counts
 
-    def barrier_timed_out(self, block: int = 256, per_cu: int = 2) -> bool:
-        """True if a grid-barrier wait of a launch with this workspace gave up
-        (bytes 8..11 of the workspace; that launch's results are invalid)."""
-        ws = self._ws.get((block, per_cu))
-        return ws is not None and bool(ws[8:12].any().item())
-
-    def reset_barrier(self, block: int = 256, per_cu: int = 2):
-        """Clear the grid barrier (arrival count, sense, time-out flag) of this
-        workspace after a time-out, before its next launch."""
-        ws = self._ws.get((block, per_cu))
-        if ws is not None:
-            ws[:16].zero_()
-
-    def isosurface(self, set_idx, isos, block: int = 256, per_cu: int = 2):
-        """List of float32 [T_j, 9] triangle tensors, one per job: a count
-        launch sizes the output, a second launch writes it."""
+    def isosurface(self, set_idx, isos, block: int = 256, unit: int = 256):
+        """List of float32 [T_j, 9] triangle tensors, one per job: a counting
+        run sizes the output, a second run writes it."""
         import numpy as np
 
         n = len(isos)
         counts = torch.zeros(n, dtype=torch.int64, device=self.device)
         jobs = self.jobs_tensor(set_idx, isos, np.zeros(n), np.zeros(n))
-        self.run_into(jobs, n, None, counts, block, per_cu)
+        self.run_into(jobs, n, None, counts, block, unit)
         c = counts.cpu().numpy()
         if (c < 0).any():
             raise AmrError(AMR_EINVAL, "batched launch: job(s) %s are invalid or on a failed build"
@@ -465,10 +452,8 @@ class AmrBatch:
         off = np.concatenate([[0], np.cumsum(c)[:-1]])
         tris = torch.empty((max(int(c.sum()), 1), 9), dtype=torch.float32, device=self.device)
         jobs = self.jobs_tensor(set_idx, isos, off, c)
-        self.run_into(jobs, n, tris, counts, block, per_cu)
+        self.run_into(jobs, n, tris, counts, block, unit)
         torch.cuda.synchronize(self.device)
-        if self.barrier_timed_out(block, per_cu):
-            raise AmrError(AMR_EHIP, "batched launch: a grid barrier wait gave up")
         return [tris[int(o):int(o) + int(k)] for o, k in zip(off, c)]
 
 

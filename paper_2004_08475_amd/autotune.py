@@ -1,8 +1,7 @@
 """Launch-shape autotuner for batched iso-surfaces.
 
-Times every (threads per work-group, work-groups per compute unit) shape
-the library accepts on the caller's actual batch, keeps the fastest, and
-caches the
+Times every (threads per work-group, groups per work-group) shape in
+SHAPES on the caller's actual batch, keeps the fastest, and caches the
 choice in a JSON file keyed by GPU architecture and batch shape, so later
 processes skip the search.  Cache path: $AMRISO_TUNE_CACHE, else
 ~/.cache/amriso/autotune.json.
@@ -16,7 +15,7 @@ import threading
 
 import torch
 
-SHAPES = ((128, 1), (128, 2), (128, 3), (256, 1), (256, 2), (256, 3), (256, 4))
+SHAPES = ((128, 64), (128, 128), (128, 256), (128, 512), (256, 64), (256, 128), (256, 256), (256, 512))
 _lock = threading.Lock()
 
 
@@ -29,7 +28,7 @@ def _key(batch, n_jobs: int) -> str:
     arch = torch.cuda.get_device_properties(batch.device).gcnArchName.split(":")[0]
     cells = batch.cells
     bucket = 0 if cells == 0 else int(round(math.log2(cells)))
-    return "%s|tiles-v2|sets=%d|cells=2^%d|jobs=%d" % (arch, len(batch.sets), bucket, n_jobs)
+    return "%s|units-v3|sets=%d|cells=2^%d|jobs=%d" % (arch, len(batch.sets), bucket, n_jobs)
 
 
 def _load() -> dict:
@@ -52,35 +51,35 @@ def _store(table: dict):
         pass  # a read-only home only costs a re-tune
 
 
-def time_shape(batch, jobs, n_jobs, tris, counts, block, per, reps=5):
-    """Mean milliseconds of one launch with this shape."""
-    ws = batch.workspace(n_jobs, block, per)
-    batch.run_into(jobs, n_jobs, tris, counts, block, per, ws)  # warm-up
+def time_shape(batch, jobs, n_jobs, tris, counts, block, unit, reps=5):
+    """Mean milliseconds of one batched run with this shape."""
+    ws = batch.workspace(n_jobs, block, unit)
+    batch.run_into(jobs, n_jobs, tris, counts, block, unit, ws)  # warm-up
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        batch.run_into(jobs, n_jobs, tris, counts, block, per, ws)
+        batch.run_into(jobs, n_jobs, tris, counts, block, unit, ws)
     e1.record()
     torch.cuda.synchronize(batch.device)
     return e0.elapsed_time(e1) / reps
 
 
 def tune(batch, jobs, n_jobs, tris, counts, reps=5, use_cache=True):
-    """(block, per_cu, table of timings) for this batch and job list."""
+    """(block, unit, table of timings) for this batch and job list."""
     key = _key(batch, n_jobs)
     with _lock:
         table = _load() if use_cache else {}
         hit = table.get(key)
     if hit:
-        return int(hit["block"]), int(hit["per_cu"]), hit.get("ms", {})
+        return int(hit["block"]), int(hit["unit"]), hit.get("ms", {})
     ms = {}
-    for block, per in SHAPES:
-        ms["%dx%d" % (block, per)] = time_shape(batch, jobs, n_jobs, tris, counts, block, per, reps)
+    for block, unit in SHAPES:
+        ms["%dx%d" % (block, unit)] = time_shape(batch, jobs, n_jobs, tris, counts, block, unit, reps)
     best = min(ms, key=ms.get)
-    block, per = (int(x) for x in best.split("x"))
+    block, unit = (int(x) for x in best.split("x"))
     if use_cache:
         with _lock:
             table = _load()
-            table[key] = {"block": block, "per_cu": per, "ms": ms}
+            table[key] = {"block": block, "unit": unit, "ms": ms}
             _store(table)
-    return block, per, ms
+    return block, unit, ms

@@ -2018,24 +2018,26 @@ __global__ __launch_bounds__(kBlock) void k_tile_scan(ExtractArgs a, int duals) 
 }
 
 // ---------------------------------------------------------------------------
-// Batched iso-surfaces: many (set, iso) jobs in one persistent launch.  The
-// dual cells do not depend on the field (sec. 4), so a tile of groups loads
-// its neighbourhoods into LDS once and runs Marching Cubes (sec. 5) for every
-// job of its set against them.  Phase A counts each job's triangles per
-// tile, phase B scans each job's tile counts, phase C loads the tiles that
-// have output again and writes; grid-wide barriers separate the phases.  A
-// group whose neighbourhood value range straddles no job's iso is skipped
-// before its neighbourhood is read when the set has recorded ranges (see
-// range culling above), else after.  Every job's triangles come out in the
-// order, and with the bits, of amr_isosurface on its set.  The grid never
-// exceeds what the GPU keeps resident, and every wait is bounded, so the
-// kernel always drains.
+// Batched iso-surfaces: many (set, iso) jobs in one enqueue.  The dual cells
+// do not depend on the field (sec. 4), so a work-group loads the
+// neighbourhoods of a unit of groups into LDS once and runs Marching Cubes
+// (sec. 5) for every job of the unit's set against them.  Four launches: a
+// one-work-group preparation orders the jobs and lays out the per-(job,
+// unit) counts; a counting launch (one work-group per unit) counts each
+// job's triangles per unit; a scan launch (one work-group per job) turns
+// them into output positions; a writing launch loads the units that have
+// output again and writes.  A group whose neighbourhood value range
+// straddles no job's iso is skipped before its neighbourhood is read when
+// the set has recorded ranges (see range culling above), else after.  Every
+// job's triangles come out in the order, and with the bits, of
+// amr_isosurface on its set.
 // ---------------------------------------------------------------------------
 
 constexpr int kMaxJobs = 256;
 constexpr int kMaxSets = 256;
+constexpr int kMaxUnit = 1024;  // groups per unit, at most
 
-// One set of a batch, as the kernel reads it (device table).
+// One set of a batch, as the kernels read it (device table).
 struct BatchSet {
     const Record* rec;
     const int32_t* glist;
@@ -2043,13 +2045,24 @@ struct BatchSet {
     const Ctrl* ctrl;            // verdict, group count, geometry
     const float2* rng;           // recorded neighbourhood ranges, when *rng_ok
     const uint32_t* rng_ok;
+    uint32_t bound;              // groups the set can hold (its extraction grid)
+    uint32_t pad;
 };
 
-struct alignas(256) GridBar {
-    unsigned int count;
-    unsigned int sense;
-    unsigned int timeout;  // set when a barrier wait gave up (results invalid)
-    unsigned int pad;
+// A valid job, by its rank among the valid jobs (by set, then iso, then index).
+struct BatchRank {
+    float iso;
+    int32_t job;
+    int64_t jbase;  // its first per-unit count
+};
+
+// The batch's job layout, written by the preparation launch.
+struct BatchTab {
+    int32_t first[kMaxSets + 1];  // first rank of each set
+    int64_t tbase[kMaxSets + 1];  // first global unit of each set
+    int64_t jbase[kMaxJobs];      // per job index: first per-unit count (-1: invalid job)
+    int64_t jn[kMaxJobs];         // per job index: units of its set
+    BatchRank rank[kMaxJobs];
 };
 
 struct BatchArgs {
@@ -2057,42 +2070,14 @@ struct BatchArgs {
     int n_sets;
     const amr_iso_job* jobs;
     int n_jobs;
+    int unit;        // groups per unit (a power of two, 64 .. kMaxUnit)
+    int unit_shift;
     float* tris;
     int64_t* counts;
-    uint32_t* tcnt;  // per (job, tile of its set): triangles
-    uint32_t* tpre;  // the same, exclusive prefix over the job's tiles
-    uint32_t* bsum;  // per work-group: sum of its stretch of one job's counts
-    GridBar* bar;
+    BatchTab* tab;
+    uint32_t* tcnt;  // per (job, unit of its set): triangles
+    uint32_t* tpre;  // the same, exclusive prefix over the job's units
 };
-
-constexpr int kMaxBatchGrid = 4096;  // work-groups of a batched launch (bsum entries)
-
-__device__ void grid_barrier(GridBar* bar, unsigned int& sense) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        sense ^= 1u;
-        __threadfence();
-        unsigned int arrived = atomicAdd(&bar->count, 1u) + 1u;
-        if (arrived == gridDim.x) {
-            __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __threadfence();
-            __hip_atomic_store(&bar->sense, sense, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            // bounded wait (about 10 s): the grid fits on the GPU, so this only
-            // gives up if something else holds the compute units that long
-            for (long long spin = 0;; ++spin) {
-                if (__hip_atomic_load(&bar->sense, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == sense) break;
-                if (spin > (1ll << 26)) {
-                    atomicOr(&bar->timeout, 1u);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(8);
-            }
-        }
-        __threadfence();
-    }
-    __syncthreads();
-}
 
 // exclusive block scan of x (blockDim.x <= 512); returns the prefix, *total = sum
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s_w, uint32_t* total) {
@@ -2110,19 +2095,36 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s_w, u
     return pre + (uint32_t)incl - x;
 }
 
-// One tile of a batched launch: kG groups of one set, eight lanes each.
-// The set's isos are sorted ascending; a group with neighbourhood value
-// range (lo, hi] has triangles only for the isos with lo < iso <= hi, the
-// sorted positions [ia, ib).  The loader reads the neighbourhoods of the
-// groups that have any, leaves each group's [ia, ib) in LDS and returns the
-// union over the tile.
+// A batched launch works through units of consecutive groups of one set.
+// A unit's candidates -- the groups whose neighbourhood value range (lo, hi]
+// contains some job's iso -- are compacted in LDS in group order, then taken
+// kG at a time (a chunk, eight lanes per group), so that sparse candidates
+// still fill the work-groups.  The set's isos are sorted ascending; a group
+// has triangles only for the isos with lo < iso <= hi, the sorted positions
+// [ia, ib).  Without recorded ranges every group is a candidate and its
+// range comes from the loaded neighbourhood.
+constexpr int kPairWin = 256;  // (group, job) pairs of a chunk listed at a time
+
 template <int kG>
 struct BatchTile {
     float v[kG][64];
     int32_t r[kG][64];
     int8_t l[kG][64];
     int16_t ia[kG], ib[kG];
+    int gm[kG];            // each chunk group's level and block coordinates
+    uint32_t gxyz[kG][3];
     int fa, fb;
+    uint16_t cl[kMaxUnit];  // the unit's candidates (group index within the unit)
+    uint32_t wc[4];
+    // the chunk's (group, job) pairs, job-major, groups in order within a job
+    uint32_t pm[kMaxJobs];      // per job (from fa): the chunk groups that straddle it
+    uint16_t pb[kMaxJobs + 1];  // per job: its first pair
+    uint16_t pair[kPairWin];    // group | job << 5
+    // per octet (eight lanes, one pair) of a writing round
+    int pg[kG];
+    uint32_t pfirst[kG];
+    float piso[kG];
+    int64_t pbase[kG], pcap[kG];
 };
 
 // first sorted position whose iso exceeds x
@@ -2136,30 +2138,55 @@ __device__ __forceinline__ int iso_upper(const float* iso_sorted, int n_iso, flo
     return a;
 }
 
+// The candidates of unit `st` (groups st * unit ..) into T.cl; returns their count.
 template <int kG>
-__device__ __forceinline__ void batch_load_tile(const BatchSet& S, const Geo& g, uint32_t ng, int64_t lt, int gi,
-                                                int j, const float* iso_sorted, int n_iso, BatchTile<kG>& T,
-                                                bool& work, int& m, uint32_t& gx, uint32_t& gy, uint32_t& gz) {
-    const int64_t gidx = lt * kG + gi;
-    const bool valid = gidx < (int64_t)ng;
-    const bool ranged = uniform_u32(*S.rng_ok) != 0;
+__device__ __forceinline__ int batch_candidates(const BatchSet& S, uint32_t ng, int64_t st, int unit, bool ranged,
+                                                const float* iso_sorted, int n_iso, BatchTile<kG>& T) {
+    constexpr int kB = kG * 8;
+    const int t = threadIdx.x, lane = lane_id(), wave = t >> 6;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int base = 0;
+    for (int r0 = 0; r0 < unit; r0 += kB) {
+        const int li = r0 + t;
+        const int64_t gidx = st * unit + li;
+        bool cand = li < unit && gidx < (int64_t)ng;
+        if (cand && ranged) {
+            const float2 rg = S.rng[gidx];
+            cand = iso_upper(iso_sorted, n_iso, rg.x) < iso_upper(iso_sorted, n_iso, rg.y);
+        }
+        const unsigned long long bal = __ballot(cand);
+        if (lane == 0) T.wc[wave] = (uint32_t)__popcll(bal);
+        __syncthreads();
+        int before = base, total = 0;
+        for (int w = 0; w < kB / 64; ++w) {
+            if (w < wave) before += T.wc[w];
+            total += T.wc[w];
+        }
+        if (cand) T.cl[before + __popcll(bal & below)] = (uint16_t)li;
+        base += total;
+        __syncthreads();
+    }
+    return base;
+}
+
+// Chunk c0 of a unit's candidates: their neighbourhoods into LDS, each
+// group's [ia, ib) and the union over the chunk (T.fa, T.fb).
+template <int kG>
+__device__ __forceinline__ void batch_load_chunk(const BatchSet& S, const Geo& g, int64_t st, int unit, int c0,
+                                                 int n_c, bool ranged, int gi, int j, const float* iso_sorted,
+                                                 int n_iso, BatchTile<kG>& T) {
+    const int k = c0 + gi;
+    const bool work = k < n_c;
     if (threadIdx.x == 0) {
         T.fa = n_iso;
         T.fb = 0;
     }
-    int ia = 0, ib = 0;
-    work = valid;
-    if (valid && ranged) {
-        const float2 rg = S.rng[gidx];
-        ia = iso_upper(iso_sorted, n_iso, rg.x);
-        ib = iso_upper(iso_sorted, n_iso, rg.y);
-        work = ia < ib;
-    }
-    m = 0;
-    gx = gy = gz = 0;
-    int own = 0;
+    int m = 0;
+    uint32_t gx = 0, gy = 0, gz = 0;
+    int64_t gidx = 0;
     if (work) {
-        own = S.glist[gidx];
+        gidx = st * unit + T.cl[k];
+        const int own = S.glist[gidx];
         const uint64_t key = S.gkey[gidx];
         m = (int)(key >> 57);
         gx = (uint32_t)(key & 0x7FFFF);
@@ -2167,8 +2194,21 @@ __device__ __forceinline__ void batch_load_tile(const BatchSet& S, const Geo& g,
         gz = (uint32_t)((key >> 38) & 0x7FFFF);
         load_neighbourhood<1>(S.rec, g, j, m, gx, gy, gz, own, T.v[gi], T.r[gi], T.l[gi]);
     }
+    if (j == 0) {
+        T.gm[gi] = m;
+        T.gxyz[gi][0] = gx;
+        T.gxyz[gi][1] = gy;
+        T.gxyz[gi][2] = gz;
+    }
     __syncthreads();
-    if (!ranged) {
+    int ia = 0, ib = 0;
+    if (ranged) {
+        if (work) {
+            const float2 rg = S.rng[gidx];
+            ia = iso_upper(iso_sorted, n_iso, rg.x);
+            ib = iso_upper(iso_sorted, n_iso, rg.y);
+        }
+    } else {
         // the range of the cells in the neighbourhood (holes and the markers
         // of refined or empty slots excluded); lane j takes 8 of the 64
         float lo = INFINITY, hi = -INFINITY;
@@ -2205,6 +2245,124 @@ __device__ __forceinline__ void batch_load_tile(const BatchSet& S, const Geo& g,
     __syncthreads();
 }
 
+// The chunk's (group, job) pairs: per job the groups straddling it (T.pm)
+// and, by an exclusive scan over the jobs [fa, fb), each job's first pair
+// (T.pb).  Returns the number of pairs.
+template <int kG>
+__device__ __forceinline__ int batch_pairs(BatchTile<kG>& T, int gi, int j, uint32_t* s_w) {
+    constexpr int kB = kG * 8;
+    const int t = threadIdx.x;
+    const int fa = uniform_i32(T.fa), fb = uniform_i32(T.fb), nf = fb > fa ? fb - fa : 0;
+    for (int f = t; f < nf; f += kB) T.pm[f] = 0;
+    __syncthreads();
+    if (j == 0 && T.ia[gi] < T.ib[gi])
+        for (int f = T.ia[gi]; f < T.ib[gi]; ++f) atomicOr(&T.pm[f - fa], 1u << gi);
+    __syncthreads();
+    uint32_t carry = 0;
+    for (int f0 = 0; f0 < nf; f0 += kB) {
+        const int f = f0 + t;
+        const uint32_t c = f < nf ? (uint32_t)__popc(T.pm[f]) : 0u;
+        uint32_t tot;
+        const uint32_t pre = block_excl_scan(c, s_w, &tot);
+        if (f < nf) T.pb[f] = (uint16_t)(carry + pre);
+        carry += tot;
+    }
+    if (t == 0) T.pb[nf] = (uint16_t)carry;
+    __syncthreads();
+    return (int)carry;
+}
+
+// Pairs [p0, p0 + kPairWin) into T.pair.
+template <int kG>
+__device__ __forceinline__ void batch_pair_window(BatchTile<kG>& T, int gi, int j, int p0) {
+    const int fa = T.fa, ib = T.ib[gi];
+    for (int f = T.ia[gi] + j; f < ib; f += 8) {
+        const int at = T.pb[f - fa] + __popc(T.pm[f - fa] & ((1u << gi) - 1u)) - p0;
+        if (at >= 0 && at < kPairWin) T.pair[at] = (uint16_t)(gi | ((f - fa) << 5));
+    }
+    __syncthreads();
+}
+
+// Triangles of one writing round of a batched launch: as write_triangles,
+// with each octet holding its own pair (group T.pg, iso T.piso), the output
+// position of the round's triangle 0 were it of the octet's job (T.pbase),
+// and the end of that job's capacity (T.pcap).
+template <int kG>
+__device__ __forceinline__ void write_pair_triangles(const int t, const Geo& g, const uint32_t (&items)[4],
+                                                     const uint32_t round_tris, const uint32_t my_first,
+                                                     BatchTile<kG>& T, float* tris,
+                                                     const unsigned long long* s_tab, uint32_t (*s_items)[4],
+                                                     uint32_t* s_list) {
+    constexpr int kB = kG * 8;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s_items[t][q] = items[q];
+    for (uint32_t c0 = 0; c0 < round_tris; c0 += kTriList) {
+        __syncthreads();
+        uint32_t idx = my_first;
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t keep = items[q] & 0x1F;
+            for (int tt = 0; tt < 5; ++tt) {
+                if (!((keep >> tt) & 1)) continue;
+                if (idx >= c0 && idx < c0 + kTriList) s_list[idx - c0] = ((uint32_t)t << 8) | (q << 4) | tt;
+                ++idx;
+            }
+        }
+        __syncthreads();
+        const uint32_t n_here = round_tris - c0 < (uint32_t)kTriList ? round_tris - c0 : (uint32_t)kTriList;
+        for (uint32_t w = t; w < n_here; w += kB) {
+            const uint32_t en = s_list[w];
+            const int owner = (int)(en >> 8), q = (int)((en >> 4) & 3), tt = (int)(en & 15);
+            const int oc = owner >> 3, og = T.pg[oc];
+            const float iso = T.piso[oc];
+            const int64_t o_t = T.pbase[oc] + (int64_t)(c0 + w);
+            if (o_t >= T.pcap[oc]) continue;
+            const uint32_t it = s_items[owner][q];
+            const int k = (it >> 20) & 31;
+            const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
+            const int om = T.gm[og];
+            const uint32_t gg[3] = {T.gxyz[og][0], T.gxyz[og][1], T.gxyz[og][2]};
+            const unsigned long long e = s_tab[(it >> 8) & 0xFF];
+            float p[9];
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                const int ed = (int)((e >> (12 * tt + 4 * v)) & 0xF);
+                float ev[2];
+                int el[2], epos[2][3];
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+                    const int sl = side ? edge_hi(ed) : edge_lo(ed);
+                    const int pp = (kx + (sl & 1)) + 4 * (ky + ((sl >> 1) & 1)) + 16 * (kz + (sl >> 2));
+                    ev[side] = T.v[og][pp];
+                    el[side] = T.l[og][pp];
+                    epos[side][0] = kx + (sl & 1) - 1;
+                    epos[side][1] = ky + ((sl >> 1) & 1) - 1;
+                    epos[side][2] = kz + ((sl >> 2) & 1) - 1;
+                }
+                // A = the end below iso, B = the end at or above it
+                const bool swap = ev[0] >= iso;
+                const float va = swap ? ev[1] : ev[0], vb = swap ? ev[0] : ev[1];
+                const int la = swap ? el[1] : el[0], lb = swap ? el[0] : el[1];
+                const float tp = (iso - va) / (vb - va);
+                const int oo[3] = {g.ox, g.oy, g.oz};
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) {
+                    const int ra = swap ? epos[1][ax] : epos[0][ax], rb = swap ? epos[0][ax] : epos[1][ax];
+                    const uint32_t pa = ((2 * gg[ax] + (uint32_t)ra) << om) & ~((1u << la) - 1u);
+                    const uint32_t pb = ((2 * gg[ax] + (uint32_t)rb) << om) & ~((1u << lb) - 1u);
+                    const float ca = (float)((int)pa + oo[ax]) + 0.5f * (float)(1 << la);
+                    const float cb = (float)((int)pb + oo[ax]) + 0.5f * (float)(1 << lb);
+                    p[3 * v + ax] = fmaf(tp, cb - ca, ca);
+                }
+            }
+            if (tris) {
+                float* o = tris + 9 * o_t;
+#pragma unroll
+                for (int c = 0; c < 9; ++c) o[c] = p[c];
+            }
+        }
+    }
+}
+
 // Values every lane of a work-group holds alike, kept in scalar registers.
 __device__ __forceinline__ int64_t uniform_i64(int64_t v) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
@@ -2224,250 +2382,303 @@ __device__ __forceinline__ BatchSet uniform_set(const BatchSet& s) {
     u.ctrl = uniform_ptr(s.ctrl);
     u.rng = uniform_ptr(s.rng);
     u.rng_ok = uniform_ptr(s.rng_ok);
+    u.bound = uniform_u32(s.bound);
+    u.pad = 0;
     return u;
 }
 
-template <int kG>
-__global__ __launch_bounds__(kG * 8, 4) void k_batch(BatchArgs a) {
-    constexpr int kB = kG * 8;
-    __shared__ BatchTile<kG> T;
-    __shared__ unsigned long long s_tab[256];
+// Preparation (one work-group of 256): every valid job's rank among the
+// valid jobs (by set, then iso, then job index), each set's first rank and
+// first global unit, each job's first per-unit count.  A job naming no set
+// of the batch, with a non-finite iso, or on a set whose build failed, takes
+// part in nothing and counts -1.
+__global__ __launch_bounds__(256) void k_batch_prep(BatchArgs a) {
     __shared__ amr_iso_job s_job[kMaxJobs];
-    __shared__ uint16_t s_order[kMaxJobs];       // valid jobs by set, then iso (then index)
-    __shared__ float s_iso[kMaxJobs];            // their isos: ascending within each set
-    __shared__ int s_first[kMaxSets + 1];        // first entry of each set in s_order / s_iso
-    __shared__ int64_t s_tbase[kMaxSets + 1];    // first global tile of each set
-    __shared__ int64_t s_jbase[kMaxJobs + 1];    // first tcnt entry of each job
-    __shared__ uint32_t s_ng[kMaxSets];
-    __shared__ uint32_t s_items[kB][4];
-    __shared__ uint32_t s_dual[kB];
-    __shared__ uint32_t s_list[kTriList];
-    __shared__ int s_gm[kG];
-    __shared__ uint32_t s_gx[kG][3];
-    __shared__ uint32_t s_w[8];
-    __shared__ uint32_t s_any;
-    __shared__ unsigned int s_sense;
+    __shared__ int s_ok[kMaxJobs];
+    __shared__ int64_t s_units[kMaxSets];
+    __shared__ int s_rank[kMaxJobs];
     const int t = threadIdx.x;
-    for (int i = t; i < 256; i += kB) s_tab[i] = kMcTable[i];
-    for (int i = t; i < a.n_jobs; i += kB) s_job[i] = a.jobs[i];
-    for (int i = t; i < a.n_sets; i += kB) {
-        const Ctrl* c = a.sets[i].ctrl;
-        s_ng[i] = c->status == AMR_OK ? (uint32_t)c->n_groups : 0u;
+    BatchTab* tab = a.tab;
+    for (int i = t; i < a.n_sets; i += blockDim.x) {
+        const BatchSet& S = a.sets[i];
+        const Ctrl* c = S.ctrl;
+        int64_t ng = c->status == AMR_OK ? (int64_t)c->n_groups : -1;
+        if (ng > (int64_t)S.bound) ng = S.bound;  // cannot happen for a set built once; bounds the layout
+        s_units[i] = ng < 0 ? -1 : (ng + a.unit - 1) >> a.unit_shift;
+    }
+    for (int i = t; i < a.n_jobs; i += blockDim.x) s_job[i] = a.jobs[i];
+    __syncthreads();
+    for (int i = t; i < a.n_jobs; i += blockDim.x) {
+        const int si = s_job[i].set;
+        s_ok[i] = si >= 0 && si < a.n_sets && isfinite(s_job[i].iso) && s_units[si] >= 0;
     }
     __syncthreads();
-    // each valid job's place among the jobs of its set (by set, then iso for
-    // the sorted isos; by set, then job index for the order); a job naming
-    // no set of the batch, or with a non-finite iso, takes part in nothing
-    auto job_ok = [&](int i) { return s_job[i].set >= 0 && s_job[i].set < a.n_sets && isfinite(s_job[i].iso); };
-    for (int i = t; i < a.n_jobs; i += kB) {
-        if (!job_ok(i)) continue;
+    for (int i = t; i < a.n_jobs; i += blockDim.x) {
+        s_rank[i] = -1;
+        if (!s_ok[i]) continue;
         const int si = s_job[i].set;
         const float vi = s_job[i].iso;
         int rank = 0;
         for (int k = 0; k < a.n_jobs; ++k) {
-            if (!job_ok(k)) continue;
+            if (!s_ok[k]) continue;
             const int sk = s_job[k].set;
             const float vk = s_job[k].iso;
             rank += sk < si || (sk == si && (vk < vi || (vk == vi && k < i)));
         }
-        s_order[rank] = (uint16_t)i;
-        s_iso[rank] = vi;
+        s_rank[i] = rank;
     }
     __syncthreads();
     if (t == 0) {
-        int n_valid = 0;
-        for (int i = 0; i < a.n_jobs; ++i) n_valid += job_ok(i) ? 1 : 0;
         int64_t acc = 0;
-        int k = 0;
-        for (int s = 0; s < a.n_sets; ++s) {
-            s_tbase[s] = acc;
-            acc += (s_ng[s] + kG - 1) / kG;
-            s_first[s] = k;
-            while (k < n_valid && s_job[s_order[k]].set == s) ++k;
+        for (int si = 0; si < a.n_sets; ++si) {
+            tab->tbase[si] = acc;
+            acc += s_units[si] > 0 ? s_units[si] : 0;
         }
-        s_tbase[a.n_sets] = acc;
-        s_first[a.n_sets] = k;
+        tab->tbase[a.n_sets] = acc;
         int64_t jb = 0;
         for (int i = 0; i < a.n_jobs; ++i) {
-            s_jbase[i] = jb;
-            const int sj = s_job[i].set;
-            if (job_ok(i)) jb += s_tbase[sj + 1] - s_tbase[sj];
+            const int64_t n = s_ok[i] ? s_units[s_job[i].set] : 0;
+            tab->jbase[i] = s_ok[i] ? jb : -1;
+            tab->jn[i] = n;
+            jb += n;
         }
-        s_jbase[a.n_jobs] = jb;
-        s_sense = __hip_atomic_load(&a.bar->sense, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // each set's first rank: the valid jobs on sets before it
+    for (int si = t; si <= a.n_sets; si += blockDim.x) {
+        int n = 0;
+        for (int k = 0; k < a.n_jobs; ++k) n += s_ok[k] && s_job[k].set < si;
+        tab->first[si] = n;
     }
     __syncthreads();
-    const int64_t n_tiles = s_tbase[a.n_sets];
-    unsigned int sense = s_sense;
-    auto set_of = [&](int64_t tile) {
-        int lo = 0, hi = a.n_sets;  // s_tbase[lo] <= tile < s_tbase[hi]
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (s_tbase[mid] <= tile) lo = mid;
-            else hi = mid;
-        }
-        return lo;
-    };
-    auto geo_of = [&](const BatchSet& S) {
-        Geo g = S.ctrl->geo;
-        g.ox = uniform_i32(g.ox);
-        g.oy = uniform_i32(g.oy);
-        g.oz = uniform_i32(g.oz);
-        g.lmax = uniform_i32(g.lmax);
-        g.shift = uniform_i32(g.shift);
-        g.mask = uniform_u32(g.mask);
-        return g;
-    };
+    for (int i = t; i < a.n_jobs; i += blockDim.x) {
+        if (s_rank[i] < 0) continue;
+        BatchRank r;
+        r.iso = s_job[i].iso;
+        r.job = i;
+        r.jbase = tab->jbase[i];
+        tab->rank[s_rank[i]] = r;
+    }
+}
 
-    // ---- phase A: triangle counts per (job, tile) ----
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+__device__ __forceinline__ Geo batch_geo(const BatchSet& S) {
+    Geo g = S.ctrl->geo;
+    g.ox = uniform_i32(g.ox);
+    g.oy = uniform_i32(g.oy);
+    g.oz = uniform_i32(g.oz);
+    g.lmax = uniform_i32(g.lmax);
+    g.shift = uniform_i32(g.shift);
+    g.mask = uniform_u32(g.mask);
+    return g;
+}
+
+// the set's groups (never more than its bound, as the layout assumes)
+__device__ __forceinline__ uint32_t batch_groups(const BatchSet& S) {
+    const uint32_t ng = uniform_u32(S.ctrl->n_groups);
+    return ng < S.bound ? ng : S.bound;
+}
+
+// The unit of global unit index `tile`: its set, the unit within the set,
+// the set's ranks [f0, f1) (isos into s_iso); false past the last unit.
+__device__ __forceinline__ bool batch_unit(const BatchArgs& a, int64_t tile, int* s_si, float* s_iso, int& si,
+                                           int64_t& lt, int& f0, int& f1) {
+    const BatchTab* tab = a.tab;
+    const int t = threadIdx.x;
+    if (t == 0) *s_si = -1;
+    __syncthreads();
+    for (int i = t; i < a.n_sets; i += blockDim.x)
+        if (tab->tbase[i] <= tile && tile < tab->tbase[i + 1]) *s_si = i;
+    __syncthreads();
+    si = uniform_i32(*s_si);
+    if (si < 0) return false;
+    lt = uniform_i64(tile - tab->tbase[si]);
+    f0 = uniform_i32(tab->first[si]);
+    f1 = uniform_i32(tab->first[si + 1]);
+    for (int f = t; f < f1 - f0; f += blockDim.x) s_iso[f] = tab->rank[f0 + f].iso;
+    __syncthreads();
+    return true;
+}
+
+// Counting: one work-group per unit; each job of the unit's set gets its
+// triangle count in the unit.
+template <int kG>
+__global__ __launch_bounds__(kG * 8) void k_batch_count(BatchArgs a) {
+    __shared__ BatchTile<kG> T;
+    __shared__ unsigned long long s_tab[256];
+    __shared__ float s_iso[kMaxJobs];     // the set's isos, ascending
+    __shared__ uint32_t s_acc[kMaxJobs];  // per rank of the set: triangles in the unit
+    __shared__ uint32_t s_w[8];
+    __shared__ int s_si;
+    const int t = threadIdx.x;
+    for (int i = t; i < 256; i += kG * 8) s_tab[i] = kMcTable[i];
+    int si, f0, f1;
+    int64_t lt;
+    if (!batch_unit(a, blockIdx.x, &s_si, s_iso, si, lt, f0, f1)) return;
+    const int n_f = f1 - f0;
+    if (n_f == 0) return;
+    for (int f = t; f < n_f; f += kG * 8) s_acc[f] = 0;
+    const BatchSet S = uniform_set(a.sets[si]);
+    const Geo g = batch_geo(S);
+    const bool ranged = uniform_u32(*S.rng_ok) != 0;
+    const int n_c = uniform_i32(batch_candidates<kG>(S, batch_groups(S), lt, a.unit, ranged, s_iso, n_f, T));
+    for (int c0 = 0; c0 < n_c; c0 += kG) {
         // the lane's place, opaque to the compiler in every iteration: what
-        // derives from it is recomputed per tile instead of being hoisted
-        // out of the loop into registers held across it
+        // derives from it is recomputed instead of held in registers across
+        // the loop
         int tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
         const int gi = tid >> 3, j = tid & 7;
-        const int si = uniform_i32(set_of(tile));
-        const int64_t lt = uniform_i64(tile - s_tbase[si]);
-        const BatchSet S = uniform_set(a.sets[si]);
-        const Geo g = geo_of(S);
-        const int f0 = uniform_i32(s_first[si]), f1 = uniform_i32(s_first[si + 1]);
-        bool work;
-        int m;
-        uint32_t gx, gy, gz;
-        batch_load_tile<kG>(S, g, uniform_u32(s_ng[si]), lt, gi, j, s_iso + f0, f1 - f0, T, work, m, gx, gy, gz);
-        const int fa = uniform_i32(T.fa), fb = uniform_i32(T.fb);
-        const int ia = T.ia[gi], ib = T.ib[gi];
-        // jobs no group of the tile straddles: no triangles here
-        for (int f = t; f < f1 - f0; f += kB)
-            if (f < fa || f >= fb) a.tcnt[s_jbase[s_order[f0 + f]] + lt] = 0;
-        for (int f = fa; f < fb; ++f) {
-            const int jb = uniform_i32(s_order[f0 + f]);
-            const float iso = __int_as_float(uniform_i32(__float_as_int(s_job[jb].iso)));
-            int tid2 = threadIdx.x;
-            asm volatile("" : "+v"(tid2));
-            const int gi2 = tid2 >> 3, j2 = tid2 & 7;
-            const bool on = ia <= f && f < ib;
-            uint32_t items[4];
-            int n_dual = 0, n_tri = 0;
-            corner_items<false>(j2, m, iso, T.v[gi2], T.r[gi2], T.l[gi2], s_tab, on, items, n_dual, n_tri);
-            uint32_t tot;
-            (void)block_excl_scan((uint32_t)n_tri, s_w, &tot);
-            if (t == 0) a.tcnt[s_jbase[jb] + lt] = tot;
-        }
-        __syncthreads();  // the tile's LDS is reused by the next tile
-    }
-    grid_barrier(a.bar, sense);
-
-    // ---- phase B: exclusive scan over each job's tiles ----
-    if (a.n_jobs >= (int)gridDim.x) {
-        // at least as many jobs as work-groups: one work-group per job
-        for (int jb = blockIdx.x; jb < a.n_jobs; jb += gridDim.x) {
-            const int64_t base = s_jbase[jb], n = s_jbase[jb + 1] - base;
-            uint64_t carry = 0;
-            for (int64_t c0 = 0; c0 < n; c0 += kB) {
-                const int64_t i = c0 + t;
-                const uint32_t x = i < n ? a.tcnt[base + i] : 0u;
-                uint32_t tot;
-                const uint32_t pre = block_excl_scan(x, s_w, &tot);
-                if (i < n) a.tpre[base + i] = (uint32_t)(carry + pre);
-                carry += tot;
+        batch_load_chunk<kG>(S, g, lt, a.unit, c0, n_c, ranged, gi, j, s_iso, n_f, T);
+        const int n_p = uniform_i32(batch_pairs<kG>(T, gi, j, s_w));
+        const int fa = uniform_i32(T.fa);
+        for (int p0 = 0; p0 < n_p; p0 += kPairWin) {
+            batch_pair_window<kG>(T, gi, j, p0);
+            const int pe = n_p - p0 < kPairWin ? n_p - p0 : kPairWin;
+            for (int r0 = 0; r0 < pe; r0 += kG) {
+                int tid2 = threadIdx.x;
+                asm volatile("" : "+v"(tid2));
+                const int gi = tid2 >> 3, j = tid2 & 7;
+                const bool on = r0 + gi < pe;
+                const uint32_t pr = on ? T.pair[r0 + gi] : 0u;
+                const int pgi = (int)(pr & 31), f = fa + (int)(pr >> 5);
+                uint32_t items[4];
+                int n_dual = 0, n_tri = 0;
+                corner_items<false>(j, T.gm[pgi], s_iso[f], T.v[pgi], T.r[pgi], T.l[pgi], s_tab, on, items, n_dual,
+                                    n_tri);
+                n_tri += __shfl_xor(n_tri, 1, 64);
+                n_tri += __shfl_xor(n_tri, 2, 64);
+                n_tri += __shfl_xor(n_tri, 4, 64);
+                if (on && j == 0 && n_tri) atomicAdd(&s_acc[f], (uint32_t)n_tri);
             }
-            if (t == 0) a.counts[jb] = (int64_t)carry;
+            __syncthreads();  // T.pair is rewritten by the next window
         }
-    } else {
-        // fewer jobs than work-groups: each job's counts are split over
-        // gridDim / n_jobs work-groups; every work-group sums its stretch,
-        // then (after a barrier) adds the sums of the stretches before its own
-        // and writes its stretch's prefixes
-        const int bj = (int)gridDim.x / a.n_jobs;
-        const int jb = blockIdx.x / bj, r = blockIdx.x % bj;
-        int64_t base = 0, c0 = 0, c1 = 0;
-        if (jb < a.n_jobs) {
-            base = s_jbase[jb];
-            const int64_t n = s_jbase[jb + 1] - base, len = (n + bj - 1) / bj;
-            c0 = (int64_t)r * len < n ? (int64_t)r * len : n;
-            c1 = c0 + len < n ? c0 + len : n;
-        }
-        uint32_t mine = 0;
-        for (int64_t c = c0 + t; c < c1; c += kB) mine += a.tcnt[base + c];
-        uint32_t part;
-        (void)block_excl_scan(mine, s_w, &part);
-        if (t == 0 && jb < a.n_jobs) a.bsum[blockIdx.x] = part;
-        grid_barrier(a.bar, sense);
-        if (jb < a.n_jobs) {
-            uint32_t before = 0;
-            for (int k = t; k < r; k += kB) before += a.bsum[jb * bj + k];
-            uint32_t pre_all;
-            (void)block_excl_scan(before, s_w, &pre_all);
-            if (t == 0 && r == bj - 1) a.counts[jb] = (int64_t)pre_all + part;
-            uint64_t carry = pre_all;
-            for (int64_t cc = c0; cc < c1; cc += kB) {
-                const int64_t i = cc + t;
-                const uint32_t x = i < c1 ? a.tcnt[base + i] : 0u;
-                uint32_t tot;
-                const uint32_t pre = block_excl_scan(x, s_w, &tot);
-                if (i < c1) a.tpre[base + i] = (uint32_t)(carry + pre);
-                carry += tot;
-            }
-        }
+        __syncthreads();  // the chunk's LDS is reused by the next chunk
     }
-    grid_barrier(a.bar, sense);
+    for (int f = t; f < n_f; f += kG * 8) a.tcnt[a.tab->rank[f0 + f].jbase + lt] = s_acc[f];
+}
 
-    // ---- phase C: write ----
-    // invalid jobs, and jobs on a set whose build failed, count -1
-    for (int jb = blockIdx.x * kB + t; jb < a.n_jobs; jb += gridDim.x * kB)
-        if (!job_ok(jb) || a.sets[s_job[jb].set].ctrl->status != AMR_OK) a.counts[jb] = -1;
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+// Scan: one work-group (256) per job over the job's per-unit counts (eight
+// consecutive per lane); the job's total into counts (-1: invalid job).
+__global__ __launch_bounds__(256) void k_batch_scan(BatchArgs a) {
+    __shared__ uint32_t s_w[8];
+    const int jb = blockIdx.x, t = threadIdx.x;
+    const int64_t base = a.tab->jbase[jb];
+    if (base < 0) {
+        if (t == 0) a.counts[jb] = -1;
+        return;
+    }
+    const int64_t n = a.tab->jn[jb];
+    uint64_t carry = 0;
+    for (int64_t c0 = 0; c0 < n; c0 += 256 * 8) {
+        const int64_t i0 = c0 + (int64_t)t * 8;
+        uint32_t x[8], sum = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            x[k] = i0 + k < n ? a.tcnt[base + i0 + k] : 0u;
+            sum += x[k];
+        }
+        uint32_t tot;
+        uint32_t run = (uint32_t)carry + block_excl_scan(sum, s_w, &tot);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (i0 + k < n) a.tpre[base + i0 + k] = run;
+            run += x[k];
+        }
+        carry += tot;
+    }
+    if (t == 0) a.counts[jb] = (int64_t)carry;
+}
+
+// Writing: one work-group per unit that has output below some job's
+// capacity; each job's triangles of the unit go to its output from the
+// unit's scanned position on, in the plain path's order.
+template <int kG>
+__global__ __launch_bounds__(kG * 8) void k_batch_write(BatchArgs a) {
+    constexpr int kB = kG * 8;
+    __shared__ BatchTile<kG> T;
+    __shared__ unsigned long long s_tab[256];
+    __shared__ float s_iso[kMaxJobs];     // the set's isos, ascending
+    __shared__ uint32_t s_acc[kMaxJobs];  // per rank: the job's next output position (from its out_offset)
+    __shared__ uint32_t s_items[kB][4];
+    __shared__ uint32_t s_list[kTriList];
+    __shared__ uint32_t s_w[8];
+    __shared__ int s_si;
+    __shared__ uint32_t s_any;
+    const int t = threadIdx.x;
+    for (int i = t; i < 256; i += kB) s_tab[i] = kMcTable[i];
+    int si, f0, f1;
+    int64_t lt;
+    if (!batch_unit(a, blockIdx.x, &s_si, s_iso, si, lt, f0, f1)) return;
+    const int n_f = f1 - f0;
+    if (n_f == 0) return;
+    if (t == 0) s_any = 0;
+    __syncthreads();
+    for (int f = t; f < n_f; f += kB) {
+        const BatchRank r = a.tab->rank[f0 + f];
+        const int64_t e = r.jbase + lt;
+        s_acc[f] = a.tpre[e];
+        if (a.tcnt[e] && (int64_t)a.tpre[e] < a.jobs[r.job].out_cap) s_any = 1;
+    }
+    __syncthreads();
+    if (uniform_u32(s_any) == 0) return;
+    const BatchSet S = uniform_set(a.sets[si]);
+    const Geo g = batch_geo(S);
+    const bool ranged = uniform_u32(*S.rng_ok) != 0;
+    const int n_c = uniform_i32(batch_candidates<kG>(S, batch_groups(S), lt, a.unit, ranged, s_iso, n_f, T));
+    for (int c0 = 0; c0 < n_c; c0 += kG) {
+        // the lane's place, opaque to the compiler in every iteration: what
+        // derives from it is recomputed instead of held in registers across
+        // the loop
         int tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
         const int gi = tid >> 3, j = tid & 7;
-        const int si = uniform_i32(set_of(tile));
-        const int64_t lt = uniform_i64(tile - s_tbase[si]);
-        const int f0 = uniform_i32(s_first[si]), f1 = uniform_i32(s_first[si + 1]);
-        // the tile is loaded again only if some job has output below its capacity here
-        if (t == 0) s_any = 0;
-        __syncthreads();
-        for (int f = f0 + t; f < f1; f += kB) {
-            const int jb = s_order[f];
-            const int64_t e = s_jbase[jb] + lt;
-            if (a.tcnt[e] && (int64_t)a.tpre[e] < s_job[jb].out_cap) s_any = 1;
+        batch_load_chunk<kG>(S, g, lt, a.unit, c0, n_c, ranged, gi, j, s_iso, n_f, T);
+        const int n_p = uniform_i32(batch_pairs<kG>(T, gi, j, s_w));
+        const int fa = uniform_i32(T.fa);
+        for (int p0 = 0; p0 < n_p; p0 += kPairWin) {
+            batch_pair_window<kG>(T, gi, j, p0);
+            const int pe = n_p - p0 < kPairWin ? n_p - p0 : kPairWin;
+            for (int r0 = 0; r0 < pe; r0 += kG) {
+                int tid2 = threadIdx.x;
+                asm volatile("" : "+v"(tid2));
+                const int gi = tid2 >> 3, j = tid2 & 7;
+                const bool on = r0 + gi < pe;
+                const uint32_t pr = on ? T.pair[r0 + gi] : 0u;
+                const int pgi = (int)(pr & 31), f = fa + (int)(pr >> 5);
+                const float iso = s_iso[f];
+                uint32_t items[4];
+                int n_dual = 0, n_tri = 0;
+                corner_items<false>(j, T.gm[pgi], iso, T.v[pgi], T.r[pgi], T.l[pgi], s_tab, on, items, n_dual,
+                                    n_tri);
+                uint32_t tot;
+                const uint32_t first = block_excl_scan((uint32_t)n_tri, s_w, &tot);
+                int osum = n_tri;
+                osum += __shfl_xor(osum, 1, 64);
+                osum += __shfl_xor(osum, 2, 64);
+                osum += __shfl_xor(osum, 4, 64);
+                if (j == 0) {
+                    T.pg[gi] = pgi;
+                    T.piso[gi] = iso;
+                    T.pfirst[gi] = first;
+                }
+                __syncthreads();
+                // an octet's round triangle 0, were it of the octet's job: the
+                // job's next position in the unit less the round position of
+                // the job's first triangle in the round (the job's pairs are
+                // consecutive, from octet k on)
+                if (on && j == 0) {
+                    const int k = T.pb[f - fa] > p0 + r0 ? T.pb[f - fa] - p0 - r0 : 0;
+                    const amr_iso_job& jo = a.jobs[a.tab->rank[f0 + f].job];
+                    T.pbase[gi] = jo.out_offset + (int64_t)s_acc[f] - (int64_t)T.pfirst[k];
+                    T.pcap[gi] = jo.out_offset + jo.out_cap;
+                }
+                __syncthreads();
+                if (on && j == 0 && osum) atomicAdd(&s_acc[f], (uint32_t)osum);
+                if (uniform_u32(tot)) write_pair_triangles<kG>(t, g, items, tot, first, T, a.tris, s_tab, s_items, s_list);
+                __syncthreads();  // s_items, s_list and the octet data are reused by the next round
+            }
+            __syncthreads();  // T.pair is rewritten by the next window
         }
-        __syncthreads();
-        const bool any = uniform_u32(s_any) != 0;
-        __syncthreads();  // every wave has read the flag before the next tile clears it
-        if (!any) continue;
-        const BatchSet S = uniform_set(a.sets[si]);
-        const Geo g = geo_of(S);
-        bool work;
-        int m;
-        uint32_t gx, gy, gz;
-        batch_load_tile<kG>(S, g, uniform_u32(s_ng[si]), lt, gi, j, s_iso + f0, f1 - f0, T, work, m, gx, gy, gz);
-        const int fa = uniform_i32(T.fa), fb = uniform_i32(T.fb);
-        const int ia = T.ia[gi], ib = T.ib[gi];
-        for (int f = fa; f < fb; ++f) {
-            const int jb = uniform_i32(s_order[f0 + f]);
-            const int64_t e = uniform_i64(s_jbase[jb] + lt);
-            const uint32_t n_out = uniform_u32(a.tcnt[e]);
-            const int64_t pre = (int64_t)uniform_u32(a.tpre[e]);
-            const float iso = __int_as_float(uniform_i32(__float_as_int(s_job[jb].iso)));
-            const int64_t out_offset = uniform_i64(s_job[jb].out_offset), out_cap = uniform_i64(s_job[jb].out_cap);
-            if (n_out == 0 || pre >= out_cap) continue;  // uniform over the work-group
-            int tid2 = threadIdx.x;
-            asm volatile("" : "+v"(tid2));
-            const int gi2 = tid2 >> 3, j2 = tid2 & 7;
-            const bool on = ia <= f && f < ib;
-            uint32_t items[4];
-            int n_dual = 0, n_tri = 0;
-            corner_items<false>(j2, m, iso, T.v[gi2], T.r[gi2], T.l[gi2], s_tab, on, items, n_dual, n_tri);
-            uint32_t tot;
-            const uint32_t first = block_excl_scan((uint32_t)n_tri, s_w, &tot);
-            write_triangles<kB>(tid2, g, iso, gi2, j2, m, gx, gy, gz, items, tot, first, 0u, out_offset + pre, 0,
-                                out_offset + out_cap, a.tris, nullptr, nullptr, nullptr, T.v, T.r, T.l, s_tab,
-                                s_items, s_dual, s_list, s_gm, s_gx);
-            __syncthreads();  // s_items / s_list are reused by the next job
-        }
-        __syncthreads();
+        __syncthreads();  // the chunk's LDS is reused by the next chunk
     }
 }
 
@@ -3515,35 +3726,35 @@ struct amr_batch {
     int n_sets = 0;
     BatchSet* d_sets = nullptr;  // device table
     uint32_t max_groups = 0;     // the largest group bound of the sets (their extraction grids)
-    int cu_count = 0;
+    uint32_t bound[kMaxSets] = {};  // each set's group bound
 };
 
 namespace {
 
-int batch_check_shape(int block, int per_cu) {
+int batch_check_shape(int block, int unit) {
     if (block != 128 && block != 256) return fail(AMR_EINVAL, "batched launch: block must be 128 or 256");
-    if (per_cu < 1 || per_cu > 4) return fail(AMR_EINVAL, "batched launch: 1..4 work-groups per compute unit");
+    if (unit < 64 || unit > kMaxUnit || (unit & (unit - 1)))
+        return fail(AMR_EINVAL, "batched launch: unit must be a power of two in 64..%d groups", kMaxUnit);
     return AMR_OK;
 }
 
-int64_t batch_tiles(const amr_batch* b, int block) {
-    const int64_t g = block / 8;
-    const int64_t t = ((int64_t)b->max_groups + g - 1) / g;
+int log2_of(int unit) {
+    int k = 0;
+    while ((1 << k) < unit) ++k;
+    return k;
+}
+
+// units of the largest set (the per-job counts are kept per unit of the job's set)
+int64_t batch_max_units(const amr_batch* b, int unit) {
+    const int64_t t = ((int64_t)b->max_groups + unit - 1) / unit;
     return t > 0 ? t : 1;
 }
 
-int batch_grid(const amr_batch* b, int block, int per_cu, int64_t n_tiles) {
-    // every work-group of the grid must be on the GPU at once (grid barriers)
-    int occ = 0;
-    hipError_t e = block == 128 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch<16>, 128, 0)
-                                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch<32>, 256, 0);
-    if (e != hipSuccess || occ < 1) occ = 1;
-    if (per_cu > occ) per_cu = occ;
-    int64_t g = (int64_t)b->cu_count * per_cu;
-    if (g > kMaxBatchGrid) g = kMaxBatchGrid;
-    if (g > n_tiles) g = n_tiles;
-    if (g < 1) g = 1;
-    return (int)g;
+// units of all sets together, at their bounds: the counting and writing grids
+int64_t batch_all_units(const amr_batch* b, int unit) {
+    int64_t n = 0;
+    for (int i = 0; i < b->n_sets; ++i) n += ((int64_t)b->bound[i] + unit - 1) / unit;
+    return n > 0 ? n : 1;
 }
 
 }  // namespace
@@ -3956,6 +4167,7 @@ int amr_batch_create(amr_batch** out, amr_set* const* sets, int n_sets) {
         host[i].ctrl = s->ctrl;
         host[i].rng = s->rng;
         host[i].rng_ok = &s->sched->rng_ok;
+        host[i].bound = s->grid_groups;
         if (s->grid_groups > mg) mg = s->grid_groups;
     }
     DeviceGuard dg(dev);
@@ -3967,9 +4179,7 @@ int amr_batch_create(amr_batch** out, amr_set* const* sets, int n_sets) {
     b->device = dev;
     b->n_sets = n_sets;
     b->max_groups = mg;
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) prop.multiProcessorCount = 1;
-    b->cu_count = prop.multiProcessorCount;
+    for (int i = 0; i < n_sets; ++i) b->bound[i] = host[i].bound;
     hipError_t e = hipMalloc((void**)&b->d_sets, sizeof(BatchSet) * (size_t)n_sets);
     if (e == hipSuccess) e = hipMemcpy(b->d_sets, host, sizeof(BatchSet) * (size_t)n_sets, hipMemcpyHostToDevice);
     free(host);
@@ -3992,46 +4202,52 @@ void amr_batch_destroy(amr_batch* b) {
     delete b;
 }
 
-int amr_batch_workspace_bytes(const amr_batch* b, int max_jobs, int block, int per_cu, size_t* bytes) {
+int amr_batch_workspace_bytes(const amr_batch* b, int max_jobs, int block, int unit, size_t* bytes) {
     if (!b || !bytes) return fail(AMR_EINVAL, "amr_batch_workspace_bytes: NULL argument");
     if (max_jobs < 1 || max_jobs > kMaxJobs) return fail(AMR_EINVAL, "amr_batch_workspace_bytes: 1..%d jobs", kMaxJobs);
-    const int st = batch_check_shape(block, per_cu);
+    const int st = batch_check_shape(block, unit);
     if (st != AMR_OK) return st;
-    const size_t per = (size_t)max_jobs * (size_t)batch_tiles(b, block) * sizeof(uint32_t);
-    *bytes = align256(sizeof(GridBar)) + align256((size_t)kMaxBatchGrid * sizeof(uint32_t)) + 2 * align256(per);
+    const size_t per = (size_t)max_jobs * (size_t)batch_max_units(b, unit) * sizeof(uint32_t);
+    *bytes = align256(sizeof(BatchTab)) + 2 * align256(per);
     g_err[0] = 0;
     return AMR_OK;
 }
 
 int amr_batch_isosurface(amr_batch* b, const amr_iso_job* jobs, int n_jobs, float* tris, int64_t* counts, void* ws,
-                         size_t bytes, int block, int per_cu, hipStream_t stream) {
+                         size_t bytes, int block, int unit, hipStream_t stream) {
     if (!b || !jobs || !counts) return fail(AMR_EINVAL, "amr_batch_isosurface: NULL argument");
     size_t need = 0;
-    int st = amr_batch_workspace_bytes(b, n_jobs, block, per_cu, &need);
+    int st = amr_batch_workspace_bytes(b, n_jobs, block, unit, &need);
     if (st != AMR_OK) return st;
     if (!ws || ((uintptr_t)ws & 255)) return fail(AMR_EINVAL, "amr_batch_isosurface: workspace NULL or unaligned");
     if (bytes < need) return fail(AMR_ENOSPACE, "amr_batch_isosurface: workspace %zu bytes, need %zu", bytes, need);
+    const int64_t grid = batch_all_units(b, unit);
+    if (grid > 0x7FFFFFFF) return fail(AMR_EINVAL, "amr_batch_isosurface: %lld units, too many", (long long)grid);
     DeviceGuard dg(b->device);
-    const int64_t tiles = batch_tiles(b, block);
-    const size_t per = align256((size_t)n_jobs * (size_t)tiles * sizeof(uint32_t));
+    const size_t per = align256((size_t)n_jobs * (size_t)batch_max_units(b, unit) * sizeof(uint32_t));
     char* w = (char*)ws;
     BatchArgs a;
     a.sets = b->d_sets;
     a.n_sets = b->n_sets;
     a.jobs = jobs;
     a.n_jobs = n_jobs;
+    a.unit = unit;
+    a.unit_shift = log2_of(unit);
     a.tris = tris;
     a.counts = counts;
-    a.bar = (GridBar*)w;
-    a.bsum = (uint32_t*)(w + align256(sizeof(GridBar)));
-    a.tcnt = (uint32_t*)(w + align256(sizeof(GridBar)) + align256((size_t)kMaxBatchGrid * sizeof(uint32_t)));
+    a.tab = (BatchTab*)w;
+    a.tcnt = (uint32_t*)(w + align256(sizeof(BatchTab)));
     a.tpre = (uint32_t*)((char*)a.tcnt + per);
-    // the grid for an upper bound of the tiles (group counts are on the device)
-    const int grid = batch_grid(b, block, per_cu, tiles * b->n_sets);
+    hipLaunchKernelGGL(k_batch_prep, dim3(1), dim3(256), 0, stream, a);
     if (block == 128)
-        hipLaunchKernelGGL(k_batch<16>, dim3(grid), dim3(128), 0, stream, a);
+        hipLaunchKernelGGL(k_batch_count<16>, dim3((unsigned)grid), dim3(128), 0, stream, a);
     else
-        hipLaunchKernelGGL(k_batch<32>, dim3(grid), dim3(256), 0, stream, a);
+        hipLaunchKernelGGL(k_batch_count<32>, dim3((unsigned)grid), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_batch_scan, dim3(n_jobs), dim3(256), 0, stream, a);
+    if (block == 128)
+        hipLaunchKernelGGL(k_batch_write<16>, dim3((unsigned)grid), dim3(128), 0, stream, a);
+    else
+        hipLaunchKernelGGL(k_batch_write<32>, dim3((unsigned)grid), dim3(256), 0, stream, a);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? AMR_OK : hipfail(e, "amr_batch_isosurface: launch");
 }

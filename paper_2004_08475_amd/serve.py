@@ -144,7 +144,7 @@ class _UploadSlot:
 
 class IsoServer:
     def __init__(self, resident: AmrSet, hbm_budget: int | None = None, upload_slots: int = 4,
-                 max_batch: int = 64, block: int | None = None, per_cu: int | None = None,
+                 max_batch: int = 64, block: int | None = None, unit: int | None = None,
                  curve_points: int = 64, upload_max_cells: int = 0):
         self.resident = resident
         self.device = resident.device
@@ -163,7 +163,7 @@ class IsoServer:
         counts = torch.zeros(curve_points, dtype=torch.int64, device=self.device)
         jobs = self.batch.jobs_tensor([0] * curve_points, self.curve_iso, np.zeros(curve_points),
                                       np.zeros(curve_points))
-        if block is None or per_cu is None:
+        if block is None or unit is None:
             # launch shape for this set: the autotuner on a counting launch of
             # a few isos from the middle of the curve (no output memory)
             from . import autotune
@@ -172,16 +172,15 @@ class IsoServer:
             mid = self.curve_iso[curve_points // 4:curve_points // 4 + k]
             tj = self.batch.jobs_tensor([0] * k, mid, np.zeros(k), np.zeros(k))
             tc = torch.zeros(k, dtype=torch.int64, device=self.device)
-            block, per_cu, _ = autotune.tune(self.batch, tj, k, None, tc, reps=2)
-        self.block, self.per_cu = block, per_cu
-        self.batch.run_into(jobs, curve_points, None, counts, block, per_cu)
+            block, unit, _ = autotune.tune(self.batch, tj, k, None, tc, reps=2)
+        self.block, self.unit = block, unit
+        self.batch.run_into(jobs, curve_points, None, counts, block, unit)
         self.curve_tri = counts.cpu().numpy()
         # per request, the plain single pass against a batched launch (fixed
         # part + part per job), timed once here; a batch of n waiting
         # requests takes whichever is cheaper for n
         self.t_plain, self.t_batch_fixed, self.t_batch_job = self._calibrate()
         self.upload_slots = upload_slots
-        self.barrier_timeouts = 0  # batched launches redone as plain passes
         self.stop = threading.Event()
         # request outputs live in buffers reused across requests
         self._iso_stream = torch.cuda.Stream(self.device)
@@ -222,8 +221,8 @@ class IsoServer:
             return (time.perf_counter() - t0) / reps
 
         t_plain = run(lambda: self.resident.isosurface_into(isos[0], tris, caps[0]))
-        t1 = run(lambda: self.batch.run_into(jobs1, 1, tris, counts, self.block, self.per_cu))
-        t2 = run(lambda: self.batch.run_into(jobs2, 2, tris, counts, self.block, self.per_cu))
+        t1 = run(lambda: self.batch.run_into(jobs1, 1, tris, counts, self.block, self.unit))
+        t2 = run(lambda: self.batch.run_into(jobs2, 2, tris, counts, self.block, self.unit))
         per_job = max(t2 - t1, 0.0)
         return t_plain, max(t1 - per_job, 0.0), per_job
 
@@ -272,23 +271,14 @@ class IsoServer:
         need = int(caps.sum()) * 36 + (1 << 20)
         held = self.mem.acquire(need, self.stop)
         t_start = time.perf_counter()
-        timed_out = False
         try:
             with torch.cuda.stream(stream):
                 off = np.concatenate([[0], np.cumsum(caps)[:-1]])
                 tris = self._iso_out.rows(int(caps.sum()))
                 counts = self._batch_counts[:n]
                 jobs = self.batch.jobs_tensor([0] * n, isos, off, caps)
-                self.batch.run_into(jobs, n, tris, counts, self.block, self.per_cu)
+                self.batch.run_into(jobs, n, tris, counts, self.block, self.unit)
                 c = counts.cpu().numpy()
-                # a grid barrier that gave up leaves invalid results and a
-                # barrier in an unknown state: clear it, serve these plainly
-                timed_out = self.batch.barrier_timed_out(self.block, self.per_cu)
-                if timed_out:
-                    self.batch.reset_barrier(self.block, self.per_cu)
-                    self.barrier_timeouts += 1
-                    stream.synchronize()
-                    return
                 kept = []
                 for k in range(n):
                     out = tris[int(off[k]):int(off[k]) + int(c[k])]
@@ -302,9 +292,6 @@ class IsoServer:
                     res.start, res.done, res.triangles, res.tris = t_start, t_done, int(c[k]), kept[k]
         finally:
             self.mem.release(held)
-            if timed_out:
-                for r in reqs:
-                    self._run_one(r, results, stream)
 
     def _keep(self, out):
         # outputs are dropped at once unless the caller keeps them, so that

@@ -65,13 +65,13 @@ def shell(amr):
     return cs, amr.from_numpy(cs.xyz, cs.level, cs.value)
 
 
-@pytest.mark.parametrize("block,per", [(256, 1), (128, 2), (256, 4), (128, 3)])
-def test_many_isos_one_set_equal_plain(amr, shell, block, per):
+@pytest.mark.parametrize("block,unit", [(256, 256), (128, 128), (256, 64), (128, 1024)])
+def test_many_isos_one_set_equal_plain(amr, shell, block, unit):
     cs, s = shell
     isos = np.quantile(cs.value, np.linspace(0.05, 0.95, 16)).astype(np.float32)
-    print("batch %d isos, block %d x %d" % (len(isos), block, per), flush=True)
+    print("batch %d isos, block %d, unit %d" % (len(isos), block, unit), flush=True)
     b = amr.AmrBatch([s])
-    outs = b.isosurface([0] * len(isos), isos, block, per)
+    outs = b.isosurface([0] * len(isos), isos, block, unit)
     for iso, got in zip(isos, outs):
         want = _plain(s, iso)
         assert got.shape == want.shape
@@ -89,7 +89,7 @@ def test_many_sets_own_iso_equal_plain(amr):
     b = amr.AmrBatch(sets)
     jobs_set = list(range(len(sets))) + [1, 3]
     jobs_iso = [c.iso for c in css] + [float(np.quantile(css[1].value, 0.2)), float(np.quantile(css[3].value, 0.8))]
-    outs = b.isosurface(jobs_set, jobs_iso, 256, 1)
+    outs = b.isosurface(jobs_set, jobs_iso, 256, 256)
     for si, iso, got in zip(jobs_set, jobs_iso, outs):
         assert torch.equal(got, _plain(sets[si], iso))
 
@@ -119,16 +119,16 @@ def test_batch_graph_replay_with_new_isos(amr, shell):
     tris = torch.zeros((n * cap, 9), dtype=torch.float32, device=s.device)
     counts = torch.zeros(n, dtype=torch.int64, device=s.device)
     jobs = b.jobs_tensor([0] * n, rounds[0], [k * cap for k in range(n)], [cap] * n)
-    ws = b.workspace(n, 256, 1)
+    ws = b.workspace(n, 256, 128)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
-        b.run_into(jobs, n, tris, counts, 256, 1, ws)  # warm-up outside the graph
+        b.run_into(jobs, n, tris, counts, 256, 128, ws)  # warm-up outside the graph
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
-        b.run_into(jobs, n, tris, counts, 256, 1, ws)
+        b.run_into(jobs, n, tris, counts, 256, 128, ws)
     for r in rounds + rounds[:1]:
         new = b.jobs_tensor([0] * n, r, [k * cap for k in range(n)], [cap] * n)
         jobs.copy_(new)
@@ -140,19 +140,18 @@ def test_batch_graph_replay_with_new_isos(amr, shell):
         for k in range(n):
             assert c[k] == len(want[k])
             assert torch.equal(tris[k * cap:k * cap + c[k]], want[k])
-    assert not b.barrier_timed_out(256, 1)
 
 
 def test_batched_launch_shapes_agree(amr, shell):
     """octree-shell-256 with 64 isos at percentiles 5 + 90 k / 63 in the
-    launch shapes 256 x 2 and 128 x 1: every job equals the plain path bit
+    launch shapes (256 threads, 256 groups) and (128, 64): every job equals the plain path bit
     for bit (the oracle tests below cover the jobs themselves)."""
     cs, s = shell
     isos = np.quantile(cs.value, 0.05 + 0.90 * np.arange(64) / 63).astype(np.float32)
     b = amr.AmrBatch([s])
     want = [_plain(s, iso) for iso in isos]
-    for block, per in ((256, 2), (128, 1)):
-        outs = b.isosurface([0] * len(isos), isos, block, per)
+    for block, unit in ((256, 256), (128, 64)):
+        outs = b.isosurface([0] * len(isos), isos, block, unit)
         for w, got in zip(want, outs):
             assert torch.equal(got, w)
 
@@ -163,7 +162,7 @@ def test_many_isos_equal_oracle(amr, shell):
     cs, s = shell
     isos = np.quantile(cs.value, 0.05 + 0.90 * np.arange(64) / 63).astype(np.float32)
     b = amr.AmrBatch([s])
-    outs = b.isosurface([0] * len(isos), isos, 256, 2)
+    outs = b.isosurface([0] * len(isos), isos, 256, 256)
     o = oracle.Oracle(cs.xyz, cs.level, cs.value)
     with ThreadPoolExecutor(ORACLE_THREADS) as ex:
         ros = list(ex.map(lambda v: o.isosurface(float(v)), isos))
@@ -180,7 +179,7 @@ def test_many_isos_two_million_cells_equal_oracle(amr):
     s = amr.from_numpy(cs.xyz, cs.level, cs.value)
     isos = np.quantile(cs.value, 0.05 + 0.90 * np.arange(64) / 63).astype(np.float32)
     b = amr.AmrBatch([s])
-    outs = b.isosurface([0] * len(isos), isos, 256, 1)
+    outs = b.isosurface([0] * len(isos), isos, 256, 128)
     pl, ids = (t.cpu().numpy() for t in s.dual_cells())
     o = oracle.Oracle(cs.xyz, cs.level, cs.value, validate=False)
     win = 40_000
@@ -206,8 +205,8 @@ def test_multiset_batch_equal_oracle(amr):
     _say("32 sets, %d cells in all" % sum(c.n for c in css))
     sets = [amr.from_numpy(c.xyz, c.level, c.value) for c in css]
     b = amr.AmrBatch(sets)
-    outs = b.isosurface(list(range(len(sets))), [c.iso for c in css], 256, 2)
-    for a, c in zip(outs, b.isosurface(list(range(len(sets))), [c.iso for c in css], 128, 1)):
+    outs = b.isosurface(list(range(len(sets))), [c.iso for c in css], 256, 256)
+    for a, c in zip(outs, b.isosurface(list(range(len(sets))), [c.iso for c in css], 128, 512)):
         assert torch.equal(a, c)  # another launch shape, the same bits
     small = [k for k, c in enumerate(css) if c.n <= 1_000_000]
     large = [k for k, c in enumerate(css) if c.n > 1_000_000]

@@ -88,47 +88,38 @@ def test_summary_percentiles_by_kind():
     assert abs(s["by_kind"]["iso"]["p99_ms"] - float(np.percentile(lat_iso, 99))) < 1e-9
 
 
-def test_batch_barrier_timeout_falls_back_to_plain_passes():
-    """A batched launch whose grid-barrier wait gave up: its results are not
-    returned; the barrier is cleared and every request of the batch is served
-    by a plain pass, after the batch's memory was given back."""
+def test_batch_result_beyond_its_estimate_is_rerun_exactly():
+    """A batched request whose triangle count exceeds the capacity estimated
+    for it gets an exact plain rerun; the others keep their batched output;
+    the batch's memory reservation is given back."""
 
     class FakeBatch:
-        def __init__(self):
-            self.resets = 0
-
         def jobs_tensor(self, *a):
             return None
 
-        def run_into(self, jobs, n, tris, counts, block, per):
-            counts.fill_(5)
+        def run_into(self, jobs, n, tris, counts, block, unit):
+            counts.copy_(torch.tensor([5, 5000, 7]))
 
-        def barrier_timed_out(self, block, per):
-            return self.resets == 0
+    class FakeResident:
+        def __init__(self):
+            self.calls = []
 
-        def reset_barrier(self, block, per):
-            self.resets += 1
+        def isosurface(self, iso, cap):
+            self.calls.append((iso, cap))
+            return {"tris": torch.zeros((cap, 9))}
 
     srv = object.__new__(serve.IsoServer)
     srv.t_plain, srv.t_batch_fixed, srv.t_batch_job = 1.0, 0.1, 0.01  # batching wins
     srv.batch = FakeBatch()
-    srv.block, srv.per_cu = 256, 1
+    srv.resident = FakeResident()
+    srv.block, srv.unit = 256, 256
     srv.mem = serve.HbmBudget(1 << 30)
     srv.stop = threading.Event()
     srv.curve_iso = np.array([0.0, 1.0])
-    srv.curve_tri = np.array([10, 10])
+    srv.curve_tri = np.array([10, 10])  # estimated capacity 2 * 10 + 4096 per request
     srv._iso_out = serve._Grow(9, torch.float32, torch.device("cpu"))
     srv._batch_counts = torch.zeros(8, dtype=torch.int64)
-    srv.keep_outputs = False
-    srv.barrier_timeouts = 0
-    plain = []
-
-    def run_one(r, results, stream):
-        assert srv.mem.used == 0  # the batch's reservation is already released
-        plain.append(r.rid)
-        results[r.rid].done = 1.0
-
-    srv._run_one = run_one
+    srv.keep_outputs = True
 
     class Stream:
         def synchronize(self):
@@ -136,7 +127,8 @@ def test_batch_barrier_timeout_falls_back_to_plain_passes():
 
     import contextlib
 
-    reqs = [serve.IsoRequest(0.5, rid=k) for k in range(3)]
+    isos = [0.25, 0.5, 0.75]
+    reqs = [serve.IsoRequest(v, rid=k) for k, v in enumerate(isos)]
     results = {k: serve.Result(k, "iso", 0.0) for k in range(3)}
     orig = torch.cuda.stream
     torch.cuda.stream = lambda s: contextlib.nullcontext()
@@ -144,6 +136,7 @@ def test_batch_barrier_timeout_falls_back_to_plain_passes():
         srv._run_batch(reqs, results, Stream())
     finally:
         torch.cuda.stream = orig
-    assert plain == [0, 1, 2]
-    assert srv.batch.resets == 1 and srv.barrier_timeouts == 1
+    assert srv.resident.calls == [(0.5, 5000)]
+    assert [results[k].triangles for k in range(3)] == [5, 5000, 7]
+    assert [tuple(results[k].tris.shape) for k in range(3)] == [(5, 9), (5000, 9), (7, 9)]
     assert srv.mem.used == 0
