@@ -77,7 +77,8 @@ enum : uint32_t { kErrLevel = 1, kErrAlign = 2, kErrValue = 4, kErrCoord = 8 };
 struct alignas(64) Record {
     float val[8];
     uint64_t key;
-    uint32_t pad[6];
+    uint32_t homed;  // group keys whose home slot this is (counted as they are created)
+    uint32_t pad[5];
 };
 static_assert(sizeof(Record) == 64, "record is one 64-byte line");
 
@@ -529,7 +530,8 @@ __global__ __launch_bounds__(256) void k_build_reset(Record* __restrict__ rec, u
         Record r;
         for (int k = 0; k < 8; ++k) r.val[k] = e;
         r.key = kEmpty;
-        for (int k = 0; k < 6; ++k) r.pad[k] = 0;
+        r.homed = 0;
+        for (int k = 0; k < 5; ++k) r.pad[k] = 0;
         rec[i] = r;
     }
     for (uint32_t i = i0; i < nc; i += step) {
@@ -594,8 +596,10 @@ __device__ __forceinline__ int find_or_insert(Record* __restrict__ rec, uint64_t
 
 // Every cell stores its value in its group record (a plain store: a
 // duplicate cell overwrites its twin and shows up later as a missing leaf in
-// the count of the compaction).  Input indices are filled in later, and only
-// when an output asks for them (k_index_ids).
+// the count of the compaction).  The cell that creates a group's record
+// counts the key at the key's home slot, which orders the group list.
+// Input indices are filled in later, and only when an output asks for them
+// (k_index_ids).
 __global__ __launch_bounds__(256) void k_index_insert(const int32_t* __restrict__ xyz, const int32_t* __restrict__ lvl,
                                                       const float* __restrict__ val, int64_t n,
                                                       Record* __restrict__ rec, Ctrl* c) {
@@ -605,11 +609,14 @@ __global__ __launch_bounds__(256) void k_index_insert(const int32_t* __restrict_
         int m = lvl[i];
         uint32_t ux = (uint32_t)(xyz[3 * i] - g.ox), uy = (uint32_t)(xyz[3 * i + 1] - g.oy),
                  uz = (uint32_t)(xyz[3 * i + 2] - g.oz);
-        int slot = find_or_insert(rec, group_key(m, ux >> (m + 1), uy >> (m + 1), uz >> (m + 1)), g);
+        const uint64_t key = group_key(m, ux >> (m + 1), uy >> (m + 1), uz >> (m + 1));
+        uint32_t created = 0;
+        int slot = find_or_insert(rec, key, g, &created);
         if (slot < 0) {
             atomicOr(&c->overflow, 1u);
             continue;
         }
+        if (created) atomicAdd(&rec[slot_of(key, g.shift)].homed, 1u);
         int child = ((ux >> m) & 1) | (((uy >> m) & 1) << 1) | (((uz >> m) & 1) << 2);
         rec[slot].val[child] = val[i];
     }
@@ -726,9 +733,17 @@ __global__ __launch_bounds__(256) void k_index_find_dup(const int32_t* __restric
     }
 }
 
-// Group list: the slots of all records holding at least one cell, in slot
-// order, by a block scan plus look-back over tiles of 4096 slots.  Also
-// counts all occupied records (groups plus marker-only records).
+// Group list: the slots and keys of all records holding at least one cell,
+// ordered by (home slot, key).  That order is a function of the set of
+// cells alone: which of two colliding keys won a slot is not, so neither is
+// plain slot order.  Every key homed at slot h lies on h's probe sequence
+// (the sequence depends on the slot only), and h's record counts them, so
+// a block scan plus look-back over the counts of tiles of slots gives each
+// home its first list position; a home with one key that sits at home (the
+// common case) writes it at once, others walk their probe sequence and write
+// their keys in ascending order.  Also counts all occupied records (groups
+// plus marker-only records) and their leaves.  At this point of a build
+// every record is a group's.
 __global__ __launch_bounds__(kBlock) void k_index_compact(const Record* __restrict__ rec, uint32_t cap,
                                                           int32_t* __restrict__ glist,
                                                           unsigned long long* __restrict__ gkey, unsigned long long* s0,
@@ -740,18 +755,24 @@ __global__ __launch_bounds__(kBlock) void k_index_compact(const Record* __restri
     __shared__ uint32_t s_tile;
     const int t = threadIdx.x;
     const int wave = t >> 6, lane = lane_id();
+    const unsigned long long below = (1ull << lane) - 1ull;
     if (t == 0) s_tile = (uint32_t)atomicAdd(&sc->cticket, 1ull);
     __syncthreads();
     const uint32_t tile = s_tile;
-    // thread t looks at slots base + r*256 + t, r < per (coalesced)
+    const int shift = c->geo.shift;
+    // thread t looks at slots base + r*256 + t, r < per (coalesced); row r
+    // precedes row r+1 in slot order
     const uint32_t base = tile * (uint32_t)(kBlock * per);
-    uint32_t grp_bits = 0;
+    uint32_t homed[kCompactMaxPerThread], excl[kCompactMaxPerThread];
     unsigned long long n_rec = 0;
-#pragma unroll 4
-    for (int r = 0; r < per; ++r) {
-        uint32_t s = base + r * kBlock + t;
+#pragma unroll
+    for (int r = 0; r < kCompactMaxPerThread; ++r) {
+        homed[r] = 0;
+        if (r >= per) continue;
+        const uint32_t s = base + r * kBlock + t;
         if (s >= cap) continue;
         const Record& R = rec[s];
+        homed[r] = R.homed;
         if (R.key == kEmpty) continue;
         const float4* pv = reinterpret_cast<const float4*>(R.val);
         float4 a = pv[0], b = pv[1];
@@ -759,11 +780,24 @@ __global__ __launch_bounds__(kBlock) void k_index_compact(const Record* __restri
                           (b.z == b.z) + (b.w == b.w);
         // records in the low 29 bits, leaves above (cap <= 2^28 keeps them apart)
         n_rec += 1ull + ((unsigned long long)leaves << 29);
-        if (leaves) grp_bits |= 1u << r;
     }
-    for (int r = 0; r < per; ++r) {
-        unsigned long long b = __ballot((grp_bits >> r) & 1);
-        if (lane == 0) s_rcount[r][wave] = (uint32_t)__popcll(b);
+    // per row, each lane's keys before its own within the wave (a ballot
+    // when no slot of the row is home to two or more keys, else a scan)
+#pragma unroll
+    for (int r = 0; r < kCompactMaxPerThread; ++r) {
+        if (r >= per) break;
+        const uint32_t x = homed[r];
+        const unsigned long long any = __ballot(x != 0), multi = __ballot(x > 1);
+        uint32_t tot;
+        if (multi == 0) {
+            excl[r] = (uint32_t)__popcll(any & below);
+            tot = (uint32_t)__popcll(any);
+        } else {
+            const unsigned long long incl = wave_incl_scan((unsigned long long)x);
+            excl[r] = (uint32_t)incl - x;
+            tot = (uint32_t)__shfl(incl, 63, 64);
+        }
+        if (lane == 0) s_rcount[r][wave] = tot;
     }
     unsigned long long recs = wave_reduce((unsigned long long)n_rec,
                                           [](unsigned long long x, unsigned long long y) { return x + y; });
@@ -787,19 +821,53 @@ __global__ __launch_bounds__(kBlock) void k_index_compact(const Record* __restri
         }
     }
     __syncthreads();
-    // slot-ordered positions: all of row r's entries precede row r+1's
-    uint32_t pos = (uint32_t)s_pre0;
-    for (int r = 0; r < per; ++r) {
-        unsigned long long b = __ballot((grp_bits >> r) & 1);
-        uint32_t before = 0;
-        for (int w = 0; w < wave; ++w) before += s_rcount[r][w];
-        if ((grp_bits >> r) & 1) {
-            const uint32_t at = pos + before + (uint32_t)__popcll(b & ((1ull << lane) - 1));
-            const uint32_t slot = base + r * kBlock + t;
-            glist[at] = (int32_t)slot;
-            gkey[at] = rec[slot].key;  // beside the slot, so extraction needs no dependent load
+    uint32_t row = (uint32_t)s_pre0;
+#pragma unroll
+    for (int r = 0; r < kCompactMaxPerThread; ++r) {
+        if (r >= per) break;
+        uint32_t before = 0, in_row = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            if (w < wave) before += s_rcount[r][w];
+            in_row += s_rcount[r][w];
         }
-        for (int w = 0; w < kBlock / 64; ++w) pos += s_rcount[r][w];
+        const uint32_t n_here = homed[r];
+        if (n_here) {
+            const uint32_t h = base + r * kBlock + t;
+            const uint32_t pos = row + before + excl[r];
+            const uint64_t k0 = rec[h].key;
+            if (n_here == 1 && slot_of(k0, shift) == h) {
+                glist[pos] = (int32_t)h;
+                gkey[pos] = k0;  // beside the slot, so extraction needs no dependent load
+            } else {
+                // the keys homed here, smallest first: one walk of the probe
+                // sequence per key, each taking the least key above the last
+                uint64_t last = 0;
+                for (uint32_t q = 0; q < n_here; ++q) {
+                    uint64_t best = kEmpty;
+                    uint32_t best_slot = h, seen = 0, x = h;
+                    for (uint32_t step = 0; step < kMaxProbe && seen < n_here; ++step) {
+                        const uint64_t k = rec[x].key;
+                        if (k == kEmpty) break;
+                        if (slot_of(k, shift) == h) {
+                            ++seen;
+                            if ((q == 0 || k > last) && k < best) {
+                                best = k;
+                                best_slot = x;
+                            }
+                        }
+                        x = next_slot(x, step, cap - 1);
+                    }
+                    if (best == kEmpty) {  // cannot happen while the counts hold
+                        atomicOr(&c->overflow, 1u);
+                        break;
+                    }
+                    glist[pos + q] = (int32_t)best_slot;
+                    gkey[pos + q] = best;
+                    last = best;
+                }
+            }
+        }
+        row += in_row;
     }
 }
 
