@@ -594,6 +594,25 @@ __device__ __forceinline__ int find_or_insert(Record* __restrict__ rec, uint64_t
     return -1;
 }
 
+// The lowest active lane of the wave holding the same key (a lane's own
+// index when it holds a key no lower lane holds).  Lanes of one group are
+// usually neighbours in a wave, so one of them probes the table for all;
+// after 16 distinct keys the rest lead themselves.
+__device__ __forceinline__ int same_key_leader(uint64_t key, bool active) {
+    const int lane = lane_id();
+    int leader = lane;
+    unsigned long long todo = __ballot(active);
+    for (int it = 0; it < 16 && todo; ++it) {
+        const int l = __ffsll((long long)todo) - 1;
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)key, l);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(key >> 32), l);
+        const bool same = active && key == (((uint64_t)hi << 32) | lo);
+        if (same) leader = l;
+        todo &= ~__ballot(same);
+    }
+    return leader;
+}
+
 // Every cell stores its value in its group record (a plain store: a
 // duplicate cell overwrites its twin and shows up later as a missing leaf in
 // the count of the compaction).  The cell that creates a group's record
@@ -605,19 +624,33 @@ __global__ __launch_bounds__(256) void k_index_insert(const int32_t* __restrict_
                                                       Record* __restrict__ rec, Ctrl* c) {
     if (c->res.status != AMR_OK) return;  // invalid cells: nothing to index
     const Geo g = c->geo;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        int m = lvl[i];
-        uint32_t ux = (uint32_t)(xyz[3 * i] - g.ox), uy = (uint32_t)(xyz[3 * i + 1] - g.oy),
-                 uz = (uint32_t)(xyz[3 * i + 2] - g.oz);
-        const uint64_t key = group_key(m, ux >> (m + 1), uy >> (m + 1), uz >> (m + 1));
-        uint32_t created = 0;
-        int slot = find_or_insert(rec, key, g, &created);
+    const int lane = lane_id();
+    // whole waves step together (the leader election needs every lane)
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x; b < n; b += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = b + threadIdx.x;
+        const bool live = i < n;
+        int m = 0, child = 0;
+        uint64_t key = 0;
+        if (live) {
+            m = lvl[i];
+            const uint32_t ux = (uint32_t)(xyz[3 * i] - g.ox), uy = (uint32_t)(xyz[3 * i + 1] - g.oy),
+                           uz = (uint32_t)(xyz[3 * i + 2] - g.oz);
+            key = group_key(m, ux >> (m + 1), uy >> (m + 1), uz >> (m + 1));
+            child = ((ux >> m) & 1) | (((uy >> m) & 1) << 1) | (((uz >> m) & 1) << 2);
+        }
+        const int leader = same_key_leader(key, live);
+        int slot = -1;
+        if (live && leader == lane) {
+            uint32_t created = 0;
+            slot = find_or_insert(rec, key, g, &created);
+            if (created) atomicAdd(&rec[slot_of(key, g.shift)].homed, 1u);
+        }
+        slot = __shfl(slot, leader, 64);
+        if (!live) continue;
         if (slot < 0) {
             atomicOr(&c->overflow, 1u);
             continue;
         }
-        if (created) atomicAdd(&rec[slot_of(key, g.shift)].homed, 1u);
-        int child = ((ux >> m) & 1) | (((uy >> m) & 1) << 1) | (((uz >> m) & 1) << 2);
         rec[slot].val[child] = val[i];
     }
 }
@@ -654,20 +687,33 @@ __global__ __launch_bounds__(256) void k_index_mark(Record* __restrict__ rec,
     if (threadIdx.x == 0) s_made = 0;
     __syncthreads();
     uint32_t made = 0;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ng; i += gridDim.x * blockDim.x) {
-        const uint64_t key = gkey[i];
+    const int lane = lane_id();
+    // whole waves step together, level by level (the leader election needs
+    // every lane); sibling groups sit side by side in the list and share
+    // the record one level up, which one of them probes for all
+    for (uint32_t b = blockIdx.x * blockDim.x; b < ng; b += gridDim.x * blockDim.x) {
+        const uint32_t i = b + threadIdx.x;
+        uint64_t key = 0;
+        if (i < ng) key = gkey[i];
         const int m = (int)(key >> 57);
-        if (m >= g.lmax) continue;
+        bool going = i < ng && m < g.lmax;
         const uint32_t gx = (uint32_t)(key & 0x7FFFF), gy = (uint32_t)((key >> 19) & 0x7FFFF),
                        gz = (uint32_t)((key >> 38) & 0x7FFFF);
-        for (int L = m + 1; L <= g.lmax; ++L) {
+        int L = m + 1;
+        while (__ballot(going)) {
             // the level-L cell holding this group's block, and its group
             const int sh = L - m - 1;
             const uint32_t cx = gx >> sh, cy = gy >> sh, cz = gz >> sh;
-            const int s2 = find_or_insert(rec, group_key(L, cx >> 1, cy >> 1, cz >> 1), g, &made);
+            const uint64_t pkey = going ? group_key(L, cx >> 1, cy >> 1, cz >> 1) : 0;
+            const int leader = same_key_leader(pkey, going);
+            int s2 = -1;
+            if (going && leader == lane) s2 = find_or_insert(rec, pkey, g, &made);
+            s2 = __shfl(s2, leader, 64);
+            if (!going) continue;
             if (s2 < 0) {
                 atomicOr(&c->overflow, 1u);
-                break;
+                going = false;
+                continue;
             }
             const int c2 = (cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2);
             unsigned int* slot_val = reinterpret_cast<unsigned int*>(&rec[s2].val[c2]);
@@ -679,12 +725,16 @@ __global__ __launch_bounds__(256) void k_index_mark(Record* __restrict__ rec,
                 if (L == m + 1) *slot_val = kValRefined;
                 else prev = atomicCAS(slot_val, kValEmpty, kValRefined);
             }
-            if (prev == kValEmpty) continue;  // marked here: carry on upwards
-            if (prev != kValRefined) {        // a coarser cell contains this group
+            if (prev == kValEmpty) {  // marked here: carry on upwards
+                ++L;
+                going = L <= g.lmax;
+                continue;
+            }
+            if (prev != kValRefined) {  // a coarser cell contains this group
                 atomicOr(&c->overlap, 1u);
                 atomicMin(&c->bad_build, (unsigned long long)s2 * 8 + c2);  // its slot * 8 + child
             }
-            break;
+            going = false;
         }
     }
     made = (uint32_t)wave_reduce((unsigned long long)made,
