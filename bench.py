@@ -173,11 +173,12 @@ def kernel_names(amr):
 def kernel_survey(amr, s, step, reps=3):
     """Each kernel of a step on its own: HIP events around the kernel itself
     (recorded on the stream it runs on), `reps` steps per kernel.  Returns
-    {kernel id: mean ms}; a kernel the step does not run (the write pass of
+    ({kernel id: mean ms}, {kernel id: the launched kernel's name, as
+    rocprofv3 shows it}); a kernel the step does not run (the write pass of
     a fused call) is left out."""
     import torch
 
-    out = {}
+    out, names = {}, {}
     stream = torch.cuda.current_stream()
     for k in kernel_names(amr):
         ms = []
@@ -190,9 +191,10 @@ def kernel_survey(amr, s, step, reps=3):
             torch.cuda.synchronize()
             s.time_kernel(0, e0, e1)  # disarm, in case the step did not run it
             ms.append(e0.elapsed_time(e1))
+            names[k] = s.timed_kernel_name()
         if min(ms) > 0.0005:
             out[k] = statistics.mean(ms)
-    return out
+    return out, names
 
 
 def time_steps(amr, s, step, iso_call, steps, warmup, kernel):
@@ -285,11 +287,8 @@ def step_measurement(amr, cs, xyz, lvl, val, steps, warmup):
 
     for _ in range(warmup):
         step()
-    survey = kernel_survey(amr, s, step)
-    names = kernel_names(amr)
+    survey, names = kernel_survey(amr, s, step)
     fused = amr.KERNEL_WRITE not in survey
-    names[amr.KERNEL_EXTRACT] = "k_extract<false, 2>" if fused else "k_extract<false, 0>"
-    names[amr.KERNEL_WRITE] = "k_extract_list<1>"
     # the roofline kernel: the longest one whose algorithmic bytes are defined
     # (every kernel of the path but the ancestor marking, which only probes)
     dom = max((k for k in survey if alg_bytes(amr, k, cs.n, n_tri, fused)), key=survey.get)

@@ -400,6 +400,12 @@ enum amr_kernel {
 
 int amr_time_kernel(amr_set* set, int kernel, hipEvent_t start, hipEvent_t stop);
 
+/* Name of the kernel the last armed timing of this set was applied to, as
+   rocprofv3 shows it without its arguments ("k_count<false>",
+   "k_extract<false, 0>", ...); "" while a timing is armed and has not run
+   yet, and before any.  The string is static. */
+const char* amr_timed_kernel_name(const amr_set* set);
+
 /* Message describing the last error on the calling thread ("" if none). */
 const char* amr_last_error(void);
 

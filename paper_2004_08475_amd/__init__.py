@@ -27,7 +27,7 @@ ABI_SYMBOLS = ("amr_create", "amr_destroy", "amr_upload", "amr_index_bytes", "am
                "amr_batch_isosurface", "amr_indexed_mesh_bytes", "amr_indexed_mesh", "amr_indexed_mesh_noalloc",
                "amr_sampler_bytes",
                "amr_sampler_build", "amr_sample", "amr_sorted_index_bytes", "amr_build_sorted_index", "amr_locate",
-               "amr_snap_count", "amr_time_kernel", "amr_last_error")
+               "amr_snap_count", "amr_time_kernel", "amr_timed_kernel_name", "amr_last_error")
 
 # amr_kernel: kernels amr_time_kernel can bracket with events
 (KERNEL_UPLOAD, KERNEL_RESET, KERNEL_INSERT, KERNEL_COMPACT, KERNEL_MARK, KERNEL_EXTRACT, KERNEL_WRITE,
@@ -101,6 +101,8 @@ def load_library(path: str = LIB_PATH):
     L.amr_snap_count.restype = C.c_int
     L.amr_time_kernel.argtypes = [vp, C.c_int, vp, vp]
     L.amr_time_kernel.restype = C.c_int
+    L.amr_timed_kernel_name.argtypes = [vp]
+    L.amr_timed_kernel_name.restype = C.c_char_p
     L.amr_last_error.argtypes = []
     L.amr_last_error.restype = C.c_char_p
     _lib = L
@@ -226,6 +228,10 @@ class AmrSet:
                 e.record(stream)  # torch creates the event on first use
         _check(self.lib.amr_time_kernel(self._h, int(kernel), C.c_void_p(start.cuda_event),
                                         C.c_void_p(stop.cuda_event)))
+
+    def timed_kernel_name(self) -> str:
+        """Name of the kernel the last armed timing went to ("" before any)."""
+        return self.lib.amr_timed_kernel_name(self._h).decode()
 
     # -- point location ---------------------------------------------------
     def build_sorted_index(self):

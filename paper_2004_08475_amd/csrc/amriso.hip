@@ -3583,6 +3583,7 @@ struct amr_set {
     // amr_time_kernel: the next launch of this kernel records these events
     int time_kernel = 0;
     hipEvent_t time_start = nullptr, time_stop = nullptr;
+    const char* timed_name = "";  // the kernel the last armed timing went to
 };
 
 namespace {
@@ -3590,10 +3591,11 @@ namespace {
 // A launch that records the set's timing events around the kernel itself
 // when amr_time_kernel armed them for `which` (once), else a plain launch.
 template <typename... KArgs, typename... Args>
-void launch(amr_set* s, int which, void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStream_t stream,
-            Args... args) {
+void launch(amr_set* s, int which, const char* name, void (*kernel)(KArgs...), dim3 grid, dim3 block,
+            hipStream_t stream, Args... args) {
     if (s->time_kernel == which) {
         s->time_kernel = 0;
+        s->timed_name = name;
         hipExtLaunchKernelGGL(kernel, grid, block, 0, stream, s->time_start, s->time_stop, 0, args...);
     } else {
         hipLaunchKernelGGL(kernel, grid, block, 0, stream, args...);
@@ -3777,9 +3779,9 @@ int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_
         a.sc0 = s->fs0;
         a.sc1 = s->fs1;
         if (duals)
-            launch(s, AMR_KERNEL_EXTRACT, k_extract<true, kPassFused>, dim3(max_tiles), dim3(kBlock), stream, a);
+            launch(s, AMR_KERNEL_EXTRACT, "k_extract<true, 2>", k_extract<true, kPassFused>, dim3(max_tiles), dim3(kBlock), stream, a);
         else
-            launch(s, AMR_KERNEL_EXTRACT, k_extract<false, kPassFused>, dim3(max_tiles), dim3(kBlock), stream, a);
+            launch(s, AMR_KERNEL_EXTRACT, "k_extract<false, 2>", k_extract<false, kPassFused>, dim3(max_tiles), dim3(kBlock), stream, a);
     } else if (a.rng_mode == kRngCull) {
         // list the candidate groups, then count, scan and write over the list
         const bool write = cap > 0 && (tris || tri_cells);
@@ -3789,18 +3791,18 @@ int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_
         a.n_list = s->n_list;
         a.list_duals = s->dual_total;
         a.list_from_cull = 1;
-        launch(s, AMR_KERNEL_EXTRACT, k_extract_list<kPassCount>, dim3(grid), dim3(kBlock), stream, a);
+        launch(s, AMR_KERNEL_EXTRACT, "k_extract_list<0>", k_extract_list<kPassCount>, dim3(grid), dim3(kBlock), stream, a);
         hipLaunchKernelGGL(k_tile_scan, dim3(a.n_scan_tiles), dim3(kBlock), 0, stream, a, 0);
-        if (write) launch(s, AMR_KERNEL_WRITE, k_extract_list<kPassWrite>, dim3(grid), dim3(kBlock), stream, a);
+        if (write) launch(s, AMR_KERNEL_WRITE, "k_extract_list<1>", k_extract_list<kPassWrite>, dim3(grid), dim3(kBlock), stream, a);
     } else if (!duals && tri_dual == nullptr && cap > 0 && (tris || tri_cells)) {
         // count pass over all groups, then list the groups with triangles (in
         // group order, with their counts) and scan and write over that list
         // only: most groups have none, and the write pass would otherwise
         // redo their neighbourhoods beside the few that have some
         if (lane_count)
-            launch(s, AMR_KERNEL_EXTRACT, k_count<false>, dim3(count_grid), dim3(256), stream, a);
+            launch(s, AMR_KERNEL_EXTRACT, "k_count<false>", k_count<false>, dim3(count_grid), dim3(256), stream, a);
         else
-            launch(s, AMR_KERNEL_EXTRACT, k_extract<false, kPassCount>, dim3(grid), dim3(kBlock), stream, a);
+            launch(s, AMR_KERNEL_EXTRACT, "k_extract<false, 0>", k_extract<false, kPassCount>, dim3(grid), dim3(kBlock), stream, a);
         hipLaunchKernelGGL(k_group_list, dim3(n_wgs), dim3(kBlock), 0, stream, nullptr, s->gcnt, s->ctrl, iso,
                            n_wgs, s->clist, s->lcnt, s->n_list, s->list_duals, s->ls0, s->ls1, s->sched);
         a.clist = s->clist;
@@ -3808,27 +3810,27 @@ int launch_extract(amr_set* s, bool duals, float iso, float* tris, int32_t* tri_
         a.lcnt = s->lcnt;
         a.list_duals = s->list_duals;
         hipLaunchKernelGGL(k_tile_scan, dim3(a.n_scan_tiles), dim3(kBlock), 0, stream, a, 0);
-        launch(s, AMR_KERNEL_WRITE, k_extract_list<kPassWrite>, dim3(grid), dim3(kBlock), stream, a);
+        launch(s, AMR_KERNEL_WRITE, "k_extract_list<1>", k_extract_list<kPassWrite>, dim3(grid), dim3(kBlock), stream, a);
     } else {
         // count pass, scan, then the write pass only when something is written;
         // the grid is a multiple of the XCD count (see the tile mapping)
         const bool write = cap > 0 && (duals ? (corner_level || verts || dvals) : (tris || tri_cells || tri_dual));
         if (lane_count) {
             if (duals)
-                launch(s, AMR_KERNEL_EXTRACT, k_count<true>, dim3(count_grid), dim3(256), stream, a);
+                launch(s, AMR_KERNEL_EXTRACT, "k_count<true>", k_count<true>, dim3(count_grid), dim3(256), stream, a);
             else
-                launch(s, AMR_KERNEL_EXTRACT, k_count<false>, dim3(count_grid), dim3(256), stream, a);
+                launch(s, AMR_KERNEL_EXTRACT, "k_count<false>", k_count<false>, dim3(count_grid), dim3(256), stream, a);
         } else if (duals) {
-            launch(s, AMR_KERNEL_EXTRACT, k_extract<true, kPassCount>, dim3(grid), dim3(kBlock), stream, a);
+            launch(s, AMR_KERNEL_EXTRACT, "k_extract<true, 0>", k_extract<true, kPassCount>, dim3(grid), dim3(kBlock), stream, a);
         } else {
-            launch(s, AMR_KERNEL_EXTRACT, k_extract<false, kPassCount>, dim3(grid), dim3(kBlock), stream, a);
+            launch(s, AMR_KERNEL_EXTRACT, "k_extract<false, 0>", k_extract<false, kPassCount>, dim3(grid), dim3(kBlock), stream, a);
         }
         hipLaunchKernelGGL(k_tile_scan, dim3(a.n_scan_tiles), dim3(kBlock), 0, stream, a, duals ? 1 : 0);
         if (write) {
             if (duals)
-                launch(s, AMR_KERNEL_WRITE, k_extract<true, kPassWrite>, dim3(grid), dim3(kBlock), stream, a);
+                launch(s, AMR_KERNEL_WRITE, "k_extract<true, 1>", k_extract<true, kPassWrite>, dim3(grid), dim3(kBlock), stream, a);
             else
-                launch(s, AMR_KERNEL_WRITE, k_extract<false, kPassWrite>, dim3(grid), dim3(kBlock), stream, a);
+                launch(s, AMR_KERNEL_WRITE, "k_extract<false, 1>", k_extract<false, kPassWrite>, dim3(grid), dim3(kBlock), stream, a);
         }
     }
     hipError_t e = hipGetLastError();
@@ -3967,7 +3969,7 @@ int amr_upload(amr_set* s, const int32_t* xyz, const int32_t* level, const float
     s->up_status = AMR_OK;
     // the replicas are clean: amr_create and every k_upload_finish leave them so
     if (n > 0) {
-        launch(s, AMR_KERNEL_UPLOAD, k_upload, dim3(grid_for(n, 256)), dim3(256), stream, xyz, level, value, n,
+        launch(s, AMR_KERNEL_UPLOAD, "k_upload", k_upload, dim3(grid_for(n, 256)), dim3(256), stream, xyz, level, value, n,
                s->ctrl);
         hipLaunchKernelGGL(k_upload_finish, dim3(1), dim3(kReplicas), 0, stream, s->ctrl);
     } else {
@@ -4188,21 +4190,21 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     {
         uint32_t work = cap > L.compact_tiles ? cap : L.compact_tiles;
         if (work < kFusedMaxTiles) work = kFusedMaxTiles;
-        launch(s, AMR_KERNEL_RESET, k_build_reset, dim3(grid_for(work, 256)), dim3(256), stream, s->rec, cap,
+        launch(s, AMR_KERNEL_RESET, "k_build_reset", k_build_reset, dim3(grid_for(work, 256)), dim3(256), stream, s->rec, cap,
                64 - log2cap, s->sched, s->ct0, s->ct1, L.compact_tiles, s->fs0, s->fs1, s->ls0, s->ls1,
                L.max_list_wgs, s->ctrl);
     }
     if (s->n > 0)
-        launch(s, AMR_KERNEL_INSERT, k_index_insert, dim3(grid_for(s->n, 256)), dim3(256), stream, s->xyz, s->lvl,
+        launch(s, AMR_KERNEL_INSERT, "k_index_insert", k_index_insert, dim3(grid_for(s->n, 256)), dim3(256), stream, s->xyz, s->lvl,
                s->val, s->n, s->rec, s->ctrl);
     // the group list only depends on the leaves, so it is compacted before
     // the ancestors are marked, and the marking runs over it; its last
     // work-group decides the verdict
-    launch(s, AMR_KERNEL_COMPACT, k_index_compact, dim3(L.compact_tiles), dim3(kBlock), stream, s->rec, cap,
+    launch(s, AMR_KERNEL_COMPACT, "k_index_compact", k_index_compact, dim3(L.compact_tiles), dim3(kBlock), stream, s->rec, cap,
            s->glist, s->gkey, s->ct0, s->ct1, s->sched, L.compact_tiles, L.compact_per, s->ctrl);
     {
         const int64_t most = s->n < (int64_t)cap ? s->n : (int64_t)cap;  // at least the number of groups
-        launch(s, AMR_KERNEL_MARK, k_index_mark, dim3(grid_for(most, 256)), dim3(256), stream, s->rec, s->gkey,
+        launch(s, AMR_KERNEL_MARK, "k_index_mark", k_index_mark, dim3(grid_for(most, 256)), dim3(256), stream, s->rec, s->gkey,
                s->ctrl);
     }
     hipLaunchKernelGGL(k_index_verdict, dim3(1), dim3(64), 0, stream, s->n, cap, s->grid_groups, s->ctrl);
@@ -4617,7 +4619,7 @@ int amr_sample(amr_set* s, const int32_t* corner_level, const int32_t* verts, in
     a.n_pts = n_points;
     a.out = values;
     a.dual = dual;
-    launch(s, AMR_KERNEL_SAMPLE, k_smp_query, dim3(grid_for(n_points, 256)), dim3(256), stream, a);
+    launch(s, AMR_KERNEL_SAMPLE, "k_smp_query", k_smp_query, dim3(grid_for(n_points, 256)), dim3(256), stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hipfail(e, "amr_sample: launch");
     g_err[0] = 0;
@@ -4798,10 +4800,10 @@ int amr_snap_count(amr_set* s, int index, uint64_t* out, hipStream_t stream) {
     hipLaunchKernelGGL(k_zero2, dim3(1), dim3(64), 0, stream, o);
     const int grid = s->n > 0 ? (grid_for(s->n, 256) < 1024 ? grid_for(s->n, 256) : 1024) : 1;
     if (index == AMR_INDEX_SORTED)
-        launch(s, AMR_KERNEL_SNAP, k_snap<true>, dim3(grid), dim3(256), stream, s->xyz, s->lvl, s->n, s->rec, s->ids,
+        launch(s, AMR_KERNEL_SNAP, "k_snap<true>", k_snap<true>, dim3(grid), dim3(256), stream, s->xyz, s->lvl, s->n, s->rec, s->ids,
                s->ctrl, si, o);
     else
-        launch(s, AMR_KERNEL_SNAP, k_snap<false>, dim3(grid), dim3(256), stream, s->xyz, s->lvl, s->n, s->rec,
+        launch(s, AMR_KERNEL_SNAP, "k_snap<false>", k_snap<false>, dim3(grid), dim3(256), stream, s->xyz, s->lvl, s->n, s->rec,
                s->ids, s->ctrl, si, o);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hipfail(e, "amr_snap_count: launch");
@@ -4816,9 +4818,12 @@ int amr_time_kernel(amr_set* s, int kernel, hipEvent_t start, hipEvent_t stop) {
     s->time_kernel = kernel;
     s->time_start = start;
     s->time_stop = stop;
+    if (kernel != 0) s->timed_name = "";
     g_err[0] = 0;
     return AMR_OK;
 }
+
+const char* amr_timed_kernel_name(const amr_set* s) { return s ? s->timed_name : ""; }
 
 const char* amr_last_error(void) { return g_err; }
 
