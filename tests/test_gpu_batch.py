@@ -94,6 +94,43 @@ def test_many_sets_own_iso_equal_plain(amr):
         assert torch.equal(got, _plain(sets[si], iso))
 
 
+def test_batch_edge_cases(amr, shell):
+    """A job with a NaN iso or naming no set of the batch counts -1 and writes
+    nothing; a job on an empty set, or at an iso outside the values, counts 0;
+    two equal jobs both equal the plain path; a set no job names costs
+    nothing; launch shapes outside the documented ones are errors."""
+    cs, s = shell
+    e = amr.from_numpy(np.zeros((0, 3), np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    sm = amrgen.two_level_sphere()
+    t = amr.from_numpy(sm.xyz, sm.level, sm.value)
+    u = amr.from_numpy(sm.xyz, sm.level, sm.value)  # named by no job
+    b = amr.AmrBatch([s, e, t, u])
+    jobs_set = [0, 0, 0, 1, 0, 0, 7, 2, -1]
+    jobs_iso = [cs.iso, cs.iso, float("nan"), 5.0, 1e30, -1e30, 5.0, sm.iso, cs.iso]
+    want = {0: _plain(s, cs.iso), 1: _plain(s, cs.iso), 7: _plain(t, sm.iso)}
+    n = len(jobs_iso)
+    caps = [len(want[k]) if k in want else 16 for k in range(n)]
+    off = np.concatenate([[0], np.cumsum(caps)[:-1]])
+    tris = torch.full((int(sum(caps)), 9), -3.0, dtype=torch.float32, device=s.device)
+    counts = torch.zeros(n, dtype=torch.int64, device=s.device)
+    for block, unit in ((256, 256), (128, 64)):
+        tris.fill_(-3.0)
+        jobs = b.jobs_tensor(jobs_set, jobs_iso, off, caps)
+        b.run_into(jobs, n, tris, counts, block, unit)
+        torch.cuda.synchronize()
+        c = counts.tolist()
+        assert c == [len(want[0]), len(want[1]), -1, 0, 0, 0, -1, len(want[7]), -1]
+        for k in range(n):
+            got = tris[int(off[k]):int(off[k]) + caps[k]]
+            if k in want:
+                assert torch.equal(got, want[k])
+            else:
+                assert torch.all(got == -3.0)
+    for block, unit in ((256, 100), (192, 256), (256, 2048), (128, 32)):
+        with pytest.raises(amr.AmrError):
+            b.workspace(n, block, unit)
+
+
 def test_batch_capacity_contract(amr, shell):
     cs, s = shell
     b = amr.AmrBatch([s])
