@@ -1,0 +1,120 @@
+"""Turn rocprofv3 output of `bench.py` runs on one workload into the counter
+summary `profiles/<workload>_counters.txt` that bench.py reads back.
+
+Inputs: the CSV directories of one `--kernel-trace --stats` run and of four
+`--pmc` runs (FETCH_SIZE; WRITE_SIZE; TCC_HIT_sum TCC_MISS_sum; SQ_INSTS_VALU
+SQ_WAVES), each of the same bench.py command with `--copy-probe-mib 256`.
+Per kernel: mean counter value per dispatch, and its mean duration from the
+trace.  HBM bytes per dispatch = FETCH_SIZE x f + WRITE_SIZE x w (KiB x 1024),
+with f and w the factors that make the 256 MiB copy read and write 256 MiB;
+L2 hit rate = hits / (hits + misses); VALU issue fraction = VALU wave
+instructions / duration / the issue peak (256 CUs x 4 SIMDs x 2.4 GHz / 4
+cycles per wave64 instruction).  The Infinity Cache (MALL) has no counter in
+rocprofv3 on gfx950, so its hit rate is '-'.
+
+    python bench_counters.py --workload W --trace D0 --fetch D1 --write D2 --tcc D3 --sq D4 \\
+        --command "..." > profiles/W_counters.txt
+"""
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import os
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+SOURCE = os.path.join(ROOT, "paper_2004_08475_amd", "csrc", "amriso.hip")
+VALU_PEAK = 256 * 4 * 2.4e9 / 4  # wave64 instructions per second
+COPY_KIB = 256 * 1024
+
+
+def short_name(k):
+    k = k.replace("(anonymous namespace)::", "")
+    if k.startswith("void "):
+        k = k[len("void "):]
+    depth, out = 0, []
+    for ch in k:  # the name up to its argument list (template arguments kept)
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            break
+        out.append(ch)
+    return "".join(out).strip()
+
+
+def one_csv(d, suffix):
+    paths = glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)
+    if len(paths) != 1:
+        raise SystemExit("expected one *%s under %s, found %d" % (suffix, d, len(paths)))
+    return paths[0]
+
+
+def counters(d):
+    acc = collections.defaultdict(lambda: collections.defaultdict(float))
+    disp = collections.defaultdict(set)
+    with open(one_csv(d, "counter_collection.csv")) as fh:
+        for row in csv.DictReader(fh):
+            k = short_name(row["Kernel_Name"])
+            disp[k].add(row["Dispatch_Id"])
+            acc[k][row["Counter_Name"]] += float(row["Counter_Value"])
+    return {k: {c: v / len(disp[k]) for c, v in cs.items()} for k, cs in acc.items()}
+
+
+def durations(d):
+    out = {}
+    with open(one_csv(d, "kernel_stats.csv")) as fh:
+        for row in csv.DictReader(fh):
+            out[short_name(row["Name"])] = (int(row["Calls"]), float(row["AverageNs"]) / 1e3)
+    return out
+
+
+def copy_kernel(c):
+    ks = [k for k in c if "MulFunctor<float>" in k]
+    if len(ks) != 1:
+        raise SystemExit("no unique copy-probe kernel among %s" % sorted(c))
+    return ks[0]
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    for a in ("workload", "trace", "fetch", "write", "tcc", "sq", "command"):
+        ap.add_argument("--" + a, required=True)
+    args = ap.parse_args()
+    dur = durations(args.trace)
+    fetch, write, tcc, sq = (counters(getattr(args, a)) for a in ("fetch", "write", "tcc", "sq"))
+    ck = copy_kernel(fetch)
+    f_scale = COPY_KIB / fetch[ck]["FETCH_SIZE"]
+    w_scale = COPY_KIB / write[copy_kernel(write)]["WRITE_SIZE"]
+    src = hashlib.sha256(open(SOURCE, "rb").read()).hexdigest()
+    print("# rocprofv3 counters of the library's kernels on workload %s, one MI355X (ROCm 7.2)." % args.workload)
+    print("# Commands (repo root $R; run from /tmp with TMPDIR=/tmp), one rocprofv3 run each:")
+    for ln in args.command.splitlines():
+        print("#   " + ln)
+    print("# Per dispatch, averaged over each kernel's dispatches.  Scale from the 256 MiB copy probe "
+          "(%s): bytes = FETCH_SIZE x %.3f + WRITE_SIZE x %.3f (KiB x 1024)." % (ck[:60], f_scale, w_scale))
+    print("# l2_hit = TCC_HIT / (TCC_HIT + TCC_MISS); valu_issue = SQ_INSTS_VALU / avg duration / %.4g; "
+          "mall_hit '-': no Infinity Cache counter on gfx950." % VALU_PEAK)
+    print("# The line 'source_sha256' is the hash of paper_2004_08475_amd/csrc/amriso.hip these were taken with;")
+    print("# bench.py uses the figures only while the source still has that hash.")
+    print("source_sha256 %s" % src)
+    for k in sorted(dur, key=lambda k: -dur[k][0] * dur[k][1]):
+        if not k.startswith("k_") or k not in fetch or k not in write:
+            continue
+        calls, us = dur[k]
+        fb = fetch[k]["FETCH_SIZE"] * f_scale * 1024
+        wb = write[k]["WRITE_SIZE"] * w_scale * 1024
+        t = tcc.get(k, {})
+        h, m = t.get("TCC_HIT_sum"), t.get("TCC_MISS_sum")
+        l2 = "%.4f" % (h / (h + m)) if h is not None and m is not None and h + m > 0 else "-"
+        v = sq.get(k, {}).get("SQ_INSTS_VALU")
+        valu = "%.4f" % (v / (us * 1e-6) / VALU_PEAK) if v is not None and us > 0 else "-"
+        waves = sq.get(k, {}).get("SQ_WAVES")
+        print("kernel %s | traffic_bytes %.6g fetch_bytes %.6g write_bytes %.6g l2_hit %s mall_hit - "
+              "valu_issue %s avg_us %.2f calls %d waves %s" % (k, fb + wb, fb, wb, l2, valu, us, calls,
+                                                                 "%.0f" % waves if waves is not None else "-"))
+
+
+if __name__ == "__main__":
+    main()

@@ -277,11 +277,15 @@ def _owner_of_duals(pl, ids, level):
     return ids[np.arange(len(ids)), first]
 
 
-@pytest.mark.parametrize("sample", [60000])
-def test_block_vortex_full_size_sampled(amr, sample):
+def test_block_vortex_full_size_sampled(amr):
     """~50M-cell block-structured set with a hole, at full size: all GPU duals
-    and triangles whose generating cell lies in a random sample of cells (a
-    contiguous range of the shuffled input) equal the oracle's for that range."""
+    and triangles whose generating cell lies in a sample of cells equal the
+    oracle's for that sample.  Samples: two contiguous ranges of 60,000 cells
+    of the shuffled input (random cells anywhere), and every cell with its
+    lower corner in a 24-unit slab along one edge of the obstacle box (cells
+    beside the hole, on both of its faces there); the oracle gets that slab's
+    cells plus every cell meeting the slab grown by 2^(Lmax+1), which holds
+    every point their duals snap."""
     cs = amrgen.block_vortex(device="cuda")
     _say("block-vortex: %d cells" % cs.n)
     s = gpu_set(amr, cs)
@@ -290,31 +294,50 @@ def test_block_vortex_full_size_sampled(amr, sample):
     r = s.isosurface(cs.iso, cells=True, dual=True)
     tg, cg, dg = r["tris"].cpu().numpy(), r["cells"].cpu().numpy(), r["dual"].cpu().numpy()
     _say("gpu: %d duals, %d triangles" % (len(pl), len(tg)))
-    assert r["n_duals"] == len(pl)
+    assert r["n_duals"] == len(pl) and len(tg) > 0
     owner = _owner_of_duals(pl, ids, cs.level)
+
+    def check(sel, opl, oids, ro, back):
+        a = oracle.canonical_duals(pl[sel], ids[sel])
+        b = oracle.canonical_duals(opl, back[oids].astype(np.int32))
+        assert len(a[0]) == len(b[0]) > 0
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        tsel = sel[dg]
+        assert int(tsel.sum()) == len(ro["tris"])
+        if len(ro["tris"]) == 0:
+            return len(a[0]), 0
+        A, AC, _ = canon_by_cells(tg[tsel], cg[tsel])
+        B, BC, _ = canon_by_cells(ro["tris"], back[ro["cells"]])
+        assert np.array_equal(AC, BC)
+        assert same_positions(A, B)
+        return len(a[0]), len(A)
+
+    # the slab beside the hole, on its own small oracle
+    (ox0, ox1), (oy0, oy1), (oz0, oz1) = cs.meta["obstacle"]
+    lo = np.array([ox0 - 12, oy0 - 12, oz0 - 12])
+    hi = np.array([ox0 + 12, oy0 + 12, oz1 + 12])
+    in_slab = np.all((cs.xyz >= lo) & (cs.xyz < hi), axis=1)
+    halo = 2 << int(cs.level.max())
+    w = (1 << cs.level.astype(np.int64))[:, None]
+    near = np.all((cs.xyz + w > lo - halo) & (cs.xyz < hi + halo), axis=1)
+    sub = np.concatenate([np.nonzero(in_slab)[0], np.nonzero(near & ~in_slab)[0]])
+    n_slab = int(in_slab.sum())
+    o = oracle.Oracle(cs.xyz[sub], cs.level[sub], cs.value[sub], validate=False)
+    opl, oids = o.dual_cells(0, n_slab)
+    nd, nt = check(in_slab[owner], opl, oids, o.isosurface(cs.iso, 0, n_slab), sub)
+    _say("slab beside the hole: %d cells, %d duals, %d triangles" % (n_slab, nd, nt))
+    del o
+
     # the set has no overlaps by construction (and the GPU build checked);
     # the oracle's own overlap check takes minutes at this size
     o = oracle.Oracle(cs.xyz, cs.level, cs.value, validate=False)
     _say("oracle index built")
-    c0 = cs.n // 3
-    c1 = c0 + sample
-    opl, oids = o.dual_cells(c0, c1)
-    _say("oracle: %d duals in the sample" % len(opl))
-    sel = (owner >= c0) & (owner < c1)
-    a = oracle.canonical_duals(pl[sel], ids[sel])
-    b = oracle.canonical_duals(opl, oids)
-    assert len(a[0]) == len(b[0]) > 0
-    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
-    ro = o.isosurface(cs.iso, c0, c1)
-    tsel = sel[dg]
-    A, AC, _ = canon_by_cells(tg[tsel], cg[tsel])
-    B, BC, _ = canon_by_cells(ro["tris"], ro["cells"])
-    assert len(A) == len(B) > 0
-    assert np.array_equal(AC, BC)
-    assert same_positions(A, B)
-    # the hole: no dual has a vertex cell inside the obstacle, and the surface
-    # is open only where the dual mesh has a boundary (checked on the sample)
-    assert len(tg) > 0
+    everyone = np.arange(cs.n, dtype=np.int64)
+    for c0 in (cs.n // 3, 2 * cs.n // 3):
+        c1 = c0 + 60000
+        opl, oids = o.dual_cells(c0, c1)
+        nd, nt = check((owner >= c0) & (owner < c1), opl, oids, o.isosurface(cs.iso, c0, c1), everyone)
+        _say("input range [%d, %d): %d duals, %d triangles" % (c0, c1, nd, nt))
 
 
 def _sweep_case(k):

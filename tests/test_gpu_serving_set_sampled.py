@@ -133,9 +133,9 @@ def test_serving_set_sampled(amr, big):
 
 def test_serving_mix_on_the_resident_set(amr, big):
     """Requests served against the 608.9M-cell resident set, mixed with
-    uploads, give what each gives alone: iso requests the same bits in the
-    same order as the plain path, uploads the same triangles (their index is
-    built afresh, so compared in canonical order)."""
+    uploads, give what each gives alone: the same bits in the same order
+    (an upload's index is built afresh, and a build's output order depends
+    on its cells alone)."""
     from paper_2004_08475_amd import serve
 
     xyz, lv, val, iso, s = big
@@ -163,6 +163,4 @@ def test_serving_mix_on_the_resident_set(amr, big):
             assert torch.equal(r.tris, want)
         else:
             alone = amr.from_numpy(req.xyz, req.level, req.value).isosurface(req.iso)["tris"]
-            a = oracle.canonical_triangles(r.tris.cpu().numpy())[0]
-            b = oracle.canonical_triangles(alone.cpu().numpy())[0]
-            assert np.array_equal(a, b)
+            assert torch.equal(r.tris, alone)
