@@ -3167,6 +3167,7 @@ __global__ void k_zero2(unsigned long long* out) {
 constexpr int kSmpPer = 16;  // cells per thread in the offset scan (4096 per work-group)
 constexpr int kSmpNewton = 40;
 constexpr double kSmpEps = 1e-9;
+constexpr int kSmpBatch = 8;  // candidate duals whose boxes a query loads at once
 constexpr double kSmpDet = 1e-14;
 
 // the dual's distinct vertex cells: slot s counts unless an earlier slot
@@ -3426,55 +3427,74 @@ __global__ __launch_bounds__(256) void k_smp_query(SampleArgs a) {
         if (c >= 0) {
             int4 bkey = make_int4(0, 0, 0, 0x7fffffff);
             const int64_t e1 = a.off[c + 1];
-            for (int64_t e = a.off[c]; e < e1; ++e) {
-                const int64_t d = a.ent[e];
-                const int4 key = reinterpret_cast<const int4*>(a.corner_level)[d];
-                if (best >= 0 && !smp_key_less(key, bkey)) continue;
-                // the dual's box, then its cells
-                const float4 b0 = a.box[2 * d], b1 = a.box[2 * d + 1];
-                if (!(p[0] >= (double)b0.x - kSmpEps && p[0] <= (double)b1.x + kSmpEps &&
-                      p[1] >= (double)b0.y - kSmpEps && p[1] <= (double)b1.y + kSmpEps &&
-                      p[2] >= (double)b0.z - kSmpEps && p[2] <= (double)b1.z + kSmpEps))
-                    continue;
-                int32_t v[8];
-                smp_load_verts(a.verts, d, v);
-                double V[8][3];
-                bool good = true;
+            // candidates kSmpBatch at a time: their indices, then their boxes,
+            // each batch's loads in flight together (cells beside much finer
+            // ones have thousands of candidates, and one candidate at a time
+            // paid two dependent loads for each); then the few whose box
+            // holds the point, in list order
+            for (int64_t e0 = a.off[c]; e0 < e1; e0 += kSmpBatch) {
+                int64_t dd[kSmpBatch];
 #pragma unroll
-                for (int s = 0; s < 8; ++s) {
-                    const int64_t id = v[s];
-                    good = good && id >= 0 && id < a.n;
-                    const int64_t ci = good ? id : 0;
-                    const double h = 0.5 * (double)(1 << a.lvl[ci]);
+                for (int u = 0; u < kSmpBatch; ++u) dd[u] = e0 + u < e1 ? (int64_t)a.ent[e0 + u] : -1;
+                uint32_t hits = 0;
 #pragma unroll
-                    for (int ax = 0; ax < 3; ++ax) V[s][ax] = (double)a.xyz[3 * ci + ax] + h;
+                for (int u = 0; u < kSmpBatch; ++u) {
+                    if (dd[u] < 0) continue;
+                    const float4 b0 = a.box[2 * dd[u]], b1 = a.box[2 * dd[u] + 1];
+                    if (p[0] >= (double)b0.x - kSmpEps && p[0] <= (double)b1.x + kSmpEps &&
+                        p[1] >= (double)b0.y - kSmpEps && p[1] <= (double)b1.y + kSmpEps &&
+                        p[2] >= (double)b0.z - kSmpEps && p[2] <= (double)b1.z + kSmpEps)
+                        hits |= 1u << u;
                 }
-                if (!good) continue;
-                // the map sends each cube corner to its slot's cell centre
-                // exactly: a vertex cell centred at p settles it (first slot)
-                int at = -1;
-#pragma unroll
-                for (int s = 7; s >= 0; --s)
-                    if (V[s][0] == p[0] && V[s][1] == p[1] && V[s][2] == p[2]) at = s;
-                if (at >= 0) {
+                for (; hits; hits &= hits - 1) {
+                    const int hu = __ffs(hits) - 1;
+                    int64_t d = dd[0];
+    #pragma unroll
+                    for (int u = 1; u < kSmpBatch; ++u)
+                        if (hu == u) d = dd[u];
+                    const int4 key = reinterpret_cast<const int4*>(a.corner_level)[d];
+                    if (best >= 0 && !smp_key_less(key, bkey)) continue;
+                    // the dual's cells
+                    int32_t v[8];
+                    smp_load_verts(a.verts, d, v);
+                    double V[8][3];
+                    bool good = true;
+    #pragma unroll
+                    for (int s = 0; s < 8; ++s) {
+                        const int64_t id = v[s];
+                        good = good && id >= 0 && id < a.n;
+                        const int64_t ci = good ? id : 0;
+                        const double h = 0.5 * (double)(1 << a.lvl[ci]);
+    #pragma unroll
+                        for (int ax = 0; ax < 3; ++ax) V[s][ax] = (double)a.xyz[3 * ci + ax] + h;
+                    }
+                    if (!good) continue;
+                    // the map sends each cube corner to its slot's cell centre
+                    // exactly: a vertex cell centred at p settles it (first slot)
+                    int at = -1;
+    #pragma unroll
+                    for (int s = 7; s >= 0; --s)
+                        if (V[s][0] == p[0] && V[s][1] == p[1] && V[s][2] == p[2]) at = s;
+                    if (at >= 0) {
+                        best = d;
+                        bkey = key;
+                        value = a.val[v[at]];
+                        continue;
+                    }
+                    double u[3];
+                    if (!smp_invert(V, p, u)) continue;
+                    double f = 0.0;
+    #pragma unroll
+                    for (int s = 0; s < 8; ++s) {
+                        const double ux = fmin(fmax(u[0], 0.0), 1.0), uy = fmin(fmax(u[1], 0.0), 1.0),
+                                     uz = fmin(fmax(u[2], 0.0), 1.0);
+                        const double w = ((s & 1) ? ux : 1.0 - ux) * ((s & 2) ? uy : 1.0 - uy) * ((s & 4) ? uz : 1.0 - uz);
+                        f += w * (double)a.val[v[s]];
+                    }
                     best = d;
                     bkey = key;
-                    value = a.val[v[at]];
-                    continue;
+                    value = (float)f;
                 }
-                double u[3];
-                if (!smp_invert(V, p, u)) continue;
-                double f = 0.0;
-#pragma unroll
-                for (int s = 0; s < 8; ++s) {
-                    const double ux = fmin(fmax(u[0], 0.0), 1.0), uy = fmin(fmax(u[1], 0.0), 1.0),
-                                 uz = fmin(fmax(u[2], 0.0), 1.0);
-                    const double w = ((s & 1) ? ux : 1.0 - ux) * ((s & 2) ? uy : 1.0 - uy) * ((s & 4) ? uz : 1.0 - uz);
-                    f += w * (double)a.val[v[s]];
-                }
-                best = d;
-                bkey = key;
-                value = (float)f;
             }
         }
         a.out[q] = value;
