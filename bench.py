@@ -8,19 +8,21 @@ and is read once after the timed steps) and extract the iso-surface
 the step rate of the ~2M-cell octree (octree-shell-256-2m).  Every kernel of
 the step is timed on its own with HIP events around the kernel (recorded on
 the stream it runs on); the dominant one is timed in every timed step and
-gives the roofline (HBM; counter figures from the committed summary under
-profiles/ while the kernel source is unchanged).
+gives the roofline (HBM, against the 8 TB/s peak and against a plain 1 GiB
+device copy measured in the same run; counter figures from the committed
+summary under profiles/ while the kernel source is unchanged).
 
 Beside the headline, the JSON line holds: iso latency and repeated isos on
 the built set; the dual mesh as an interpolant (point queries on the
 headline set); the same step on the 137k-cell octree of the literal recipe
 and on the 50.8M-cell block-structured set with holes; the host-to-host
 pipeline (PCIe-inclusive); 64 isos of the headline set in one batched
-launch and 32 uneven sets (10k..5M cells) in one batched launch, each
-against the plain path; serving a Poisson request mix against the
-608.9M-cell resident octree against the serial plain path; and the CPU
-oracle's rate on the headline set, on a sample of the 50.8M-cell set and on
-the 32 sets.
+run and 32 uneven sets (10k..5M cells) in one batched run, each against
+the plain path; on the 608.9M-cell resident octree, 64 isos in one batched
+run against the plain path and serving a Poisson request mix against the
+serial plain path; the index comparison (hash against sorted cells); and
+the CPU oracle's rate on the headline set, on a sample of the 50.8M-cell
+set and on the 32 sets.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -251,6 +253,27 @@ def alg_bytes(amr, kernel, n_cells, n_tri, fused):
     if kernel == amr.KERNEL_WRITE:
         return 36.0 * n_tri
     return None
+
+
+def copy_peak_gbs(mib=1024, reps=10):
+    """Measured HBM bandwidth of a plain device copy (torch.mul by 1 of a
+    `mib` MiB float32 tensor into another): bytes read + written / time,
+    HIP events around `reps` copies."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.mul(a, 1.0, out=b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.mul(a, 1.0, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * n * 4 / (ms * 1e-3) / 1e9
 
 
 def roofline_of(name, alg, kernel_ms, counters, launches):
@@ -810,6 +833,10 @@ def main():
         torch.cuda.synchronize()
 
     ms_per_step = r["ms_per_step"]
+    # the roofline also against what a plain copy reaches on this GPU
+    copy_gbs = copy_peak_gbs()
+    r["roofline"]["measured_copy_gbs"] = copy_gbs
+    r["roofline"]["frac_of_copy"] = r["roofline"]["achieved"] / copy_gbs
     out = {
         "metric": METRIC,
         "value": cs.n / (ms_per_step * 1e-3),
