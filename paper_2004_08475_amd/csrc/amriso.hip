@@ -77,7 +77,7 @@ enum : uint32_t { kErrLevel = 1, kErrAlign = 2, kErrValue = 4, kErrCoord = 8 };
 struct alignas(64) Record {
     float val[8];
     uint64_t key;
-    uint32_t homed;  // group keys whose home slot this is (counted as they are created)
+    uint32_t homed;  // group keys homed at this slot that sit elsewhere (counted as they are created)
     uint32_t pad[5];
 };
 static_assert(sizeof(Record) == 64, "record is one 64-byte line");
@@ -616,7 +616,8 @@ __device__ __forceinline__ int same_key_leader(uint64_t key, bool active) {
 // Every cell stores its value in its group record (a plain store: a
 // duplicate cell overwrites its twin and shows up later as a missing leaf in
 // the count of the compaction).  The cell that creates a group's record
-// counts the key at the key's home slot, which orders the group list.
+// away from the key's home slot counts the key there (a key at home is
+// counted by the compaction), which orders the group list.
 // Input indices are filled in later, and only when an output asks for them
 // (k_index_ids).
 __global__ __launch_bounds__(256) void k_index_insert(const int32_t* __restrict__ xyz, const int32_t* __restrict__ lvl,
@@ -643,7 +644,10 @@ __global__ __launch_bounds__(256) void k_index_insert(const int32_t* __restrict_
         if (live && leader == lane) {
             uint32_t created = 0;
             slot = find_or_insert(rec, key, g, &created);
-            if (created) atomicAdd(&rec[slot_of(key, g.shift)].homed, 1u);
+            if (created) {
+                const uint32_t hs = slot_of(key, g.shift);
+                if ((uint32_t)slot != hs) atomicAdd(&rec[hs].homed, 1u);  // a key at home counts itself
+            }
         }
         slot = __shfl(slot, leader, 64);
         if (!live) continue;
@@ -787,8 +791,9 @@ __global__ __launch_bounds__(256) void k_index_find_dup(const int32_t* __restric
 // ordered by (home slot, key).  That order is a function of the set of
 // cells alone: which of two colliding keys won a slot is not, so neither is
 // plain slot order.  Every key homed at slot h lies on h's probe sequence
-// (the sequence depends on the slot only), and h's record counts them, so
-// a block scan plus look-back over the counts of tiles of slots gives each
+// (the sequence depends on the slot only), and h's record counts those that
+// sit elsewhere (the one at h, if homed there, is seen here), so a block
+// scan plus look-back over the counts of tiles of slots gives each
 // home its first list position; a home with one key that sits at home (the
 // common case) writes it at once, others walk their probe sequence and write
 // their keys in ascending order.  Also counts all occupied records (groups
@@ -822,8 +827,9 @@ __global__ __launch_bounds__(kBlock) void k_index_compact(const Record* __restri
         const uint32_t s = base + r * kBlock + t;
         if (s >= cap) continue;
         const Record& R = rec[s];
-        homed[r] = R.homed;
-        if (R.key == kEmpty) continue;
+        const uint64_t key = R.key;
+        homed[r] = R.homed + (key != kEmpty && slot_of(key, shift) == s ? 1u : 0u);
+        if (key == kEmpty) continue;
         const float4* pv = reinterpret_cast<const float4*>(R.val);
         float4 a = pv[0], b = pv[1];
         uint32_t leaves = (a.x == a.x) + (a.y == a.y) + (a.z == a.z) + (a.w == a.w) + (b.x == b.x) + (b.y == b.y) +
