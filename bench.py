@@ -256,19 +256,20 @@ def alg_bytes(amr, kernel, n_cells, n_tri, fused):
 
 
 def copy_peak_gbs(mib=1024, reps=10):
-    """Measured HBM bandwidth of a plain device copy (torch.mul by 1 of a
-    `mib` MiB float32 tensor into another): bytes read + written / time,
-    HIP events around `reps` copies."""
+    """Measured HBM bandwidth of a plain device-to-device copy of `mib` MiB
+    (Tensor.copy_, the runtime's copy kernel): bytes read + written / time,
+    HIP events around `reps` copies.  (The counter-scale probe of
+    --copy-probe-mib is a different kernel, so the two never mix.)"""
     import torch
 
     n = mib * (1 << 20) // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
-    torch.mul(a, 1.0, out=b)
+    b.copy_(a)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        torch.mul(a, 1.0, out=b)
+        b.copy_(a)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps

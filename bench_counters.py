@@ -71,6 +71,8 @@ def durations(d):
 
 
 def copy_kernel(c):
+    """The probe of `bench.py --copy-probe-mib 256` (torch.mul by 1 into a
+    second tensor), the run's only float multiply kernel."""
     ks = [k for k in c if "MulFunctor<float>" in k]
     if len(ks) != 1:
         raise SystemExit("no unique copy-probe kernel among %s" % sorted(c))
