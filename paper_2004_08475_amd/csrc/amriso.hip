@@ -8,7 +8,7 @@
 // Data layout in HBM
 //   input (caller, borrowed): SoA  xyz int32[n][3], level int32[n], value f32[n]
 //   index workspace (caller): records | cell ids | group list + keys | scan states
-//     record (64 B, one per hash slot): val f32[8] | key u64 | pad
+//     record (64 B, one per hash slot): val f32[8] | key u64 | homed u32 | pad
 //       A record belongs to one 2x2x2 block of level-m logical cells (a
 //       "group"): key = (m, block coordinates).  val[c] is the value of
 //       child c (c = bx + 2 by + 4 bz) when that child is an actual cell of
@@ -19,7 +19,9 @@
 //       (Morton order inside), so neighbours share a few cache lines.
 //     cell ids  int32[slots][8]: input index of the cell in each child slot,
 //       filled in when an output first asks for cell indices
-//     group list int32[] + keys u64[]: the records that hold at least one cell
+//     group list int32[] + keys u64[]: the records that hold at least one
+//       cell, ordered by (home slot, key) -- a function of the cells alone,
+//       unlike slot order, which follows the races of the insertion
 //     scan states: look-back words of the compaction and of the extraction
 //
 // Extraction kernel (paper sec. 4.2-5): one work-group processes 32 groups,
@@ -36,6 +38,12 @@
 // whose tiles find their output positions by a decoupled look-back; large
 // sets run a count pass, a scan of the tile totals and a write pass, so no
 // tile waits for another.  Output positions are deterministic either way.
+//
+// Also here: batched runs of many (set, iso) jobs (a unit of groups loaded
+// once per pass for all jobs of its set), the dual mesh as an interpolant
+// (a cell-to-dual map and point queries), the paper's own sorted-cells
+// index beside the hash (for the comparison), and the weld of fat triangles
+// into an indexed face set.
 
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
