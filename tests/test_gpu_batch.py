@@ -1,4 +1,4 @@
-"""Batched iso-surfaces (one persistent launch over many (set, iso) jobs).
+"""Batched iso-surfaces (one batched run over many (set, iso) jobs).
 
 Every job's output must equal the CPU oracle's iso-surface of its set at its
 iso: the triangle count, the triangle positions bit for bit, and (through
