@@ -81,3 +81,55 @@ def test_cpu_baseline_reports_one_thread_and_brute_force():
     assert r["kind"] == "oracle" and r["unit"] == "cells/s" and r["value"] > 0 and r["cores"] >= 1
     assert r["one_thread"]["value"] > 0
     assert r["brute_force"]["cells"] == 960 and r["brute_force"]["value"] > 0
+
+
+def _csv(path, header, rows):
+    import csv
+
+    path.parent.mkdir(parents=True, exist_ok=True)
+    with open(path, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def test_counter_summary_from_rocprof_csv(tmp_path):
+    """bench_counters.py: per-kernel means per dispatch, the copy probe's
+    scale (FETCH_SIZE reads half of what the copy moves, WRITE_SIZE all of
+    it), L2 hit rate and VALU issue fraction; the summary parses back
+    through bench.counters_for while the source is unchanged."""
+    import bench_counters
+
+    mul = "void at::native::vectorized_elementwise_kernel<4, at::native::AUnaryFunctor<float, float, float, " \
+          "at::native::binary_internal::MulFunctor<float> > >(int, F)"
+    kern = "(anonymous namespace)::k_extract<false, 0>((anonymous namespace)::ExtractArgs)"
+    hdr = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    _csv(tmp_path / "f" / "x" / "run_counter_collection.csv", hdr,
+         [[1, kern, "FETCH_SIZE", 100.0], [2, kern, "FETCH_SIZE", 300.0], [3, mul, "FETCH_SIZE", 131072.0]])
+    _csv(tmp_path / "w" / "run_counter_collection.csv", hdr,
+         [[1, kern, "WRITE_SIZE", 10.0], [2, kern, "WRITE_SIZE", 30.0], [3, mul, "WRITE_SIZE", 262144.0]])
+    _csv(tmp_path / "t" / "run_counter_collection.csv", hdr,
+         [[1, kern, "TCC_HIT_sum", 80.0], [1, kern, "TCC_MISS_sum", 20.0]])
+    _csv(tmp_path / "s" / "run_counter_collection.csv", hdr,
+         [[1, kern, "SQ_INSTS_VALU", 614.4e3], [1, kern, "SQ_WAVES", 64.0]])
+    _csv(tmp_path / "d" / "run_kernel_stats.csv", ["Name", "Calls", "TotalDurationNs", "AverageNs"],
+         [[kern, 2, 4000, 2000.0], [mul, 1, 500, 500.0]])
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench_counters.py"), "--workload", "wl",
+                          "--trace", str(tmp_path / "d"), "--fetch", str(tmp_path / "f"), "--write",
+                          str(tmp_path / "w"), "--tcc", str(tmp_path / "t"), "--sq", str(tmp_path / "s"),
+                          "--command", "rocprofv3 ..."], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0, out.stderr
+    lines = out.stdout.splitlines()
+    line = [ln for ln in lines if ln.startswith("kernel ")]
+    assert len(line) == 1 and line[0].startswith("kernel k_extract<false, 0> | ")
+    f = line[0].split(" | ", 1)[1].split()
+    c = {k: v for k, v in zip(f[0::2], f[1::2])}
+    # fetch (100 + 300) / 2 KiB x 2, write (10 + 30) / 2 KiB x 1
+    assert float(c["fetch_bytes"]) == 400.0 * 1024 and float(c["write_bytes"]) == 20.0 * 1024
+    assert float(c["traffic_bytes"]) == 420.0 * 1024
+    assert c["l2_hit"] == "0.8000" and c["mall_hit"] == "-"
+    # 614.4e3 wave instructions in 2 us = 3.072e11/s, half the issue peak
+    assert c["valu_issue"] == "0.5000" and c["avg_us"] == "2.00"
+    assert bench_counters.short_name(kern) == "k_extract<false, 0>"
+    sha = [ln.split()[1] for ln in lines if ln.startswith("source_sha256")]
+    assert sha and len(sha[0]) == 64
