@@ -532,15 +532,16 @@ __global__ __launch_bounds__(256) void k_build_reset(Record* __restrict__ rec, u
                                                      unsigned long long* fs0, unsigned long long* fs1,
                                                      unsigned long long* ls0, unsigned long long* ls1, uint32_t nl,
                                                      Ctrl* c) {
-    const float e = __uint_as_float(kValEmpty);
     const uint32_t i0 = blockIdx.x * blockDim.x + threadIdx.x, step = gridDim.x * blockDim.x;
-    for (uint32_t i = i0; i < cap; i += step) {
-        Record r;
-        for (int k = 0; k < 8; ++k) r.val[k] = e;
-        r.key = kEmpty;
-        r.homed = 0;
-        for (int k = 0; k < 5; ++k) r.pad[k] = 0;
-        rec[i] = r;
+    // the table as 16-byte quarters of records, consecutive lanes on
+    // consecutive quarters: values (two quarters of NaN), then key (all ones),
+    // homed and padding (zero)
+    static_assert(offsetof(Record, key) == 32 && offsetof(Record, homed) == 40, "record quarters");
+    uint4* q = reinterpret_cast<uint4*>(rec);
+    for (uint32_t i = i0; i < cap * 4u; i += step) {
+        const uint32_t part = i & 3u;
+        const uint32_t w = part < 2 ? kValEmpty : 0u, kw = part == 2 ? 0xffffffffu : w;
+        q[i] = make_uint4(kw, kw, w, w);
     }
     for (uint32_t i = i0; i < nc; i += step) {
         ct0[i] = 0;
@@ -1821,7 +1822,7 @@ __global__ __launch_bounds__(kBlock) void k_extract_list(ExtractArgs a) {
 
 constexpr uint32_t kPosValid = 0x80u, kPosAbove = 0x40u, kPosLevel = 0x1Fu;
 constexpr uint32_t kLaneCountMinGroups = 1u << 21;  // group bound from which full count passes use k_count
-constexpr int kCountBatch = 3;  // neighbours whose home slots are read at once (3 of 9 and 27 measured fastest)
+constexpr int kCountBatch = 3;  // neighbours whose home slots are read at once (3 of 1, 2, 9 and 27 measured fastest)
 
 template <int p>
 __device__ __forceinline__ uint32_t pos_byte(const uint32_t (&pos)[16]) {
@@ -4224,7 +4225,7 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     int log2cap = 0;
     while ((1u << log2cap) < cap) ++log2cap;
     {
-        uint32_t work = cap > L.compact_tiles ? cap : L.compact_tiles;
+        uint32_t work = cap * 4u > L.compact_tiles ? cap * 4u : L.compact_tiles;  // a lane per record quarter
         if (work < kFusedMaxTiles) work = kFusedMaxTiles;
         launch(s, AMR_KERNEL_RESET, "k_build_reset", k_build_reset, dim3(grid_for(work, 256)), dim3(256), stream, s->rec, cap,
                64 - log2cap, s->sched, s->ct0, s->ct1, L.compact_tiles, s->fs0, s->fs1, s->ls0, s->ls1,
