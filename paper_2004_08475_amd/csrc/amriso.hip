@@ -828,23 +828,42 @@ __global__ __launch_bounds__(kBlock) void k_index_compact(const Record* __restri
     // precedes row r+1 in slot order
     const uint32_t base = tile * (uint32_t)(kBlock * per);
     uint32_t homed[kCompactMaxPerThread], excl[kCompactMaxPerThread];
-    unsigned long long n_rec = 0;
 #pragma unroll
-    for (int r = 0; r < kCompactMaxPerThread; ++r) {
-        homed[r] = 0;
-        if (r >= per) continue;
-        const uint32_t s = base + r * kBlock + t;
-        if (s >= cap) continue;
-        const Record& R = rec[s];
-        const uint64_t key = R.key;
-        homed[r] = R.homed + (key != kEmpty && slot_of(key, shift) == s ? 1u : 0u);
-        if (key == kEmpty) continue;
-        const float4* pv = reinterpret_cast<const float4*>(R.val);
-        float4 a = pv[0], b = pv[1];
-        uint32_t leaves = (a.x == a.x) + (a.y == a.y) + (a.z == a.z) + (a.w == a.w) + (b.x == b.x) + (b.y == b.y) +
-                          (b.z == b.z) + (b.w == b.w);
-        // records in the low 29 bits, leaves above (cap <= 2^28 keeps them apart)
-        n_rec += 1ull + ((unsigned long long)leaves << 29);
+    for (int r = 0; r < kCompactMaxPerThread; ++r) homed[r] = 0;
+    unsigned long long n_rec = 0;
+    // rows in batches of four, each record's first three quarters loaded
+    // whatever its key (one line either way), so that a batch's loads are
+    // all in flight together
+#pragma unroll
+    for (int r0 = 0; r0 < kCompactMaxPerThread; r0 += 4) {
+        if (r0 >= per) break;
+        uint4 q0[4], q1[4], q2[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t s = base + (r0 + j) * kBlock + t;
+            const bool in = r0 + j < per && s < cap;
+            const uint4* pq = reinterpret_cast<const uint4*>(rec + (in ? s : 0u));
+            q0[j] = pq[0];
+            q1[j] = pq[1];
+            q2[j] = pq[2];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = r0 + j;
+            const uint32_t s = base + r * kBlock + t;
+            if (r >= per || s >= cap) continue;
+            const uint64_t key = ((uint64_t)q2[j].y << 32) | q2[j].x;
+            homed[r] = q2[j].z + (key != kEmpty && slot_of(key, shift) == s ? 1u : 0u);
+            if (key == kEmpty) continue;
+            const float a[8] = {__uint_as_float(q0[j].x), __uint_as_float(q0[j].y), __uint_as_float(q0[j].z),
+                                __uint_as_float(q0[j].w), __uint_as_float(q1[j].x), __uint_as_float(q1[j].y),
+                                __uint_as_float(q1[j].z), __uint_as_float(q1[j].w)};
+            uint32_t leaves = 0;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) leaves += a[c] == a[c] ? 1u : 0u;
+            // records in the low 29 bits, leaves above (cap <= 2^28 keeps them apart)
+            n_rec += 1ull + ((unsigned long long)leaves << 29);
+        }
     }
     // per row, each lane's keys before its own within the wave (a ballot
     // when no slot of the row is home to two or more keys, else a scan)
