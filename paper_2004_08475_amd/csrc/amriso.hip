@@ -75,6 +75,11 @@ constexpr int kTriList = 256;           // triangle entries staged per round
 constexpr uint32_t kMaxCap = 1u << 28;  // slot * 8 + child fits int32
 constexpr uint32_t kMaxProbe = 1024;    // longer chains mean the table is too full
 constexpr int kCompactMaxPerThread = 16;
+// Threads per work-group of the compaction: each work-group takes one
+// ticket and one look-back step, so fewer, larger tiles (measured: 2^20
+// slots 61 us against 66 with 256 threads and 62 with 1024; 2^24 slots
+// 0.41 ms against 0.50 and 0.39)
+constexpr int kCompactBlock = 512;
 constexpr int kReplicas = 64;           // spread of the upload reduction atomics
 constexpr uint32_t kFusedMaxTiles = 2048;  // sets up to this many tiles extract in one fused pass
 constexpr uint32_t kXcds = 8;              // accelerator complex dies of an MI355X
@@ -808,13 +813,13 @@ __global__ __launch_bounds__(256) void k_index_find_dup(const int32_t* __restric
 // their keys in ascending order.  Also counts all occupied records (groups
 // plus marker-only records) and their leaves.  At this point of a build
 // every record is a group's.
-__global__ __launch_bounds__(kBlock) void k_index_compact(const Record* __restrict__ rec, uint32_t cap,
+__global__ __launch_bounds__(kCompactBlock) void k_index_compact(const Record* __restrict__ rec, uint32_t cap,
                                                           int32_t* __restrict__ glist,
                                                           unsigned long long* __restrict__ gkey, unsigned long long* s0,
                                                           unsigned long long* s1, Sched* sc, uint32_t n_tiles,
                                                           int per, Ctrl* c) {
-    __shared__ uint32_t s_rcount[kCompactMaxPerThread][kBlock / 64];
-    __shared__ unsigned long long s_wave[kBlock / 64];
+    __shared__ uint32_t s_rcount[kCompactMaxPerThread][kCompactBlock / 64];
+    __shared__ unsigned long long s_wave[kCompactBlock / 64];
     __shared__ unsigned long long s_pre0;
     __shared__ uint32_t s_tile;
     const int t = threadIdx.x;
@@ -824,9 +829,9 @@ __global__ __launch_bounds__(kBlock) void k_index_compact(const Record* __restri
     __syncthreads();
     const uint32_t tile = s_tile;
     const int shift = c->geo.shift;
-    // thread t looks at slots base + r*256 + t, r < per (coalesced); row r
+    // thread t looks at slots base + r*512 + t, r < per (coalesced); row r
     // precedes row r+1 in slot order
-    const uint32_t base = tile * (uint32_t)(kBlock * per);
+    const uint32_t base = tile * (uint32_t)(kCompactBlock * per);
     uint32_t homed[kCompactMaxPerThread], excl[kCompactMaxPerThread];
 #pragma unroll
     for (int r = 0; r < kCompactMaxPerThread; ++r) homed[r] = 0;
@@ -840,7 +845,7 @@ __global__ __launch_bounds__(kBlock) void k_index_compact(const Record* __restri
         uint4 q0[4], q1[4], q2[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const uint32_t s = base + (r0 + j) * kBlock + t;
+            const uint32_t s = base + (r0 + j) * kCompactBlock + t;
             const bool in = r0 + j < per && s < cap;
             const uint4* pq = reinterpret_cast<const uint4*>(rec + (in ? s : 0u));
             q0[j] = pq[0];
@@ -850,7 +855,7 @@ __global__ __launch_bounds__(kBlock) void k_index_compact(const Record* __restri
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int r = r0 + j;
-            const uint32_t s = base + r * kBlock + t;
+            const uint32_t s = base + r * kCompactBlock + t;
             if (r >= per || s >= cap) continue;
             const uint64_t key = ((uint64_t)q2[j].y << 32) | q2[j].x;
             homed[r] = q2[j].z + (key != kEmpty && slot_of(key, shift) == s ? 1u : 0u);
@@ -890,8 +895,8 @@ __global__ __launch_bounds__(kBlock) void k_index_compact(const Record* __restri
     uint32_t total_g = 0;
     unsigned long long total_r = 0;
     for (int r = 0; r < per; ++r)
-        for (int w = 0; w < kBlock / 64; ++w) total_g += s_rcount[r][w];
-    for (int w = 0; w < kBlock / 64; ++w) total_r += s_wave[w];
+        for (int w = 0; w < kCompactBlock / 64; ++w) total_g += s_rcount[r][w];
+    for (int w = 0; w < kCompactBlock / 64; ++w) total_r += s_wave[w];
     if (wave == 0) {
         unsigned long long p0, p1;
         lookback(s0, s1, tile, 0ull, total_g, total_r, p0, p1);
@@ -910,13 +915,13 @@ __global__ __launch_bounds__(kBlock) void k_index_compact(const Record* __restri
     for (int r = 0; r < kCompactMaxPerThread; ++r) {
         if (r >= per) break;
         uint32_t before = 0, in_row = 0;
-        for (int w = 0; w < kBlock / 64; ++w) {
+        for (int w = 0; w < kCompactBlock / 64; ++w) {
             if (w < wave) before += s_rcount[r][w];
             in_row += s_rcount[r][w];
         }
         const uint32_t n_here = homed[r];
         if (n_here) {
-            const uint32_t h = base + r * kBlock + t;
+            const uint32_t h = base + r * kCompactBlock + t;
             const uint32_t pos = row + before + excl[r];
             const uint64_t k0 = rec[h].key;
             if (n_here == 1 && slot_of(k0, shift) == h) {
@@ -3676,10 +3681,11 @@ Layout layout_for(uint32_t cap) {
     uint32_t max_groups = cap;  // at most one group per slot
     L.max_tiles = (max_groups + kGroupsPerTile - 1) / kGroupsPerTile + 1;
     // small tables: more, smaller compaction tiles (latency); large: fewer
-    // tickets (measured: 2^16 slots 18 us with 256 tiles against 28 us with
-    // 64; 2^20 slots 65 us with 1024 tiles against 93 with 4096 and 77 with 512)
+    // tickets (measured with 256 threads per work-group: 2^16 slots 18 us
+    // with 256 tiles against 28 us with 64; 2^20 slots 65 us with 1024 tiles
+    // against 93 with 4096 and 77 with 512)
     L.compact_per = cap <= (1u << 17) ? 1 : cap <= (1u << 20) ? 4 : kCompactMaxPerThread;
-    uint32_t ctile = (uint32_t)(kBlock * L.compact_per);
+    uint32_t ctile = (uint32_t)(kCompactBlock * L.compact_per);
     L.compact_tiles = (cap + ctile - 1) / ctile;
     size_t off = 0;
     L.rec = off;
@@ -4256,7 +4262,7 @@ int amr_build_index(amr_set* s, void* ws, size_t bytes, hipStream_t stream) {
     // the group list only depends on the leaves, so it is compacted before
     // the ancestors are marked, and the marking runs over it; its last
     // work-group decides the verdict
-    launch(s, AMR_KERNEL_COMPACT, "k_index_compact", k_index_compact, dim3(L.compact_tiles), dim3(kBlock), stream, s->rec, cap,
+    launch(s, AMR_KERNEL_COMPACT, "k_index_compact", k_index_compact, dim3(L.compact_tiles), dim3(kCompactBlock), stream, s->rec, cap,
            s->glist, s->gkey, s->ct0, s->ct1, s->sched, L.compact_tiles, L.compact_per, s->ctrl);
     {
         const int64_t most = s->n < (int64_t)cap ? s->n : (int64_t)cap;  // at least the number of groups
