@@ -2082,10 +2082,13 @@ __global__ __launch_bounds__(256) void k_count(ExtractArgs a) {
 }
 
 // Exclusive scan of the per-tile (triangles, duals) totals of a count pass:
-// 4096 tiles per work-group, decoupled look-back across work-groups (tickets
+// 1024 tiles per work-group, decoupled look-back across work-groups (tickets
 // keep the look-back waiting only on work-groups that already run).  The
-// last work-group writes the grand totals.
-constexpr int kScanPer = 16;
+// last work-group writes the grand totals.  (Measured: 4 rows per thread
+// beat 8 and 16, by 5 us of the 2M-cell octree's 0.26 ms iso call against
+// 16; the scan is a chain of dependent round trips, which more, smaller
+// work-groups shorten.)
+constexpr int kScanPer = 4;
 
 __global__ __launch_bounds__(kBlock) void k_tile_scan(ExtractArgs a, int duals) {
     __shared__ unsigned long long s_row[kScanPer][kBlock / 64];
@@ -2101,7 +2104,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_scan(ExtractArgs a, int duals) 
     const uint64_t base = (uint64_t)st * (kBlock * kScanPer);
     // row r covers tiles base + r*256 + [0, 256); values are packed
     // triangles << 32 | duals, and no half carries inside one work-group
-    // (at most 4096 tiles of at most 4320 triangles each)
+    // (at most 1024 tiles of at most 4320 triangles each)
     unsigned long long v[kScanPer], incl[kScanPer];
     const uint32_t n_entries = a.lcnt ? (uint32_t)*a.n_list : 0u;
 #pragma unroll
