@@ -1,5 +1,7 @@
 """Turn rocprofv3 output of `bench.py` runs on one workload into the counter
-summary `profiles/<workload>_counters.txt` that bench.py reads back.
+summary `profiles/<workload>_counters.txt` that bench.py reads back, or, with
+--kernel-stats, one `--kernel-trace --stats` run into the kernel time summary
+`profiles/<workload>_kernel_stats.txt`.
 
 Inputs: the CSV directories of one `--kernel-trace --stats` run and of four
 `--pmc` runs (FETCH_SIZE; WRITE_SIZE; TCC_HIT_sum TCC_MISS_sum; SQ_INSTS_VALU
@@ -14,6 +16,8 @@ rocprofv3 on gfx950, so its hit rate is '-'.
 
     python bench_counters.py --workload W --trace D0 --fetch D1 --write D2 --tcc D3 --sq D4 \\
         --command "..." > profiles/W_counters.txt
+    python bench_counters.py --kernel-stats --workload W --trace D0 --command "..." \\
+        [--note "..."]... > profiles/W_kernel_stats.txt
 """
 import argparse
 import collections
@@ -70,6 +74,35 @@ def durations(d):
     return out
 
 
+def stats_rows(d):
+    """The library's kernels (names starting k_) of one trace's stats CSV:
+    (name, calls, total, average, min, max), durations in us, longest total
+    first."""
+    rows = []
+    with open(one_csv(d, "kernel_stats.csv")) as fh:
+        for row in csv.DictReader(fh):
+            k = short_name(row["Name"])
+            if k.startswith("k_"):
+                rows.append((k, int(row["Calls"]), float(row["TotalDurationNs"]) / 1e3,
+                             float(row["AverageNs"]) / 1e3, float(row["MinNs"]) / 1e3, float(row["MaxNs"]) / 1e3))
+    return sorted(rows, key=lambda r: -r[2])
+
+
+def kernel_stats(args):
+    print("# rocprofv3 kernel trace summary, one MI355X (ROCm 7.2): %s" % args.workload)
+    print("# Command (repo root $R; run from /tmp with TMPDIR=/tmp):")
+    for ln in args.command.splitlines():
+        print("#   " + ln)
+    print("#   then: python $R/bench_counters.py --kernel-stats --workload %s --trace <out> --command ... --note ..."
+          % args.workload)
+    for ln in args.note:
+        print("# " + ln)
+    print("# From run_kernel_stats.csv: the library's kernels (name without arguments), calls, durations in us.")
+    print("%-30s %5s %12s %12s %12s %12s" % ("kernel", "calls", "total_us", "avg_us", "min_us", "max_us"))
+    for k, calls, tot, avg, lo, hi in stats_rows(args.trace):
+        print("%-30s %5d %12.1f %12.2f %12.2f %12.2f" % (k, calls, tot, avg, lo, hi))
+
+
 def copy_kernel(c):
     """The probe of `bench.py --copy-probe-mib 256` (torch.mul by 1 into a
     second tensor), the run's only float multiply kernel."""
@@ -81,9 +114,19 @@ def copy_kernel(c):
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    for a in ("workload", "trace", "fetch", "write", "tcc", "sq", "command"):
+    ap.add_argument("--kernel-stats", action="store_true", help="summarise the --trace run's kernel times only")
+    for a in ("workload", "trace", "command"):
         ap.add_argument("--" + a, required=True)
+    for a in ("fetch", "write", "tcc", "sq"):
+        ap.add_argument("--" + a)
+    ap.add_argument("--note", action="append", default=[], help="a line describing the run (kernel stats)")
     args = ap.parse_args()
+    if args.kernel_stats:
+        kernel_stats(args)
+        return
+    missing = [a for a in ("fetch", "write", "tcc", "sq") if getattr(args, a) is None]
+    if missing:
+        ap.error("counter summaries need --" + ", --".join(missing))
     dur = durations(args.trace)
     fetch, write, tcc, sq = (counters(getattr(args, a)) for a in ("fetch", "write", "tcc", "sq"))
     ck = copy_kernel(fetch)

@@ -1,5 +1,6 @@
 """Host-side checks of bench.py: the one-GPU contract, the counter lookup
 keyed to the kernel source, the roofline fields (no GPU needed)."""
+import glob
 import os
 import subprocess
 import sys
@@ -133,3 +134,43 @@ def test_counter_summary_from_rocprof_csv(tmp_path):
     assert bench_counters.short_name(kern) == "k_extract<false, 0>"
     sha = [ln.split()[1] for ln in lines if ln.startswith("source_sha256")]
     assert sha and len(sha[0]) == 64
+
+
+def test_kernel_stats_summary_from_rocprof_csv(tmp_path):
+    """bench_counters.py --kernel-stats: the library's kernels only (names
+    starting k_, arguments dropped), durations in us, longest total first,
+    with the command and the notes in the header."""
+    mul = "void at::native::vectorized_elementwise_kernel<4, at::native::AUnaryFunctor<float, float, float, " \
+          "at::native::binary_internal::MulFunctor<float> > >(int, F)"
+    k0 = "(anonymous namespace)::k_index_insert(int const*, int const*, float const*, long)"
+    k1 = "void (anonymous namespace)::k_extract<false, 0>((anonymous namespace)::ExtractArgs)"
+    _csv(tmp_path / "d" / "x" / "run_kernel_stats.csv",
+         ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs", "MaxNs", "StdDev"],
+         [[k0, 2, 3000, 1500.0, 10, 1000, 2000, 1], [mul, 9, 90000, 10000.0, 80, 10000, 10000, 0],
+          [k1, 4, 8000, 2000.0, 10, 1500, 2500, 1]])
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench_counters.py"), "--kernel-stats", "--workload",
+                          "wl", "--trace", str(tmp_path / "d"), "--command", "rocprofv3 ...", "--note", "first",
+                          "--note", "second"], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0, out.stderr
+    lines = out.stdout.splitlines()
+    assert lines[0].endswith(": wl") and "#   rocprofv3 ..." in lines and "# first" in lines and "# second" in lines
+    rows = [ln.split() for ln in lines if ln.startswith("k_")]
+    assert [r[0] for r in rows] == ["k_extract<false,", "k_index_insert"]
+    assert rows[0][2:] == ["4", "8.0", "2.00", "1.50", "2.50"]
+    assert rows[1][1:] == ["2", "3.0", "1.50", "1.00", "2.00"]
+    # counter summaries still need all four counter runs
+    bad = subprocess.run([sys.executable, os.path.join(ROOT, "bench_counters.py"), "--workload", "wl", "--trace",
+                          str(tmp_path / "d"), "--command", "c"], capture_output=True, text=True, timeout=60)
+    assert bad.returncode != 0 and "--fetch" in bad.stderr
+
+
+def test_committed_kernel_stats_summaries_name_their_commands():
+    """Every kernel time summary under profiles/ gives the rocprofv3 command
+    it came from (committed bench.py) and the summary step."""
+    paths = sorted(glob.glob(os.path.join(ROOT, "profiles", "*_kernel_stats.txt")))
+    assert paths
+    for p in paths:
+        text = open(p).read()
+        assert "rocprofv3 --kernel-trace --stats" in text and "$R/bench.py" in text, p
+        assert "bench_counters.py --kernel-stats" in text, p
+        assert any(ln.startswith("k_") for ln in text.splitlines()), p
